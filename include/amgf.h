@@ -1,0 +1,155 @@
+/*
+ * amgf.h -- C ABI of the MI355X (gfx950) AMGF solver library.
+ *
+ * Solves A u = b with A = K + J^T D J, the Schur complement of the interior-point
+ * Newton system (arXiv 2505.18576, Sec. 3, the condensed system), by preconditioned
+ * CG (stopping rule of Sec. 4 / Sec. 6.1: relative preconditioned residual below
+ * rtol, iteration cap) with the multiplicative AMG-with-filtering preconditioner of
+ * Definition 5.3:
+ *     I - M A = (I - B A)(I - P A_w^{-1} P^T A)(I - B A),
+ * where B is one AMG V-cycle on A and P embeds the filtering space of contact DOFs
+ * I_c (Sec. 5.1) with A_w = P^T A P.
+ *
+ * Conventions for every entry point
+ *  - All array arguments are DEVICE pointers unless the comment says "host".
+ *  - The caller owns every pointer it passes; the library never frees them.
+ *    amgf_setup copies what it keeps (stream-ordered on `stream`) and returns once
+ *    the copies are enqueued; inputs must stay valid until `stream` reaches that point.
+ *  - The handle owns all hierarchy memory (allocated with hipMalloc) and releases it
+ *    in amgf_destroy.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call runs on it.
+ *  - Every entry point returns an amgf_status; nothing throws across the ABI.  On an
+ *    error the output arrays are unspecified; amgf_last_error() gives a message.
+ *  - Indices are int32; value arrays are FP64 at the boundary whatever the internal
+ *    precision.  A handle is not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef AMGF_H
+#define AMGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amgf_handle_s* amgf_handle;
+
+typedef enum {
+  AMGF_OK = 0,
+  AMGF_EINVAL = 1,   /* bad sizes / pattern / non-finite input / D <= 0            */
+  AMGF_ENOTSPD = 2,  /* non-positive Cholesky pivot, or p.Ap <= 0 in CG            */
+  AMGF_ENOCONV = 3,  /* max_iters reached; x holds the last iterate                 */
+  AMGF_ENOMEM = 4,   /* device allocation failed or a setup capacity was exceeded   */
+  AMGF_EDEVICE = 5   /* a HIP runtime call failed                                  */
+} amgf_status;
+
+enum { AMGF_FP64 = 0, AMGF_MIXED_FP32 = 1 };          /* V-cycle arithmetic        */
+enum { AMGF_L1JACOBI = 0, AMGF_LEARNED = 2 };         /* smoother damping          */
+
+typedef struct {
+  int32_t struct_size;        /* sizeof(amgf_options), for ABI versioning            */
+  int32_t precision;          /* AMGF_FP64 or AMGF_MIXED_FP32 (FP32 V-cycle, FP64
+                                 contact term, coarse solve, filter and outer CG)     */
+  int32_t smoother;           /* AMGF_L1JACOBI (theta = 1) or AMGF_LEARNED          */
+  int32_t filter;             /* 1: AMGF (Definition 5.3); 0: plain AMG-PCG, M = B   */
+  int32_t max_levels;         /* hierarchy depth cap (default 10)                    */
+  int32_t coarse_max_nodes;   /* stop coarsening at or below this many nodes (256)   */
+  int32_t max_iters;          /* CG iteration cap (default 5000, Sec. 6.1)           */
+  int32_t sa_power_iters;     /* power steps for rho(D_l1^{-1}A) (default 10)        */
+  double strength_theta;      /* level-0 strength threshold (default 0.08)           */
+  double rtol;                /* relative preconditioned residual (default 1e-10)    */
+  double sa_omega;            /* prolongator damping numerator (default 4/3)          */
+  double qr_tol;              /* dead near-null column threshold (default 1e-10)      */
+  double max_coarse_ratio;    /* stop if n_agg > ratio * n_nodes (default 0.9)        */
+  const float* mlp_weights;   /* host; 1313 MLP parameters + 12 feature normalisers,
+                                 required iff smoother == AMGF_LEARNED                */
+} amgf_options;
+
+typedef struct {
+  int32_t iterations;         /* CG iterations performed                              */
+  int32_t converged;          /* 1 if the stopping rule was met                       */
+  int32_t n_levels;           /* AMG levels (1 = dense solve only)                    */
+  int32_t n_c;                /* filtering-space dimension |I_c|                       */
+  double rel_prec_res;        /* sqrt(r.Mr / r0.Mr0) at exit                          */
+  double rel_true_res;        /* ||b - A x|| / ||b|| at exit (FP64)                   */
+  double op_complexity;       /* sum of level nonzeros / level-0 nonzeros             */
+  float ms_solve;             /* wall time of amgf_pcg (hipEvents)                    */
+  int32_t used_fallback;      /* learned smoother fell back to theta = 1              */
+} amgf_solve_info;
+
+/* Fill `o` with the defaults listed above. */
+void amgf_default_options(amgf_options* o);
+
+/* Build the hierarchy and the filter factorisation for
+ *   A = K + J^T diag(D) J,  n = 3 * n_nodes DOFs, m constraints.
+ * K: symmetric BSR with 3x3 row-major blocks: K_rowptr[n_nodes+1], K_col[nnzb]
+ *    (ascending per row, symmetric pattern), K_val[9 * nnzb].  Decoupled DOFs
+ *    (rows without off-diagonal nonzeros, e.g. Dirichlet) are detected.
+ * J: m x n scalar CSR, J_rowptr[m+1], J_col (ascending per row), J_val.
+ * D: m barrier values, all > 0 (Sec. 3: D = diag(M_s z / s)).  m may be 0.
+ * coords: 3 * n_nodes node coordinates (rigid-body near-null space); required.
+ * Ic / n_c: optional filtering-space DOF list (ascending, device); NULL/0 selects
+ *    every DOF of every node that J touches (Sec. 5.1, supp(phi_i) meets the
+ *    contact surface).  The error estimate holds for any full-rank P (Remark 5.5).
+ * Returns EINVAL for inconsistent sizes or D <= 0, ENOTSPD if a Cholesky pivot is
+ * not positive, ENOMEM if an allocation or internal capacity fails.           */
+amgf_status amgf_setup(const amgf_options* opts, int32_t n_nodes,
+                       const int32_t* K_rowptr, const int32_t* K_col, const double* K_val,
+                       int32_t m, const int32_t* J_rowptr, const int32_t* J_col,
+                       const double* J_val, const double* D, const double* coords,
+                       const int32_t* Ic, int32_t n_c, void* stream, amgf_handle* out);
+
+/* z = M r, one application of the AMGF preconditioner (Definition 5.3); r, z: n
+ * FP64 device vectors (may not alias).  With filter = 0, z = B r.            */
+amgf_status amgf_apply(amgf_handle h, const double* r, double* z, void* stream);
+
+/* z = B r, one V-cycle of the AMG part alone (the B of Assumptions 1-2).        */
+amgf_status amgf_vcycle(amgf_handle h, const double* r, double* z, void* stream);
+
+/* y = A x with A = K + J^T D J applied in FP64 (the operator of the CG loop).    */
+amgf_status amgf_operator_apply(amgf_handle h, const double* x, double* y, void* stream);
+
+/* Preconditioned CG for A x = b.  x: initial guess in, solution out (device, n).
+ * Stops when sqrt(r.Mr) <= rtol * sqrt(r0.Mr0) (Sec. 6.1) or after max_iters, then
+ * fills *info (host) and returns AMGF_ENOCONV if not converged.                  */
+amgf_status amgf_pcg(amgf_handle h, const double* b, double* x, amgf_solve_info* info,
+                     void* stream);
+
+/* Release every device buffer of the handle.  NULL is ignored.                   */
+void amgf_destroy(amgf_handle h);
+
+/* Human-readable name of a status code (static string).                           */
+const char* amgf_status_string(amgf_status s);
+
+/* Message of the last error raised on the calling thread (static buffer).          */
+const char* amgf_last_error(void);
+
+/* ---------------- inspection (tests and benchmarks) ---------------------------------
+ * Level data are copied to HOST buffers of the stated size; `which` selects the array:
+ *  AMGF_Q_SIZES    int32[8]: n_nodes, block size, nnzb(A), n_agg, nnzb(P), nnzb(G),
+ *                  nnzb(K), n_isolated
+ *  AMGF_Q_A_ROWPTR/A_COL/A_VAL  assembled operator A_l (BSR b x b, FP64)
+ *  AMGF_Q_AGG      int32[n_nodes] aggregate of each node (-1 = isolated)
+ *  AMGF_Q_ROOT     int32[n_nodes] 1 for MIS-2 roots
+ *  AMGF_Q_G_ROWPTR/G_COL        aggregation graph
+ *  AMGF_Q_P_ROWPTR/P_COL/P_VAL  prolongator P_l (b x 6 blocks)
+ *  AMGF_Q_L1       double[n_nodes*b] l1 row norms d
+ *  AMGF_Q_K_VAL    double stiffness values of level l (pattern = K rowptr/col below)
+ *  AMGF_Q_K_ROWPTR/K_COL
+ *  AMGF_Q_OMEGA    double[2]: rho estimate, prolongator damping
+ *  AMGF_Q_IC       int32[n_c] filtering-space DOFs (level argument ignored)
+ * Returns EINVAL for a bad level or selector; `bytes` must equal the array size.    */
+enum {
+  AMGF_Q_SIZES = 0, AMGF_Q_A_ROWPTR, AMGF_Q_A_COL, AMGF_Q_A_VAL, AMGF_Q_AGG, AMGF_Q_ROOT,
+  AMGF_Q_G_ROWPTR, AMGF_Q_G_COL, AMGF_Q_P_ROWPTR, AMGF_Q_P_COL, AMGF_Q_P_VAL, AMGF_Q_L1,
+  AMGF_Q_K_ROWPTR, AMGF_Q_K_COL, AMGF_Q_K_VAL, AMGF_Q_OMEGA, AMGF_Q_IC
+};
+int32_t amgf_num_levels(amgf_handle h);
+amgf_status amgf_query(amgf_handle h, int32_t level, int32_t which, void* host_dst,
+                       size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMGF_H */

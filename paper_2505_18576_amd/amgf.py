@@ -1,0 +1,250 @@
+"""ctypes binding of ``libamgf.so`` (the C ABI in include/amgf.h).
+
+Argument marshalling only: every step of setup, V-cycle, filter and CG runs in the
+library's HIP kernels.  PyTorch provides device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamgf.so")
+
+AMGF_OK, AMGF_EINVAL, AMGF_ENOTSPD, AMGF_ENOCONV, AMGF_ENOMEM, AMGF_EDEVICE = range(6)
+FP64, MIXED_FP32 = 0, 1
+L1JACOBI, LEARNED = 0, 2
+(Q_SIZES, Q_A_ROWPTR, Q_A_COL, Q_A_VAL, Q_AGG, Q_ROOT, Q_G_ROWPTR, Q_G_COL, Q_P_ROWPTR,
+ Q_P_COL, Q_P_VAL, Q_L1, Q_K_ROWPTR, Q_K_COL, Q_K_VAL, Q_OMEGA, Q_IC) = range(17)
+
+ABI_FUNCTIONS = ["amgf_default_options", "amgf_setup", "amgf_apply", "amgf_vcycle",
+                 "amgf_operator_apply", "amgf_pcg", "amgf_destroy", "amgf_status_string",
+                 "amgf_last_error", "amgf_num_levels", "amgf_query"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("smoother", ctypes.c_int32), ("filter", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("coarse_max_nodes", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32), ("sa_power_iters", ctypes.c_int32),
+                ("strength_theta", ctypes.c_double), ("rtol", ctypes.c_double),
+                ("sa_omega", ctypes.c_double), ("qr_tol", ctypes.c_double),
+                ("max_coarse_ratio", ctypes.c_double),
+                ("mlp_weights", ctypes.POINTER(ctypes.c_float))]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("n_c", ctypes.c_int32),
+                ("rel_prec_res", ctypes.c_double), ("rel_true_res", ctypes.c_double),
+                ("op_complexity", ctypes.c_double), ("ms_solve", ctypes.c_float),
+                ("used_fallback", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libamgf.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_2505_18576_amd.build` (there is no CPU path)")
+    L = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.amgf_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.amgf_default_options.restype = None
+    L.amgf_setup.argtypes = [ctypes.POINTER(Options), i32, vp, vp, vp, i32, vp, vp, vp, vp, vp,
+                             vp, i32, vp, ctypes.POINTER(vp)]
+    L.amgf_setup.restype = ctypes.c_int
+    for f in ("amgf_apply", "amgf_vcycle", "amgf_operator_apply"):
+        getattr(L, f).argtypes = [vp, vp, vp, vp]
+        getattr(L, f).restype = ctypes.c_int
+    L.amgf_pcg.argtypes = [vp, vp, vp, ctypes.POINTER(SolveInfo), vp]
+    L.amgf_pcg.restype = ctypes.c_int
+    L.amgf_destroy.argtypes = [vp]
+    L.amgf_destroy.restype = None
+    L.amgf_status_string.argtypes = [ctypes.c_int]
+    L.amgf_status_string.restype = ctypes.c_char_p
+    L.amgf_last_error.argtypes = []
+    L.amgf_last_error.restype = ctypes.c_char_p
+    L.amgf_num_levels.argtypes = [vp]
+    L.amgf_num_levels.restype = i32
+    L.amgf_query.argtypes = [vp, i32, i32, vp, ctypes.c_size_t]
+    L.amgf_query.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+class AMGFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+def _check(status, what):
+    if status != AMGF_OK:
+        L = load_library()
+        raise AMGFError(status, f"{what}: {L.amgf_status_string(status).decode()}: "
+                                f"{L.amgf_last_error().decode()}")
+
+
+def default_options(**kw):
+    L = load_library()
+    o = Options()
+    L.amgf_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the AMGF library needs a ROCm GPU (torch.cuda is unavailable)")
+    return torch
+
+
+def _dev(x, dtype):
+    torch = _torch()
+    if isinstance(x, torch.Tensor):
+        t = x.to(device="cuda", dtype=dtype)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class AMGF:
+    """Handle of an AMGF hierarchy on the current GPU.
+
+    Inputs may be numpy arrays or torch tensors; they are placed on the GPU with the
+    dtypes of the C ABI (int32 indices, float64 values).
+    """
+
+    def __init__(self, n_nodes, K_rowptr, K_col, K_val, J_rowptr, J_col, J_val, D, coords,
+                 Ic=None, options=None, **kw):
+        torch = _torch()
+        self.L = load_library()
+        self.options = options if options is not None else default_options(**kw)
+        i32, f64 = torch.int32, torch.float64
+        self._keep = [_dev(K_rowptr, i32), _dev(K_col, i32), _dev(K_val, f64),
+                      _dev(J_rowptr, i32), _dev(J_col, i32), _dev(J_val, f64), _dev(D, f64),
+                      _dev(coords, f64)]
+        self.m = int(len(self._keep[3]) - 1)
+        self.n_nodes = int(n_nodes)
+        self.n = 3 * self.n_nodes
+        ic = _dev(Ic, i32) if Ic is not None else None
+        h = ctypes.c_void_p()
+        st = self.L.amgf_setup(ctypes.byref(self.options), self.n_nodes,
+                               *[_ptr(t) for t in self._keep[:3]], self.m,
+                               *[_ptr(t) for t in self._keep[3:]],
+                               _ptr(ic), 0 if ic is None else int(ic.numel()), _stream(),
+                               ctypes.byref(h))
+        _check(st, "amgf_setup")
+        self.h = h
+        torch.cuda.synchronize()
+        self._keep = None
+
+    @classmethod
+    def from_problem(cls, p, **kw):
+        return cls(p.n_nodes, p.K_rowptr, p.K_col, p.K_val.reshape(-1), p.J_rowptr, p.J_col,
+                   p.J_val, p.D, p.coords.reshape(-1), **kw)
+
+    def _vec_op(self, fn, x, name):
+        torch = _torch()
+        xd = _dev(x, torch.float64)
+        y = torch.empty_like(xd)
+        _check(fn(self.h, _ptr(xd), _ptr(y), _stream()), name)
+        return y
+
+    def apply(self, r):
+        return self._vec_op(self.L.amgf_apply, r, "amgf_apply")
+
+    def vcycle(self, r):
+        return self._vec_op(self.L.amgf_vcycle, r, "amgf_vcycle")
+
+    def operator(self, x):
+        return self._vec_op(self.L.amgf_operator_apply, x, "amgf_operator_apply")
+
+    def pcg(self, b, x0=None, raise_on_noconv=False):
+        torch = _torch()
+        bd = _dev(b, torch.float64)
+        x = torch.zeros_like(bd) if x0 is None else _dev(x0, torch.float64).clone()
+        info = SolveInfo()
+        st = self.L.amgf_pcg(self.h, _ptr(bd), _ptr(x), ctypes.byref(info), _stream())
+        if st == AMGF_ENOCONV and not raise_on_noconv:
+            return x, info
+        _check(st, "amgf_pcg")
+        return x, info
+
+    @property
+    def n_levels(self):
+        return int(self.L.amgf_num_levels(self.h))
+
+    def query(self, level, which, dtype=None, count=None):
+        """Copy one hierarchy array of ``level`` to a numpy array."""
+        if which == Q_SIZES:
+            out = np.zeros(8, np.int32)
+        elif which == Q_OMEGA:
+            out = np.zeros(2, np.float64)
+        else:
+            out = np.zeros(count, dtype)
+        st = self.L.amgf_query(self.h, level, which, out.ctypes.data_as(ctypes.c_void_p),
+                               out.nbytes)
+        _check(st, "amgf_query")
+        return out
+
+    def level_arrays(self, level):
+        """Dict of the level's operator, aggregation and prolongator arrays."""
+        s = self.query(level, Q_SIZES)
+        nn, b, nnzA, n_agg, nnzP, nnzG, nnzK = [int(v) for v in s[:7]]
+        q = self.query
+        d = dict(n_nodes=nn, b=b, n_agg=n_agg,
+                 A_rowptr=q(level, Q_A_ROWPTR, np.int32, nn + 1),
+                 A_col=q(level, Q_A_COL, np.int32, nnzA),
+                 A_val=q(level, Q_A_VAL, np.float64, nnzA * b * b).reshape(-1, b, b),
+                 K_rowptr=q(level, Q_K_ROWPTR, np.int32, nn + 1),
+                 K_col=q(level, Q_K_COL, np.int32, nnzK),
+                 K_val=q(level, Q_K_VAL, np.float64, nnzK * b * b).reshape(-1, b, b),
+                 l1=q(level, Q_L1, np.float64, nn * b))
+        if n_agg:
+            d.update(agg=q(level, Q_AGG, np.int32, nn), root=q(level, Q_ROOT, np.int32, nn),
+                     G_rowptr=q(level, Q_G_ROWPTR, np.int32, nn + 1),
+                     G_col=q(level, Q_G_COL, np.int32, nnzG),
+                     P_rowptr=q(level, Q_P_ROWPTR, np.int32, nn + 1),
+                     P_col=q(level, Q_P_COL, np.int32, nnzP),
+                     P_val=q(level, Q_P_VAL, np.float64, nnzP * b * 6).reshape(-1, b, 6),
+                     rho_omega=q(level, Q_OMEGA))
+        return d
+
+    def filter_dofs(self, n_c):
+        return self.query(0, Q_IC, np.int32, n_c)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.amgf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,627 @@
+// Host runtime and C ABI of the AMGF library: hierarchy setup, V-cycle, the AMGF
+// preconditioner of Definition 5.3 and the preconditioned CG driver.
+#include <chrono>
+#include <cmath>
+#include <memory>
+
+#include "apply.h"
+#include "dense.h"
+#include "setup.h"
+
+namespace amgf {
+
+struct Level {
+  int nn = 0, b = 0;            // block rows (nodes) and block size
+  BSR A;                        // assembled operator (kept for inspection)
+  BSR K;                        // stiffness part (FP64 + FP32 copy in mixed mode)
+  BSR J, JT;                    // contact Jacobian (m x nn, 1 x b) and transpose
+  BSR P, PT;                    // prolongator to the next level and its transpose
+  Graph G;                      // aggregation graph
+  DBuf<int> agg, root;
+  DBuf<double> d, w;
+  DBuf<float> w32;
+  int n_agg = 0;
+  double rho = 1.0, omega = 0.0;
+  // V-cycle work vectors
+  DBuf<double> vb, vx, vr, vxn;
+  DBuf<float> fb, fx, fr, fxn;
+  int64_t n() const { return int64_t(nn) * b; }
+};
+
+struct Handle {
+  amgf_options opt{};
+  Ctx ctx;
+  int n_nodes = 0, m = 0;
+  std::vector<std::unique_ptr<Level>> lev;
+  DBuf<double> D, coords;
+  DBuf<unsigned char> dec0;
+  DBuf<double> t;               // contact scratch (m)
+  // coarsest dense solve
+  int nc_dense = 0;
+  DBuf<double> coarse_Linv, coarse_b, coarse_x, coarse_tmp;
+  // filter
+  int n_c = 0;
+  DBuf<int> Ic;
+  DBuf<double> Aw_Linv, f_r, f_w, f_tmp;
+  // apply scratch
+  DBuf<double> z1, ra, r2, z3;
+  // pcg scratch
+  DBuf<double> pr, pz, pzo, pp, pq;
+  double op_complexity = 1.0;
+  bool mixed() const { return opt.precision == AMGF_MIXED_FP32; }
+  int64_t n() const { return int64_t(n_nodes) * 3; }
+};
+
+static thread_local std::string g_last_error;
+
+// ------------------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------------------
+static void copy_in(Ctx& c, void* dst, const void* src, size_t bytes) {
+  if (bytes) AMGF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.s));
+}
+
+static double power_estimate(Handle& h, Level& L, const unsigned char* dec) {
+  Ctx& c = h.ctx;
+  const int64_t n = L.n();
+  DBuf<double> x(n), y(n);
+  fill_power_start(c, n, x.p, dec);
+  const double* xs[1] = {x.p};
+  double nrm;
+  dots(c, n, 1, xs, xs, &nrm);
+  vscale(c, n, 1.0 / std::sqrt(nrm), x.p);
+  double lam = 1.0;
+  for (int it = 0; it < h.opt.sa_power_iters; ++it) {
+    bsr_spmv<double>(c, SPMV_Y, L.A, L.A.val.p, x.p, y.p, nullptr, nullptr, nullptr);
+    scale_div_zero(c, n, y.p, L.d.p, dec);
+    const double* ys[1] = {y.p};
+    dots(c, n, 1, ys, ys, &nrm);
+    lam = std::sqrt(nrm);
+    if (!(lam > 0.0)) return 1.0;
+    vcopy(c, y.p, x.p, n);
+    vscale(c, n, 1.0 / lam, x.p);
+  }
+  return std::min(1.0, lam);
+}
+
+static void to_fp32(Ctx& c, BSR& A) {
+  const int64_t nv = std::max<int64_t>(A.nnzb, 1) * A.bsz();
+  A.val32.alloc(nv);
+  cast_d2f(c, A.val.p, A.val32.p, nv);
+}
+
+// ------------------------------------------------------------------------------------
+// setup
+// ------------------------------------------------------------------------------------
+static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, const double* K_val,
+                  const int32_t* J_rowptr, const int32_t* J_col, const double* J_val,
+                  const double* D, const double* coords, const int32_t* Ic_user, int n_c_user) {
+  Ctx& c = h.ctx;
+  const amgf_options& o = h.opt;
+  const int nn = h.n_nodes, m = h.m;
+  // ---- input checks
+  std::vector<int> rp_host = d2h(K_rowptr, 2, c.s);
+  AMGF_REQUIRE(rp_host[0] == 0, AMGF_EINVAL, "K_rowptr[0] must be 0");
+  const int nnzb = d2h_scalar(K_rowptr + nn, c.s);
+  AMGF_REQUIRE(nnzb >= nn, AMGF_EINVAL, "K needs a diagonal block per row");
+  int nnzJ = 0;
+  if (m > 0) nnzJ = d2h_scalar(J_rowptr + m, c.s);
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  check_values(c, K_val, int64_t(nnzb) * 9, false, c.flag.p);
+  if (m > 0) {
+    check_values(c, J_val, nnzJ, false, c.flag.p);
+    check_values(c, D, m, true, c.flag.p);
+  }
+  check_values(c, coords, int64_t(nn) * 3, false, c.flag.p);
+  const int fl = d2h_scalar(c.flag.p, c.s);
+  AMGF_REQUIRE(fl == 0, AMGF_EINVAL,
+               (fl & 2) ? "D must be positive" : "non-finite value in K, J, D or coords");
+
+  // ---- level 0 inputs
+  h.lev.emplace_back(new Level());
+  Level* L0 = h.lev.back().get();
+  L0->nn = nn;
+  L0->b = 3;
+  BSR& K = L0->K;
+  K.nrows = K.ncols = nn;
+  K.br = K.bc = 3;
+  K.nnzb = nnzb;
+  K.rowptr.alloc(size_t(nn) + 1);
+  K.col.alloc(std::max(nnzb, 1));
+  K.val.alloc(size_t(std::max(nnzb, 1)) * 9);
+  copy_in(c, K.rowptr.p, K_rowptr, sizeof(int) * (size_t(nn) + 1));
+  copy_in(c, K.col.p, K_col, sizeof(int) * size_t(nnzb));
+  copy_in(c, K.val.p, K_val, sizeof(double) * size_t(nnzb) * 9);
+  h.D.alloc(std::max(m, 1));
+  copy_in(c, h.D.p, D, sizeof(double) * size_t(m));
+  h.coords.alloc(size_t(nn) * 3);
+  copy_in(c, h.coords.p, coords, sizeof(double) * size_t(nn) * 3);
+  h.t.alloc(std::max(m, 1));
+  j_to_node_blocks(c, m, nn, J_rowptr, J_col, J_val, L0->J);
+  bsr_transpose(c, L0->J, L0->JT);
+  {
+    BSR C;
+    contact_operator(c, L0->J, L0->JT, h.D.p, C);
+    bsr_add(c, K, C, L0->A);
+  }
+  // ---- levels
+  DBuf<double> Rprev;
+  Graph Gnext;
+  int64_t nz0 = L0->A.nnzb * 9, nzsum = nz0;
+  for (int l = 0; l < o.max_levels; ++l) {
+    Level& L = *h.lev[l];
+    l1_norms(c, L.A, L.d);
+    L.w.alloc(L.n());
+    weights_from_l1(c, L.n(), L.d.p, nullptr, L.w.p);
+    if (L.nn <= o.coarse_max_nodes || l == o.max_levels - 1) break;
+    if (l == 0) strength_graph(c, L.A, o.strength_theta, L.G);
+    else L.G = std::move(Gnext);
+    int rounds = 0;
+    const int n_agg = mis2_aggregate(c, L.G, l, L.agg, L.root, &rounds);
+    if (n_agg == 0 || n_agg > o.max_coarse_ratio * L.nn) break;
+    L.n_agg = n_agg;
+    DBuf<int> moff, members;
+    group_by_key(c, L.agg.p, L.nn, n_agg, moff, members);
+    const unsigned char* dec = nullptr;
+    if (l == 0) {
+      decoupled_dofs(c, L.A, h.dec0);
+      dec = h.dec0.p;
+    }
+    DBuf<double> Pt, R;
+    DBuf<unsigned char> dead;
+    tentative_prolongator(c, L.b, L.nn, n_agg, moff.p, members.p, l == 0 ? h.coords.p : nullptr,
+                          dec, Rprev.p, o.qr_tol, Pt, R, dead);
+    L.rho = power_estimate(h, L, dec);
+    L.omega = o.sa_omega / L.rho;
+    smooth_prolongator(c, L.A, L.agg.p, n_agg, Pt.p, L.d.p, L.omega, L.P);
+    bsr_transpose(c, L.P, L.PT);
+    h.lev.emplace_back(new Level());
+    Level& N = *h.lev.back();
+    Level& Lc = *h.lev[l];  // re-fetch (vector may have reallocated)
+    N.nn = n_agg;
+    N.b = 6;
+    {
+      BSR KP;
+      spgemm(c, Lc.K, Lc.P, KP);
+      spgemm(c, Lc.PT, KP, N.K);
+    }
+    dead_identity(c, N.K, dead.p);
+    spgemm(c, Lc.J, Lc.P, N.J);
+    bsr_transpose(c, N.J, N.JT);
+    {
+      BSR C;
+      contact_operator(c, N.J, N.JT, h.D.p, C);
+      bsr_add(c, N.K, C, N.A);
+    }
+    nzsum += N.A.nnzb * 36;
+    coarse_graph(c, Lc.G, Lc.agg.p, n_agg, moff.p, members.p, Gnext);
+    Rprev = std::move(R);
+  }
+  h.op_complexity = double(nzsum) / double(std::max<int64_t>(nz0, 1));
+  // ---- coarsest dense factor
+  Level& LL = *h.lev.back();
+  h.nc_dense = int(LL.n());
+  {
+    DBuf<double> Ad(size_t(h.nc_dense) * h.nc_dense);
+    bsr_to_dense(c, LL.A, Ad.p);
+    dense_cholesky_inverse(c, Ad.p, h.nc_dense, h.coarse_Linv);
+  }
+  h.coarse_b.alloc(h.nc_dense);
+  h.coarse_x.alloc(h.nc_dense);
+  h.coarse_tmp.alloc(h.nc_dense);
+  // ---- filter (Sec. 5.1)
+  if (Ic_user && n_c_user > 0) {
+    h.Ic.alloc(n_c_user);
+    copy_in(c, h.Ic.p, Ic_user, sizeof(int) * size_t(n_c_user));
+    h.n_c = n_c_user;
+  } else {
+    h.n_c = filter_space_from_J(c, L0->J, nn, h.Ic);
+  }
+  if (o.filter && h.n_c > 0) {
+    DBuf<double> Aw(size_t(h.n_c) * h.n_c);
+    gather_filter_matrix(c, L0->A, h.Ic.p, h.n_c, Aw.p);
+    dense_cholesky_inverse(c, Aw.p, h.n_c, h.Aw_Linv);
+    h.f_r.alloc(h.n_c);
+    h.f_w.alloc(h.n_c);
+    h.f_tmp.alloc(h.n_c);
+  }
+  // ---- precision copies and work vectors
+  for (size_t l = 0; l < h.lev.size(); ++l) {
+    Level& L = *h.lev[l];
+    const int64_t n = L.n();
+    L.vb.alloc(n); L.vx.alloc(n); L.vr.alloc(n); L.vxn.alloc(n);
+    if (h.mixed()) {
+      to_fp32(c, L.K);
+      if (L.P.nnzb) { to_fp32(c, L.P); to_fp32(c, L.PT); }
+      L.w32.alloc(n);
+      cast_d2f(c, L.w.p, L.w32.p, n);
+      L.fb.alloc(n); L.fx.alloc(n); L.fr.alloc(n); L.fxn.alloc(n);
+    }
+  }
+  const int64_t n = h.n();
+  h.z1.alloc(n); h.ra.alloc(n); h.r2.alloc(n); h.z3.alloc(n);
+  h.pr.alloc(n); h.pz.alloc(n); h.pzo.alloc(n); h.pp.alloc(n); h.pq.alloc(n);
+  AMGF_HIP(hipStreamSynchronize(c.s));
+}
+
+// ------------------------------------------------------------------------------------
+// V-cycle
+// ------------------------------------------------------------------------------------
+static void coarse_solve(Handle& h, const double* b, double* x) {
+  dense_solve(h.ctx, h.coarse_Linv.p, h.nc_dense, b, x, h.coarse_tmp.p);
+}
+
+// FP64 V(1,1) on level l: L.vb -> L.vx
+static void vcycle64(Handle& h, size_t l) {
+  Ctx& c = h.ctx;
+  Level& L = *h.lev[l];
+  if (l + 1 == h.lev.size()) {
+    coarse_solve(h, L.vb.p, L.vx.p);
+    return;
+  }
+  Level& N = *h.lev[l + 1];
+  bsr_spmv<double>(c, SPMV_PRE, L.K, L.K.val.p, nullptr, L.vr.p, L.vb.p, L.w.p, L.vx.p);
+  contact_apply<double>(c, CT_SUB_RES, L.J, L.JT, h.D.p, L.vx.p, h.t.p, L.vr.p, nullptr);
+  bsr_spmv<double>(c, SPMV_Y, L.PT, L.PT.val.p, L.vr.p, N.vb.p, nullptr, nullptr, nullptr);
+  vcycle64(h, l + 1);
+  bsr_spmv<double>(c, SPMV_ADD, L.P, L.P.val.p, N.vx.p, L.vx.p, nullptr, nullptr, nullptr);
+  bsr_spmv<double>(c, SPMV_POST, L.K, L.K.val.p, L.vx.p, nullptr, L.vb.p, L.w.p, L.vxn.p);
+  contact_apply<double>(c, CT_SUB_W, L.J, L.JT, h.D.p, L.vx.p, h.t.p, L.vxn.p, L.w.p);
+  std::swap(L.vx, L.vxn);
+}
+
+// FP32 V(1,1) (contact term and coarsest solve in FP64): L.fb -> L.fx
+static void vcycle32(Handle& h, size_t l) {
+  Ctx& c = h.ctx;
+  Level& L = *h.lev[l];
+  if (l + 1 == h.lev.size()) {
+    cast_f2d(c, L.fb.p, h.coarse_b.p, L.n());
+    coarse_solve(h, h.coarse_b.p, h.coarse_x.p);
+    cast_d2f(c, h.coarse_x.p, L.fx.p, L.n());
+    return;
+  }
+  Level& N = *h.lev[l + 1];
+  bsr_spmv<float>(c, SPMV_PRE, L.K, L.K.val32.p, nullptr, L.fr.p, L.fb.p, L.w32.p, L.fx.p);
+  contact_apply<float>(c, CT_SUB_RES, L.J, L.JT, h.D.p, L.fx.p, h.t.p, L.fr.p, nullptr);
+  bsr_spmv<float>(c, SPMV_Y, L.PT, L.PT.val32.p, L.fr.p, N.fb.p, nullptr, nullptr, nullptr);
+  vcycle32(h, l + 1);
+  bsr_spmv<float>(c, SPMV_ADD, L.P, L.P.val32.p, N.fx.p, L.fx.p, nullptr, nullptr, nullptr);
+  bsr_spmv<float>(c, SPMV_POST, L.K, L.K.val32.p, L.fx.p, nullptr, L.fb.p, L.w32.p, L.fxn.p);
+  contact_apply<float>(c, CT_SUB_W, L.J, L.JT, h.D.p, L.fx.p, h.t.p, L.fxn.p, L.w32.p);
+  std::swap(L.fx, L.fxn);
+}
+
+// z = B r (FP64 boundary vectors)
+static void vcycle(Handle& h, const double* r, double* z) {
+  Ctx& c = h.ctx;
+  Level& L0 = *h.lev[0];
+  const int64_t n = h.n();
+  if (h.mixed()) {
+    cast_d2f(c, r, L0.fb.p, n);
+    vcycle32(h, 0);
+    cast_f2d(c, L0.fx.p, z, n);
+  } else {
+    vcopy(c, r, L0.vb.p, n);
+    vcycle64(h, 0);
+    vcopy(c, L0.vx.p, z, n);
+  }
+}
+
+// y = A x (FP64), or y = b - A x when b != nullptr
+static void operator_apply(Handle& h, const double* x, double* y, const double* b) {
+  Ctx& c = h.ctx;
+  Level& L0 = *h.lev[0];
+  if (b) {
+    bsr_spmv<double>(c, SPMV_RES, L0.K, L0.K.val.p, x, y, b, nullptr, nullptr);
+    contact_apply<double>(c, CT_SUB_RES, L0.J, L0.JT, h.D.p, x, h.t.p, y, nullptr);
+  } else {
+    bsr_spmv<double>(c, SPMV_Y, L0.K, L0.K.val.p, x, y, nullptr, nullptr, nullptr);
+    contact_apply<double>(c, CT_ADD, L0.J, L0.JT, h.D.p, x, h.t.p, y, nullptr);
+  }
+}
+
+// z = M r, Definition 5.3
+static void amgf_apply_impl(Handle& h, const double* r, double* z) {
+  Ctx& c = h.ctx;
+  const int64_t n = h.n();
+  if (!h.opt.filter) {
+    vcycle(h, r, z);
+    return;
+  }
+  vcycle(h, r, h.z1.p);                               // z1 = B r
+  if (h.n_c > 0) {
+    operator_apply(h, h.z1.p, h.ra.p, r);             // ra = r - A z1
+    gather(c, h.ra.p, h.Ic.p, h.n_c, h.f_r.p);        // P^T ra
+    dense_solve(c, h.Aw_Linv.p, h.n_c, h.f_r.p, h.f_w.p, h.f_tmp.p);   // A_w^{-1}
+    scatter_add(c, h.f_w.p, h.Ic.p, h.n_c, h.z1.p);   // z2 = z1 + P w
+  }
+  operator_apply(h, h.z1.p, h.r2.p, r);               // r2 = r - A z2
+  vcycle(h, h.r2.p, h.z3.p);                          // B r2
+  vcopy(c, h.z1.p, z, n);
+  axpby(c, n, 1.0, h.z3.p, 1.0, z);                   // z = z2 + B r2
+}
+
+// ------------------------------------------------------------------------------------
+// PCG (Sec. 4 / 6.1 stopping rule), Polak-Ribiere beta
+// ------------------------------------------------------------------------------------
+static amgf_status pcg_impl(Handle& h, const double* b, double* x, amgf_solve_info* info) {
+  Ctx& c = h.ctx;
+  const int64_t n = h.n();
+  hipEvent_t e0, e1;
+  AMGF_HIP(hipEventCreate(&e0));
+  AMGF_HIP(hipEventCreate(&e1));
+  AMGF_HIP(hipEventRecord(e0, c.s));
+  operator_apply(h, x, h.pr.p, b);                    // r = b - A x0
+  amgf_apply_impl(h, h.pr.p, h.pz.p);
+  vcopy(c, h.pz.p, h.pp.p, n);
+  double d2[2];
+  {
+    const double* xs[2] = {h.pr.p, b};
+    const double* ys[2] = {h.pz.p, b};
+    dots(c, n, 2, xs, ys, d2);
+  }
+  double rz = d2[0];
+  const double rz0 = rz;
+  int it = 0;
+  bool conv = rz0 == 0.0;
+  double rel = conv ? 0.0 : 1.0;
+  amgf_status st = AMGF_OK;
+  while (!conv && it < h.opt.max_iters) {
+    operator_apply(h, h.pp.p, h.pq.p, nullptr);       // q = A p
+    double pq;
+    {
+      const double* xs[1] = {h.pp.p};
+      const double* ys[1] = {h.pq.p};
+      dots(c, n, 1, xs, ys, &pq);
+    }
+    if (!(pq > 0.0)) { st = AMGF_ENOTSPD; break; }
+    const double alpha = rz / pq;
+    pcg_update_xr(c, n, alpha, h.pp.p, h.pq.p, x, h.pr.p);
+    std::swap(h.pz, h.pzo);
+    amgf_apply_impl(h, h.pr.p, h.pz.p);
+    {
+      const double* xs[2] = {h.pr.p, h.pr.p};
+      const double* ys[2] = {h.pz.p, h.pzo.p};
+      dots(c, n, 2, xs, ys, d2);
+    }
+    ++it;
+    rel = std::sqrt(std::fabs(d2[0]) / rz0);
+    if (!std::isfinite(rel)) { st = AMGF_ENOTSPD; break; }
+    if (rel <= h.opt.rtol) { conv = true; break; }
+    const double beta = (d2[0] - d2[1]) / rz;
+    pcg_update_p(c, n, beta, h.pz.p, h.pp.p);
+    rz = d2[0];
+  }
+  AMGF_HIP(hipEventRecord(e1, c.s));
+  AMGF_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  AMGF_HIP(hipEventElapsedTime(&ms, e0, e1));
+  AMGF_HIP(hipEventDestroy(e0));
+  AMGF_HIP(hipEventDestroy(e1));
+  if (info) {
+    operator_apply(h, x, h.ra.p, b);
+    double tr[2];
+    const double* xs[2] = {h.ra.p, b};
+    const double* ys[2] = {h.ra.p, b};
+    dots(c, n, 2, xs, ys, tr);
+    info->iterations = it;
+    info->converged = conv ? 1 : 0;
+    info->n_levels = int(h.lev.size());
+    info->n_c = h.n_c;
+    info->rel_prec_res = rel;
+    info->rel_true_res = tr[1] > 0 ? std::sqrt(tr[0] / tr[1]) : 0.0;
+    info->op_complexity = h.op_complexity;
+    info->ms_solve = ms;
+    info->used_fallback = 0;
+  }
+  if (st != AMGF_OK) return st;
+  return conv ? AMGF_OK : AMGF_ENOCONV;
+}
+
+}  // namespace amgf
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+using amgf::Handle;
+
+struct amgf_handle_s {
+  Handle h;
+};
+
+template <class F>
+static amgf_status guard(F&& f) {
+  try {
+    return f();
+  } catch (const amgf::Error& e) {
+    amgf::g_last_error = e.what();
+    return e.status;
+  } catch (const std::exception& e) {
+    amgf::g_last_error = e.what();
+    return AMGF_EDEVICE;
+  }
+}
+
+extern "C" {
+
+void amgf_default_options(amgf_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(amgf_options);
+  o->precision = AMGF_FP64;
+  o->smoother = AMGF_L1JACOBI;
+  o->filter = 1;
+  o->max_levels = 10;
+  o->coarse_max_nodes = 256;
+  o->max_iters = 5000;
+  o->sa_power_iters = 10;
+  o->strength_theta = 0.08;
+  o->rtol = 1e-10;
+  o->sa_omega = 4.0 / 3.0;
+  o->qr_tol = 1e-10;
+  o->max_coarse_ratio = 0.9;
+  o->mlp_weights = nullptr;
+}
+
+const char* amgf_status_string(amgf_status s) {
+  switch (s) {
+    case AMGF_OK: return "AMGF_OK";
+    case AMGF_EINVAL: return "AMGF_EINVAL";
+    case AMGF_ENOTSPD: return "AMGF_ENOTSPD";
+    case AMGF_ENOCONV: return "AMGF_ENOCONV";
+    case AMGF_ENOMEM: return "AMGF_ENOMEM";
+    case AMGF_EDEVICE: return "AMGF_EDEVICE";
+  }
+  return "AMGF_UNKNOWN";
+}
+
+const char* amgf_last_error(void) { return amgf::g_last_error.c_str(); }
+
+amgf_status amgf_setup(const amgf_options* opts, int32_t n_nodes, const int32_t* K_rowptr,
+                       const int32_t* K_col, const double* K_val, int32_t m,
+                       const int32_t* J_rowptr, const int32_t* J_col, const double* J_val,
+                       const double* D, const double* coords, const int32_t* Ic, int32_t n_c,
+                       void* stream, amgf_handle* out) {
+  if (!out) return AMGF_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<amgf_handle_s> hs(new (std::nothrow) amgf_handle_s());
+  if (!hs) return AMGF_ENOMEM;
+  amgf_status st_ = guard([&]() -> amgf_status {
+    Handle& h = hs->h;
+    if (opts) {
+      AMGF_REQUIRE(opts->struct_size == int32_t(sizeof(amgf_options)), AMGF_EINVAL,
+                   "amgf_options.struct_size mismatch");
+      h.opt = *opts;
+    } else {
+      amgf_default_options(&h.opt);
+    }
+    AMGF_REQUIRE(n_nodes > 0 && m >= 0 && K_rowptr && K_col && K_val && coords, AMGF_EINVAL,
+                 "bad sizes or null K / coords");
+    AMGF_REQUIRE(m == 0 || (J_rowptr && J_col && J_val && D), AMGF_EINVAL, "null J or D");
+    AMGF_REQUIRE(int64_t(n_nodes) * 6 < (int64_t(1) << 31), AMGF_EINVAL, "too many nodes");
+    AMGF_REQUIRE(h.opt.precision == AMGF_FP64 || h.opt.precision == AMGF_MIXED_FP32,
+                 AMGF_EINVAL, "precision");
+    AMGF_REQUIRE(h.opt.smoother == AMGF_L1JACOBI, AMGF_EINVAL,
+                 "smoother not supported by this entry point");
+    AMGF_REQUIRE(h.opt.max_levels >= 1 && h.opt.max_iters >= 0 && h.opt.rtol >= 0,
+                 AMGF_EINVAL, "options");
+    AMGF_REQUIRE(n_c >= 0 && (n_c == 0 || Ic), AMGF_EINVAL, "Ic");
+    h.ctx.s = static_cast<hipStream_t>(stream);
+    h.ctx.flag.alloc(1);
+    h.n_nodes = n_nodes;
+    h.m = m;
+    amgf::setup(h, K_rowptr, K_col, K_val, J_rowptr, J_col, J_val, D, coords, Ic, n_c);
+    return AMGF_OK;
+  });
+  if (st_ != AMGF_OK) return st_;
+  *out = hs.release();
+  return AMGF_OK;
+}
+
+amgf_status amgf_apply(amgf_handle hd, const double* r, double* z, void* stream) {
+  if (!hd || !r || !z) return AMGF_EINVAL;
+  amgf_status st_ = guard([&]() -> amgf_status {
+    hd->h.ctx.s = static_cast<hipStream_t>(stream);
+    amgf::amgf_apply_impl(hd->h, r, z);
+    return AMGF_OK;
+  });
+  if (st_ != AMGF_OK) return st_;
+  return AMGF_OK;
+}
+
+amgf_status amgf_vcycle(amgf_handle hd, const double* r, double* z, void* stream) {
+  if (!hd || !r || !z) return AMGF_EINVAL;
+  amgf_status st_ = guard([&]() -> amgf_status {
+    hd->h.ctx.s = static_cast<hipStream_t>(stream);
+    amgf::vcycle(hd->h, r, z);
+    return AMGF_OK;
+  });
+  if (st_ != AMGF_OK) return st_;
+  return AMGF_OK;
+}
+
+amgf_status amgf_operator_apply(amgf_handle hd, const double* x, double* y, void* stream) {
+  if (!hd || !x || !y) return AMGF_EINVAL;
+  amgf_status st_ = guard([&]() -> amgf_status {
+    hd->h.ctx.s = static_cast<hipStream_t>(stream);
+    amgf::operator_apply(hd->h, x, y, nullptr);
+    return AMGF_OK;
+  });
+  if (st_ != AMGF_OK) return st_;
+  return AMGF_OK;
+}
+
+amgf_status amgf_pcg(amgf_handle hd, const double* b, double* x, amgf_solve_info* info,
+                     void* stream) {
+  if (!hd || !b || !x) return AMGF_EINVAL;
+  amgf_status st_ = guard([&]() -> amgf_status {
+    hd->h.ctx.s = static_cast<hipStream_t>(stream);
+    return amgf::pcg_impl(hd->h, b, x, info);
+  });
+  if (st_ != AMGF_OK) return st_;
+  return AMGF_OK;
+}
+
+void amgf_destroy(amgf_handle hd) {
+  if (!hd) return;
+  (void)hipStreamSynchronize(hd->h.ctx.s);
+  delete hd;
+}
+
+int32_t amgf_num_levels(amgf_handle hd) { return hd ? int32_t(hd->h.lev.size()) : 0; }
+
+amgf_status amgf_query(amgf_handle hd, int32_t level, int32_t which, void* dst, size_t bytes) {
+  if (!hd || !dst) return AMGF_EINVAL;
+  amgf_status st_ = guard([&]() -> amgf_status {
+    Handle& h = hd->h;
+    amgf::Ctx& c = h.ctx;
+    if (which == AMGF_Q_IC) {
+      AMGF_REQUIRE(bytes == sizeof(int) * size_t(h.n_c), AMGF_EINVAL, "size");
+      if (bytes) AMGF_HIP(hipMemcpy(dst, h.Ic.p, bytes, hipMemcpyDeviceToHost));
+      return AMGF_OK;
+    }
+    AMGF_REQUIRE(level >= 0 && level < int(h.lev.size()), AMGF_EINVAL, "level");
+    amgf::Level& L = *h.lev[level];
+    auto cp = [&](const void* src, size_t want) {
+      AMGF_REQUIRE(bytes == want, AMGF_EINVAL, "query size mismatch");
+      AMGF_REQUIRE(src != nullptr || want == 0, AMGF_EINVAL, "array not available");
+      if (want) AMGF_HIP(hipMemcpy(dst, src, want, hipMemcpyDeviceToHost));
+    };
+    AMGF_HIP(hipStreamSynchronize(c.s));
+    switch (which) {
+      case AMGF_Q_SIZES: {
+        int32_t s[8] = {L.nn, L.b, int32_t(L.A.nnzb), L.n_agg, int32_t(L.P.nnzb),
+                        int32_t(L.G.nnz), int32_t(L.K.nnzb), 0};
+        AMGF_REQUIRE(bytes == sizeof(s), AMGF_EINVAL, "size");
+        std::memcpy(dst, s, sizeof(s));
+        break;
+      }
+      case AMGF_Q_A_ROWPTR: cp(L.A.rowptr.p, sizeof(int) * (size_t(L.nn) + 1)); break;
+      case AMGF_Q_A_COL: cp(L.A.col.p, sizeof(int) * size_t(L.A.nnzb)); break;
+      case AMGF_Q_A_VAL: cp(L.A.val.p, sizeof(double) * size_t(L.A.nnzb) * L.A.bsz()); break;
+      case AMGF_Q_AGG: cp(L.agg.p, L.n_agg ? sizeof(int) * size_t(L.nn) : 0); break;
+      case AMGF_Q_ROOT: cp(L.root.p, L.n_agg ? sizeof(int) * size_t(L.nn) : 0); break;
+      case AMGF_Q_G_ROWPTR: cp(L.G.rowptr.p, L.G.n ? sizeof(int) * (size_t(L.G.n) + 1) : 0); break;
+      case AMGF_Q_G_COL: cp(L.G.col.p, sizeof(int) * size_t(L.G.nnz)); break;
+      case AMGF_Q_P_ROWPTR: cp(L.P.rowptr.p, L.n_agg ? sizeof(int) * (size_t(L.nn) + 1) : 0); break;
+      case AMGF_Q_P_COL: cp(L.P.col.p, sizeof(int) * size_t(L.P.nnzb)); break;
+      case AMGF_Q_P_VAL: cp(L.P.val.p, sizeof(double) * size_t(L.P.nnzb) * L.P.bsz()); break;
+      case AMGF_Q_L1: cp(L.d.p, sizeof(double) * size_t(L.n())); break;
+      case AMGF_Q_K_ROWPTR: cp(L.K.rowptr.p, sizeof(int) * (size_t(L.nn) + 1)); break;
+      case AMGF_Q_K_COL: cp(L.K.col.p, sizeof(int) * size_t(L.K.nnzb)); break;
+      case AMGF_Q_K_VAL: cp(L.K.val.p, sizeof(double) * size_t(L.K.nnzb) * L.K.bsz()); break;
+      case AMGF_Q_OMEGA: {
+        double s[2] = {L.rho, L.omega};
+        AMGF_REQUIRE(bytes == sizeof(s), AMGF_EINVAL, "size");
+        std::memcpy(dst, s, sizeof(s));
+        break;
+      }
+      default:
+        throw amgf::Error(AMGF_EINVAL, "query selector");
+    }
+    return AMGF_OK;
+  });
+  if (st_ != AMGF_OK) return st_;
+  return AMGF_OK;
+}
+
+}  // extern "C"

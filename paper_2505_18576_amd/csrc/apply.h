@@ -1,0 +1,54 @@
+// Apply-phase kernels (apply.hip): SpMV with fused smoother modes, contact term,
+// transfers, vector updates and deterministic reductions.
+#pragma once
+#include "common.h"
+
+namespace amgf {
+
+enum SpmvMode {
+  SPMV_Y = 0,     // y = A x
+  SPMV_ADD = 1,   // y += A x
+  SPMV_PRE = 2,   // xo = w.b ; y = b - A (w.b)          (first smoothing step from 0)
+  SPMV_POST = 3,  // xo = x + w.(b - A x)                (Jacobi step, new buffer)
+  SPMV_RES = 4    // y = b - A x
+};
+
+// y/xo per mode; val is T-typed (double or float) and the vectors are T too.
+template <class T>
+void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, const T* b,
+              const T* w, T* xo);
+
+// contact term of level l: t = D.(J x) then, per mode,
+//   CT_SUB_RES:  y -= J^T t          (residual update)
+//   CT_SUB_W:    y -= w.(J^T t)      (Jacobi step correction)
+//   CT_ADD:      y += J^T t          (operator apply)
+enum ContactMode { CT_SUB_RES = 0, CT_SUB_W = 1, CT_ADD = 2 };
+template <class T>
+void contact_apply(Ctx& c, int mode, const BSR& J, const BSR& JT, const double* D, const T* x,
+                   double* t, T* y, const T* w);
+
+// elementwise helpers
+void cast_d2f(Ctx& c, const double* a, float* b, int64_t n);
+void cast_f2d(Ctx& c, const float* a, double* b, int64_t n);
+void vcopy(Ctx& c, const double* a, double* b, int64_t n);
+void axpby(Ctx& c, int64_t n, double alpha, const double* x, double beta, double* y);  // y = a x + b y
+void gather(Ctx& c, const double* x, const int* idx, int n, double* y);               // y = x[idx]
+void scatter_add(Ctx& c, const double* w, const int* idx, int n, double* y);          // y[idx] += w
+void scale_div_zero(Ctx& c, int64_t n, double* y, const double* d, const unsigned char* dec);
+void fill_power_start(Ctx& c, int64_t n, double* x, const unsigned char* dec);
+void weights_from_l1(Ctx& c, int64_t n, const double* d, const double* theta, double* w);
+void vscale(Ctx& c, int64_t n, double s, double* x);
+
+// deterministic dot products: out[i] = sum_k x_i[k] y_i[k] (host results)
+void dots(Ctx& c, int64_t n, int nd, const double* const* xs, const double* const* ys,
+          double* out_host);
+
+// PCG updates
+void pcg_update_xr(Ctx& c, int64_t n, double alpha, const double* p, const double* q, double* x,
+                   double* r);
+void pcg_update_p(Ctx& c, int64_t n, double beta, const double* z, double* p);
+
+// input validation: flag bit 1 non-finite, bit 2 non-positive
+void check_values(Ctx& c, const double* v, int64_t n, bool require_positive, int* flag);
+
+}  // namespace amgf

@@ -1,0 +1,347 @@
+// Apply-phase kernels: the V-cycle, the filter correction and the CG loop are built
+// from these.  All are memory-bound; reductions are two-stage with a fixed
+// assignment of elements to lanes, so results do not depend on scheduling.
+#include "apply.h"
+
+namespace amgf {
+
+// ======================================================================================
+// BSR SpMV with fused smoother modes
+// ======================================================================================
+// G lanes cooperate on one block row; lane l takes blocks l, l+G, ...; the BR partial
+// row sums are reduced across the G lanes and lane p < BR writes output p.
+template <int BR, int BC, int G, class T, int MODE>
+__global__ void __launch_bounds__(256) k_bsr(int nrows, const int* __restrict__ rp,
+                                             const int* __restrict__ col,
+                                             const T* __restrict__ val, const T* __restrict__ x,
+                                             T* __restrict__ y, const T* __restrict__ b,
+                                             const T* __restrict__ w, T* __restrict__ xo) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = gid / G, l = gid % G;
+  if (r >= nrows) return;
+  T acc[BR];
+#pragma unroll
+  for (int p = 0; p < BR; ++p) acc[p] = T(0);
+  const int j1 = rp[r + 1];
+  for (int j = rp[r] + l; j < j1; j += G) {
+    const int cc = col[j];
+    T xv[BC];
+#pragma unroll
+    for (int q = 0; q < BC; ++q) {
+      const int64_t ix = int64_t(cc) * BC + q;
+      xv[q] = (MODE == SPMV_PRE) ? w[ix] * b[ix] : x[ix];
+    }
+    const T* v = val + int64_t(j) * (BR * BC);
+#pragma unroll
+    for (int p = 0; p < BR; ++p)
+#pragma unroll
+      for (int q = 0; q < BC; ++q) acc[p] += v[p * BC + q] * xv[q];
+  }
+#pragma unroll
+  for (int p = 0; p < BR; ++p) acc[p] = group_sum(acc[p], G);
+  if (l >= BR) return;
+  T ax = T(0);
+#pragma unroll
+  for (int p = 0; p < BR; ++p)
+    if (l == p) ax = acc[p];
+  const int64_t i = int64_t(r) * BR + l;
+  if (MODE == SPMV_Y) y[i] = ax;
+  else if (MODE == SPMV_ADD) y[i] += ax;
+  else if (MODE == SPMV_PRE) {
+    const T xi = w[i] * b[i];
+    xo[i] = xi;
+    y[i] = b[i] - ax;
+  } else if (MODE == SPMV_POST) {
+    xo[i] = x[i] + w[i] * (b[i] - ax);
+  } else {
+    y[i] = b[i] - ax;
+  }
+}
+
+template <int BR, int BC, int G, class T>
+static void launch_bsr(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y,
+                       const T* b, const T* w, T* xo) {
+  const int64_t threads = int64_t(A.nrows) * G;
+  const dim3 g(grid_for(threads, 256)), blk(256);
+  switch (mode) {
+#define AMGF_MODE(MD)                                                                        \
+  case MD:                                                                                   \
+    hipLaunchKernelGGL((k_bsr<BR, BC, G, T, MD>), g, blk, 0, c.s, A.nrows, A.rowptr.p,       \
+                       A.col.p, val, x, y, b, w, xo);                                        \
+    break;
+    AMGF_MODE(SPMV_Y)
+    AMGF_MODE(SPMV_ADD)
+    AMGF_MODE(SPMV_PRE)
+    AMGF_MODE(SPMV_POST)
+    AMGF_MODE(SPMV_RES)
+#undef AMGF_MODE
+    default:
+      throw Error(AMGF_EINVAL, "spmv mode");
+  }
+  AMGF_LAUNCH_CHECK();
+}
+
+template <class T>
+void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, const T* b,
+              const T* w, T* xo) {
+  if (A.nrows == 0) return;
+  const double avg = A.nrows ? double(A.nnzb) / A.nrows : 0.0;
+  if (A.br == 3 && A.bc == 3) return launch_bsr<3, 3, 8, T>(c, mode, A, val, x, y, b, w, xo);
+  if (A.br == 3 && A.bc == 6) return launch_bsr<3, 6, 8, T>(c, mode, A, val, x, y, b, w, xo);
+  if (A.br == 6 && A.bc == 3) return launch_bsr<6, 3, 64, T>(c, mode, A, val, x, y, b, w, xo);
+  if (A.br == 6 && A.bc == 6) {
+    if (avg > 24) return launch_bsr<6, 6, 64, T>(c, mode, A, val, x, y, b, w, xo);
+    return launch_bsr<6, 6, 16, T>(c, mode, A, val, x, y, b, w, xo);
+  }
+  throw Error(AMGF_EINVAL, "spmv block size");
+}
+template void bsr_spmv<double>(Ctx&, int, const BSR&, const double*, const double*, double*,
+                               const double*, const double*, double*);
+template void bsr_spmv<float>(Ctx&, int, const BSR&, const float*, const float*, float*,
+                              const float*, const float*, float*);
+
+// ======================================================================================
+// contact term  J^T D J x  (always FP64)
+// ======================================================================================
+template <int B, class T>
+__global__ void k_contact_t(int m, const int* __restrict__ rp, const int* __restrict__ col,
+                            const double* __restrict__ val, const double* __restrict__ D,
+                            const T* __restrict__ x, double* __restrict__ t) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  double s = 0.0;
+  for (int u = rp[k]; u < rp[k + 1]; ++u) {
+    const int64_t base = int64_t(col[u]) * B;
+#pragma unroll
+    for (int q = 0; q < B; ++q) s += val[int64_t(u) * B + q] * double(x[base + q]);
+  }
+  t[k] = D[k] * s;
+}
+
+template <int B, class T, int MODE>
+__global__ void k_contact_y(int nn, const int* __restrict__ rp, const int* __restrict__ col,
+                            const double* __restrict__ val, const double* __restrict__ t,
+                            T* __restrict__ y, const T* __restrict__ w) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nn) return;
+  const int k0 = rp[a], k1 = rp[a + 1];
+  if (k0 == k1) return;
+  double acc[B];
+#pragma unroll
+  for (int p = 0; p < B; ++p) acc[p] = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const double tk = t[col[k]];
+#pragma unroll
+    for (int p = 0; p < B; ++p) acc[p] += val[int64_t(k) * B + p] * tk;
+  }
+#pragma unroll
+  for (int p = 0; p < B; ++p) {
+    const int64_t i = int64_t(a) * B + p;
+    if (MODE == CT_SUB_RES) y[i] = T(double(y[i]) - acc[p]);
+    else if (MODE == CT_SUB_W) y[i] = T(double(y[i]) - double(w[i]) * acc[p]);
+    else y[i] = T(double(y[i]) + acc[p]);
+  }
+}
+
+template <class T>
+void contact_apply(Ctx& c, int mode, const BSR& J, const BSR& JT, const double* D, const T* x,
+                   double* t, T* y, const T* w) {
+  if (J.nrows == 0 || J.nnzb == 0) return;
+  const int m = J.nrows, nn = JT.nrows;
+  const dim3 gm(grid_for(m, 256)), gn(grid_for(nn, 256)), blk(256);
+  if (J.bc == 3) {
+    hipLaunchKernelGGL((k_contact_t<3, T>), gm, blk, 0, c.s, m, J.rowptr.p, J.col.p, J.val.p, D,
+                       x, t);
+    if (mode == CT_SUB_RES)
+      hipLaunchKernelGGL((k_contact_y<3, T, CT_SUB_RES>), gn, blk, 0, c.s, nn, JT.rowptr.p,
+                         JT.col.p, JT.val.p, t, y, w);
+    else if (mode == CT_SUB_W)
+      hipLaunchKernelGGL((k_contact_y<3, T, CT_SUB_W>), gn, blk, 0, c.s, nn, JT.rowptr.p,
+                         JT.col.p, JT.val.p, t, y, w);
+    else
+      hipLaunchKernelGGL((k_contact_y<3, T, CT_ADD>), gn, blk, 0, c.s, nn, JT.rowptr.p,
+                         JT.col.p, JT.val.p, t, y, w);
+  } else {
+    hipLaunchKernelGGL((k_contact_t<6, T>), gm, blk, 0, c.s, m, J.rowptr.p, J.col.p, J.val.p, D,
+                       x, t);
+    if (mode == CT_SUB_RES)
+      hipLaunchKernelGGL((k_contact_y<6, T, CT_SUB_RES>), gn, blk, 0, c.s, nn, JT.rowptr.p,
+                         JT.col.p, JT.val.p, t, y, w);
+    else if (mode == CT_SUB_W)
+      hipLaunchKernelGGL((k_contact_y<6, T, CT_SUB_W>), gn, blk, 0, c.s, nn, JT.rowptr.p,
+                         JT.col.p, JT.val.p, t, y, w);
+    else
+      hipLaunchKernelGGL((k_contact_y<6, T, CT_ADD>), gn, blk, 0, c.s, nn, JT.rowptr.p,
+                         JT.col.p, JT.val.p, t, y, w);
+  }
+  AMGF_LAUNCH_CHECK();
+}
+template void contact_apply<double>(Ctx&, int, const BSR&, const BSR&, const double*,
+                                    const double*, double*, double*, const double*);
+template void contact_apply<float>(Ctx&, int, const BSR&, const BSR&, const double*,
+                                   const float*, double*, float*, const float*);
+
+// ======================================================================================
+// elementwise
+// ======================================================================================
+#define AMGF_ELEMWISE(name, params, body)                                                    \
+  __global__ void name params {                                                              \
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;                        \
+    if (i < n) { body; }                                                                     \
+  }
+
+AMGF_ELEMWISE(k_d2f, (const double* __restrict__ a, float* __restrict__ b, int64_t n),
+              b[i] = float(a[i]))
+AMGF_ELEMWISE(k_f2d, (const float* __restrict__ a, double* __restrict__ b, int64_t n),
+              b[i] = double(a[i]))
+AMGF_ELEMWISE(k_copy, (const double* __restrict__ a, double* __restrict__ b, int64_t n),
+              b[i] = a[i])
+AMGF_ELEMWISE(k_axpby, (int64_t n, double al, const double* __restrict__ x, double be,
+                        double* __restrict__ y),
+              y[i] = al * x[i] + be * y[i])
+AMGF_ELEMWISE(k_scale, (int64_t n, double s, double* __restrict__ x), x[i] *= s)
+AMGF_ELEMWISE(k_scale_div, (int64_t n, double* __restrict__ y, const double* __restrict__ d,
+                            const unsigned char* __restrict__ dec),
+              y[i] = (dec && dec[i]) ? 0.0 : y[i] / d[i])
+AMGF_ELEMWISE(k_weights, (int64_t n, const double* __restrict__ d,
+                          const double* __restrict__ th, double* __restrict__ w),
+              w[i] = (th ? th[i] : 1.0) / d[i])
+AMGF_ELEMWISE(k_xr, (int64_t n, double al, const double* __restrict__ p,
+                     const double* __restrict__ q, double* __restrict__ x,
+                     double* __restrict__ r),
+              x[i] += al * p[i];
+              r[i] -= al * q[i])
+AMGF_ELEMWISE(k_pupd, (int64_t n, double be, const double* __restrict__ z, double* __restrict__ p),
+              p[i] = z[i] + be * p[i])
+AMGF_ELEMWISE(k_power_start, (int64_t n, double* __restrict__ x,
+                              const unsigned char* __restrict__ dec),
+              x[i] = (dec && dec[i]) ? 0.0
+                                     : double(fmix32(uint32_t(i))) * 0x1p-32 - 0.5)
+
+__global__ void k_gather(const double* __restrict__ x, const int* __restrict__ idx, int n,
+                         double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[idx[i]];
+}
+__global__ void k_scatter_add(const double* __restrict__ w, const int* __restrict__ idx, int n,
+                              double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[idx[i]] += w[i];
+}
+__global__ void k_check(const double* __restrict__ v, int64_t n, int pos, int* flag) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = v[i];
+  if (!isfinite(x)) atomicOr(flag, 1);
+  if (pos && !(x > 0.0)) atomicOr(flag, 2);
+}
+
+#define AMGF_L1D(n) dim3(grid_for((n), 256)), dim3(256), 0, c.s
+void cast_d2f(Ctx& c, const double* a, float* b, int64_t n) {
+  if (n) hipLaunchKernelGGL(k_d2f, AMGF_L1D(n), a, b, n);
+}
+void cast_f2d(Ctx& c, const float* a, double* b, int64_t n) {
+  if (n) hipLaunchKernelGGL(k_f2d, AMGF_L1D(n), a, b, n);
+}
+void vcopy(Ctx& c, const double* a, double* b, int64_t n) {
+  if (n) hipLaunchKernelGGL(k_copy, AMGF_L1D(n), a, b, n);
+}
+void axpby(Ctx& c, int64_t n, double alpha, const double* x, double beta, double* y) {
+  if (n) hipLaunchKernelGGL(k_axpby, AMGF_L1D(n), n, alpha, x, beta, y);
+}
+void vscale(Ctx& c, int64_t n, double s, double* x) {
+  if (n) hipLaunchKernelGGL(k_scale, AMGF_L1D(n), n, s, x);
+}
+void gather(Ctx& c, const double* x, const int* idx, int n, double* y) {
+  if (n) hipLaunchKernelGGL(k_gather, AMGF_L1D(n), x, idx, n, y);
+}
+void scatter_add(Ctx& c, const double* w, const int* idx, int n, double* y) {
+  if (n) hipLaunchKernelGGL(k_scatter_add, AMGF_L1D(n), w, idx, n, y);
+}
+void scale_div_zero(Ctx& c, int64_t n, double* y, const double* d, const unsigned char* dec) {
+  if (n) hipLaunchKernelGGL(k_scale_div, AMGF_L1D(n), n, y, d, dec);
+}
+void fill_power_start(Ctx& c, int64_t n, double* x, const unsigned char* dec) {
+  if (n) hipLaunchKernelGGL(k_power_start, AMGF_L1D(n), n, x, dec);
+}
+void weights_from_l1(Ctx& c, int64_t n, const double* d, const double* theta, double* w) {
+  if (n) hipLaunchKernelGGL(k_weights, AMGF_L1D(n), n, d, theta, w);
+}
+void pcg_update_xr(Ctx& c, int64_t n, double alpha, const double* p, const double* q, double* x,
+                   double* r) {
+  if (n) hipLaunchKernelGGL(k_xr, AMGF_L1D(n), n, alpha, p, q, x, r);
+}
+void pcg_update_p(Ctx& c, int64_t n, double beta, const double* z, double* p) {
+  if (n) hipLaunchKernelGGL(k_pupd, AMGF_L1D(n), n, beta, z, p);
+}
+void check_values(Ctx& c, const double* v, int64_t n, bool require_positive, int* flag) {
+  if (n) hipLaunchKernelGGL(k_check, AMGF_L1D(n), v, n, int(require_positive), flag);
+  AMGF_LAUNCH_CHECK();
+}
+
+// ======================================================================================
+// deterministic dots: fixed grid, per-block partials, single-block final sum
+// ======================================================================================
+constexpr int DOT_BLOCKS = 1024;
+constexpr int DOT_MAX = 4;
+
+struct DotArgs {
+  const double* x[DOT_MAX];
+  const double* y[DOT_MAX];
+};
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < int(blockDim.x >> 6); ++i) s += sh[i];
+  return s;
+}
+
+__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, int nd, DotArgs a,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[4];
+  double acc[DOT_MAX] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    for (int d = 0; d < nd; ++d) acc[d] += a.x[d][i] * a.y[d][i];
+  for (int d = 0; d < nd; ++d) {
+    const double s = block_sum(acc[d], sh);
+    if (threadIdx.x == 0) part[d * DOT_BLOCKS + blockIdx.x] = s;
+  }
+}
+__global__ void __launch_bounds__(256) k_dot_final(int nd, const double* __restrict__ part,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[4];
+  for (int d = 0; d < nd; ++d) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < DOT_BLOCKS; i += blockDim.x) acc += part[d * DOT_BLOCKS + i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[d] = s;
+  }
+}
+
+void dots(Ctx& c, int64_t n, int nd, const double* const* xs, const double* const* ys,
+          double* out_host) {
+  AMGF_REQUIRE(nd >= 1 && nd <= DOT_MAX, AMGF_EINVAL, "dots count");
+  if (c.dot.n == 0) c.dot.alloc(size_t(DOT_MAX) * DOT_BLOCKS + DOT_MAX);
+  DBuf<double>* part = &c.dot;
+  DotArgs a{};
+  for (int d = 0; d < nd; ++d) {
+    a.x[d] = xs[d];
+    a.y[d] = ys[d];
+  }
+  hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, nd, a, part->p);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, c.s, nd, part->p,
+                     part->p + DOT_MAX * DOT_BLOCKS);
+  AMGF_LAUNCH_CHECK();
+  AMGF_HIP(hipMemcpyAsync(out_host, part->p + DOT_MAX * DOT_BLOCKS, nd * sizeof(double),
+                          hipMemcpyDeviceToHost, c.s));
+  AMGF_HIP(hipStreamSynchronize(c.s));
+}
+
+}  // namespace amgf

@@ -1,0 +1,171 @@
+// Shared declarations of the AMGF HIP library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/amgf.h"
+
+namespace amgf {
+
+// ------------------------------------------------------------------------------------
+// errors: thrown inside the library, converted to amgf_status at the C boundary
+// ------------------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  amgf_status status;
+  Error(amgf_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define AMGF_HIP(call)                                                                 \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::amgf::Error(e_ == hipErrorOutOfMemory ? AMGF_ENOMEM : AMGF_EDEVICE,      \
+                          std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+#define AMGF_REQUIRE(cond, status, msg)                                                \
+  do {                                                                                 \
+    if (!(cond)) throw ::amgf::Error(status, msg);                                     \
+  } while (0)
+
+#define AMGF_LAUNCH_CHECK() AMGF_HIP(hipGetLastError())
+
+// ------------------------------------------------------------------------------------
+// device buffers (owned by the handle)
+// ------------------------------------------------------------------------------------
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  explicit DBuf(size_t count) { alloc(count); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count) AMGF_HIP(hipMalloc(&p, count * sizeof(T)));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+  operator T*() const { return p; }
+};
+
+// Block-row sparse matrix with br x bc row-major blocks and ascending columns.
+struct BSR {
+  int nrows = 0, ncols = 0, br = 0, bc = 0;
+  int64_t nnzb = 0;
+  DBuf<int> rowptr, col;
+  DBuf<double> val;
+  DBuf<float> val32;       // FP32 copy used by the mixed-precision V-cycle
+  size_t bsz() const { return size_t(br) * bc; }
+};
+
+// per-stream context passed to every host helper
+struct Ctx {
+  hipStream_t s = nullptr;
+  DBuf<int> flag;          // device error/capacity flag
+  DBuf<double> dot;        // partial sums of the deterministic dot products
+};
+
+// ------------------------------------------------------------------------------------
+// small host helpers
+// ------------------------------------------------------------------------------------
+template <class T>
+inline T d2h_scalar(const T* dptr, hipStream_t s) {
+  T v;
+  AMGF_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  AMGF_HIP(hipStreamSynchronize(s));
+  return v;
+}
+template <class T>
+inline std::vector<T> d2h(const T* dptr, size_t n, hipStream_t s) {
+  std::vector<T> v(n);
+  if (n) {
+    AMGF_HIP(hipMemcpyAsync(v.data(), dptr, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    AMGF_HIP(hipStreamSynchronize(s));
+  }
+  return v;
+}
+inline unsigned grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  return unsigned(g < 1 ? 1 : g);
+}
+
+// ------------------------------------------------------------------------------------
+// device helpers
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// Separately rounded FP64 multiply and add.  Contraction into FMA is switched off in
+// these bodies (the HIP intrinsics of the same name are plain operators that the
+// compiler may fuse), so results match a reference that rounds every operation.
+__device__ __forceinline__ double mul_rn(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+__device__ __forceinline__ double add_rn(double a, double b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <class T>
+__device__ __forceinline__ T group_sum(T v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
+  return v;
+}
+
+// ------------------------------------------------------------------------------------
+// primitives (primitives.hip)
+// ------------------------------------------------------------------------------------
+// out[0..n] = exclusive scan of in[0..n-1]; out[n] = total.  Returns the total.
+int scan_exclusive(Ctx& c, const int* in, int* out, int n, bool want_total = true);
+// rows[k] = block row of block k, for a CSR rowptr of nrows rows
+void expand_rows(Ctx& c, const int* rowptr, int nrows, int* rows);
+// Deterministic grouping: for keys[i] in [0, nkeys) (negative keys skipped),
+// offsets[nkeys+1] and perm[] listing the indices i of each key in ascending order.
+void group_by_key(Ctx& c, const int* keys, int n, int nkeys, DBuf<int>& offsets,
+                  DBuf<int>& perm);
+// Transpose a BSR matrix (blocks transposed too).  Deterministic.
+void bsr_transpose(Ctx& c, const BSR& A, BSR& T);
+// Symbolic union: row r of C collects map(col2[u]) for u in rows col1[t] of the inner
+// CSR, t in row r of the outer CSR (inner == nullptr: map(col1[t]) directly).
+// Negative mapped ids are skipped; exclude_diag drops id == r; row_mask (optional)
+// selects the rows that get entries.  Produces C.rowptr / C.col (sorted).
+void union_symbolic(Ctx& c, int nrows, int ncols, const int* rp1, const int* col1,
+                    const int* rp2, const int* col2, const int* map, bool exclude_diag,
+                    const int* row_mask, BSR& C);
+// C = A + B pattern union (sorted merge) and exact values (A + B where both exist).
+void bsr_add(Ctx& c, const BSR& A, const BSR& B, BSR& C);
+
+}  // namespace amgf

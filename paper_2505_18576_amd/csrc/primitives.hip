@@ -1,0 +1,385 @@
+// Setup primitives: scans, deterministic grouping and transposes, symbolic unions.
+//
+// Every output here is independent of thread scheduling: atomics only count or claim
+// slots, and each group/row is put into ascending order afterwards, so two runs of a
+// setup give bitwise-identical hierarchies.
+#include "common.h"
+
+namespace amgf {
+
+// ======================================================================================
+// exclusive scan (int32 data, int64 carries)
+// ======================================================================================
+constexpr int SCAN_T = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_CHUNK = SCAN_T * SCAN_ITEMS;
+
+__device__ __forceinline__ long long block_excl_scan(long long v, long long* wsum,
+                                                     long long* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  long long inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    long long t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long acc = 0;
+    for (int w = 0; w < SCAN_T / 64; ++w) {
+      long long t = wsum[w];
+      wsum[w] = acc;
+      acc += t;
+    }
+    *total = acc;
+  }
+  __syncthreads();
+  return inc - v + wsum[wid];
+}
+
+__global__ void k_scan_sums(const int* __restrict__ in, int n, long long* __restrict__ sums) {
+  __shared__ long long wsum[SCAN_T / 64];
+  __shared__ long long tot;
+  const int64_t base = int64_t(blockIdx.x) * SCAN_CHUNK + int64_t(threadIdx.x) * SCAN_ITEMS;
+  long long s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i)
+    if (base + i < n) s += in[base + i];
+  block_excl_scan(s, wsum, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of the per-chunk sums in place
+__global__ void k_scan_sums_single(long long* sums, int nb, int* flag) {
+  __shared__ long long wsum[SCAN_T / 64];
+  __shared__ long long tot;
+  const int per = (nb + SCAN_T - 1) / SCAN_T;
+  const int lo = threadIdx.x * per;
+  long long s = 0;
+  for (int i = 0; i < per; ++i)
+    if (lo + i < nb) s += sums[lo + i];
+  long long off = block_excl_scan(s, wsum, &tot);
+  for (int i = 0; i < per; ++i)
+    if (lo + i < nb) {
+      long long t = sums[lo + i];
+      sums[lo + i] = off;
+      off += t;
+    }
+  if (threadIdx.x == 0) {
+    sums[nb] = tot;
+    if (tot > 0x7fffffffLL) atomicOr(flag, 1);
+  }
+}
+
+__global__ void k_scan_final(const int* __restrict__ in, int* __restrict__ out, int n,
+                             const long long* __restrict__ sums) {
+  __shared__ long long wsum[SCAN_T / 64];
+  __shared__ long long tot;
+  const int64_t base = int64_t(blockIdx.x) * SCAN_CHUNK + int64_t(threadIdx.x) * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  long long s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    s += v[i];
+  }
+  long long off = block_excl_scan(s, wsum, &tot) + sums[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i)
+    if (base + i < n) {
+      out[base + i] = int(off);
+      off += v[i];
+    }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = int(sums[gridDim.x]);
+}
+
+int scan_exclusive(Ctx& c, const int* in, int* out, int n, bool want_total) {
+  if (n == 0) {
+    AMGF_HIP(hipMemsetAsync(out, 0, sizeof(int), c.s));
+    return 0;
+  }
+  const int nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  DBuf<long long> sums(nb + 1);
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_T), 0, c.s, in, n, sums.p);
+  hipLaunchKernelGGL(k_scan_sums_single, dim3(1), dim3(SCAN_T), 0, c.s, sums.p, nb, c.flag.p);
+  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_T), 0, c.s, in, out, n, sums.p);
+  AMGF_LAUNCH_CHECK();
+  if (!want_total) return -1;
+  int total = d2h_scalar(out + n, c.s);
+  int fl = d2h_scalar(c.flag.p, c.s);
+  AMGF_REQUIRE(fl == 0, AMGF_ENOMEM, "scan total exceeds int32");
+  return total;
+}
+
+// ======================================================================================
+// row expansion
+// ======================================================================================
+__global__ void k_expand_rows(const int* __restrict__ rowptr, int nrows, int* __restrict__ rows) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) rows[k] = r;
+}
+
+void expand_rows(Ctx& c, const int* rowptr, int nrows, int* rows) {
+  if (nrows == 0) return;
+  hipLaunchKernelGGL(k_expand_rows, dim3(grid_for(nrows, 256)), dim3(256), 0, c.s, rowptr,
+                     nrows, rows);
+  AMGF_LAUNCH_CHECK();
+}
+
+// ======================================================================================
+// deterministic group-by-key
+// ======================================================================================
+__global__ void k_count_keys(const int* __restrict__ keys, int n, int* __restrict__ counts) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && keys[i] >= 0) atomicAdd(&counts[keys[i]], 1);
+}
+__global__ void k_fill_keys(const int* __restrict__ keys, int n, const int* __restrict__ off,
+                            int* __restrict__ cursor, int* __restrict__ perm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || keys[i] < 0) return;
+  const int k = keys[i];
+  perm[off[k] + atomicAdd(&cursor[k], 1)] = i;
+}
+// one wavefront per segment: rank sort of distinct values (ascending)
+__global__ void k_segment_sort(const int* __restrict__ off, int nseg, const int* __restrict__ in,
+                               int* __restrict__ out) {
+  const int seg = blockIdx.x;
+  if (seg >= nseg) return;
+  const int a = off[seg], b = off[seg + 1];
+  for (int j = a + threadIdx.x; j < b; j += blockDim.x) {
+    const int v = in[j];
+    int rank = 0;
+    for (int i = a; i < b; ++i) rank += in[i] < v;
+    out[a + rank] = v;
+  }
+}
+
+void group_by_key(Ctx& c, const int* keys, int n, int nkeys, DBuf<int>& offsets,
+                  DBuf<int>& perm) {
+  offsets.alloc(size_t(nkeys) + 1);
+  DBuf<int> counts(std::max(nkeys, 1));
+  AMGF_HIP(hipMemsetAsync(counts.p, 0, counts.bytes(), c.s));
+  if (n > 0)
+    hipLaunchKernelGGL(k_count_keys, dim3(grid_for(n, 256)), dim3(256), 0, c.s, keys, n,
+                       counts.p);
+  const int total = scan_exclusive(c, counts.p, offsets.p, nkeys);
+  perm.alloc(std::max(total, 1));
+  if (total == 0) return;
+  AMGF_HIP(hipMemsetAsync(counts.p, 0, counts.bytes(), c.s));
+  DBuf<int> tmp(total);
+  hipLaunchKernelGGL(k_fill_keys, dim3(grid_for(n, 256)), dim3(256), 0, c.s, keys, n,
+                     offsets.p, counts.p, tmp.p);
+  hipLaunchKernelGGL(k_segment_sort, dim3(nkeys), dim3(64), 0, c.s, offsets.p, nkeys, tmp.p,
+                     perm.p);
+  AMGF_LAUNCH_CHECK();
+}
+
+// ======================================================================================
+// BSR transpose
+// ======================================================================================
+__global__ void k_transpose_fill(int64_t nnzb, const int* __restrict__ perm,
+                                 const int* __restrict__ rows, const double* __restrict__ val,
+                                 int br, int bc, int* __restrict__ tcol,
+                                 double* __restrict__ tval) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= nnzb) return;
+  const int src = perm[k];
+  tcol[k] = rows[src];
+  const double* s = val + int64_t(src) * br * bc;
+  double* d = tval + k * br * bc;
+  for (int p = 0; p < br; ++p)
+    for (int q = 0; q < bc; ++q) d[q * br + p] = s[p * bc + q];
+}
+
+void bsr_transpose(Ctx& c, const BSR& A, BSR& T) {
+  T.nrows = A.ncols;
+  T.ncols = A.nrows;
+  T.br = A.bc;
+  T.bc = A.br;
+  T.nnzb = A.nnzb;
+  DBuf<int> rows(std::max<int64_t>(A.nnzb, 1));
+  expand_rows(c, A.rowptr.p, A.nrows, rows.p);
+  DBuf<int> perm;
+  group_by_key(c, A.col.p, int(A.nnzb), A.ncols, T.rowptr, perm);
+  T.col.alloc(std::max<int64_t>(A.nnzb, 1));
+  T.val.alloc(std::max<int64_t>(A.nnzb, 1) * A.bsz());
+  if (A.nnzb)
+    hipLaunchKernelGGL(k_transpose_fill, dim3(grid_for(A.nnzb, 256)), dim3(256), 0, c.s,
+                       A.nnzb, perm.p, rows.p, A.val.p, A.br, A.bc, T.col.p, T.val.p);
+  AMGF_LAUNCH_CHECK();
+}
+
+// ======================================================================================
+// symbolic union (one 64-lane workgroup per output row, LDS hash set)
+// ======================================================================================
+constexpr int HS = 2048;                 // hash slots per row
+constexpr int HS_MAX_UNIQUE = 1536;      // capacity before the row is rejected
+
+__device__ __forceinline__ void hs_insert(int* table, int* list, int* cnt, int key,
+                                          bool fill, int* flag) {
+  unsigned h = (unsigned(key) * 2654435761u) & (HS - 1);
+  for (int probe = 0; probe < HS; ++probe) {
+    const int old = atomicCAS(&table[h], -1, key);
+    if (old == -1) {
+      const int pos = atomicAdd(cnt, 1);
+      if (pos < HS_MAX_UNIQUE) {
+        if (fill) list[pos] = key;
+      } else {
+        atomicOr(flag, 2);
+      }
+      return;
+    }
+    if (old == key) return;
+    h = (h + 1) & (HS - 1);
+  }
+  atomicOr(flag, 2);
+}
+
+__global__ void __launch_bounds__(64) k_union(int nrows, const int* __restrict__ rp1,
+                                              const int* __restrict__ col1,
+                                              const int* __restrict__ rp2,
+                                              const int* __restrict__ col2,
+                                              const int* __restrict__ map, int exclude_diag,
+                                              const int* __restrict__ row_mask, int fill,
+                                              int* __restrict__ counts,
+                                              const int* __restrict__ rowptr,
+                                              int* __restrict__ outcol, int* flag) {
+  __shared__ int table[HS];
+  __shared__ int list[HS_MAX_UNIQUE];
+  __shared__ int cnt;
+  const int r = blockIdx.x;
+  if (r >= nrows) return;
+  if (row_mask && !row_mask[r]) {
+    if (!fill && threadIdx.x == 0) counts[r] = 0;
+    return;
+  }
+  for (int i = threadIdx.x; i < HS; i += 64) table[i] = -1;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int t = rp1[r] + threadIdx.x; t < rp1[r + 1]; t += 64) {
+    const int mid = col1[t];
+    if (rp2) {
+      for (int u = rp2[mid]; u < rp2[mid + 1]; ++u) {
+        int cand = col2[u];
+        if (map) cand = map[cand];
+        if (cand < 0 || (exclude_diag && cand == r)) continue;
+        hs_insert(table, list, &cnt, cand, fill, flag);
+      }
+    } else {
+      int cand = map ? map[mid] : mid;
+      if (cand < 0 || (exclude_diag && cand == r)) continue;
+      hs_insert(table, list, &cnt, cand, fill, flag);
+    }
+  }
+  __syncthreads();
+  const int n = min(cnt, HS_MAX_UNIQUE);
+  if (!fill) {
+    if (threadIdx.x == 0) counts[r] = n;
+    return;
+  }
+  const int base = rowptr[r];
+  for (int j = threadIdx.x; j < n; j += 64) {
+    const int v = list[j];
+    int rank = 0;
+    for (int i = 0; i < n; ++i) rank += list[i] < v;
+    outcol[base + rank] = v;
+  }
+}
+
+void union_symbolic(Ctx& c, int nrows, int ncols, const int* rp1, const int* col1,
+                    const int* rp2, const int* col2, const int* map, bool exclude_diag,
+                    const int* row_mask, BSR& C) {
+  C.nrows = nrows;
+  C.ncols = ncols;
+  DBuf<int> counts(std::max(nrows, 1));
+  C.rowptr.alloc(size_t(nrows) + 1);
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  if (nrows)
+    hipLaunchKernelGGL(k_union, dim3(nrows), dim3(64), 0, c.s, nrows, rp1, col1, rp2, col2,
+                       map, int(exclude_diag), row_mask, 0, counts.p, nullptr, nullptr,
+                       c.flag.p);
+  AMGF_LAUNCH_CHECK();
+  int fl = d2h_scalar(c.flag.p, c.s);
+  AMGF_REQUIRE(fl == 0, AMGF_ENOMEM, "symbolic product row exceeds the union capacity");
+  C.nnzb = scan_exclusive(c, counts.p, C.rowptr.p, nrows);
+  C.col.alloc(std::max<int64_t>(C.nnzb, 1));
+  if (nrows && C.nnzb)
+    hipLaunchKernelGGL(k_union, dim3(nrows), dim3(64), 0, c.s, nrows, rp1, col1, rp2, col2,
+                       map, int(exclude_diag), row_mask, 1, nullptr, C.rowptr.p, C.col.p,
+                       c.flag.p);
+  AMGF_LAUNCH_CHECK();
+}
+
+// ======================================================================================
+// C = A + B (pattern union, exact values)
+// ======================================================================================
+__global__ void k_merge_count(int nrows, const int* __restrict__ ra, const int* __restrict__ ca,
+                              const int* __restrict__ rb, const int* __restrict__ cb,
+                              int* __restrict__ counts) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int i = ra[r], ie = ra[r + 1], j = rb[r], je = rb[r + 1], n = 0;
+  while (i < ie || j < je) {
+    if (j >= je || (i < ie && ca[i] < cb[j])) ++i;
+    else if (i >= ie || cb[j] < ca[i]) ++j;
+    else { ++i; ++j; }
+    ++n;
+  }
+  counts[r] = n;
+}
+
+__global__ void k_merge_fill(int nrows, int bsz, const int* __restrict__ ra,
+                             const int* __restrict__ ca, const double* __restrict__ va,
+                             const int* __restrict__ rb, const int* __restrict__ cb,
+                             const double* __restrict__ vb, const int* __restrict__ rc,
+                             int* __restrict__ cc, double* __restrict__ vc) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int i = ra[r], ie = ra[r + 1], j = rb[r], je = rb[r + 1], o = rc[r];
+  while (i < ie || j < je) {
+    double* d = vc + int64_t(o) * bsz;
+    if (j >= je || (i < ie && ca[i] < cb[j])) {
+      cc[o] = ca[i];
+      for (int e = 0; e < bsz; ++e) d[e] = va[int64_t(i) * bsz + e];
+      ++i;
+    } else if (i >= ie || cb[j] < ca[i]) {
+      cc[o] = cb[j];
+      for (int e = 0; e < bsz; ++e) d[e] = vb[int64_t(j) * bsz + e];
+      ++j;
+    } else {
+      cc[o] = ca[i];
+      for (int e = 0; e < bsz; ++e)
+        d[e] = add_rn(va[int64_t(i) * bsz + e], vb[int64_t(j) * bsz + e]);
+      ++i;
+      ++j;
+    }
+    ++o;
+  }
+}
+
+void bsr_add(Ctx& c, const BSR& A, const BSR& B, BSR& C) {
+  AMGF_REQUIRE(A.nrows == B.nrows && A.br == B.br && A.bc == B.bc, AMGF_EINVAL,
+               "bsr_add shape mismatch");
+  C.nrows = A.nrows;
+  C.ncols = A.ncols;
+  C.br = A.br;
+  C.bc = A.bc;
+  DBuf<int> counts(std::max(A.nrows, 1));
+  C.rowptr.alloc(size_t(A.nrows) + 1);
+  if (A.nrows)
+    hipLaunchKernelGGL(k_merge_count, dim3(grid_for(A.nrows, 256)), dim3(256), 0, c.s,
+                       A.nrows, A.rowptr.p, A.col.p, B.rowptr.p, B.col.p, counts.p);
+  C.nnzb = scan_exclusive(c, counts.p, C.rowptr.p, A.nrows);
+  C.col.alloc(std::max<int64_t>(C.nnzb, 1));
+  C.val.alloc(std::max<int64_t>(C.nnzb, 1) * C.bsz());
+  if (A.nrows)
+    hipLaunchKernelGGL(k_merge_fill, dim3(grid_for(A.nrows, 256)), dim3(256), 0, c.s,
+                       A.nrows, int(A.bsz()), A.rowptr.p, A.col.p, A.val.p, B.rowptr.p,
+                       B.col.p, B.val.p, C.rowptr.p, C.col.p, C.val.p);
+  AMGF_LAUNCH_CHECK();
+}
+
+}  // namespace amgf

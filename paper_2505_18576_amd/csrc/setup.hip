@@ -1,0 +1,778 @@
+// AMG hierarchy setup kernels: Schur operator, strength, MIS-2 aggregation,
+// tentative and smoothed prolongators, Galerkin products.
+//
+// The level-0 operator and strength test are computed with separately rounded
+// multiplies and adds (no contraction) in a fixed order, so they are bitwise
+// reproducible; aggregation decisions on later levels are integer-only.
+#include "setup.h"
+
+namespace amgf {
+
+// ======================================================================================
+// J (scalar CSR m x n) -> node blocks (1 x 3)
+// ======================================================================================
+__global__ void k_jnode_count(int m, const int* __restrict__ rp, const int* __restrict__ col,
+                             int* __restrict__ counts) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  int n = 0, last = -1;
+  for (int t = rp[k]; t < rp[k + 1]; ++t) {
+    const int nd = col[t] / 3;
+    if (nd != last) { ++n; last = nd; }
+  }
+  counts[k] = n;
+}
+__global__ void k_jnode_fill(int m, const int* __restrict__ rp, const int* __restrict__ col,
+                            const double* __restrict__ val, const int* __restrict__ brp,
+                            int* __restrict__ bcol, double* __restrict__ bval) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  int o = brp[k] - 1, last = -1;
+  for (int t = rp[k]; t < rp[k + 1]; ++t) {
+    const int nd = col[t] / 3;
+    if (nd != last) {
+      ++o;
+      last = nd;
+      bcol[o] = nd;
+      bval[3 * int64_t(o)] = 0.0;
+      bval[3 * int64_t(o) + 1] = 0.0;
+      bval[3 * int64_t(o) + 2] = 0.0;
+    }
+    bval[3 * int64_t(o) + col[t] % 3] = val[t];
+  }
+}
+
+void j_to_node_blocks(Ctx& c, int m, int n_nodes, const int* rp, const int* col,
+                      const double* val, BSR& J) {
+  J.nrows = m;
+  J.ncols = n_nodes;
+  J.br = 1;
+  J.bc = 3;
+  J.rowptr.alloc(size_t(m) + 1);
+  DBuf<int> counts(std::max(m, 1));
+  if (m)
+    hipLaunchKernelGGL(k_jnode_count, dim3(grid_for(m, 256)), dim3(256), 0, c.s, m, rp, col,
+                       counts.p);
+  J.nnzb = scan_exclusive(c, counts.p, J.rowptr.p, m);
+  J.col.alloc(std::max<int64_t>(J.nnzb, 1));
+  J.val.alloc(std::max<int64_t>(J.nnzb, 1) * 3);
+  if (m)
+    hipLaunchKernelGGL(k_jnode_fill, dim3(grid_for(m, 256)), dim3(256), 0, c.s, m, rp, col,
+                       val, J.rowptr.p, J.col.p, J.val.p);
+  AMGF_LAUNCH_CHECK();
+}
+
+// ======================================================================================
+// contact term C = J^T diag(D) J with a fixed rounding order
+// ======================================================================================
+__device__ __forceinline__ int lower_bound_i(const int* a, int lo, int hi, int key) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Row a: for constraint rows k of JT row a in ascending order, for each block (k, b):
+//   C_ab(p, q) = C_ab(p, q) + D_k * (J_ka[p] * J_kb[q])   (each op rounded)
+template <int B>
+__global__ void k_contact_numeric(int nn, const int* __restrict__ jtrp,
+                                  const int* __restrict__ jtcol,
+                                  const double* __restrict__ jtval,
+                                  const int* __restrict__ jrp, const int* __restrict__ jcol,
+                                  const double* __restrict__ jval,
+                                  const double* __restrict__ D, const int* __restrict__ crp,
+                                  const int* __restrict__ ccol, double* __restrict__ cval,
+                                  int* flag) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nn) return;
+  const int c0 = crp[a], c1 = crp[a + 1];
+  for (int t = jtrp[a]; t < jtrp[a + 1]; ++t) {
+    const int k = jtcol[t];
+    const double Dk = D[k];
+    double ja[B];
+#pragma unroll
+    for (int p = 0; p < B; ++p) ja[p] = jtval[int64_t(t) * B + p];
+    for (int u = jrp[k]; u < jrp[k + 1]; ++u) {
+      const int b = jcol[u];
+      const int s = lower_bound_i(ccol, c0, c1, b);
+      if (s >= c1 || ccol[s] != b) { atomicOr(flag, 32); continue; }
+      double* C = cval + int64_t(s) * B * B;
+      const double* jb = jval + int64_t(u) * B;
+#pragma unroll
+      for (int p = 0; p < B; ++p)
+#pragma unroll
+        for (int q = 0; q < B; ++q)
+          C[p * B + q] = add_rn(C[p * B + q], mul_rn(Dk, mul_rn(ja[p], jb[q])));
+    }
+  }
+}
+
+void contact_operator(Ctx& c, const BSR& J, const BSR& JT, const double* D, BSR& C) {
+  const int nn = J.ncols, b = J.bc;
+  union_symbolic(c, nn, nn, JT.rowptr.p, JT.col.p, J.rowptr.p, J.col.p, nullptr, false,
+                 nullptr, C);
+  C.br = C.bc = b;
+  C.val.alloc(std::max<int64_t>(C.nnzb, 1) * b * b);
+  AMGF_HIP(hipMemsetAsync(C.val.p, 0, C.val.bytes(), c.s));
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  if (nn && C.nnzb) {
+    if (b == 3)
+      hipLaunchKernelGGL(k_contact_numeric<3>, dim3(grid_for(nn, 128)), dim3(128), 0, c.s, nn,
+                         JT.rowptr.p, JT.col.p, JT.val.p, J.rowptr.p, J.col.p, J.val.p, D,
+                         C.rowptr.p, C.col.p, C.val.p, c.flag.p);
+    else
+      hipLaunchKernelGGL(k_contact_numeric<6>, dim3(grid_for(nn, 128)), dim3(128), 0, c.s, nn,
+                         JT.rowptr.p, JT.col.p, JT.val.p, J.rowptr.p, J.col.p, J.val.p, D,
+                         C.rowptr.p, C.col.p, C.val.p, c.flag.p);
+  }
+  AMGF_LAUNCH_CHECK();
+  AMGF_REQUIRE(d2h_scalar(c.flag.p, c.s) == 0, AMGF_EDEVICE, "contact pattern mismatch");
+}
+
+// ======================================================================================
+// level-0 strength of connection and decoupled DOFs
+// ======================================================================================
+__global__ void k_block_nu(int64_t nnzb, int bsz, const double* __restrict__ val,
+                           double* __restrict__ nu) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= nnzb) return;
+  double acc = 0.0;
+  for (int e = 0; e < bsz; ++e) {
+    const double v = val[k * bsz + e];
+    acc = add_rn(acc, mul_rn(v, v));
+  }
+  nu[k] = acc;
+}
+
+__global__ void k_diag_pos(int nrows, const int* __restrict__ rp, const int* __restrict__ col,
+                           int* __restrict__ dpos) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int s = lower_bound_i(col, rp[r], rp[r + 1], r);
+  dpos[r] = (s < rp[r + 1] && col[s] == r) ? s : -1;
+}
+
+__global__ void k_strong(int64_t nnzb, const int* __restrict__ rows, const int* __restrict__ rp,
+                         const int* __restrict__ col, const double* __restrict__ nu,
+                         const int* __restrict__ dpos, double theta4, int* __restrict__ strong,
+                         int* flag) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= nnzb) return;
+  const int a = rows[k], b = col[k];
+  if (a == b) { strong[k] = 0; return; }
+  const int t = lower_bound_i(col, rp[b], rp[b + 1], a);
+  if (t >= rp[b + 1] || col[t] != a || dpos[a] < 0 || dpos[b] < 0) {
+    atomicOr(flag, 4);
+    strong[k] = 0;
+    return;
+  }
+  const double naa = nu[dpos[a]], nbb = nu[dpos[b]];
+  const double lhs = mul_rn(nu[k], nu[k]);
+  const double rhs = mul_rn(theta4, mul_rn(naa, nbb));
+  const double lhs_t = mul_rn(nu[t], nu[t]);
+  const double rhs_t = mul_rn(theta4, mul_rn(nbb, naa));
+  strong[k] = (lhs >= rhs) && (lhs_t >= rhs_t);
+}
+
+__global__ void k_count_flags(int nrows, const int* __restrict__ rp, const int* __restrict__ f,
+                              int* __restrict__ counts) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int n = 0;
+  for (int k = rp[r]; k < rp[r + 1]; ++k) n += f[k];
+  counts[r] = n;
+}
+__global__ void k_compact_graph(int nrows, const int* __restrict__ rp, const int* __restrict__ col,
+                                const int* __restrict__ f, const double* __restrict__ nu,
+                                const int* __restrict__ grp, int* __restrict__ gcol,
+                                double* __restrict__ gw) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int o = grp[r];
+  for (int k = rp[r]; k < rp[r + 1]; ++k)
+    if (f[k]) {
+      gcol[o] = col[k];
+      gw[o] = nu[k];
+      ++o;
+    }
+}
+
+void strength_graph(Ctx& c, const BSR& A, double theta, Graph& G) {
+  const int n = A.nrows;
+  const int64_t nz = A.nnzb;
+  DBuf<double> nu(std::max<int64_t>(nz, 1));
+  DBuf<int> rows(std::max<int64_t>(nz, 1)), dpos(std::max(n, 1)),
+      strong(std::max<int64_t>(nz, 1)), counts(std::max(n, 1));
+  expand_rows(c, A.rowptr.p, n, rows.p);
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  hipLaunchKernelGGL(k_block_nu, dim3(grid_for(nz, 256)), dim3(256), 0, c.s, nz, int(A.bsz()),
+                     A.val.p, nu.p);
+  hipLaunchKernelGGL(k_diag_pos, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, A.rowptr.p,
+                     A.col.p, dpos.p);
+  const double t2 = theta * theta;
+  const double t4 = t2 * t2;
+  hipLaunchKernelGGL(k_strong, dim3(grid_for(nz, 256)), dim3(256), 0, c.s, nz, rows.p,
+                     A.rowptr.p, A.col.p, nu.p, dpos.p, t4, strong.p, c.flag.p);
+  hipLaunchKernelGGL(k_count_flags, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, A.rowptr.p,
+                     strong.p, counts.p);
+  AMGF_LAUNCH_CHECK();
+  AMGF_REQUIRE(d2h_scalar(c.flag.p, c.s) == 0, AMGF_EINVAL,
+               "operator pattern is not symmetric or lacks a diagonal block");
+  G.n = n;
+  G.rowptr.alloc(size_t(n) + 1);
+  G.nnz = scan_exclusive(c, counts.p, G.rowptr.p, n);
+  G.col.alloc(std::max<int64_t>(G.nnz, 1));
+  G.w.alloc(std::max<int64_t>(G.nnz, 1));
+  hipLaunchKernelGGL(k_compact_graph, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n,
+                     A.rowptr.p, A.col.p, strong.p, nu.p, G.rowptr.p, G.col.p, G.w.p);
+  AMGF_LAUNCH_CHECK();
+}
+
+// DOF i of node a is decoupled when every off-diagonal entry of its row is 0.
+template <int B>
+__global__ void k_decoupled(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                            const double* __restrict__ val, unsigned char* __restrict__ dec) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  bool coupled[B];
+#pragma unroll
+  for (int p = 0; p < B; ++p) coupled[p] = false;
+  for (int k = rp[a]; k < rp[a + 1]; ++k) {
+    const int b = col[k];
+    const double* v = val + int64_t(k) * B * B;
+#pragma unroll
+    for (int p = 0; p < B; ++p)
+#pragma unroll
+      for (int q = 0; q < B; ++q)
+        if ((b != a || q != p) && v[p * B + q] != 0.0) coupled[p] = true;
+  }
+#pragma unroll
+  for (int p = 0; p < B; ++p) dec[int64_t(a) * B + p] = coupled[p] ? 0 : 1;
+}
+
+void decoupled_dofs(Ctx& c, const BSR& A, DBuf<unsigned char>& dec) {
+  dec.alloc(size_t(A.nrows) * A.br);
+  AMGF_REQUIRE(A.br == 3 || A.br == 6, AMGF_EINVAL, "block size");
+  if (A.br == 3)
+    hipLaunchKernelGGL(k_decoupled<3>, dim3(grid_for(A.nrows, 256)), dim3(256), 0, c.s,
+                       A.nrows, A.rowptr.p, A.col.p, A.val.p, dec.p);
+  else
+    hipLaunchKernelGGL(k_decoupled<6>, dim3(grid_for(A.nrows, 256)), dim3(256), 0, c.s,
+                       A.nrows, A.rowptr.p, A.col.p, A.val.p, dec.p);
+  AMGF_LAUNCH_CHECK();
+}
+
+// ======================================================================================
+// MIS-2 by parallel rounds
+// ======================================================================================
+// state: 0 undecided, 1 root, 2 out.  code(v) = ~0 for roots, the priority key
+// (fmix32(v) << 32 | v) for undecided nodes, 0 otherwise.  A round takes the maximum
+// code over the distance-2 ball: a ball holding a root excludes v, a ball whose
+// maximum is v's own key makes v a root.  This yields the set the sequential greedy
+// pass (descending keys) produces.
+__device__ __forceinline__ unsigned long long mis_code(int v, unsigned char st) {
+  if (st == 1) return ~0ull;
+  if (st == 0) return (static_cast<unsigned long long>(fmix32(uint32_t(v))) << 32) | uint32_t(v);
+  return 0ull;
+}
+
+__global__ void k_mis_init(int n, const int* __restrict__ rp, unsigned char* __restrict__ st) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) st[v] = (rp[v + 1] > rp[v]) ? 0 : 2;
+}
+__global__ void k_mis_ball1(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                            const unsigned char* __restrict__ st,
+                            unsigned long long* __restrict__ m1) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  unsigned long long m = mis_code(v, st[v]);
+  for (int k = rp[v]; k < rp[v + 1]; ++k) {
+    const int u = col[k];
+    const unsigned long long cu = mis_code(u, st[u]);
+    m = cu > m ? cu : m;
+  }
+  m1[v] = m;
+}
+__global__ void k_mis_ball2(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                            const unsigned long long* __restrict__ m1,
+                            unsigned char* __restrict__ st, int* __restrict__ undecided) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || st[v] != 0) return;
+  unsigned long long m = m1[v];
+  for (int k = rp[v]; k < rp[v + 1]; ++k) m = m1[col[k]] > m ? m1[col[k]] : m;
+  if (m == ~0ull) st[v] = 2;
+  else if (m == mis_code(v, 0)) st[v] = 1;
+  else atomicAdd(undecided, 1);
+}
+
+// ======================================================================================
+// aggregation
+// ======================================================================================
+__global__ void k_root_flags(int n, const unsigned char* __restrict__ st, int* __restrict__ f) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) f[v] = st[v] == 1;
+}
+__global__ void k_agg_phase1(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                             const int* __restrict__ isroot, const int* __restrict__ rid,
+                             int* __restrict__ p1, int* flag) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (isroot[v]) { p1[v] = rid[v]; return; }
+  int a = -1;
+  for (int k = rp[v]; k < rp[v + 1]; ++k) {
+    const int u = col[k];
+    if (isroot[u]) {
+      if (a >= 0) atomicOr(flag, 8);
+      a = rid[u];
+    }
+  }
+  p1[v] = a;
+}
+// Phase 2 from phase-1 state only.  Level 0: the neighbour with the largest edge weight;
+// later levels: the aggregate holding most neighbours; ties -> smallest aggregate id.
+__global__ void k_agg_phase2(int n, int level, const int* __restrict__ rp,
+                             const int* __restrict__ col, const double* __restrict__ w,
+                             const int* __restrict__ p1, int* __restrict__ agg, int* flag) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int own = p1[v];
+  if (own >= 0 || rp[v + 1] == rp[v]) { agg[v] = own; return; }
+  int best = -1;
+  if (level == 0) {
+    double bw = 0.0;
+    for (int k = rp[v]; k < rp[v + 1]; ++k) {
+      const int J = p1[col[k]];
+      if (J < 0) continue;
+      if (best < 0 || w[k] > bw || (w[k] == bw && J < best)) { bw = w[k]; best = J; }
+    }
+  } else {
+    int bc = 0;
+    for (int k = rp[v]; k < rp[v + 1]; ++k) {
+      const int J = p1[col[k]];
+      if (J < 0) continue;
+      int cnt = 0;
+      for (int k2 = rp[v]; k2 < rp[v + 1]; ++k2) cnt += p1[col[k2]] == J;
+      if (best < 0 || cnt > bc || (cnt == bc && J < best)) { bc = cnt; best = J; }
+    }
+  }
+  if (best < 0) atomicOr(flag, 16);
+  agg[v] = best;
+}
+
+int mis2_aggregate(Ctx& c, const Graph& G, int level, DBuf<int>& agg, DBuf<int>& root_flag,
+                   int* rounds_out) {
+  const int n = G.n;
+  DBuf<unsigned char> st(std::max(n, 1));
+  DBuf<unsigned long long> m1(std::max(n, 1));
+  DBuf<int> und(1);
+  hipLaunchKernelGGL(k_mis_init, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, G.rowptr.p,
+                     st.p);
+  int rounds = 0;
+  for (;;) {
+    AMGF_HIP(hipMemsetAsync(und.p, 0, sizeof(int), c.s));
+    hipLaunchKernelGGL(k_mis_ball1, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, G.rowptr.p,
+                       G.col.p, st.p, m1.p);
+    hipLaunchKernelGGL(k_mis_ball2, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, G.rowptr.p,
+                       G.col.p, m1.p, st.p, und.p);
+    AMGF_LAUNCH_CHECK();
+    ++rounds;
+    if (d2h_scalar(und.p, c.s) == 0) break;
+    AMGF_REQUIRE(rounds < 10000, AMGF_EDEVICE, "MIS-2 did not terminate");
+  }
+  if (rounds_out) *rounds_out = rounds;
+  root_flag.alloc(std::max(n, 1));
+  DBuf<int> rid(size_t(n) + 1), p1(std::max(n, 1));
+  hipLaunchKernelGGL(k_root_flags, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, st.p,
+                     root_flag.p);
+  const int n_agg = scan_exclusive(c, root_flag.p, rid.p, n);
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  hipLaunchKernelGGL(k_agg_phase1, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, G.rowptr.p,
+                     G.col.p, root_flag.p, rid.p, p1.p, c.flag.p);
+  agg.alloc(std::max(n, 1));
+  hipLaunchKernelGGL(k_agg_phase2, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, level,
+                     G.rowptr.p, G.col.p, G.w.p, p1.p, agg.p, c.flag.p);
+  AMGF_LAUNCH_CHECK();
+  AMGF_REQUIRE(d2h_scalar(c.flag.p, c.s) == 0, AMGF_EDEVICE,
+               "aggregation invariant violated (MIS-2 not maximal or not independent)");
+  return n_agg;
+}
+
+// aggregate adjacency graph of the next level
+void coarse_graph(Ctx& c, const Graph& G, const int* agg, int n_agg, const int* moff,
+                  const int* members, Graph& Gc) {
+  BSR tmp;
+  union_symbolic(c, n_agg, n_agg, moff, members, G.rowptr.p, G.col.p, agg, true, nullptr, tmp);
+  Gc.n = n_agg;
+  Gc.nnz = tmp.nnzb;
+  Gc.rowptr = std::move(tmp.rowptr);
+  Gc.col = std::move(tmp.col);
+  Gc.w.alloc(std::max<int64_t>(Gc.nnz, 1));
+  hipLaunchKernelGGL(k_fill_ones, dim3(grid_for(std::max<int64_t>(Gc.nnz, 1), 256)), dim3(256),
+                     0, c.s, Gc.w.p, std::max<int64_t>(Gc.nnz, 1));
+  AMGF_LAUNCH_CHECK();
+}
+
+__global__ void k_fill_ones(double* w, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = 1.0;
+}
+
+// ======================================================================================
+// tentative prolongator: per-aggregate Gram-Schmidt QR of the near-null space
+// ======================================================================================
+// One 64-lane workgroup per aggregate; lane l owns rows l, l+64, ... of the aggregate's
+// (BR * k) x 6 near-null matrix, which is built in place in the P_t storage and
+// orthonormalised there (two projection passes per column, dead columns zeroed).
+template <int BR>
+__global__ void __launch_bounds__(64) k_tentative(int n_agg, const int* __restrict__ off,
+                                                  const int* __restrict__ members,
+                                                  const double* __restrict__ coords,
+                                                  const unsigned char* __restrict__ dec,
+                                                  const double* __restrict__ Rprev,
+                                                  double qr_tol, double* __restrict__ Pt,
+                                                  double* __restrict__ Rout,
+                                                  unsigned char* __restrict__ dead) {
+  const int J = blockIdx.x;
+  if (J >= n_agg) return;
+  const int lane = threadIdx.x;
+  const int a0 = off[J], k = off[J + 1] - a0;
+  const int rows = BR * k;
+  __shared__ double cen[3];
+  if (coords) {
+    if (lane == 0) {
+      double cx = 0.0, cy = 0.0, cz = 0.0;
+      for (int i = 0; i < k; ++i) {
+        const int v = members[a0 + i];
+        cx = cx + coords[3 * int64_t(v)];
+        cy = cy + coords[3 * int64_t(v) + 1];
+        cz = cz + coords[3 * int64_t(v) + 2];
+      }
+      cen[0] = cx / k;
+      cen[1] = cy / k;
+      cen[2] = cz / k;
+    }
+    __syncthreads();
+  }
+  // build
+  for (int idx = lane; idx < rows; idx += 64) {
+    const int v = members[a0 + idx / BR], p = idx % BR;
+    double* row = Pt + (int64_t(v) * BR + p) * 6;
+    if (coords) {
+      const double x = coords[3 * int64_t(v)] - cen[0];
+      const double y = coords[3 * int64_t(v) + 1] - cen[1];
+      const double z = coords[3 * int64_t(v) + 2] - cen[2];
+      double b[6] = {0, 0, 0, 0, 0, 0};
+      b[p] = 1.0;
+      if (p == 0) { b[4] = z; b[5] = -y; }
+      if (p == 1) { b[3] = -z; b[5] = x; }
+      if (p == 2) { b[3] = y; b[4] = -x; }
+      const bool off_row = dec && dec[int64_t(v) * BR + p];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) row[j] = off_row ? 0.0 : b[j];
+    } else {
+      const double* src = Rprev + (int64_t(v) * 6 + p) * 6;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) row[j] = src[j];
+    }
+  }
+  double R[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) R[i][j] = 0.0;
+  bool isdead[6];
+  for (int j = 0; j < 6; ++j) {
+    double s = 0.0;
+    for (int idx = lane; idx < rows; idx += 64) {
+      const int v = members[a0 + idx / BR], p = idx % BR;
+      const double x = Pt[(int64_t(v) * BR + p) * 6 + j];
+      s += x * x;
+    }
+    const double nb = sqrt(wave_sum(s));
+    for (int pass = 0; pass < 2; ++pass) {
+      double cc[6];
+      for (int i = 0; i < j; ++i) {
+        double d = 0.0;
+        for (int idx = lane; idx < rows; idx += 64) {
+          const int v = members[a0 + idx / BR], p = idx % BR;
+          const double* row = Pt + (int64_t(v) * BR + p) * 6;
+          d += row[i] * row[j];
+        }
+        cc[i] = wave_sum(d);
+      }
+      for (int idx = lane; idx < rows; idx += 64) {
+        const int v = members[a0 + idx / BR], p = idx % BR;
+        double* row = Pt + (int64_t(v) * BR + p) * 6;
+        double x = row[j];
+        for (int i = 0; i < j; ++i) x -= cc[i] * row[i];
+        row[j] = x;
+      }
+      for (int i = 0; i < j; ++i) R[i][j] += cc[i];
+    }
+    double s2 = 0.0;
+    for (int idx = lane; idx < rows; idx += 64) {
+      const int v = members[a0 + idx / BR], p = idx % BR;
+      const double x = Pt[(int64_t(v) * BR + p) * 6 + j];
+      s2 += x * x;
+    }
+    const double nv = sqrt(wave_sum(s2));
+    isdead[j] = (nb == 0.0) || (nv <= qr_tol * nb);
+    const double scale = isdead[j] ? 0.0 : 1.0 / nv;
+    R[j][j] = isdead[j] ? 0.0 : nv;
+    for (int idx = lane; idx < rows; idx += 64) {
+      const int v = members[a0 + idx / BR], p = idx % BR;
+      double* row = Pt + (int64_t(v) * BR + p) * 6;
+      row[j] = isdead[j] ? 0.0 : row[j] * scale;
+    }
+  }
+  if (lane == 0) {
+    for (int i = 0; i < 6; ++i) {
+      dead[int64_t(J) * 6 + i] = isdead[i];
+      for (int j = 0; j < 6; ++j) Rout[int64_t(J) * 36 + i * 6 + j] = isdead[i] ? 0.0 : R[i][j];
+    }
+  }
+}
+
+void tentative_prolongator(Ctx& c, int br, int n_nodes, int n_agg, const int* moff,
+                           const int* members, const double* coords,
+                           const unsigned char* dec, const double* Rprev, double qr_tol,
+                           DBuf<double>& Pt, DBuf<double>& R, DBuf<unsigned char>& dead) {
+  Pt.alloc(size_t(n_nodes) * br * 6);
+  AMGF_HIP(hipMemsetAsync(Pt.p, 0, Pt.bytes(), c.s));
+  R.alloc(size_t(n_agg) * 36);
+  dead.alloc(size_t(n_agg) * 6);
+  if (br == 3)
+    hipLaunchKernelGGL(k_tentative<3>, dim3(n_agg), dim3(64), 0, c.s, n_agg, moff, members,
+                       coords, dec, Rprev, qr_tol, Pt.p, R.p, dead.p);
+  else
+    hipLaunchKernelGGL(k_tentative<6>, dim3(n_agg), dim3(64), 0, c.s, n_agg, moff, members,
+                       coords, dec, Rprev, qr_tol, Pt.p, R.p, dead.p);
+  AMGF_LAUNCH_CHECK();
+}
+
+// ======================================================================================
+// prolongator smoothing  P = P_t - omega D_l1^{-1} A P_t   (thread per aggregated row)
+// ======================================================================================
+template <int B>
+__global__ void k_sa_numeric(int n, const int* __restrict__ arp, const int* __restrict__ acol,
+                             const double* __restrict__ aval, const int* __restrict__ agg,
+                             const double* __restrict__ Pt, const double* __restrict__ d,
+                             double omega, const int* __restrict__ prp,
+                             const int* __restrict__ pcol, double* __restrict__ pval,
+                             int* flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || agg[i] < 0) return;
+  const int c0 = prp[i], c1 = prp[i + 1];
+  for (int t = arp[i]; t < arp[i + 1]; ++t) {
+    const int v = acol[t];
+    const int J = agg[v];
+    if (J < 0) continue;
+    const int s = lower_bound_i(pcol, c0, c1, J);
+    if (s >= c1 || pcol[s] != J) { atomicOr(flag, 64); continue; }
+    double* out = pval + int64_t(s) * B * 6;
+    const double* A = aval + int64_t(t) * B * B;
+    const double* Q = Pt + int64_t(v) * B * 6;
+#pragma unroll
+    for (int p = 0; p < B; ++p)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < B; ++r) acc += A[p * B + r] * Q[r * 6 + q];
+        out[p * 6 + q] += acc;
+      }
+  }
+  for (int s = c0; s < c1; ++s) {
+    double* out = pval + int64_t(s) * B * 6;
+#pragma unroll
+    for (int p = 0; p < B; ++p) {
+      const double sc = omega / d[int64_t(i) * B + p];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) out[p * 6 + q] = -(out[p * 6 + q] * sc);
+    }
+  }
+  const int s = lower_bound_i(pcol, c0, c1, agg[i]);
+  if (s >= c1 || pcol[s] != agg[i]) { atomicOr(flag, 64); return; }
+  double* out = pval + int64_t(s) * B * 6;
+  const double* Q = Pt + int64_t(i) * B * 6;
+  for (int e = 0; e < B * 6; ++e) out[e] = Q[e] + out[e];
+}
+
+void smooth_prolongator(Ctx& c, const BSR& A, const int* agg, int n_agg, const double* Pt,
+                        const double* d, double omega, BSR& P) {
+  const int n = A.nrows;
+  DBuf<int> mask(std::max(n, 1));
+  hipLaunchKernelGGL(k_nonneg_mask, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, agg, mask.p);
+  union_symbolic(c, n, n_agg, A.rowptr.p, A.col.p, nullptr, nullptr, agg, false, mask.p, P);
+  P.br = A.br;
+  P.bc = 6;
+  P.val.alloc(std::max<int64_t>(P.nnzb, 1) * P.bsz());
+  AMGF_HIP(hipMemsetAsync(P.val.p, 0, P.val.bytes(), c.s));
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  if (A.br == 3)
+    hipLaunchKernelGGL(k_sa_numeric<3>, dim3(grid_for(n, 128)), dim3(128), 0, c.s, n,
+                       A.rowptr.p, A.col.p, A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p,
+                       P.val.p, c.flag.p);
+  else
+    hipLaunchKernelGGL(k_sa_numeric<6>, dim3(grid_for(n, 128)), dim3(128), 0, c.s, n,
+                       A.rowptr.p, A.col.p, A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p,
+                       P.val.p, c.flag.p);
+  AMGF_LAUNCH_CHECK();
+  AMGF_REQUIRE(d2h_scalar(c.flag.p, c.s) == 0, AMGF_EDEVICE, "prolongator pattern mismatch");
+}
+
+__global__ void k_nonneg_mask(int n, const int* __restrict__ a, int* __restrict__ m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) m[i] = a[i] >= 0;
+}
+
+// ======================================================================================
+// generic BSR product C = A B (thread per row, fixed accumulation order)
+// ======================================================================================
+template <int RA, int KA, int CB>
+__global__ void k_spgemm_numeric(int nrows, const int* __restrict__ arp,
+                                 const int* __restrict__ acol, const double* __restrict__ aval,
+                                 const int* __restrict__ brp, const int* __restrict__ bcol,
+                                 const double* __restrict__ bval, const int* __restrict__ crp,
+                                 const int* __restrict__ ccol, double* __restrict__ cval,
+                                 int* flag) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int c0 = crp[r], c1 = crp[r + 1];
+  for (int t = arp[r]; t < arp[r + 1]; ++t) {
+    const int k = acol[t];
+    double a[RA * KA];
+#pragma unroll
+    for (int e = 0; e < RA * KA; ++e) a[e] = aval[int64_t(t) * RA * KA + e];
+    for (int u = brp[k]; u < brp[k + 1]; ++u) {
+      const int s = lower_bound_i(ccol, c0, c1, bcol[u]);
+      if (s >= c1 || ccol[s] != bcol[u]) { atomicOr(flag, 128); continue; }
+      double* out = cval + int64_t(s) * RA * CB;
+      const double* b = bval + int64_t(u) * KA * CB;
+#pragma unroll
+      for (int p = 0; p < RA; ++p)
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+          double acc = 0.0;
+#pragma unroll
+          for (int x = 0; x < KA; ++x) acc += a[p * KA + x] * b[x * CB + q];
+          out[p * CB + q] += acc;
+        }
+    }
+  }
+}
+
+void spgemm(Ctx& c, const BSR& A, const BSR& B, BSR& C) {
+  AMGF_REQUIRE(A.bc == B.br && A.ncols == B.nrows, AMGF_EINVAL, "spgemm shape");
+  union_symbolic(c, A.nrows, B.ncols, A.rowptr.p, A.col.p, B.rowptr.p, B.col.p, nullptr,
+                 false, nullptr, C);
+  C.br = A.br;
+  C.bc = B.bc;
+  C.val.alloc(std::max<int64_t>(C.nnzb, 1) * C.bsz());
+  AMGF_HIP(hipMemsetAsync(C.val.p, 0, C.val.bytes(), c.s));
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  const dim3 g(grid_for(A.nrows, 64)), b(64);
+#define AMGF_SPGEMM_CASE(ra, ka, cb)                                                         \
+  if (A.br == ra && A.bc == ka && B.bc == cb) {                                              \
+    hipLaunchKernelGGL((k_spgemm_numeric<ra, ka, cb>), g, b, 0, c.s, A.nrows, A.rowptr.p,    \
+                       A.col.p, A.val.p, B.rowptr.p, B.col.p, B.val.p, C.rowptr.p, C.col.p,  \
+                       C.val.p, c.flag.p);                                                   \
+    AMGF_LAUNCH_CHECK();                                                                     \
+    AMGF_REQUIRE(d2h_scalar(c.flag.p, c.s) == 0, AMGF_EDEVICE, "spgemm pattern mismatch");  \
+    return;                                                                                  \
+  }
+  AMGF_SPGEMM_CASE(3, 3, 6)
+  AMGF_SPGEMM_CASE(6, 6, 6)
+  AMGF_SPGEMM_CASE(6, 3, 6)
+  AMGF_SPGEMM_CASE(1, 3, 6)
+  AMGF_SPGEMM_CASE(1, 6, 6)
+#undef AMGF_SPGEMM_CASE
+  throw Error(AMGF_EINVAL, "spgemm: unsupported block sizes");
+}
+
+// coarse DOFs whose prolongator column is dead get a unit diagonal
+__global__ void k_dead_identity(int n_agg, const unsigned char* __restrict__ dead,
+                                const int* __restrict__ dpos, double* __restrict__ val) {
+  const int J = blockIdx.x * blockDim.x + threadIdx.x;
+  if (J >= n_agg || dpos[J] < 0) return;
+  for (int j = 0; j < 6; ++j)
+    if (dead[int64_t(J) * 6 + j]) val[int64_t(dpos[J]) * 36 + j * 6 + j] = 1.0;
+}
+
+void dead_identity(Ctx& c, BSR& Kc, const unsigned char* dead) {
+  DBuf<int> dpos(std::max(Kc.nrows, 1));
+  hipLaunchKernelGGL(k_diag_pos, dim3(grid_for(Kc.nrows, 256)), dim3(256), 0, c.s, Kc.nrows,
+                     Kc.rowptr.p, Kc.col.p, dpos.p);
+  hipLaunchKernelGGL(k_dead_identity, dim3(grid_for(Kc.nrows, 256)), dim3(256), 0, c.s,
+                     Kc.nrows, dead, dpos.p, Kc.val.p);
+  AMGF_LAUNCH_CHECK();
+}
+
+// ======================================================================================
+// l1 row norms
+// ======================================================================================
+template <int B>
+__global__ void k_l1(int n, const int* __restrict__ rp, const double* __restrict__ val,
+                     double* __restrict__ d) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  double s[B];
+#pragma unroll
+  for (int p = 0; p < B; ++p) s[p] = 0.0;
+  for (int k = rp[a]; k < rp[a + 1]; ++k) {
+    const double* v = val + int64_t(k) * B * B;
+#pragma unroll
+    for (int p = 0; p < B; ++p)
+#pragma unroll
+      for (int q = 0; q < B; ++q) s[p] += fabs(v[p * B + q]);
+  }
+#pragma unroll
+  for (int p = 0; p < B; ++p) d[int64_t(a) * B + p] = s[p];
+}
+
+void l1_norms(Ctx& c, const BSR& A, DBuf<double>& d) {
+  d.alloc(size_t(A.nrows) * A.br);
+  if (A.br == 3)
+    hipLaunchKernelGGL(k_l1<3>, dim3(grid_for(A.nrows, 256)), dim3(256), 0, c.s, A.nrows,
+                       A.rowptr.p, A.val.p, d.p);
+  else
+    hipLaunchKernelGGL(k_l1<6>, dim3(grid_for(A.nrows, 256)), dim3(256), 0, c.s, A.nrows,
+                       A.rowptr.p, A.val.p, d.p);
+  AMGF_LAUNCH_CHECK();
+}
+
+// ======================================================================================
+// filtering space: every DOF of every node touched by J
+// ======================================================================================
+__global__ void k_mark_nodes(int64_t nnzb, const int* __restrict__ col, int* __restrict__ mark) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k < nnzb) mark[col[k]] = 1;
+}
+__global__ void k_node_dofs(int nn, const int* __restrict__ mark, const int* __restrict__ pos,
+                            int* __restrict__ ic) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nn || !mark[v]) return;
+  const int o = 3 * pos[v];
+  ic[o] = 3 * v;
+  ic[o + 1] = 3 * v + 1;
+  ic[o + 2] = 3 * v + 2;
+}
+
+int filter_space_from_J(Ctx& c, const BSR& J, int n_nodes, DBuf<int>& Ic) {
+  DBuf<int> mark(std::max(n_nodes, 1)), pos(size_t(n_nodes) + 1);
+  AMGF_HIP(hipMemsetAsync(mark.p, 0, mark.bytes(), c.s));
+  if (J.nnzb)
+    hipLaunchKernelGGL(k_mark_nodes, dim3(grid_for(J.nnzb, 256)), dim3(256), 0, c.s, J.nnzb,
+                       J.col.p, mark.p);
+  const int nodes = scan_exclusive(c, mark.p, pos.p, n_nodes);
+  Ic.alloc(std::max(3 * nodes, 1));
+  if (nodes)
+    hipLaunchKernelGGL(k_node_dofs, dim3(grid_for(n_nodes, 256)), dim3(256), 0, c.s, n_nodes,
+                       mark.p, pos.p, Ic.p);
+  AMGF_LAUNCH_CHECK();
+  return 3 * nodes;
+}
+
+}  // namespace amgf

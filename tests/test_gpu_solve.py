@@ -1,0 +1,99 @@
+"""GPU V-cycle, AMGF apply and PCG against the oracle (FP64 and mixed precision)."""
+import numpy as np
+import pytest
+
+from gpu_util import gpu, oracle, problem, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name,opts", [("C1", {}), ("C1", {"coarse_max_nodes": 8}),
+                                       ("N12", {"coarse_max_nodes": 16})])
+def test_operator_vcycle_and_apply_fp64(name, opts):
+    import torch
+    o = oracle(name, **opts)
+    h = gpu(name, **opts)
+    rng = np.random.default_rng(1)
+    r = rng.standard_normal(o.n)
+    assert rel(h.operator(r).cpu().numpy(), o.A_apply(r)) < 1e-14
+    assert rel(h.vcycle(r).cpu().numpy(), o.vcycle(r)) < 1e-10
+    # the filter solve's forward error grows with cond(A_w) (D spans 8 decades here):
+    # 2-norm bound 1e-8, and the energy norm, which the CG iteration sees, 1e-10
+    z, zr = h.apply(r).cpu().numpy(), o.apply(r)
+    S = o.S.csr()
+    e = z - zr
+    e_A = float(np.sqrt(e @ (S @ e)) / np.sqrt(zr @ (S @ zr)))
+    print(f"{name}: apply rel {rel(z, zr):.2e}, energy-norm rel {e_A:.2e}")
+    assert rel(z, zr) < 1e-8 and e_A < 1e-10
+    torch.cuda.synchronize()
+    h.close()
+
+
+def test_apply_mixed_precision_close_to_fp64():
+    o = oracle("C1")
+    h = gpu("C1", precision=1)
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal(o.n)
+    e_b = rel(h.vcycle(r).cpu().numpy(), o.vcycle(r))
+    e_m = rel(h.apply(r).cpu().numpy(), o.apply(r))
+    print(f"mixed vcycle rel {e_b:.2e} apply rel {e_m:.2e}")
+    assert e_b < 1e-4 and e_m < 1e-4
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pcg_matches_oracle(precision):
+    p = problem("C1")
+    o = oracle("C1")
+    ref = o.pcg(p.b)
+    h = gpu("C1", precision=precision)
+    x, info = h.pcg(p.b)
+    x = x.cpu().numpy()
+    err = rel(x, ref.x)
+    S = o.S.csr()
+    e = x - ref.x
+    err_S = float(np.sqrt(e @ (S @ e)) / np.sqrt(ref.x @ (S @ ref.x)))
+    print(f"precision {precision}: gpu {info.iterations} it, oracle {ref.iterations} it, "
+          f"rel err {err:.2e}, S-norm {err_S:.2e}, true res {info.rel_true_res:.2e}")
+    assert info.converged and info.rel_prec_res <= 1e-10
+    if precision == 0:
+        assert abs(info.iterations - ref.iterations) <= 1
+        assert err <= 1e-8
+    else:
+        assert info.iterations <= ref.iterations + 5
+        assert err_S <= 1e-8
+
+
+def test_error_codes():
+    from paper_2505_18576_amd import AMGF, AMGFError
+    from paper_2505_18576_amd import amgf as b
+    p = problem("C1")
+    D = p.D.copy()
+    D[3] = -1.0
+    with pytest.raises(AMGFError) as ei:
+        AMGF(p.n_nodes, p.K_rowptr, p.K_col, p.K_val.reshape(-1), p.J_rowptr, p.J_col,
+             p.J_val, D, p.coords.reshape(-1))
+    assert ei.value.status == b.AMGF_EINVAL
+    K = p.K_val.copy()
+    K[5, 1, 1] = np.nan
+    with pytest.raises(AMGFError) as ei:
+        AMGF(p.n_nodes, p.K_rowptr, p.K_col, K.reshape(-1), p.J_rowptr, p.J_col, p.J_val,
+             p.D, p.coords.reshape(-1))
+    assert ei.value.status == b.AMGF_EINVAL
+    h = gpu("C1", max_iters=2)
+    x, info = h.pcg(p.b)
+    assert info.iterations == 2 and not info.converged
+    with pytest.raises(AMGFError) as ei:
+        h.pcg(p.b, raise_on_noconv=True)
+    assert ei.value.status == b.AMGF_ENOCONV
+    h.close()
+
+
+def test_pcg_run_to_run_bitwise():
+    p = problem("C1")
+    h = gpu("C1")
+    x1, i1 = h.pcg(p.b)
+    x2, i2 = h.pcg(p.b)
+    assert i1.iterations == i2.iterations
+    assert np.array_equal(x1.cpu().numpy().view(np.uint64), x2.cpu().numpy().view(np.uint64))
+    h.close()

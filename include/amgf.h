@@ -146,6 +146,18 @@ enum {
   AMGF_Q_K_ROWPTR, AMGF_Q_K_COL, AMGF_Q_K_VAL, AMGF_Q_OMEGA, AMGF_Q_IC
 };
 int32_t amgf_num_levels(amgf_handle h);
+
+/* Benchmark helper: launch one hot-path kernel `reps` times on `stream` between two
+ * hipEvents and store the mean time per launch (milliseconds) in *avg_ms (host).
+ *   AMGF_K_PRESMOOTH   level-0 fused "x = w.b, r = b - K x" SpMV in the handle's
+ *                      V-cycle precision (reads the level-0 V-cycle buffers)
+ *   AMGF_K_POSTSMOOTH  level-0 fused Jacobi step "x' = x + w.(b - K x)"
+ *   AMGF_K_VCYCLE      one whole V-cycle B r on level-0 buffers
+ *   AMGF_K_OPERATOR    the FP64 operator y = A x of the CG loop
+ * Work vectors are overwritten; the hierarchy is not modified.                      */
+enum { AMGF_K_PRESMOOTH = 0, AMGF_K_POSTSMOOTH = 1, AMGF_K_VCYCLE = 2, AMGF_K_OPERATOR = 3 };
+amgf_status amgf_time_kernel(amgf_handle h, int32_t which, int32_t reps, void* stream,
+                             double* avg_ms);
 amgf_status amgf_query(amgf_handle h, int32_t level, int32_t which, void* host_dst,
                        size_t bytes);
 

@@ -21,7 +21,8 @@ L1JACOBI, LEARNED = 0, 2
 
 ABI_FUNCTIONS = ["amgf_default_options", "amgf_setup", "amgf_apply", "amgf_vcycle",
                  "amgf_operator_apply", "amgf_pcg", "amgf_destroy", "amgf_status_string",
-                 "amgf_last_error", "amgf_num_levels", "amgf_query"]
+                 "amgf_last_error", "amgf_num_levels", "amgf_query", "amgf_time_kernel"]
+K_PRESMOOTH, K_POSTSMOOTH, K_VCYCLE, K_OPERATOR = range(4)
 
 
 class Options(ctypes.Structure):
@@ -79,6 +80,8 @@ def load_library(path=LIB_PATH):
     L.amgf_num_levels.restype = i32
     L.amgf_query.argtypes = [vp, i32, i32, vp, ctypes.c_size_t]
     L.amgf_query.restype = ctypes.c_int
+    L.amgf_time_kernel.argtypes = [vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double)]
+    L.amgf_time_kernel.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -234,6 +237,13 @@ class AMGF:
                      P_val=q(level, Q_P_VAL, np.float64, nnzP * b * 6).reshape(-1, b, 6),
                      rho_omega=q(level, Q_OMEGA))
         return d
+
+    def time_kernel(self, which, reps=20):
+        """Mean milliseconds per launch of a hot-path kernel (hipEvents, library stream)."""
+        ms = ctypes.c_double()
+        _check(self.L.amgf_time_kernel(self.h, which, reps, _stream(), ctypes.byref(ms)),
+               "amgf_time_kernel")
+        return ms.value
 
     def filter_dofs(self, n_c):
         return self.query(0, Q_IC, np.int32, n_c)

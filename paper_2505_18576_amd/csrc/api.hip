@@ -5,6 +5,7 @@
 #include <memory>
 
 #include "apply.h"
+#include "btd.h"
 #include "dense.h"
 #include "setup.h"
 
@@ -15,6 +16,8 @@ struct Level {
   BSR A;                        // assembled operator (kept for inspection)
   BSR K;                        // stiffness part (FP64 + FP32 copy in mixed mode)
   BSR J, JT;                    // contact Jacobian (m x nn, 1 x b) and transpose
+  DBuf<int> crows;              // node rows with a contact term (nonempty J^T rows)
+  int ncrows = 0;
   BSR P, PT;                    // prolongator to the next level and its transpose
   Graph G;                      // aggregation graph
   DBuf<int> agg, root;
@@ -36,15 +39,23 @@ struct Handle {
   DBuf<double> D, coords;
   DBuf<unsigned char> dec0;
   DBuf<double> t;               // contact scratch (m)
-  // coarsest dense solve
+  // coarsest solve (one dense block)
   int nc_dense = 0;
-  DBuf<double> coarse_Linv, coarse_b, coarse_x, coarse_tmp;
+  BTDSolver coarse;
+  DBuf<double> coarse_b, coarse_x;
   // filter
   int n_c = 0;
+  int filter_refine = 0;
   DBuf<int> Ic;
-  DBuf<double> Aw_Linv, f_r, f_w, f_tmp;
+  BTDSolver aw;
+  DBuf<double> f_r, f_w, f_res, f_dw;
+  DBuf<int> aw_rp, aw_col;      // sparse A_w for refinement residuals
+  DBuf<double> aw_val;
   // apply scratch
   DBuf<double> z1, ra, r2, z3;
+  DBuf<float> zf, r2f;
+  DBuf<int> ic_nodes;           // node rows holding filter DOFs
+  int n_icn = 0;
   // pcg scratch
   DBuf<double> pr, pz, pzo, pp, pq;
   double op_complexity = 1.0;
@@ -139,6 +150,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   h.t.alloc(std::max(m, 1));
   j_to_node_blocks(c, m, nn, J_rowptr, J_col, J_val, L0->J);
   bsr_transpose(c, L0->J, L0->JT);
+  L0->ncrows = nonempty_rows(c, L0->JT.rowptr.p, nn, L0->crows);
   {
     BSR C;
     contact_operator(c, L0->J, L0->JT, h.D.p, C);
@@ -188,6 +200,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     dead_identity(c, N.K, dead.p);
     spgemm(c, Lc.J, Lc.P, N.J);
     bsr_transpose(c, N.J, N.JT);
+    N.ncrows = nonempty_rows(c, N.JT.rowptr.p, N.nn, N.crows);
     {
       BSR C;
       contact_operator(c, N.J, N.JT, h.D.p, C);
@@ -198,18 +211,18 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     Rprev = std::move(R);
   }
   h.op_complexity = double(nzsum) / double(std::max<int64_t>(nz0, 1));
-  // ---- coarsest dense factor
+  // ---- coarsest level: one dense block
   Level& LL = *h.lev.back();
   h.nc_dense = int(LL.n());
   {
-    DBuf<double> Ad(size_t(h.nc_dense) * h.nc_dense);
-    bsr_to_dense(c, LL.A, Ad.p);
-    dense_cholesky_inverse(c, Ad.p, h.nc_dense, h.coarse_Linv);
+    DBuf<int> rp, cl;
+    DBuf<double> vl;
+    bsr_to_csr(c, LL.A, rp, cl, vl);
+    h.coarse.setup(c, h.nc_dense, rp.p, cl.p, vl.p, h.nc_dense);
   }
   h.coarse_b.alloc(h.nc_dense);
   h.coarse_x.alloc(h.nc_dense);
-  h.coarse_tmp.alloc(h.nc_dense);
-  // ---- filter (Sec. 5.1)
+  // ---- filter (Sec. 5.1): A_w = S[I_c, I_c], level-set block-tridiagonal Cholesky
   if (Ic_user && n_c_user > 0) {
     h.Ic.alloc(n_c_user);
     copy_in(c, h.Ic.p, Ic_user, sizeof(int) * size_t(n_c_user));
@@ -217,13 +230,27 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   } else {
     h.n_c = filter_space_from_J(c, L0->J, nn, h.Ic);
   }
+  if (h.n_c > 0) {
+    std::vector<int> ic = d2h(h.Ic.p, h.n_c, c.s);
+    std::vector<int> nodes;
+    for (int i = 0; i < h.n_c; ++i) {
+      AMGF_REQUIRE(ic[i] >= 0 && ic[i] < 3 * nn && (i == 0 || ic[i] > ic[i - 1]), AMGF_EINVAL,
+                   "Ic must be ascending DOF indices in [0, n)");
+      if (nodes.empty() || nodes.back() != ic[i] / 3) nodes.push_back(ic[i] / 3);
+    }
+    h.n_icn = int(nodes.size());
+    h.ic_nodes.alloc(h.n_icn);
+    AMGF_HIP(hipMemcpyAsync(h.ic_nodes.p, nodes.data(), sizeof(int) * h.n_icn,
+                            hipMemcpyHostToDevice, c.s));
+    AMGF_HIP(hipStreamSynchronize(c.s));
+  }
   if (o.filter && h.n_c > 0) {
-    DBuf<double> Aw(size_t(h.n_c) * h.n_c);
-    gather_filter_matrix(c, L0->A, h.Ic.p, h.n_c, Aw.p);
-    dense_cholesky_inverse(c, Aw.p, h.n_c, h.Aw_Linv);
+    filter_csr(c, L0->A, h.Ic.p, h.n_c, h.aw_rp, h.aw_col, h.aw_val);
+    h.aw.setup(c, h.n_c, h.aw_rp.p, h.aw_col.p, h.aw_val.p, 1536);
     h.f_r.alloc(h.n_c);
     h.f_w.alloc(h.n_c);
-    h.f_tmp.alloc(h.n_c);
+    h.f_res.alloc(h.n_c);
+    h.f_dw.alloc(h.n_c);
   }
   // ---- precision copies and work vectors
   for (size_t l = 0; l < h.lev.size(); ++l) {
@@ -240,6 +267,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   }
   const int64_t n = h.n();
   h.z1.alloc(n); h.ra.alloc(n); h.r2.alloc(n); h.z3.alloc(n);
+  if (h.mixed()) { h.zf.alloc(n); h.r2f.alloc(n); }
   h.pr.alloc(n); h.pz.alloc(n); h.pzo.alloc(n); h.pp.alloc(n); h.pq.alloc(n);
   AMGF_HIP(hipStreamSynchronize(c.s));
 }
@@ -248,7 +276,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
 // V-cycle
 // ------------------------------------------------------------------------------------
 static void coarse_solve(Handle& h, const double* b, double* x) {
-  dense_solve(h.ctx, h.coarse_Linv.p, h.nc_dense, b, x, h.coarse_tmp.p);
+  h.coarse.solve(h.ctx, b, x);
 }
 
 // FP64 V(1,1) on level l: L.vb -> L.vx
@@ -261,12 +289,14 @@ static void vcycle64(Handle& h, size_t l) {
   }
   Level& N = *h.lev[l + 1];
   bsr_spmv<double>(c, SPMV_PRE, L.K, L.K.val.p, nullptr, L.vr.p, L.vb.p, L.w.p, L.vx.p);
-  contact_apply<double>(c, CT_SUB_RES, L.J, L.JT, h.D.p, L.vx.p, h.t.p, L.vr.p, nullptr);
+  contact_apply<double, double>(c, CT_SUB_RES, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.vx.p,
+                                h.t.p, L.vr.p, nullptr);
   bsr_spmv<double>(c, SPMV_Y, L.PT, L.PT.val.p, L.vr.p, N.vb.p, nullptr, nullptr, nullptr);
   vcycle64(h, l + 1);
   bsr_spmv<double>(c, SPMV_ADD, L.P, L.P.val.p, N.vx.p, L.vx.p, nullptr, nullptr, nullptr);
   bsr_spmv<double>(c, SPMV_POST, L.K, L.K.val.p, L.vx.p, nullptr, L.vb.p, L.w.p, L.vxn.p);
-  contact_apply<double>(c, CT_SUB_W, L.J, L.JT, h.D.p, L.vx.p, h.t.p, L.vxn.p, L.w.p);
+  contact_apply<double, double>(c, CT_SUB_W, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.vx.p,
+                                h.t.p, L.vxn.p, L.w.p);
   std::swap(L.vx, L.vxn);
 }
 
@@ -282,12 +312,14 @@ static void vcycle32(Handle& h, size_t l) {
   }
   Level& N = *h.lev[l + 1];
   bsr_spmv<float>(c, SPMV_PRE, L.K, L.K.val32.p, nullptr, L.fr.p, L.fb.p, L.w32.p, L.fx.p);
-  contact_apply<float>(c, CT_SUB_RES, L.J, L.JT, h.D.p, L.fx.p, h.t.p, L.fr.p, nullptr);
+  contact_apply<float, float>(c, CT_SUB_RES, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.fx.p,
+                              h.t.p, L.fr.p, nullptr);
   bsr_spmv<float>(c, SPMV_Y, L.PT, L.PT.val32.p, L.fr.p, N.fb.p, nullptr, nullptr, nullptr);
   vcycle32(h, l + 1);
   bsr_spmv<float>(c, SPMV_ADD, L.P, L.P.val32.p, N.fx.p, L.fx.p, nullptr, nullptr, nullptr);
   bsr_spmv<float>(c, SPMV_POST, L.K, L.K.val32.p, L.fx.p, nullptr, L.fb.p, L.w32.p, L.fxn.p);
-  contact_apply<float>(c, CT_SUB_W, L.J, L.JT, h.D.p, L.fx.p, h.t.p, L.fxn.p, L.w32.p);
+  contact_apply<float, float>(c, CT_SUB_W, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.fx.p,
+                              h.t.p, L.fxn.p, L.w32.p);
   std::swap(L.fx, L.fxn);
 }
 
@@ -313,14 +345,31 @@ static void operator_apply(Handle& h, const double* x, double* y, const double* 
   Level& L0 = *h.lev[0];
   if (b) {
     bsr_spmv<double>(c, SPMV_RES, L0.K, L0.K.val.p, x, y, b, nullptr, nullptr);
-    contact_apply<double>(c, CT_SUB_RES, L0.J, L0.JT, h.D.p, x, h.t.p, y, nullptr);
+    contact_apply<double, double>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p, x,
+                                  h.t.p, y, nullptr);
   } else {
     bsr_spmv<double>(c, SPMV_Y, L0.K, L0.K.val.p, x, y, nullptr, nullptr, nullptr);
-    contact_apply<double>(c, CT_ADD, L0.J, L0.JT, h.D.p, x, h.t.p, y, nullptr);
+    contact_apply<double, double>(c, CT_ADD, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p, x,
+                                  h.t.p, y, nullptr);
   }
 }
 
-// z = M r, Definition 5.3
+// w = A_w^{-1} r: solve with the factored inverse, then refinement steps with the
+// sparse A_w residual (restores the accuracy the explicit inverse gives up)
+static void filter_solve(Handle& h, const double* r, double* w) {
+  Ctx& c = h.ctx;
+  h.aw.solve(c, r, w);
+  for (int it = 0; it < h.filter_refine; ++it) {
+    csr_residual(c, h.n_c, h.aw_rp.p, h.aw_col.p, h.aw_val.p, w, r, h.f_res.p);
+    h.aw.solve(c, h.f_res.p, h.f_dw.p);
+    axpby(c, h.n_c, 1.0, h.f_dw.p, 1.0, w);
+  }
+}
+
+// z = M r, Definition 5.3:  z1 = B r;  z2 = z1 + P A_w^{-1} P^T (r - A z1);
+// z = z2 + B (r - A z2).  The filter residual is formed on the filter rows only.  In
+// mixed precision the second residual keeps the stiffness product in FP32 (it only
+// feeds the FP32 V-cycle) and the contact term in FP64.
 static void amgf_apply_impl(Handle& h, const double* r, double* z) {
   Ctx& c = h.ctx;
   const int64_t n = h.n();
@@ -328,17 +377,31 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
     vcycle(h, r, z);
     return;
   }
+  Level& L0 = *h.lev[0];
   vcycle(h, r, h.z1.p);                               // z1 = B r
   if (h.n_c > 0) {
-    operator_apply(h, h.z1.p, h.ra.p, r);             // ra = r - A z1
+    bsr_res_rows(c, L0.K, h.ic_nodes.p, h.n_icn, h.z1.p, r, h.ra.p);
+    contact_apply<double, double>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
+                                  h.z1.p, h.t.p, h.ra.p, nullptr);     // ra = r - A z1 on I_c
     gather(c, h.ra.p, h.Ic.p, h.n_c, h.f_r.p);        // P^T ra
-    dense_solve(c, h.Aw_Linv.p, h.n_c, h.f_r.p, h.f_w.p, h.f_tmp.p);   // A_w^{-1}
+    filter_solve(h, h.f_r.p, h.f_w.p);                // w = A_w^{-1} P^T ra
     scatter_add(c, h.f_w.p, h.Ic.p, h.n_c, h.z1.p);   // z2 = z1 + P w
   }
-  operator_apply(h, h.z1.p, h.r2.p, r);               // r2 = r - A z2
-  vcycle(h, h.r2.p, h.z3.p);                          // B r2
-  vcopy(c, h.z1.p, z, n);
-  axpby(c, n, 1.0, h.z3.p, 1.0, z);                   // z = z2 + B r2
+  if (h.mixed()) {
+    cast_d2f(c, h.z1.p, h.zf.p, n);
+    bsr_spmv<float>(c, SPMV_RES, L0.K, L0.K.val32.p, h.zf.p, h.r2f.p, L0.fb.p, nullptr, nullptr);
+    contact_apply<double, float>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
+                                 h.z1.p, h.t.p, h.r2f.p, nullptr);     // r2 = r - A z2
+    std::swap(L0.fb, h.r2f);
+    vcycle32(h, 0);                                   // B r2
+    std::swap(L0.fb, h.r2f);
+    add_f32(c, n, h.z1.p, L0.fx.p, z);                // z = z2 + B r2
+  } else {
+    operator_apply(h, h.z1.p, h.r2.p, r);             // r2 = r - A z2
+    vcycle(h, h.r2.p, h.z3.p);                        // B r2
+    vcopy(c, h.z1.p, z, n);
+    axpby(c, n, 1.0, h.z3.p, 1.0, z);                 // z = z2 + B r2
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -568,6 +631,68 @@ void amgf_destroy(amgf_handle hd) {
 }
 
 int32_t amgf_num_levels(amgf_handle hd) { return hd ? int32_t(hd->h.lev.size()) : 0; }
+
+amgf_status amgf_time_kernel(amgf_handle hd, int32_t which, int32_t reps, void* stream,
+                             double* avg_ms) {
+  if (!hd || !avg_ms || reps <= 0 || which < 0 || which > AMGF_K_OPERATOR) return AMGF_EINVAL;
+  amgf_status st_ = guard([&]() -> amgf_status {
+    Handle& h = hd->h;
+    amgf::Ctx& c = h.ctx;
+    c.s = static_cast<hipStream_t>(stream);
+    amgf::Level& L = *h.lev[0];
+    const int64_t n = h.n();
+    AMGF_REQUIRE(h.lev.size() > 1 || which >= AMGF_K_VCYCLE, AMGF_EINVAL,
+                 "single-level hierarchy has no smoother");
+    // deterministic non-trivial data in the buffers the kernels read
+    amgf::fill_power_start(c, n, h.ra.p, nullptr);
+    amgf::vcopy(c, h.ra.p, L.vb.p, n);
+    amgf::vcopy(c, h.ra.p, L.vx.p, n);
+    if (h.mixed()) {
+      amgf::cast_d2f(c, h.ra.p, L.fb.p, n);
+      amgf::cast_d2f(c, h.ra.p, L.fx.p, n);
+    }
+    auto launch = [&]() {
+      switch (which) {
+        case AMGF_K_PRESMOOTH:
+          if (h.mixed())
+            amgf::bsr_spmv<float>(c, amgf::SPMV_PRE, L.K, L.K.val32.p, nullptr, L.fr.p, L.fb.p,
+                                  L.w32.p, L.fx.p);
+          else
+            amgf::bsr_spmv<double>(c, amgf::SPMV_PRE, L.K, L.K.val.p, nullptr, L.vr.p, L.vb.p,
+                                   L.w.p, L.vx.p);
+          break;
+        case AMGF_K_POSTSMOOTH:
+          if (h.mixed())
+            amgf::bsr_spmv<float>(c, amgf::SPMV_POST, L.K, L.K.val32.p, L.fx.p, nullptr, L.fb.p,
+                                  L.w32.p, L.fxn.p);
+          else
+            amgf::bsr_spmv<double>(c, amgf::SPMV_POST, L.K, L.K.val.p, L.vx.p, nullptr, L.vb.p,
+                                   L.w.p, L.vxn.p);
+          break;
+        case AMGF_K_VCYCLE:
+          amgf::vcycle(h, h.ra.p, h.z3.p);
+          break;
+        default:
+          amgf::operator_apply(h, h.ra.p, h.z3.p, nullptr);
+      }
+    };
+    launch();
+    hipEvent_t e0, e1;
+    AMGF_HIP(hipEventCreate(&e0));
+    AMGF_HIP(hipEventCreate(&e1));
+    AMGF_HIP(hipEventRecord(e0, c.s));
+    for (int i = 0; i < reps; ++i) launch();
+    AMGF_HIP(hipEventRecord(e1, c.s));
+    AMGF_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    AMGF_HIP(hipEventElapsedTime(&ms, e0, e1));
+    AMGF_HIP(hipEventDestroy(e0));
+    AMGF_HIP(hipEventDestroy(e1));
+    *avg_ms = double(ms) / reps;
+    return AMGF_OK;
+  });
+  return st_;
+}
 
 amgf_status amgf_query(amgf_handle hd, int32_t level, int32_t which, void* dst, size_t bytes) {
   if (!hd || !dst) return AMGF_EINVAL;

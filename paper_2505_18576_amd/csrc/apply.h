@@ -18,19 +18,26 @@ template <class T>
 void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, const T* b,
               const T* w, T* xo);
 
-// contact term of level l: t = D.(J x) then, per mode,
+// contact term of a level over its contact node rows (crows, ncrows):
+// t = D.(J x) then, per mode,
 //   CT_SUB_RES:  y -= J^T t          (residual update)
 //   CT_SUB_W:    y -= w.(J^T t)      (Jacobi step correction)
 //   CT_ADD:      y += J^T t          (operator apply)
 enum ContactMode { CT_SUB_RES = 0, CT_SUB_W = 1, CT_ADD = 2 };
-template <class T>
-void contact_apply(Ctx& c, int mode, const BSR& J, const BSR& JT, const double* D, const T* x,
-                   double* t, T* y, const T* w);
+template <class TX, class TY>
+void contact_apply(Ctx& c, int mode, const BSR& J, const BSR& JT, const int* crows, int ncrows,
+                   const double* D, const TX* x, double* t, TY* y, const TY* w);
+// indices of the nonempty rows of a CSR pattern
+int nonempty_rows(Ctx& c, const int* rp, int n, DBuf<int>& rows);
+// y = b - A x on the listed block rows only (FP64, 3x3 blocks)
+void bsr_res_rows(Ctx& c, const BSR& A, const int* rows, int nlist, const double* x,
+                  const double* b, double* y);
 
 // elementwise helpers
 void cast_d2f(Ctx& c, const double* a, float* b, int64_t n);
 void cast_f2d(Ctx& c, const float* a, double* b, int64_t n);
 void vcopy(Ctx& c, const double* a, double* b, int64_t n);
+void add_f32(Ctx& c, int64_t n, const double* a, const float* f, double* z);  // z = a + f
 void axpby(Ctx& c, int64_t n, double alpha, const double* x, double beta, double* y);  // y = a x + b y
 void gather(Ctx& c, const double* x, const int* idx, int n, double* y);               // y = x[idx]
 void scatter_add(Ctx& c, const double* w, const int* idx, int n, double* y);          // y[idx] += w

@@ -58,6 +58,44 @@ __global__ void __launch_bounds__(256) k_bsr(int nrows, const int* __restrict__ 
   }
 }
 
+// y[i] = b[i] - (A x)[i] on the listed block rows only (FP64, 3x3 blocks)
+__global__ void __launch_bounds__(256) k_bsr_res_rows(int nlist, const int* __restrict__ rows,
+                                                      const int* __restrict__ rp,
+                                                      const int* __restrict__ col,
+                                                      const double* __restrict__ val,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ b,
+                                                      double* __restrict__ y) {
+  constexpr int G = 8;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int li = gid / G, l = gid % G;
+  if (li >= nlist) return;
+  const int r = rows[li];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int j = rp[r] + l; j < rp[r + 1]; j += G) {
+    const int cc = col[j];
+    const double* v = val + int64_t(j) * 9;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[p] += v[p * 3 + q] * x[int64_t(cc) * 3 + q];
+  }
+#pragma unroll
+  for (int p = 0; p < 3; ++p) acc[p] = group_sum(acc[p], G);
+  if (l >= 3) return;
+  double ax = l == 0 ? acc[0] : (l == 1 ? acc[1] : acc[2]);
+  const int64_t i = int64_t(r) * 3 + l;
+  y[i] = b[i] - ax;
+}
+
+void bsr_res_rows(Ctx& c, const BSR& A, const int* rows, int nlist, const double* x,
+                  const double* b, double* y) {
+  if (nlist == 0) return;
+  hipLaunchKernelGGL(k_bsr_res_rows, dim3(grid_for(int64_t(nlist) * 8, 256)), dim3(256), 0, c.s,
+                     nlist, rows, A.rowptr.p, A.col.p, A.val.p, x, b, y);
+  AMGF_LAUNCH_CHECK();
+}
+
 template <int BR, int BC, int G, class T>
 static void launch_bsr(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y,
                        const T* b, const T* w, T* xo) {
@@ -103,83 +141,118 @@ template void bsr_spmv<float>(Ctx&, int, const BSR&, const float*, const float*,
 // ======================================================================================
 // contact term  J^T D J x  (always FP64)
 // ======================================================================================
-template <int B, class T>
-__global__ void k_contact_t(int m, const int* __restrict__ rp, const int* __restrict__ col,
-                            const double* __restrict__ val, const double* __restrict__ D,
-                            const T* __restrict__ x, double* __restrict__ t) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// t_k = D_k (J x)_k: one wavefront per constraint row, lanes over the row's blocks.
+template <int B, class TX>
+__global__ void __launch_bounds__(256) k_contact_t(int m, const int* __restrict__ rp,
+                                                   const int* __restrict__ col,
+                                                   const double* __restrict__ val,
+                                                   const double* __restrict__ D,
+                                                   const TX* __restrict__ x,
+                                                   double* __restrict__ t) {
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (k >= m) return;
   double s = 0.0;
-  for (int u = rp[k]; u < rp[k + 1]; ++u) {
+  for (int u = rp[k] + lane; u < rp[k + 1]; u += 64) {
     const int64_t base = int64_t(col[u]) * B;
 #pragma unroll
     for (int q = 0; q < B; ++q) s += val[int64_t(u) * B + q] * double(x[base + q]);
   }
-  t[k] = D[k] * s;
+  s = wave_sum(s);
+  if (lane == 0) t[k] = D[k] * s;
 }
 
-template <int B, class T, int MODE>
-__global__ void k_contact_y(int nn, const int* __restrict__ rp, const int* __restrict__ col,
-                            const double* __restrict__ val, const double* __restrict__ t,
-                            T* __restrict__ y, const T* __restrict__ w) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= nn) return;
-  const int k0 = rp[a], k1 = rp[a + 1];
-  if (k0 == k1) return;
+// y_a (op)= (J^T t)_a over the listed node rows: one wavefront per row.
+template <int B, class TY, int MODE>
+__global__ void __launch_bounds__(256) k_contact_y(int nrows, const int* __restrict__ rows,
+                                                   const int* __restrict__ rp,
+                                                   const int* __restrict__ col,
+                                                   const double* __restrict__ val,
+                                                   const double* __restrict__ t,
+                                                   TY* __restrict__ y,
+                                                   const TY* __restrict__ w) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= nrows) return;
+  const int a = rows[i];
   double acc[B];
 #pragma unroll
   for (int p = 0; p < B; ++p) acc[p] = 0.0;
-  for (int k = k0; k < k1; ++k) {
+  for (int k = rp[a] + lane; k < rp[a + 1]; k += 64) {
     const double tk = t[col[k]];
 #pragma unroll
     for (int p = 0; p < B; ++p) acc[p] += val[int64_t(k) * B + p] * tk;
   }
 #pragma unroll
-  for (int p = 0; p < B; ++p) {
-    const int64_t i = int64_t(a) * B + p;
-    if (MODE == CT_SUB_RES) y[i] = T(double(y[i]) - acc[p]);
-    else if (MODE == CT_SUB_W) y[i] = T(double(y[i]) - double(w[i]) * acc[p]);
-    else y[i] = T(double(y[i]) + acc[p]);
-  }
+  for (int p = 0; p < B; ++p) acc[p] = wave_sum(acc[p]);
+  if (lane >= B) return;
+  double v = 0.0;
+#pragma unroll
+  for (int p = 0; p < B; ++p)
+    if (lane == p) v = acc[p];
+  const int64_t ix = int64_t(a) * B + lane;
+  if (MODE == CT_SUB_RES) y[ix] = TY(double(y[ix]) - v);
+  else if (MODE == CT_SUB_W) y[ix] = TY(double(y[ix]) - double(w[ix]) * v);
+  else y[ix] = TY(double(y[ix]) + v);
 }
 
-template <class T>
-void contact_apply(Ctx& c, int mode, const BSR& J, const BSR& JT, const double* D, const T* x,
-                   double* t, T* y, const T* w) {
-  if (J.nrows == 0 || J.nnzb == 0) return;
-  const int m = J.nrows, nn = JT.nrows;
-  const dim3 gm(grid_for(m, 256)), gn(grid_for(nn, 256)), blk(256);
+template <class TX, class TY>
+void contact_apply(Ctx& c, int mode, const BSR& J, const BSR& JT, const int* crows, int ncrows,
+                   const double* D, const TX* x, double* t, TY* y, const TY* w) {
+  if (J.nrows == 0 || J.nnzb == 0 || ncrows == 0) return;
+  const int m = J.nrows;
+  const dim3 gm(grid_for(m, 4)), gn(grid_for(ncrows, 4)), blk(256);
+#define AMGF_CT(BB)                                                                          \
+  hipLaunchKernelGGL((k_contact_t<BB, TX>), gm, blk, 0, c.s, m, J.rowptr.p, J.col.p,        \
+                     J.val.p, D, x, t);                                                      \
+  if (mode == CT_SUB_RES)                                                                    \
+    hipLaunchKernelGGL((k_contact_y<BB, TY, CT_SUB_RES>), gn, blk, 0, c.s, ncrows, crows,    \
+                       JT.rowptr.p, JT.col.p, JT.val.p, t, y, w);                            \
+  else if (mode == CT_SUB_W)                                                                 \
+    hipLaunchKernelGGL((k_contact_y<BB, TY, CT_SUB_W>), gn, blk, 0, c.s, ncrows, crows,      \
+                       JT.rowptr.p, JT.col.p, JT.val.p, t, y, w);                            \
+  else                                                                                       \
+    hipLaunchKernelGGL((k_contact_y<BB, TY, CT_ADD>), gn, blk, 0, c.s, ncrows, crows,        \
+                       JT.rowptr.p, JT.col.p, JT.val.p, t, y, w);
   if (J.bc == 3) {
-    hipLaunchKernelGGL((k_contact_t<3, T>), gm, blk, 0, c.s, m, J.rowptr.p, J.col.p, J.val.p, D,
-                       x, t);
-    if (mode == CT_SUB_RES)
-      hipLaunchKernelGGL((k_contact_y<3, T, CT_SUB_RES>), gn, blk, 0, c.s, nn, JT.rowptr.p,
-                         JT.col.p, JT.val.p, t, y, w);
-    else if (mode == CT_SUB_W)
-      hipLaunchKernelGGL((k_contact_y<3, T, CT_SUB_W>), gn, blk, 0, c.s, nn, JT.rowptr.p,
-                         JT.col.p, JT.val.p, t, y, w);
-    else
-      hipLaunchKernelGGL((k_contact_y<3, T, CT_ADD>), gn, blk, 0, c.s, nn, JT.rowptr.p,
-                         JT.col.p, JT.val.p, t, y, w);
+    AMGF_CT(3)
   } else {
-    hipLaunchKernelGGL((k_contact_t<6, T>), gm, blk, 0, c.s, m, J.rowptr.p, J.col.p, J.val.p, D,
-                       x, t);
-    if (mode == CT_SUB_RES)
-      hipLaunchKernelGGL((k_contact_y<6, T, CT_SUB_RES>), gn, blk, 0, c.s, nn, JT.rowptr.p,
-                         JT.col.p, JT.val.p, t, y, w);
-    else if (mode == CT_SUB_W)
-      hipLaunchKernelGGL((k_contact_y<6, T, CT_SUB_W>), gn, blk, 0, c.s, nn, JT.rowptr.p,
-                         JT.col.p, JT.val.p, t, y, w);
-    else
-      hipLaunchKernelGGL((k_contact_y<6, T, CT_ADD>), gn, blk, 0, c.s, nn, JT.rowptr.p,
-                         JT.col.p, JT.val.p, t, y, w);
+    AMGF_CT(6)
   }
+#undef AMGF_CT
   AMGF_LAUNCH_CHECK();
 }
-template void contact_apply<double>(Ctx&, int, const BSR&, const BSR&, const double*,
-                                    const double*, double*, double*, const double*);
-template void contact_apply<float>(Ctx&, int, const BSR&, const BSR&, const double*,
-                                   const float*, double*, float*, const float*);
+template void contact_apply<double, double>(Ctx&, int, const BSR&, const BSR&, const int*, int,
+                                            const double*, const double*, double*, double*,
+                                            const double*);
+template void contact_apply<float, float>(Ctx&, int, const BSR&, const BSR&, const int*, int,
+                                          const double*, const float*, double*, float*,
+                                          const float*);
+template void contact_apply<double, float>(Ctx&, int, const BSR&, const BSR&, const int*, int,
+                                           const double*, const double*, double*, float*,
+                                           const float*);
+
+// nonempty rows of a CSR (compact list)
+__global__ void k_nonempty_flag(int n, const int* __restrict__ rp, int* __restrict__ f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = rp[i + 1] > rp[i];
+}
+__global__ void k_compact_index(int n, const int* __restrict__ f, const int* __restrict__ pos,
+                                int* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && f[i]) out[pos[i]] = i;
+}
+int nonempty_rows(Ctx& c, const int* rp, int n, DBuf<int>& rows) {
+  DBuf<int> f(std::max(n, 1)), pos(size_t(n) + 1);
+  if (n) hipLaunchKernelGGL(k_nonempty_flag, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, rp, f.p);
+  const int cnt = scan_exclusive(c, f.p, pos.p, n);
+  rows.alloc(std::max(cnt, 1));
+  if (n && cnt)
+    hipLaunchKernelGGL(k_compact_index, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, f.p, pos.p,
+                       rows.p);
+  AMGF_LAUNCH_CHECK();
+  return cnt;
+}
 
 // ======================================================================================
 // elementwise
@@ -200,6 +273,9 @@ AMGF_ELEMWISE(k_axpby, (int64_t n, double al, const double* __restrict__ x, doub
                         double* __restrict__ y),
               y[i] = al * x[i] + be * y[i])
 AMGF_ELEMWISE(k_scale, (int64_t n, double s, double* __restrict__ x), x[i] *= s)
+AMGF_ELEMWISE(k_add_f, (int64_t n, const double* __restrict__ a, const float* __restrict__ f,
+                        double* __restrict__ z),
+              z[i] = a[i] + double(f[i]))
 AMGF_ELEMWISE(k_scale_div, (int64_t n, double* __restrict__ y, const double* __restrict__ d,
                             const unsigned char* __restrict__ dec),
               y[i] = (dec && dec[i]) ? 0.0 : y[i] / d[i])
@@ -248,6 +324,9 @@ void vcopy(Ctx& c, const double* a, double* b, int64_t n) {
 }
 void axpby(Ctx& c, int64_t n, double alpha, const double* x, double beta, double* y) {
   if (n) hipLaunchKernelGGL(k_axpby, AMGF_L1D(n), n, alpha, x, beta, y);
+}
+void add_f32(Ctx& c, int64_t n, const double* a, const float* f, double* z) {
+  if (n) hipLaunchKernelGGL(k_add_f, AMGF_L1D(n), n, a, f, z);
 }
 void vscale(Ctx& c, int64_t n, double s, double* x) {
   if (n) hipLaunchKernelGGL(k_scale, AMGF_L1D(n), n, s, x);

@@ -14,3 +14,4 @@ from .twoblock import (  # noqa: F401
     CONFIGS,
     make_config,
 )
+from . import learning  # noqa: F401

@@ -139,13 +139,47 @@ const char* amgf_last_error(void);
  *  AMGF_Q_K_ROWPTR/K_COL
  *  AMGF_Q_OMEGA    double[2]: rho estimate, prolongator damping
  *  AMGF_Q_IC       int32[n_c] filtering-space DOFs (level argument ignored)
+ *  AMGF_Q_FEATURES double[6 * n] learned-smoother features of the level's scalar rows,
+ *                  feature-major: log10 a_ii, log10 d_i, a_ii/d_i, log10(1 + sum D J^2),
+ *                  contact flag, level/(levels-1)  (smoothed levels only)
+ *  AMGF_Q_THETA    double[n] smoother damping theta of the level (1 when not learned)
  * Returns EINVAL for a bad level or selector; `bytes` must equal the array size.    */
 enum {
   AMGF_Q_SIZES = 0, AMGF_Q_A_ROWPTR, AMGF_Q_A_COL, AMGF_Q_A_VAL, AMGF_Q_AGG, AMGF_Q_ROOT,
   AMGF_Q_G_ROWPTR, AMGF_Q_G_COL, AMGF_Q_P_ROWPTR, AMGF_Q_P_COL, AMGF_Q_P_VAL, AMGF_Q_L1,
-  AMGF_Q_K_ROWPTR, AMGF_Q_K_COL, AMGF_Q_K_VAL, AMGF_Q_OMEGA, AMGF_Q_IC
+  AMGF_Q_K_ROWPTR, AMGF_Q_K_COL, AMGF_Q_K_VAL, AMGF_Q_OMEGA, AMGF_Q_IC, AMGF_Q_FEATURES,
+  AMGF_Q_THETA
 };
 int32_t amgf_num_levels(amgf_handle h);
+
+/* ---------------- learned smoother damping --------------------------------------------
+ * Not part of the paper: a per-row MLP (6 -> 32 tanh -> 32 tanh -> 1) maps the features
+ * listed under AMGF_Q_FEATURES, standardised with 6 means and 6 deviations, to
+ * theta = 1 + 0.98 tanh(y) in (0.02, 1.98), and the l1-Jacobi weights become theta / d.
+ * Any theta in (0, 2) keeps the smoother convergent (2 D_l1 / theta - A is SPD), so B
+ * stays an SPD, convergent V-cycle.  Parameter vector (1325 floats):
+ *   W1[32][6] b1[32] W2[32][32] b2[32] W3[32] b3 mu[6] sigma[6].
+ * With options.smoother = AMGF_LEARNED, amgf_pcg falls back to theta = 1 when CG does
+ * not converge and sets info.used_fallback.                                          */
+
+/* Replace the damping of every smoothed level by the MLP with device parameters W
+ * (1325 floats), or restore theta = 1 when W is NULL.                                  */
+amgf_status amgf_set_mlp(amgf_handle h, const float* W, void* stream);
+
+/* Training loss and gradient on an FP64 handle: for each probe e0 (device, column q of
+ * the n x n_probes array `probes`), loss_q = (1/k) log(||E^k e0||_S / ||e0||_S) with
+ * E = I - M S and M the AMGF preconditioner with MLP damping W (device).  *loss (host)
+ * = mean over probes; grad (device, 1313 doubles) = d loss / d (W1 b1 W2 b2 W3 b3),
+ * obtained by reverse mode through both V-cycles and the filter correction.  The
+ * handle's own damping is left unchanged.                                              */
+amgf_status amgf_mlp_loss_grad(amgf_handle h, const float* W, int32_t k, int32_t n_probes,
+                               const double* probes, double* loss, double* grad,
+                               void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the 1313 trainable parameters:
+ * W, m1, m2 device floats (m1/m2 zero before step t = 1), grad device doubles.          */
+amgf_status amgf_adam_step(float* W, const double* grad, float* m1, float* m2, int32_t t,
+                           float lr, void* stream);
 
 /* Benchmark helper: launch one hot-path kernel `reps` times on `stream` between two
  * hipEvents and store the mean time per launch (milliseconds) in *avg_ms (host).

@@ -17,11 +17,14 @@ AMGF_OK, AMGF_EINVAL, AMGF_ENOTSPD, AMGF_ENOCONV, AMGF_ENOMEM, AMGF_EDEVICE = ra
 FP64, MIXED_FP32 = 0, 1
 L1JACOBI, LEARNED = 0, 2
 (Q_SIZES, Q_A_ROWPTR, Q_A_COL, Q_A_VAL, Q_AGG, Q_ROOT, Q_G_ROWPTR, Q_G_COL, Q_P_ROWPTR,
- Q_P_COL, Q_P_VAL, Q_L1, Q_K_ROWPTR, Q_K_COL, Q_K_VAL, Q_OMEGA, Q_IC) = range(17)
+ Q_P_COL, Q_P_VAL, Q_L1, Q_K_ROWPTR, Q_K_COL, Q_K_VAL, Q_OMEGA, Q_IC, Q_FEATURES,
+ Q_THETA) = range(19)
+MLP_NPARAM, MLP_NTOTAL = 1313, 1325
 
 ABI_FUNCTIONS = ["amgf_default_options", "amgf_setup", "amgf_apply", "amgf_vcycle",
                  "amgf_operator_apply", "amgf_pcg", "amgf_destroy", "amgf_status_string",
-                 "amgf_last_error", "amgf_num_levels", "amgf_query", "amgf_time_kernel"]
+                 "amgf_last_error", "amgf_num_levels", "amgf_query", "amgf_time_kernel",
+                 "amgf_set_mlp", "amgf_mlp_loss_grad", "amgf_adam_step"]
 K_PRESMOOTH, K_POSTSMOOTH, K_VCYCLE, K_OPERATOR = range(4)
 
 
@@ -82,6 +85,12 @@ def load_library(path=LIB_PATH):
     L.amgf_query.restype = ctypes.c_int
     L.amgf_time_kernel.argtypes = [vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double)]
     L.amgf_time_kernel.restype = ctypes.c_int
+    L.amgf_set_mlp.argtypes = [vp, vp, vp]
+    L.amgf_set_mlp.restype = ctypes.c_int
+    L.amgf_mlp_loss_grad.argtypes = [vp, vp, i32, i32, vp, ctypes.POINTER(dbl), vp, vp]
+    L.amgf_mlp_loss_grad.restype = ctypes.c_int
+    L.amgf_adam_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp]
+    L.amgf_adam_step.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -143,10 +152,17 @@ class AMGF:
     """
 
     def __init__(self, n_nodes, K_rowptr, K_col, K_val, J_rowptr, J_col, J_val, D, coords,
-                 Ic=None, options=None, **kw):
+                 Ic=None, options=None, mlp_weights=None, **kw):
         torch = _torch()
         self.L = load_library()
         self.options = options if options is not None else default_options(**kw)
+        self._w = None
+        if mlp_weights is not None:
+            self._w = np.ascontiguousarray(mlp_weights, dtype=np.float32)
+            if self._w.size != MLP_NTOTAL:
+                raise ValueError(f"mlp_weights needs {MLP_NTOTAL} values")
+            self.options.smoother = LEARNED
+            self.options.mlp_weights = self._w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         i32, f64 = torch.int32, torch.float64
         self._keep = [_dev(K_rowptr, i32), _dev(K_col, i32), _dev(K_val, f64),
                       _dev(J_rowptr, i32), _dev(J_col, i32), _dev(J_val, f64), _dev(D, f64),
@@ -245,6 +261,37 @@ class AMGF:
                "amgf_time_kernel")
         return ms.value
 
+    def set_mlp(self, W):
+        """Damping from the MLP with parameters W (1325 values), or theta = 1 for None."""
+        torch = _torch()
+        if W is None:
+            _check(self.L.amgf_set_mlp(self.h, None, _stream()), "amgf_set_mlp")
+            return
+        Wd = _dev(W, torch.float32)
+        _check(self.L.amgf_set_mlp(self.h, _ptr(Wd), _stream()), "amgf_set_mlp")
+        torch.cuda.synchronize()
+
+    def loss_grad(self, W, probes, k=2):
+        """(loss, grad) of the learned-damping objective; probes is (n, count)."""
+        torch = _torch()
+        Wd = _dev(W, torch.float32)
+        P = _dev(np.asarray(probes).T if not isinstance(probes, torch.Tensor) else probes.T,
+                 torch.float64)                       # column q contiguous
+        g = torch.zeros(MLP_NPARAM, dtype=torch.float64, device="cuda")
+        loss = ctypes.c_double()
+        _check(self.L.amgf_mlp_loss_grad(self.h, _ptr(Wd), k, int(P.shape[0]), _ptr(P),
+                                         ctypes.byref(loss), _ptr(g), _stream()),
+               "amgf_mlp_loss_grad")
+        return loss.value, g
+
+    def features(self, level):
+        n = int(self.query(level, Q_SIZES)[0]) * int(self.query(level, Q_SIZES)[1])
+        return self.query(level, Q_FEATURES, np.float64, 6 * n).reshape(6, n)
+
+    def theta(self, level):
+        n = int(self.query(level, Q_SIZES)[0]) * int(self.query(level, Q_SIZES)[1])
+        return self.query(level, Q_THETA, np.float64, n)
+
     def filter_dofs(self, n_c):
         return self.query(0, Q_IC, np.int32, n_c)
 
@@ -258,3 +305,10 @@ class AMGF:
             self.close()
         except Exception:
             pass
+
+
+def adam_step(W, grad, m1, m2, t, lr):
+    """In-place Adam step on device tensors (W, m1, m2 float32; grad float64)."""
+    L = load_library()
+    _check(L.amgf_adam_step(_ptr(W), _ptr(grad), _ptr(m1), _ptr(m2), int(t), float(lr),
+                            _stream()), "amgf_adam_step")

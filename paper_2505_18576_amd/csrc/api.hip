@@ -7,6 +7,7 @@
 #include "apply.h"
 #include "btd.h"
 #include "dense.h"
+#include "learn.h"
 #include "setup.h"
 
 namespace amgf {
@@ -25,6 +26,10 @@ struct Level {
   DBuf<float> w32;
   int n_agg = 0;
   double rho = 1.0, omega = 0.0;
+  // learned smoother: features (6 x n) and damping theta
+  DBuf<double> F, theta;
+  // adjoint work vectors and the damping gradient
+  DBuf<double> ay, ab, ax, ar, ax2, wbar;
   // V-cycle work vectors
   DBuf<double> vb, vx, vr, vxn;
   DBuf<float> fb, fx, fr, fxn;
@@ -59,6 +64,8 @@ struct Handle {
   // pcg scratch
   DBuf<double> pr, pz, pzo, pp, pq;
   double op_complexity = 1.0;
+  DBuf<float> mlpW;             // device copy of the MLP parameters (learned smoother)
+  bool learned = false;
   bool mixed() const { return opt.precision == AMGF_MIXED_FP32; }
   int64_t n() const { return int64_t(n_nodes) * 3; }
 };
@@ -252,6 +259,26 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     h.f_res.alloc(h.n_c);
     h.f_dw.alloc(h.n_c);
   }
+  // ---- learned-smoother features of the smoothed levels
+  const int nlev = int(h.lev.size());
+  for (int l = 0; l + 1 < nlev; ++l) {
+    Level& L = *h.lev[l];
+    L.F.alloc(size_t(6) * L.n());
+    L.theta.alloc(L.n());
+    level_features(c, L.b, L.nn, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.d.p, L.JT.rowptr.p,
+                   L.JT.col.p, L.JT.val.p, h.D.p, nlev > 1 ? double(l) / double(nlev - 1) : 0.0,
+                   L.F.p);
+  }
+  if (o.smoother == AMGF_LEARNED) {
+    h.mlpW.alloc(MLP_NTOTAL);
+    AMGF_HIP(hipMemcpyAsync(h.mlpW.p, o.mlp_weights, sizeof(float) * MLP_NTOTAL,
+                            hipMemcpyHostToDevice, c.s));
+    h.learned = true;
+    for (int l = 0; l + 1 < nlev; ++l) {
+      Level& L = *h.lev[l];
+      mlp_theta(c, L.n(), h.mlpW.p, L.F.p, L.d.p, L.theta.p, L.w.p);
+    }
+  }
   // ---- precision copies and work vectors
   for (size_t l = 0; l < h.lev.size(); ++l) {
     Level& L = *h.lev[l];
@@ -405,9 +432,218 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
 }
 
 // ------------------------------------------------------------------------------------
+// learned smoother: damping from the MLP, taped forward and adjoint of M
+// ------------------------------------------------------------------------------------
+// w = theta / d on every smoothed level; W == nullptr restores theta = 1
+static void set_damping(Handle& h, const float* W) {
+  Ctx& c = h.ctx;
+  for (size_t l = 0; l + 1 < h.lev.size(); ++l) {
+    Level& L = *h.lev[l];
+    if (W) mlp_theta(c, L.n(), W, L.F.p, L.d.p, L.theta.p, L.w.p);
+    else weights_from_l1(c, L.n(), L.d.p, nullptr, L.w.p);
+    if (h.mixed()) cast_d2f(c, L.w.p, L.w32.p, L.n());
+  }
+}
+
+struct Tape {
+  std::vector<DBuf<double>> b, s2;   // per level: V-cycle input and post-smoothing residual
+  void alloc(const Handle& h) {
+    b.resize(h.lev.size());
+    s2.resize(h.lev.size());
+    for (size_t l = 0; l < h.lev.size(); ++l) {
+      b[l].alloc(h.lev[l]->n());
+      s2[l].alloc(h.lev[l]->n());
+    }
+  }
+};
+
+// FP64 V-cycle L.vb -> L.vx, recording b and s2 = b - A x' of every level
+static void vcycle64_tape(Handle& h, size_t l, Tape& T) {
+  Ctx& c = h.ctx;
+  Level& L = *h.lev[l];
+  vcopy(c, L.vb.p, T.b[l].p, L.n());
+  if (l + 1 == h.lev.size()) {
+    coarse_solve(h, L.vb.p, L.vx.p);
+    return;
+  }
+  Level& N = *h.lev[l + 1];
+  bsr_spmv<double>(c, SPMV_PRE, L.K, L.K.val.p, nullptr, L.vr.p, L.vb.p, L.w.p, L.vx.p);
+  contact_apply<double, double>(c, CT_SUB_RES, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.vx.p,
+                                h.t.p, L.vr.p, nullptr);
+  bsr_spmv<double>(c, SPMV_Y, L.PT, L.PT.val.p, L.vr.p, N.vb.p, nullptr, nullptr, nullptr);
+  vcycle64_tape(h, l + 1, T);
+  bsr_spmv<double>(c, SPMV_ADD, L.P, L.P.val.p, N.vx.p, L.vx.p, nullptr, nullptr, nullptr);
+  bsr_spmv<double>(c, SPMV_RES, L.K, L.K.val.p, L.vx.p, T.s2[l].p, L.vb.p, nullptr, nullptr);
+  contact_apply<double, double>(c, CT_SUB_RES, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.vx.p,
+                                h.t.p, T.s2[l].p, nullptr);
+  axpy_hadamard(c, L.n(), L.w.p, T.s2[l].p, L.vx.p);
+}
+
+// y = b - A x on level l (K_l plus the contact term), FP64
+static void level_residual(Handle& h, Level& L, const double* x, double* y, const double* b) {
+  bsr_spmv<double>(h.ctx, SPMV_RES, L.K, L.K.val.p, x, y, b, nullptr, nullptr);
+  contact_apply<double, double>(h.ctx, CT_SUB_RES, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, x,
+                                h.t.p, y, nullptr);
+}
+
+// adjoint of the V-cycle: L.ay (adjoint of the output) -> L.ab (adjoint of the input),
+// accumulating d/dw into L.wbar.  Reverse of
+//   x = w.b; r = b - A x; xc = B_c(P^T r); x' = x + P xc; s2 = b - A x'; x'' = x' + w.s2
+static void vcycle64_adj(Handle& h, size_t l, const Tape& T) {
+  Ctx& c = h.ctx;
+  Level& L = *h.lev[l];
+  const int64_t n = L.n();
+  if (l + 1 == h.lev.size()) {
+    coarse_solve(h, L.ay.p, L.ab.p);
+    return;
+  }
+  Level& N = *h.lev[l + 1];
+  hadamard(c, n, L.w.p, L.ay.p, L.ab.p);                  // s2bar = w.ybar (-> bbar)
+  acc_hadamard(c, n, L.ay.p, T.s2[l].p, L.wbar.p);        // wbar += ybar.s2
+  level_residual(h, L, L.ab.p, L.ax.p, L.ay.p);           // x'bar = ybar - A s2bar
+  bsr_spmv<double>(c, SPMV_Y, L.PT, L.PT.val.p, L.ax.p, N.ay.p, nullptr, nullptr, nullptr);
+  vcycle64_adj(h, l + 1, T);                              // bcbar = B_c^T xcbar
+  bsr_spmv<double>(c, SPMV_Y, L.P, L.P.val.p, N.ab.p, L.ar.p, nullptr, nullptr, nullptr);
+  axpby(c, n, 1.0, L.ar.p, 1.0, L.ab.p);                  // bbar += rbar
+  level_residual(h, L, L.ar.p, L.ax2.p, L.ax.p);          // xbar = x'bar - A rbar
+  axpy_hadamard(c, n, L.w.p, L.ax2.p, L.ab.p);            // bbar += w.xbar
+  acc_hadamard(c, n, L.ax2.p, T.b[l].p, L.wbar.p);        // wbar += xbar.b
+}
+
+// z = M v (FP64) recording both V-cycles
+static void apply_tape(Handle& h, const double* v, double* z, Tape& T1, Tape& T2) {
+  Ctx& c = h.ctx;
+  Level& L0 = *h.lev[0];
+  const int64_t n = h.n();
+  vcopy(c, v, L0.vb.p, n);
+  vcycle64_tape(h, 0, T1);
+  vcopy(c, L0.vx.p, h.z1.p, n);
+  if (h.n_c > 0) {
+    bsr_res_rows(c, L0.K, h.ic_nodes.p, h.n_icn, h.z1.p, v, h.ra.p);
+    contact_apply<double, double>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
+                                  h.z1.p, h.t.p, h.ra.p, nullptr);
+    gather(c, h.ra.p, h.Ic.p, h.n_c, h.f_r.p);
+    filter_solve(h, h.f_r.p, h.f_w.p);
+    scatter_add(c, h.f_w.p, h.Ic.p, h.n_c, h.z1.p);
+  }
+  operator_apply(h, h.z1.p, L0.vb.p, v);                  // r2 = v - A z2
+  vcycle64_tape(h, 0, T2);
+  vcopy(c, h.z1.p, z, n);
+  axpby(c, n, 1.0, L0.vx.p, 1.0, z);
+}
+
+// vbar = M^T zbar, accumulating d/dw of both V-cycles (reverse of apply_tape)
+static void apply_adj(Handle& h, const double* zbar, double* vbar, const Tape& T1,
+                      const Tape& T2) {
+  Ctx& c = h.ctx;
+  Level& L0 = *h.lev[0];
+  const int64_t n = h.n();
+  vcopy(c, zbar, L0.ay.p, n);
+  vcycle64_adj(h, 0, T2);                                 // r2bar = B^T zbar
+  vcopy(c, L0.ab.p, vbar, n);                             // vbar = r2bar
+  operator_apply(h, L0.ab.p, h.z3.p, zbar);               // z2bar = zbar - A r2bar
+  if (h.n_c > 0) {
+    gather(c, h.z3.p, h.Ic.p, h.n_c, h.f_r.p);
+    filter_solve(h, h.f_r.p, h.f_w.p);                    // rabar = A_w^{-1} P^T z2bar
+    AMGF_HIP(hipMemsetAsync(h.r2.p, 0, sizeof(double) * n, c.s));
+    scatter_add(c, h.f_w.p, h.Ic.p, h.n_c, h.r2.p);       // u = P rabar
+    axpby(c, n, 1.0, h.r2.p, 1.0, vbar);                  // vbar += u
+    operator_apply(h, h.r2.p, L0.ay.p, h.z3.p);           // z1bar = z2bar - A u
+  } else {
+    vcopy(c, h.z3.p, L0.ay.p, n);
+  }
+  vcycle64_adj(h, 0, T1);
+  axpby(c, n, 1.0, L0.ab.p, 1.0, vbar);                   // vbar += B^T z1bar
+}
+
+// mean over probes of (1/k) log(||E^k e||_S / ||e||_S), E = I - M S, and d/dW
+static double loss_grad(Handle& h, const float* W, int k, int np, const double* probes,
+                        double* grad) {
+  Ctx& c = h.ctx;
+  const int64_t n = h.n();
+  AMGF_REQUIRE(!h.mixed(), AMGF_EINVAL, "training runs on an FP64 handle");
+  AMGF_REQUIRE(h.lev.size() > 1, AMGF_EINVAL, "no smoothed level");
+  set_damping(h, W);
+  for (auto& Lp : h.lev) {
+    Level& L = *Lp;
+    if (!L.ay.n) {
+      L.ay.alloc(L.n()); L.ab.alloc(L.n()); L.ax.alloc(L.n());
+      L.ar.alloc(L.n()); L.ax2.alloc(L.n()); L.wbar.alloc(L.n());
+    }
+    AMGF_HIP(hipMemsetAsync(L.wbar.p, 0, L.wbar.bytes(), c.s));
+  }
+  std::vector<Tape> T(2 * size_t(k));
+  for (auto& t : T) t.alloc(h);
+  DBuf<double> e(n), Se(n), r(n), z(n), eb(n), vb(n);
+  double loss = 0.0;
+  for (int q = 0; q < np; ++q) {
+    vcopy(c, probes + int64_t(q) * n, e.p, n);
+    operator_apply(h, e.p, Se.p, nullptr);
+    double s0;
+    {
+      const double* xs[1] = {e.p};
+      const double* ys[1] = {Se.p};
+      dots(c, n, 1, xs, ys, &s0);
+    }
+    for (int j = 0; j < k; ++j) {
+      operator_apply(h, e.p, r.p, nullptr);               // r_j = S e_j
+      apply_tape(h, r.p, z.p, T[2 * j], T[2 * j + 1]);    // z_j = M r_j
+      axpby(c, n, -1.0, z.p, 1.0, e.p);                   // e_{j+1} = e_j - z_j
+    }
+    operator_apply(h, e.p, Se.p, nullptr);
+    double sk;
+    {
+      const double* xs[1] = {e.p};
+      const double* ys[1] = {Se.p};
+      dots(c, n, 1, xs, ys, &sk);
+    }
+    AMGF_REQUIRE(s0 > 0.0 && sk > 0.0, AMGF_ENOTSPD, "probe has zero energy");
+    loss += (std::log(sk) - std::log(s0)) / (2.0 * k);
+    vcopy(c, Se.p, eb.p, n);
+    vscale(c, n, 1.0 / (k * sk), eb.p);                   // ebar_k = S e_k / (k s_k)
+    for (int j = k - 1; j >= 0; --j) {
+      vcopy(c, eb.p, z.p, n);
+      vscale(c, n, -1.0, z.p);                            // zbar_j = -ebar_{j+1}
+      apply_adj(h, z.p, vb.p, T[2 * j], T[2 * j + 1]);
+      operator_apply(h, vb.p, r.p, nullptr);
+      axpby(c, n, 1.0, r.p, 1.0, eb.p);                   // ebar_j = ebar_{j+1} + S vbar
+    }
+  }
+  // dL/dtheta = wbar / d / np on every smoothed level, then through the MLP
+  bool first = true;
+  for (size_t l = 0; l + 1 < h.lev.size(); ++l) {
+    Level& L = *h.lev[l];
+    vdiv(c, L.n(), L.wbar.p, L.d.p, L.ax.p);
+    vscale(c, L.n(), 1.0 / np, L.ax.p);
+    mlp_backward(c, L.n(), W, L.F.p, L.ax.p, grad, !first);
+    first = false;
+  }
+  return loss / np;
+}
+
+// ------------------------------------------------------------------------------------
 // PCG (Sec. 4 / 6.1 stopping rule), Polak-Ribiere beta
 // ------------------------------------------------------------------------------------
+static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_info* info);
+
+// Learned damping: if CG does not converge (or breaks down), rerun from the same initial
+// guess with theta = 1 (plain l1-Jacobi) and report the fallback.
 static amgf_status pcg_impl(Handle& h, const double* b, double* x, amgf_solve_info* info) {
+  if (!h.learned) return pcg_run(h, b, x, info);
+  Ctx& c = h.ctx;
+  DBuf<double> x0(h.n());
+  vcopy(c, x, x0.p, h.n());
+  amgf_status st = pcg_run(h, b, x, info);
+  if (st == AMGF_OK) return st;
+  set_damping(h, nullptr);
+  vcopy(c, x0.p, x, h.n());
+  st = pcg_run(h, b, x, info);
+  set_damping(h, h.mlpW.p);
+  if (info) info->used_fallback = 1;
+  return st;
+}
+
+static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_info* info) {
   Ctx& c = h.ctx;
   const int64_t n = h.n();
   hipEvent_t e0, e1;
@@ -563,8 +799,10 @@ amgf_status amgf_setup(const amgf_options* opts, int32_t n_nodes, const int32_t*
     AMGF_REQUIRE(int64_t(n_nodes) * 6 < (int64_t(1) << 31), AMGF_EINVAL, "too many nodes");
     AMGF_REQUIRE(h.opt.precision == AMGF_FP64 || h.opt.precision == AMGF_MIXED_FP32,
                  AMGF_EINVAL, "precision");
-    AMGF_REQUIRE(h.opt.smoother == AMGF_L1JACOBI, AMGF_EINVAL,
-                 "smoother not supported by this entry point");
+    AMGF_REQUIRE(h.opt.smoother == AMGF_L1JACOBI || h.opt.smoother == AMGF_LEARNED, AMGF_EINVAL,
+                 "smoother");
+    AMGF_REQUIRE(h.opt.smoother != AMGF_LEARNED || h.opt.mlp_weights, AMGF_EINVAL,
+                 "the learned smoother needs mlp_weights");
     AMGF_REQUIRE(h.opt.max_levels >= 1 && h.opt.max_iters >= 0 && h.opt.rtol >= 0,
                  AMGF_EINVAL, "options");
     AMGF_REQUIRE(n_c >= 0 && (n_c == 0 || Ic), AMGF_EINVAL, "Ic");
@@ -631,6 +869,52 @@ void amgf_destroy(amgf_handle hd) {
 }
 
 int32_t amgf_num_levels(amgf_handle hd) { return hd ? int32_t(hd->h.lev.size()) : 0; }
+
+amgf_status amgf_set_mlp(amgf_handle hd, const float* W, void* stream) {
+  if (!hd) return AMGF_EINVAL;
+  amgf_status st_ = guard([&]() -> amgf_status {
+    Handle& h = hd->h;
+    h.ctx.s = static_cast<hipStream_t>(stream);
+    if (W) {
+      if (!h.mlpW.n) h.mlpW.alloc(amgf::MLP_NTOTAL);
+      AMGF_HIP(hipMemcpyAsync(h.mlpW.p, W, sizeof(float) * amgf::MLP_NTOTAL,
+                              hipMemcpyDeviceToDevice, h.ctx.s));
+      h.learned = true;
+      amgf::set_damping(h, h.mlpW.p);
+    } else {
+      h.learned = false;
+      amgf::set_damping(h, nullptr);
+    }
+    return AMGF_OK;
+  });
+  return st_;
+}
+
+amgf_status amgf_mlp_loss_grad(amgf_handle hd, const float* W, int32_t k, int32_t n_probes,
+                               const double* probes, double* loss, double* grad, void* stream) {
+  if (!hd || !W || !probes || !loss || !grad || k < 1 || n_probes < 1) return AMGF_EINVAL;
+  amgf_status st_ = guard([&]() -> amgf_status {
+    Handle& h = hd->h;
+    h.ctx.s = static_cast<hipStream_t>(stream);
+    *loss = amgf::loss_grad(h, W, k, n_probes, probes, grad);
+    // leave the handle's damping as it was
+    amgf::set_damping(h, h.learned ? h.mlpW.p : nullptr);
+    return AMGF_OK;
+  });
+  return st_;
+}
+
+amgf_status amgf_adam_step(float* W, const double* grad, float* m1, float* m2, int32_t t,
+                           float lr, void* stream) {
+  if (!W || !grad || !m1 || !m2 || t < 1) return AMGF_EINVAL;
+  amgf_status st_ = guard([&]() -> amgf_status {
+    amgf::Ctx c;
+    c.s = static_cast<hipStream_t>(stream);
+    amgf::adam_step(c, W, grad, m1, m2, t, lr);
+    return AMGF_OK;
+  });
+  return st_;
+}
 
 amgf_status amgf_time_kernel(amgf_handle hd, int32_t which, int32_t reps, void* stream,
                              double* avg_ms) {
@@ -734,6 +1018,17 @@ amgf_status amgf_query(amgf_handle hd, int32_t level, int32_t which, void* dst, 
       case AMGF_Q_K_ROWPTR: cp(L.K.rowptr.p, sizeof(int) * (size_t(L.nn) + 1)); break;
       case AMGF_Q_K_COL: cp(L.K.col.p, sizeof(int) * size_t(L.K.nnzb)); break;
       case AMGF_Q_K_VAL: cp(L.K.val.p, sizeof(double) * size_t(L.K.nnzb) * L.K.bsz()); break;
+      case AMGF_Q_FEATURES: cp(L.F.p, L.F.n ? sizeof(double) * size_t(6) * L.n() : 0); break;
+      case AMGF_Q_THETA: {
+        AMGF_REQUIRE(bytes == sizeof(double) * size_t(L.n()), AMGF_EINVAL, "size");
+        if (h.learned && L.theta.n) {
+          AMGF_HIP(hipMemcpy(dst, L.theta.p, bytes, hipMemcpyDeviceToHost));
+        } else {
+          std::vector<double> one(L.n(), 1.0);
+          std::memcpy(dst, one.data(), bytes);
+        }
+        break;
+      }
       case AMGF_Q_OMEGA: {
         double s[2] = {L.rho, L.omega};
         AMGF_REQUIRE(bytes == sizeof(s), AMGF_EINVAL, "size");

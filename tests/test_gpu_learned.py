@@ -1,0 +1,119 @@
+"""GPU learned-smoother kernels against the oracle: features, damping, loss, gradient."""
+import numpy as np
+import pytest
+
+from amgf_inputs import learning, make_two_block
+from gpu_util import rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def case():
+    from oracle import OracleAMGF, OracleOptions, learned
+    p = make_two_block(4, D_log10=(0.0, 3.0), D_seed=31, rhs_seed=32)
+    o = OracleAMGF(p.n_nodes, p.K_rowptr, p.K_col, p.K_val, p.J_rowptr, p.J_col, p.J_val,
+                   p.D, p.coords, OracleOptions(coarse_max_nodes=16))
+    feats = learned.level_features(o)
+    allf = np.concatenate(feats, axis=1)
+    W = learning.init_params(seed=11, mu=allf.mean(axis=1), sd=allf.std(axis=1) + 1e-3,
+                             last_scale=0.3)
+    P = learning.probes(o.n, p.free, 3, seed=12)
+    return p, o, feats, W, P
+
+
+def test_features_match_oracle(case):
+    from paper_2505_18576_amd import AMGF
+    p, o, feats, W, P = case
+    h = AMGF.from_problem(p, coarse_max_nodes=16)
+    assert h.n_levels == o.nlev
+    for l, F in enumerate(feats):
+        G = h.features(l)
+        assert rel(G, F) < 1e-13, l
+    h.close()
+
+
+def test_loss_and_gradient_match_oracle(case):
+    from oracle import learned
+    from paper_2505_18576_amd import AMGF
+    p, o, feats, W, P = case
+    L_o, g_o = learned.loss_grad(o, W, P, k=2, feats=feats)
+    learned.reset_damping(o)
+    h = AMGF.from_problem(p, coarse_max_nodes=16)
+    L_g, g_g = h.loss_grad(W, P, k=2)
+    g_g = g_g.cpu().numpy()
+    print(f"loss gpu {L_g:.12f} oracle {L_o:.12f}; grad rel {rel(g_g, g_o):.2e}")
+    assert abs(L_g - L_o) <= 1e-10 * abs(L_o)
+    assert rel(g_g, g_o) < 1e-9
+    # the handle keeps theta = 1 after the gradient call
+    assert np.all(h.theta(0) == 1.0)
+    h.close()
+
+
+def test_learned_damping_applies_the_mlp(case):
+    from oracle import learned
+    from paper_2505_18576_amd import AMGF
+    p, o, feats, W, P = case
+    h = AMGF.from_problem(p, coarse_max_nodes=16, mlp_weights=W)
+    learned.set_damping(o, W, feats)
+    for l, F in enumerate(feats):
+        assert rel(h.theta(l), learned.mlp_forward(W, F)[0]) < 1e-13
+    r = np.random.default_rng(4).standard_normal(o.n)
+    assert rel(h.apply(r).cpu().numpy(), o.apply(r)) < 1e-11
+    x, info = h.pcg(p.b)
+    ref = o.pcg(p.b)
+    learned.reset_damping(o)
+    assert info.converged and abs(info.iterations - ref.iterations) <= 1
+    assert info.used_fallback == 0
+    h.close()
+
+
+def test_zero_last_layer_is_bitwise_plain(case):
+    from paper_2505_18576_amd import AMGF
+    p, o, feats, W, P = case
+    W0 = W.copy()
+    W0[1280:1313] = 0.0
+    a = AMGF.from_problem(p, coarse_max_nodes=16, mlp_weights=W0)
+    b = AMGF.from_problem(p, coarse_max_nodes=16)
+    xa, ia = a.pcg(p.b)
+    xb, ib = b.pcg(p.b)
+    assert ia.iterations == ib.iterations
+    assert np.array_equal(xa.cpu().numpy().view(np.uint64), xb.cpu().numpy().view(np.uint64))
+    a.close()
+    b.close()
+
+
+def test_fallback_when_learned_damping_fails(case):
+    """NaN weights make the learned V-cycle non-finite: CG breaks down, the solve reruns
+    with theta = 1 from the same initial guess and reports the fallback."""
+    from paper_2505_18576_amd import AMGF
+    p, o, feats, W, P = case
+    Wbad = W.copy()
+    Wbad[1312] = np.nan
+    ref = AMGF.from_problem(p, coarse_max_nodes=16)
+    xr, iref = ref.pcg(p.b)
+    h = AMGF.from_problem(p, coarse_max_nodes=16, mlp_weights=Wbad)
+    x, info = h.pcg(p.b)
+    assert info.used_fallback == 1 and info.converged
+    assert info.iterations == iref.iterations
+    assert np.array_equal(x.cpu().numpy(), xr.cpu().numpy())
+    h.close()
+    ref.close()
+
+
+def test_adam_step_matches_reference():
+    import torch
+    from paper_2505_18576_amd.amgf import adam_step
+    rng = np.random.default_rng(0)
+    W = rng.standard_normal(1325).astype(np.float32)
+    g = rng.standard_normal(1313)
+    Wd = torch.from_numpy(W.copy()).cuda()
+    gd = torch.from_numpy(g).cuda()
+    m1 = torch.zeros(1313, dtype=torch.float32, device="cuda")
+    m2 = torch.zeros_like(m1)
+    adam_step(Wd, gd, m1, m2, 1, 1e-3)
+    torch.cuda.synchronize()
+    # t = 1: m_hat = g, v_hat = g^2, step = lr * g / (|g| + eps)
+    ref = W.copy()
+    ref[:1313] -= (1e-3 * g / (np.abs(g) + 1e-8)).astype(np.float32)
+    assert np.allclose(Wd.cpu().numpy(), ref, rtol=1e-5, atol=1e-6)

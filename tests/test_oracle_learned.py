@@ -1,0 +1,92 @@
+"""Pins of the oracle's learned-smoother loss and gradient."""
+import numpy as np
+import pytest
+
+from amgf_inputs import learning
+from oracle import learned
+from oracle_util import build, dense_of, small_problem
+
+
+@pytest.fixture(scope="module")
+def setup():
+    p = small_problem(N=3, D_log10=(0.0, 3.0))
+    o = build(p, coarse_max_nodes=8, max_levels=3)
+    feats = learned.level_features(o)
+    mu = np.concatenate(feats, axis=1).mean(axis=1)
+    sd = np.concatenate(feats, axis=1).std(axis=1) + 1e-3
+    W = learning.init_params(seed=3, mu=mu, sd=sd, last_scale=0.3)
+    P = learning.probes(o.n, p.free, 2, seed=5)
+    return p, o, feats, W, P
+
+
+def test_zero_last_layer_is_plain_l1_jacobi(setup):
+    p, o, feats, W, P = setup
+    W0 = W.copy()
+    W0[1280:1313] = 0.0
+    learned.set_damping(o, W0, feats)
+    r = np.random.default_rng(0).standard_normal(o.n)
+    z_l = o.apply(r)
+    learned.reset_damping(o)
+    assert np.array_equal(z_l, o.apply(r))
+
+
+def test_theta_range_keeps_B_spd_and_convergent(setup):
+    p, o, feats, W, P = setup
+    Wb = W.copy()
+    Wb[1280:1312] *= 40.0                  # drive theta towards its bounds
+    learned.set_damping(o, Wb, feats)
+    th = np.concatenate([learned.mlp_forward(Wb, F)[0] for F in feats])
+    assert th.min() > 0.02 and th.max() < 1.98 and (th.max() - th.min()) > 1.0
+    A = o.S.todense()
+    B = dense_of(o.vcycle, o.n)
+    lam = np.linalg.eigvals(B @ A).real
+    assert np.abs(B - B.T).max() <= 1e-9 * np.abs(B).max()
+    assert lam.min() > 0 and lam.max() < 2.0
+    learned.reset_damping(o)
+
+
+def test_gradient_matches_central_differences(setup):
+    p, o, feats, W, P = setup
+    L0, g = learned.loss_grad(o, W, P, k=2, feats=feats)
+    assert abs(L0 - learned.loss(o, W, P, k=2, feats=feats)) <= 1e-12 * abs(L0)
+    rng = np.random.default_rng(7)
+    idx = np.concatenate([rng.choice(192, 6, replace=False), 192 + rng.choice(32, 3),
+                          224 + rng.choice(1024, 8, replace=False), 1248 + rng.choice(32, 3),
+                          1280 + rng.choice(32, 5, replace=False), [1312]])
+    h = 1e-3
+    for i in idx:
+        Wp = W.astype(np.float64).copy()
+        Wm = Wp.copy()
+        Wp[i] += h
+        Wm[i] -= h
+        fd = (learned.loss(o, Wp, P, 2, feats) - learned.loss(o, Wm, P, 2, feats)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1e-4, abs(g).max()) + 1e-5 * abs(g[i]), (i, fd, g[i])
+    # a random direction through all parameters
+    v = rng.standard_normal(1313)
+    h = 1e-5
+    Wp = W.astype(np.float64).copy()
+    Wm = Wp.copy()
+    Wp[:1313] += h * v
+    Wm[:1313] -= h * v
+    fd = (learned.loss(o, Wp, P, 2, feats) - learned.loss(o, Wm, P, 2, feats)) / (2 * h)
+    assert abs(fd - g @ v) <= 1e-5 * abs(fd)
+    learned.reset_damping(o)
+
+
+def test_loss_is_error_reduction(setup):
+    """theta = 1: the loss equals the measured log energy-norm reduction of E = I - MS."""
+    p, o, feats, W, P = setup
+    W0 = W.copy()
+    W0[1280:1313] = 0.0
+    L = learned.loss(o, W0, P, k=2, feats=feats)
+    A = o.S.todense()
+    M = dense_of(o.apply, o.n)
+    E = np.eye(o.n) - M @ A
+    vals = []
+    for q in range(P.shape[1]):
+        e = P[:, q]
+        ek = E @ (E @ e)
+        vals.append(np.log((ek @ A @ ek) / (e @ A @ e)) / (2 * 2))   # (1/k) log of the norm ratio
+    assert abs(L - np.mean(vals)) <= 1e-10 * abs(L)
+    assert L < 0
+    learned.reset_damping(o)

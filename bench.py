@@ -117,16 +117,21 @@ def main():
     bvec = torch.from_numpy(p.b).to(dev, f64)
     torch.cuda.synchronize()
 
-    def solve(precision):
+    from paper_2505_18576_amd.train_smoother import load_weights
+    wpath = os.path.join(ROOT, "paper_2505_18576_amd", "weights", "smoother_ip.bin")
+    W = load_weights(wpath)
+
+    def solve(precision, weights):
         h = AMGF(p.n_nodes, d["K_rowptr"], d["K_col"], d["K_val"], d["J_rowptr"], d["J_col"],
-                 d["J_val"], d["D"], d["coords"], precision=precision)
+                 d["J_val"], d["D"], d["coords"], precision=precision, mlp_weights=weights)
         x, info = h.pcg(bvec)
         return h, x, info
 
     res = {}
-    for mode, prec in (("fp64", b.FP64), ("mixed", b.MIXED_FP32)):
+    for mode, prec, weights in (("fp64", b.FP64, None), ("mixed", b.MIXED_FP32, None),
+                                ("mixed_learned", b.MIXED_FP32, W)):
         for w in range(args.warmup):
-            h, x, info = solve(prec)
+            h, x, info = solve(prec, weights)
             log(f"{mode} warmup {w}: {info.iterations} it, conv {info.converged}")
             h.close()
         torch.cuda.synchronize()
@@ -134,13 +139,13 @@ def main():
         for s in range(args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            h, x, info = solve(prec)
+            h, x, info = solve(prec, weights)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             log(f"{mode} step {s}: {times[-1]:.3f}s, {info.iterations} it, "
                 f"solve {info.ms_solve:.1f} ms, rel prec res {info.rel_prec_res:.2e}, "
                 f"true res {info.rel_true_res:.2e}, levels {info.n_levels}, "
-                f"op complexity {info.op_complexity:.3f}")
+                f"op complexity {info.op_complexity:.3f}, fallback {info.used_fallback}")
             if s < args.steps - 1:
                 h.close()
         vb = 4 if prec == b.MIXED_FP32 else 8
@@ -149,6 +154,7 @@ def main():
         ms_op = h.time_kernel(b.K_OPERATOR, args.reps)
         res[mode] = dict(s_per_solve=float(np.mean(times)), iterations=int(info.iterations),
                          converged=bool(info.converged), ms_solve=float(info.ms_solve),
+                         used_fallback=int(info.used_fallback),
                          rel_true_res=float(info.rel_true_res), n_levels=int(info.n_levels),
                          op_complexity=float(info.op_complexity),
                          smoother_ms=ms_pre, smoother_bytes=smoother_bytes(h, vb),
@@ -156,10 +162,13 @@ def main():
                          x=x)
         h.close()
         log(f"{mode}: pre-smooth {ms_pre:.3f} ms, V-cycle {ms_vc:.3f} ms, operator {ms_op:.3f} ms")
-    xm, xd = res["mixed"].pop("x"), res["fp64"].pop("x")
-    rel_mixed_vs_fp64 = float(torch.linalg.norm(xm - xd) / torch.linalg.norm(xd))
+    xd = res["fp64"].pop("x")
+    rel_vs_fp64 = {}
+    for k in ("mixed", "mixed_learned"):
+        xk = res[k].pop("x")
+        rel_vs_fp64[k] = float(torch.linalg.norm(xk - xd) / torch.linalg.norm(xd))
 
-    m = res["mixed"]
+    m = res["mixed_learned"]
     ach = m["smoother_bytes"] / (m["smoother_ms"] * 1e-3) / 1e9
     vc_gbs = m["vcycle_bytes"] / (m["vcycle_ms"] * 1e-3) / 1e9
     out = {
@@ -173,15 +182,21 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f32 V-cycle / f64 CG",
+        "dtype": "f32 V-cycle (learned damping) / f64 CG",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: two-body contact, n={p.n} DOFs, m={p.m}, "
                                f"D log-uniform, rtol 1e-10",
                    "n": p.n, "m": p.m, "nnzb": p.nnzb,
-                   "mixed": {k: v for k, v in m.items()},
-                   "fp64_plain": {k: v for k, v in res["fp64"].items()},
-                   "speedup_mixed_vs_fp64": res["fp64"]["s_per_solve"] / m["s_per_solve"],
-                   "rel_diff_mixed_vs_fp64_solution": rel_mixed_vs_fp64,
+                   "mixed_learned": dict(m),
+                   "mixed_plain": dict(res["mixed"]),
+                   "fp64_plain": dict(res["fp64"]),
+                   "speedup_mixed_learned_vs_fp64_plain":
+                       res["fp64"]["s_per_solve"] / m["s_per_solve"],
+                   "speedup_mixed_plain_vs_fp64_plain":
+                       res["fp64"]["s_per_solve"] / res["mixed"]["s_per_solve"],
+                   "rel_diff_vs_fp64_solution": rel_vs_fp64,
+                   "learned_weights": "paper_2505_18576_amd/weights/smoother_ip.bin "
+                                      "(trained on interior-point steps 1-10, N=32)",
                    "vcycle_GBs_mixed": vc_gbs,
                    "vcycle_GBs_fp64": res["fp64"]["vcycle_bytes"]
                    / (res["fp64"]["vcycle_ms"] * 1e-3) / 1e9},

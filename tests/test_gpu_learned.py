@@ -117,3 +117,26 @@ def test_adam_step_matches_reference():
     ref = W.copy()
     ref[:1313] -= (1e-3 * g / (np.abs(g) + 1e-8)).astype(np.float32)
     assert np.allclose(Wd.cpu().numpy(), ref, rtol=1e-5, atol=1e-6)
+
+
+def test_trained_network_reduces_iterations_on_held_out_systems():
+    """The committed parameters (trained on interior-point steps 1-10) against plain
+    l1-Jacobi AMGF on held-out steps 13 and 19: fewer CG iterations, same solution."""
+    import os
+    from amgf_inputs import make_config
+    from paper_2505_18576_amd import AMGF
+    from paper_2505_18576_amd.train_smoother import load_weights
+    W = load_weights(os.path.join(os.path.dirname(os.path.dirname(__file__)),
+                                  "paper_2505_18576_amd", "weights", "smoother_ip.bin"))
+    for t in (13, 19):
+        p = make_config("C4", ip_step=t)
+        a = AMGF.from_problem(p)
+        b = AMGF.from_problem(p, mlp_weights=W)
+        xa, ia = a.pcg(p.b)
+        xb, ib = b.pcg(p.b)
+        print(f"t={t}: plain {ia.iterations}, learned {ib.iterations}")
+        assert ia.converged and ib.converged and ib.used_fallback == 0
+        assert ib.iterations <= 0.9 * ia.iterations
+        assert rel(xb.cpu().numpy(), xa.cpu().numpy()) < 1e-7
+        a.close()
+        b.close()

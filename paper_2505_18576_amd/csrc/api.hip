@@ -20,6 +20,7 @@ struct Level {
   DBuf<int> crows;              // node rows with a contact term (nonempty J^T rows)
   int ncrows = 0;
   BSR P, PT;                    // prolongator to the next level and its transpose
+  BSR C;                        // contact term J^T D J of this level (interface rows only)
   Graph G;                      // aggregation graph
   DBuf<int> agg, root;
   DBuf<double> d, w;
@@ -158,11 +159,8 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   j_to_node_blocks(c, m, nn, J_rowptr, J_col, J_val, L0->J);
   bsr_transpose(c, L0->J, L0->JT);
   L0->ncrows = nonempty_rows(c, L0->JT.rowptr.p, nn, L0->crows);
-  {
-    BSR C;
-    contact_operator(c, L0->J, L0->JT, h.D.p, C);
-    bsr_add(c, K, C, L0->A);
-  }
+  contact_operator(c, L0->J, L0->JT, h.D.p, L0->C);
+  bsr_add(c, K, L0->C, L0->A);
   // ---- levels
   DBuf<double> Rprev;
   Graph Gnext;
@@ -209,9 +207,11 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     bsr_transpose(c, N.J, N.JT);
     N.ncrows = nonempty_rows(c, N.JT.rowptr.p, N.nn, N.crows);
     {
-      BSR C;
-      contact_operator(c, N.J, N.JT, h.D.p, C);
-      bsr_add(c, N.K, C, N.A);
+      // C_{l+1} = P^T C_l P (= J_{l+1}^T D J_{l+1}), local to the interface rows
+      BSR CP;
+      spgemm(c, Lc.C, Lc.P, CP);
+      spgemm(c, Lc.PT, CP, N.C);
+      bsr_add(c, N.K, N.C, N.A);
     }
     nzsum += N.A.nnzb * 36;
     coarse_graph(c, Lc.G, Lc.agg.p, n_agg, moff.p, members.p, Gnext);

@@ -1,8 +1,8 @@
 // Dense FP64 SPD factorisation used for the coarsest level and the filter A_w.
 //
-// A = L L^T by a right-looking blocked Cholesky (64-wide panels, tiled DGEMM trailing
-// update), then Linv = L^{-1} by block rows, so that each later solve
-// x = Linv^T (Linv b) is two bandwidth-bound matrix-vector products instead of a
+// A = L L^T together with Linv = L^{-1} by recursive halving (all products are large
+// MFMA GEMMs; 64x64 leaves are factored in LDS by one wavefront), so that each later
+// solve x = Linv^T (Linv b) is two bandwidth-bound matrix-vector products instead of a
 // sequence of dependent triangular steps.
 #include "dense.h"
 
@@ -10,69 +10,14 @@ namespace amgf {
 
 constexpr int NB = 64;
 
-// ---------------------------------------------------------------- unblocked panel
-__global__ void __launch_bounds__(256) k_potf2(double* A, int lda, int k0, int kb, int* info) {
-  __shared__ double L[NB][NB + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kb * kb; e += 256) {
-    const int i = e / kb, j = e % kb;
-    L[i][j] = A[int64_t(k0 + i) * lda + k0 + j];
-  }
-  __syncthreads();
-  for (int j = 0; j < kb; ++j) {
-    if (tid == 0) {
-      const double p = L[j][j];
-      if (!(p > 0.0)) atomicOr(info, 1);
-      L[j][j] = sqrt(p > 0.0 ? p : 1.0);
-    }
-    __syncthreads();
-    for (int i = j + 1 + tid; i < kb; i += 256) L[i][j] /= L[j][j];
-    __syncthreads();
-    const int m = kb - j - 1;
-    for (int e = tid; e < m * m; e += 256) {
-      const int i = j + 1 + e / m, l = j + 1 + e % m;
-      if (l <= i) L[i][l] -= L[i][j] * L[l][j];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < kb * kb; e += 256) {
-    const int i = e / kb, j = e % kb;
-    A[int64_t(k0 + i) * lda + k0 + j] = (j <= i) ? L[i][j] : 0.0;
-  }
-}
-
-// rows below the panel: X L_kk^T = A_ik (forward substitution per row)
-__global__ void __launch_bounds__(256) k_trsm_panel(double* A, int lda, int n, int k0, int kb) {
-  __shared__ double L[NB][NB + 1];
-  for (int e = threadIdx.x; e < kb * kb; e += 256) {
-    const int i = e / kb, j = e % kb;
-    L[i][j] = A[int64_t(k0 + i) * lda + k0 + j];
-  }
-  __syncthreads();
-  const int r = k0 + kb + blockIdx.x * 256 + threadIdx.x;
-  if (r >= n) return;
-  double* row = A + int64_t(r) * lda + k0;
-  double x[NB];
-#pragma unroll
-  for (int j = 0; j < NB; ++j) x[j] = (j < kb) ? row[j] : 0.0;
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    if (j < kb) {
-      double s = x[j];
-#pragma unroll
-      for (int l = 0; l < j; ++l) s -= x[l] * L[j][l];
-      x[j] = s / L[j][j];
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < NB; ++j)
-    if (j < kb) row[j] = x[j];
-}
-
-// ---------------------------------------------------------------- tiled DGEMM
+// ---------------------------------------------------------------- tiled DGEMM on MFMA
 // C[M x N] = beta C + alpha A[M x K] op(B);  op(B) = B^T (B is N x K) or B (K x N).
-// 64x64 tiles, 256 threads, 4x4 outputs per thread.  lower_only skips tiles strictly
-// above the diagonal (row-block origin offset by diag_off).
+// A 256-thread workgroup owns a 64x64 tile of C; each wavefront owns a 32x32 quarter as
+// 2x2 tiles of v_mfma_f64_16x16x4f64 (operand lane l: A[l%16][l/16], B[l/16][l%16];
+// result lane l, register r: D[4r + l/16][l%16]).  K advances in steps of 16 staged in
+// LDS.  lower_only skips tiles strictly above the diagonal.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 template <bool TB>
 __global__ void __launch_bounds__(256) k_dgemm(int M, int N, int K, double alpha,
                                                const double* __restrict__ A, int lda,
@@ -81,66 +26,143 @@ __global__ void __launch_bounds__(256) k_dgemm(int M, int N, int K, double alpha
                                                int lower_only) {
   const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
   if (lower_only && bn > bm + 63) return;
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4];
+  __shared__ double As[64][17];     // [row][k]
+  __shared__ double Bs[16][65];     // [k][col]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;   // wave quarter of the tile
+  v4d acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += 16) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int e = threadIdx.x + 256 * t;     // 0..1023
-      const int kk = e & 15, rr = e >> 4;      // rr 0..63
+      const int e = tid + 256 * t;            // 0..1023
+      const int kk = e & 15, rr = e >> 4;     // A: 64 rows x 16 k, contiguous along k
       const int gr = bm + rr, gk = k0 + kk;
-      As[kk][rr] = (gr < M && gk < K) ? A[int64_t(gr) * lda + gk] : 0.0;
-      const int gc = bn + rr;
-      double bv = 0.0;
+      As[rr][kk] = (gr < M && gk < K) ? A[int64_t(gr) * lda + gk] : 0.0;
       if (TB) {
-        if (gc < N && gk < K) bv = B[int64_t(gc) * ldb + gk];
+        const int gc = bn + rr;
+        Bs[kk][rr] = (gc < N && gk < K) ? B[int64_t(gc) * ldb + gk] : 0.0;
       } else {
-        const int kk2 = e >> 6, cc = e & 63;   // coalesced along N for B (K x N)
-        const int gk2 = k0 + kk2, gc2 = bn + cc;
-        if (gk2 < K && gc2 < N) bv = B[int64_t(gk2) * ldb + gc2];
-        Bs[kk2][cc] = bv;
-        continue;
+        const int kb = e >> 6, cc = e & 63;   // B: 16 k x 64 cols, contiguous along cols
+        const int gkb = k0 + kb, gc = bn + cc;
+        Bs[kb][cc] = (gkb < K && gc < N) ? B[int64_t(gkb) * ldb + gc] : 0.0;
       }
-      Bs[kk][rr] = bv;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kq = ks * 4 + (lane >> 4);
+      double af[2], bf[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int a = 0; a < 2; ++a) af[a] = As[wr + a * 16 + (lane & 15)][kq];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+      for (int b = 0; b < 2; ++b) bf[b] = Bs[kq][wc + b * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = bm + ty + 16 * i;
-    if (r >= M) continue;
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int cidx = bn + tx + 16 * j;
-      if (cidx >= N) continue;
-      double* cp = C + int64_t(r) * ldc + cidx;
-      *cp = alpha * acc[i][j] + (beta == 0.0 ? 0.0 : beta * *cp);
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = bm + wr + a * 16 + 4 * r + (lane >> 4);
+        const int col = bn + wc + b * 16 + (lane & 15);
+        if (row < M && col < N) {
+          double* cp = C + int64_t(row) * ldc + col;
+          *cp = alpha * acc[a][b][r] + (beta == 0.0 ? 0.0 : beta * *cp);
+        }
+      }
+}
+
+// Same product with a 32x32 tile per 64-lane workgroup (2x2 MFMA tiles per wavefront):
+// four times as many workgroups, for products too small to fill the chip with 64x64.
+template <bool TB>
+__global__ void __launch_bounds__(64) k_dgemm32(int M, int N, int K, double alpha,
+                                                const double* __restrict__ A, int lda,
+                                                const double* __restrict__ B, int ldb,
+                                                double beta, double* __restrict__ C, int ldc,
+                                                int lower_only) {
+  const int bm = blockIdx.y * 32, bn = blockIdx.x * 32;
+  if (lower_only && bn > bm + 31) return;
+  __shared__ double As[32][17];
+  __shared__ double Bs[16][33];
+  const int lane = threadIdx.x;
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = lane + 64 * t;            // 0..511
+      const int kk = e & 15, rr = e >> 4;     // 32 rows x 16 k
+      const int gr = bm + rr, gk = k0 + kk;
+      As[rr][kk] = (gr < M && gk < K) ? A[int64_t(gr) * lda + gk] : 0.0;
+      if (TB) {
+        const int gc = bn + rr;
+        Bs[kk][rr] = (gc < N && gk < K) ? B[int64_t(gc) * ldb + gk] : 0.0;
+      } else {
+        const int kb = e >> 5, cc = e & 31;
+        const int gkb = k0 + kb, gc = bn + cc;
+        Bs[kb][cc] = (gkb < K && gc < N) ? B[int64_t(gkb) * ldb + gc] : 0.0;
+      }
     }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kq = ks * 4 + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) af[a] = As[a * 16 + (lane & 15)][kq];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bf[b] = Bs[kq][b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
   }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = bm + a * 16 + 4 * r + (lane >> 4);
+        const int col = bn + b * 16 + (lane & 15);
+        if (row < M && col < N) {
+          double* cp = C + int64_t(row) * ldc + col;
+          *cp = alpha * acc[a][b][r] + (beta == 0.0 ? 0.0 : beta * *cp);
+        }
+      }
 }
 
 void dgemm(Ctx& c, bool transB, int M, int N, int K, double alpha, const double* A, int lda,
            const double* B, int ldb, double beta, double* C, int ldc, bool lower_only) {
   if (M <= 0 || N <= 0) return;
+  if (int64_t((M + 63) / 64) * ((N + 63) / 64) < 512) {
+    const dim3 g((N + 31) / 32, (M + 31) / 32);
+    if (transB)
+      hipLaunchKernelGGL(k_dgemm32<true>, g, dim3(64), 0, c.s, M, N, K, alpha, A, lda, B, ldb,
+                         beta, C, ldc, int(lower_only));
+    else
+      hipLaunchKernelGGL(k_dgemm32<false>, g, dim3(64), 0, c.s, M, N, K, alpha, A, lda, B, ldb,
+                         beta, C, ldc, int(lower_only));
+    AMGF_LAUNCH_CHECK();
+    return;
+  }
   const dim3 g((N + 63) / 64, (M + 63) / 64);
   if (transB)
     hipLaunchKernelGGL(k_dgemm<true>, g, dim3(256), 0, c.s, M, N, K, alpha, A, lda, B, ldb,
@@ -151,67 +173,104 @@ void dgemm(Ctx& c, bool transB, int M, int N, int K, double alpha, const double*
   AMGF_LAUNCH_CHECK();
 }
 
-// ---------------------------------------------------------------- inverse of a diagonal block
-// X = L_ii^{-1} (lower triangular), one column per thread.
-__global__ void __launch_bounds__(64) k_trtri_diag(const double* L, int lda, int k0, int kb,
-                                                   double* X, int ldx) {
+// ---------------------------------------------------------------- recursive factorisation
+// Leaf (n <= 64): one wavefront; lane t keeps row t of the tile in registers (a tile
+// smaller than 64 is padded with the identity).  Step j broadcasts column j through
+// LDS and every lane updates its row; then lane t forms column t of L^{-1} by forward
+// substitution against L rows read (as broadcasts) from LDS.  Writes L (zero upper)
+// and L^{-1}.
+__global__ void __launch_bounds__(64) k_chol_leaf(double* A, double* Li, int ld, int n,
+                                                  int* info) {
+  __shared__ double colj[NB];
   __shared__ double Ls[NB][NB + 1];
-  for (int e = threadIdx.x; e < kb * kb; e += 64) {
-    const int i = e / kb, j = e % kb;
-    Ls[i][j] = L[int64_t(k0 + i) * lda + k0 + j];
-  }
+  const int t = threadIdx.x;
+  // coalesced load of the tile (identity padding beyond n)
+  for (int i = 0; i < NB; ++i)
+    Ls[i][t] = (i < n && t < n) ? A[int64_t(i) * ld + t] : (i == t ? 1.0 : 0.0);
   __syncthreads();
-  const int cidx = threadIdx.x;
-  if (cidx >= kb) return;
+  double row[NB];
+#pragma unroll
+  for (int l = 0; l < NB; ++l) row[l] = Ls[t][l];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    colj[t] = row[j];
+    __syncthreads();
+    const double p = colj[j];
+    if (t == 0 && !(p > 0.0)) atomicOr(info, 1);
+    const double dj = sqrt(p > 0.0 ? p : 1.0);
+    const double lj = (t > j) ? row[j] / dj : dj;
+    if (t >= j) row[j] = lj;
+    __syncthreads();
+    colj[t] = lj;
+    __syncthreads();
+    if (t > j) {
+#pragma unroll
+      for (int l = j + 1; l < NB; ++l)
+        if (l <= t) row[l] -= lj * colj[l];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int l = 0; l < NB; ++l) Ls[t][l] = (l <= t) ? row[l] : 0.0;
+  __syncthreads();
+  for (int i = 0; i < n; ++i)
+    if (t < n) A[int64_t(i) * ld + t] = Ls[i][t];
   double x[NB];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) x[i] = 0.0;
-#pragma unroll
   for (int i = 0; i < NB; ++i) {
-    if (i < kb && i >= cidx) {
-      double s = (i == cidx) ? 1.0 : 0.0;
+    double s = (i == t) ? 1.0 : 0.0;
 #pragma unroll
-      for (int l = 0; l < i; ++l) s -= Ls[i][l] * x[l];
-      x[i] = s / Ls[i][i];
-    }
+    for (int l = 0; l < i; ++l) s -= Ls[i][l] * x[l];
+    x[i] = (i >= t) ? s / Ls[i][i] : 0.0;
   }
+  __syncthreads();
 #pragma unroll
-  for (int i = 0; i < NB; ++i)
-    if (i < kb) X[int64_t(k0 + i) * ldx + k0 + cidx] = x[i];
+  for (int i = 0; i < NB; ++i) Ls[i][t] = x[i];     // column t of L^{-1}
+  __syncthreads();
+  for (int i = 0; i < n; ++i)
+    if (t < n) Li[int64_t(i) * ld + t] = Ls[i][t];
+}
+
+__global__ void k_copy2d(int rows, int cols, const double* __restrict__ S, int lds,
+                         double* __restrict__ D, int ldd) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= int64_t(rows) * cols) return;
+  const int i = int(e / cols), j = int(e % cols);
+  D[int64_t(i) * ldd + j] = S[int64_t(i) * lds + j];
+}
+
+// [A11 . ; A21 A22] = L L^T with Linv = L^{-1}, both in place in row-major n x n blocks of
+// leading dimension ld:  L11 = chol(A11); L21 = A21 L11^{-T}; L22 = chol(A22 - L21 L21^T);
+// Linv21 = -Linv22 (L21 Linv11).  Every product is one large GEMM.
+static void chol_inv_rec(Ctx& c, double* A, double* Li, int n, int ld, double* T) {
+  if (n <= NB) {
+    hipLaunchKernelGGL(k_chol_leaf, dim3(1), dim3(64), 0, c.s, A, Li, ld, n, c.flag.p);
+    AMGF_LAUNCH_CHECK();
+    return;
+  }
+  const int n1 = ((n / 2 + NB - 1) / NB) * NB, n2 = n - n1;
+  double* A21 = A + int64_t(n1) * ld;
+  double* A22 = A21 + n1;
+  double* Li21 = Li + int64_t(n1) * ld;
+  double* Li22 = Li21 + n1;
+  chol_inv_rec(c, A, Li, n1, ld, T);
+  dgemm(c, true, n2, n1, n1, 1.0, A21, ld, Li, ld, 0.0, T, n1, false);       // L21
+  hipLaunchKernelGGL(k_copy2d, dim3(grid_for(int64_t(n2) * n1, 256)), dim3(256), 0, c.s, n2,
+                     n1, T, n1, A21, ld);
+  dgemm(c, true, n2, n2, n1, -1.0, A21, ld, A21, ld, 1.0, A22, ld, true);     // A22 -= L21 L21^T
+  chol_inv_rec(c, A22, Li22, n2, ld, T);
+  dgemm(c, false, n2, n1, n1, 1.0, A21, ld, Li, ld, 0.0, T, n1, false);      // L21 Linv11
+  dgemm(c, false, n2, n1, n2, -1.0, Li22, ld, T, n1, 0.0, Li21, ld, false);  // Linv21
 }
 
 void dense_cholesky_inverse(Ctx& c, double* A, int n, DBuf<double>& Linv) {
   AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int kb = std::min(NB, n - k0);
-    hipLaunchKernelGGL(k_potf2, dim3(1), dim3(256), 0, c.s, A, n, k0, kb, c.flag.p);
-    const int rest = n - k0 - kb;
-    if (rest > 0) {
-      hipLaunchKernelGGL(k_trsm_panel, dim3((rest + 255) / 256), dim3(256), 0, c.s, A, n, n, k0,
-                         kb);
-      // trailing lower update: A22 -= L21 L21^T
-      double* A21 = A + int64_t(k0 + kb) * n + k0;
-      double* A22 = A + int64_t(k0 + kb) * n + k0 + kb;
-      dgemm(c, true, rest, rest, kb, -1.0, A21, n, A21, n, 1.0, A22, n, true);
-    }
-    AMGF_LAUNCH_CHECK();
-  }
-  AMGF_REQUIRE(d2h_scalar(c.flag.p, c.s) == 0, AMGF_ENOTSPD,
-               "dense Cholesky: non-positive pivot (matrix not SPD)");
-  // Linv by block rows: Linv_ii = inv(L_ii); Linv[i, :i] = -Linv_ii (L[i, :i] Linv[:i, :i])
   Linv.alloc(size_t(n) * n);
   AMGF_HIP(hipMemsetAsync(Linv.p, 0, Linv.bytes(), c.s));
-  DBuf<double> T(size_t(NB) * n);
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int kb = std::min(NB, n - k0);
-    hipLaunchKernelGGL(k_trtri_diag, dim3(1), dim3(64), 0, c.s, A, n, k0, kb, Linv.p, n);
-    AMGF_LAUNCH_CHECK();
-    if (k0 > 0) {
-      dgemm(c, false, kb, k0, k0, 1.0, A + int64_t(k0) * n, n, Linv.p, n, 0.0, T.p, k0, false);
-      dgemm(c, false, kb, k0, kb, -1.0, Linv.p + int64_t(k0) * n + k0, n, T.p, k0, 0.0,
-            Linv.p + int64_t(k0) * n, n, false);
-    }
-  }
+  DBuf<double> T(size_t(n) * ((n + 1) / 2 + NB));
+  chol_inv_rec(c, A, Linv.p, n, n, T.p);
+  AMGF_REQUIRE(d2h_scalar(c.flag.p, c.s) == 0, AMGF_ENOTSPD,
+               "dense Cholesky: non-positive pivot (matrix not SPD)");
 }
 
 // ---------------------------------------------------------------- solves

@@ -143,18 +143,58 @@ __global__ void k_fill_keys(const int* __restrict__ keys, int n, const int* __re
   const int k = keys[i];
   perm[off[k] + atomicAdd(&cursor[k], 1)] = i;
 }
-// one wavefront per segment: rank sort of distinct values (ascending)
+constexpr int SMALL_SEGMENT = 2048;
+
+// one wavefront per segment: rank sort of distinct values (ascending); segments longer
+// than SMALL_SEGMENT are left to k_bitonic_segments
 __global__ void k_segment_sort(const int* __restrict__ off, int nseg, const int* __restrict__ in,
                                int* __restrict__ out) {
   const int seg = blockIdx.x;
   if (seg >= nseg) return;
   const int a = off[seg], b = off[seg + 1];
+  if (b - a > SMALL_SEGMENT) return;
   for (int j = a + threadIdx.x; j < b; j += blockDim.x) {
     const int v = in[j];
     int rank = 0;
     for (int i = a; i < b; ++i) rank += in[i] < v;
     out[a + rank] = v;
   }
+}
+
+__global__ void k_max_segment(const int* __restrict__ off, int nseg, int* __restrict__ mx) {
+  const int seg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (seg < nseg) atomicMax(mx, off[seg + 1] - off[seg]);
+}
+
+// one 1024-thread workgroup per long segment: bitonic sort in a padded scratch region
+__global__ void __launch_bounds__(1024) k_bitonic_segments(const int* __restrict__ list,
+                                                           const int* __restrict__ off,
+                                                           const int64_t* __restrict__ soff,
+                                                           const int* __restrict__ in,
+                                                           int* __restrict__ out,
+                                                           int* __restrict__ scratch) {
+  const int seg = list[blockIdx.x];
+  const int a = off[seg], s = off[seg + 1] - a;
+  int P = 1;
+  while (P < s) P <<= 1;
+  int* buf = scratch + soff[blockIdx.x];
+  for (int i = threadIdx.x; i < P; i += 1024) buf[i] = i < s ? in[a + i] : 0x7fffffff;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += 1024) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int x = buf[i], y = buf[ixj];
+          if (((i & k) == 0) ? (x > y) : (x < y)) {
+            buf[i] = y;
+            buf[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < s; i += 1024) out[a + i] = buf[i];
 }
 
 void group_by_key(Ctx& c, const int* keys, int n, int nkeys, DBuf<int>& offsets,
@@ -175,6 +215,34 @@ void group_by_key(Ctx& c, const int* keys, int n, int nkeys, DBuf<int>& offsets,
   hipLaunchKernelGGL(k_segment_sort, dim3(nkeys), dim3(64), 0, c.s, offsets.p, nkeys, tmp.p,
                      perm.p);
   AMGF_LAUNCH_CHECK();
+  DBuf<int> mx(1);
+  AMGF_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), c.s));
+  hipLaunchKernelGGL(k_max_segment, dim3(grid_for(nkeys, 256)), dim3(256), 0, c.s, offsets.p,
+                     nkeys, mx.p);
+  if (d2h_scalar(mx.p, c.s) <= SMALL_SEGMENT) return;
+  // long segments: list them on the host and bitonic-sort each in one workgroup
+  std::vector<int> off = d2h(offsets.p, size_t(nkeys) + 1, c.s);
+  std::vector<int> big;
+  std::vector<int64_t> soff(1, 0);
+  for (int k = 0; k < nkeys; ++k) {
+    const int s = off[k + 1] - off[k];
+    if (s > SMALL_SEGMENT) {
+      int P = 1;
+      while (P < s) P <<= 1;
+      big.push_back(k);
+      soff.push_back(soff.back() + P);
+    }
+  }
+  DBuf<int> dlist(big.size()), scratch(soff.back());
+  DBuf<int64_t> dsoff(soff.size());
+  AMGF_HIP(hipMemcpyAsync(dlist.p, big.data(), sizeof(int) * big.size(), hipMemcpyHostToDevice,
+                          c.s));
+  AMGF_HIP(hipMemcpyAsync(dsoff.p, soff.data(), sizeof(int64_t) * soff.size(),
+                          hipMemcpyHostToDevice, c.s));
+  hipLaunchKernelGGL(k_bitonic_segments, dim3(big.size()), dim3(1024), 0, c.s, dlist.p, offsets.p,
+                     dsoff.p, tmp.p, perm.p, scratch.p);
+  AMGF_LAUNCH_CHECK();
+  AMGF_HIP(hipStreamSynchronize(c.s));
 }
 
 // ======================================================================================
@@ -219,9 +287,9 @@ constexpr int HS = 2048;                 // hash slots per row
 constexpr int HS_MAX_UNIQUE = 1536;      // capacity before the row is rejected
 
 __device__ __forceinline__ void hs_insert(int* table, int* list, int* cnt, int key,
-                                          bool fill, int* flag) {
-  unsigned h = (unsigned(key) * 2654435761u) & (HS - 1);
-  for (int probe = 0; probe < HS; ++probe) {
+                                          bool fill, int* flag, unsigned mask) {
+  unsigned h = (unsigned(key) * 2654435761u) & mask;
+  for (unsigned probe = 0; probe <= mask; ++probe) {
     const int old = atomicCAS(&table[h], -1, key);
     if (old == -1) {
       const int pos = atomicAdd(cnt, 1);
@@ -233,7 +301,7 @@ __device__ __forceinline__ void hs_insert(int* table, int* list, int* cnt, int k
       return;
     }
     if (old == key) return;
-    h = (h + 1) & (HS - 1);
+    h = (h + 1) & mask;
   }
   atomicOr(flag, 2);
 }
@@ -252,11 +320,19 @@ __global__ void __launch_bounds__(64) k_union(int nrows, const int* __restrict__
   __shared__ int cnt;
   const int r = blockIdx.x;
   if (r >= nrows) return;
-  if (row_mask && !row_mask[r]) {
+  if ((row_mask && !row_mask[r]) || rp1[r] == rp1[r + 1]) {
     if (!fill && threadIdx.x == 0) counts[r] = 0;
     return;
   }
-  for (int i = threadIdx.x; i < HS; i += 64) table[i] = -1;
+  // table size: next power of two >= 2 x (number of candidates), at most HS
+  int bound = 0;
+  for (int t = rp1[r] + threadIdx.x; t < rp1[r + 1]; t += 64)
+    bound += rp2 ? rp2[col1[t] + 1] - rp2[col1[t]] : 1;
+  bound = wave_sum(bound);
+  unsigned ts = 64;
+  while (ts < 2u * unsigned(bound) && ts < unsigned(HS)) ts <<= 1;
+  const unsigned mask = ts - 1;
+  for (int i = threadIdx.x; i < int(ts); i += 64) table[i] = -1;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
   for (int t = rp1[r] + threadIdx.x; t < rp1[r + 1]; t += 64) {
@@ -266,12 +342,12 @@ __global__ void __launch_bounds__(64) k_union(int nrows, const int* __restrict__
         int cand = col2[u];
         if (map) cand = map[cand];
         if (cand < 0 || (exclude_diag && cand == r)) continue;
-        hs_insert(table, list, &cnt, cand, fill, flag);
+        hs_insert(table, list, &cnt, cand, fill, flag, mask);
       }
     } else {
       int cand = map ? map[mid] : mid;
       if (cand < 0 || (exclude_diag && cand == r)) continue;
-      hs_insert(table, list, &cnt, cand, fill, flag);
+      hs_insert(table, list, &cnt, cand, fill, flag, mask);
     }
   }
   __syncthreads();
@@ -331,14 +407,29 @@ __global__ void k_merge_count(int nrows, const int* __restrict__ ra, const int* 
   counts[r] = n;
 }
 
-__global__ void k_merge_fill(int nrows, int bsz, const int* __restrict__ ra,
-                             const int* __restrict__ ca, const double* __restrict__ va,
-                             const int* __restrict__ rb, const int* __restrict__ cb,
-                             const double* __restrict__ vb, const int* __restrict__ rc,
-                             int* __restrict__ cc, double* __restrict__ vc) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// one wavefront per row: rows without entries of B are copied block-parallel (the
+// common case), rows with both are merged by lane 0
+__global__ void __launch_bounds__(256) k_merge_fill(int nrows, int bsz, const int* __restrict__ ra,
+                                                    const int* __restrict__ ca,
+                                                    const double* __restrict__ va,
+                                                    const int* __restrict__ rb,
+                                                    const int* __restrict__ cb,
+                                                    const double* __restrict__ vb,
+                                                    const int* __restrict__ rc,
+                                                    int* __restrict__ cc,
+                                                    double* __restrict__ vc) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (r >= nrows) return;
-  int i = ra[r], ie = ra[r + 1], j = rb[r], je = rb[r + 1], o = rc[r];
+  const int i0 = ra[r], ie = ra[r + 1], j0 = rb[r], je = rb[r + 1], o0 = rc[r];
+  if (j0 == je) {
+    for (int k = lane; k < ie - i0; k += 64) cc[o0 + k] = ca[i0 + k];
+    const int64_t nv = int64_t(ie - i0) * bsz;
+    for (int64_t e = lane; e < nv; e += 64) vc[int64_t(o0) * bsz + e] = va[int64_t(i0) * bsz + e];
+    return;
+  }
+  if (lane != 0) return;
+  int i = i0, j = j0, o = o0;
   while (i < ie || j < je) {
     double* d = vc + int64_t(o) * bsz;
     if (j >= je || (i < ie && ca[i] < cb[j])) {
@@ -376,7 +467,7 @@ void bsr_add(Ctx& c, const BSR& A, const BSR& B, BSR& C) {
   C.col.alloc(std::max<int64_t>(C.nnzb, 1));
   C.val.alloc(std::max<int64_t>(C.nnzb, 1) * C.bsz());
   if (A.nrows)
-    hipLaunchKernelGGL(k_merge_fill, dim3(grid_for(A.nrows, 256)), dim3(256), 0, c.s,
+    hipLaunchKernelGGL(k_merge_fill, dim3(grid_for(A.nrows, 4)), dim3(256), 0, c.s,
                        A.nrows, int(A.bsz()), A.rowptr.p, A.col.p, A.val.p, B.rowptr.p,
                        B.col.p, B.val.p, C.rowptr.p, C.col.p, C.val.p);
   AMGF_LAUNCH_CHECK();

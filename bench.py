@@ -202,7 +202,7 @@ def main():
                    / (res["fp64"]["vcycle_ms"] * 1e-3) / 1e9},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "level-0 fused pre-smooth SpMV (FP32 values, 3x3 BSR)"},
+                     "kernel": "level-0 fused pre-smooth SpMV (FP32 values, 3x3 blocks, sliced ELL)"},
     }
     if not args.no_cpu_baseline:
         n_s, t_setup, t_it = cpu_baseline(args.cpu_sample, args.cpu_iters)

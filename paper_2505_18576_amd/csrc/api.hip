@@ -284,8 +284,9 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     Level& L = *h.lev[l];
     const int64_t n = L.n();
     L.vb.alloc(n); L.vx.alloc(n); L.vr.alloc(n); L.vxn.alloc(n);
+    if (l == 0) bsr_build_sell(c, L.K, true, h.mixed());
     if (h.mixed()) {
-      to_fp32(c, L.K);
+      if (l != 0) to_fp32(c, L.K);
       if (L.P.nnzb) { to_fp32(c, L.P); to_fp32(c, L.PT); }
       L.w32.alloc(n);
       cast_d2f(c, L.w.p, L.w32.p, n);

@@ -18,6 +18,10 @@ template <class T>
 void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, const T* b,
               const T* w, T* xo);
 
+// Build the sliced-ELL copy (FP64 values when fp64, FP32 values when fp32) of a 3x3
+// BSR matrix; bsr_spmv then reads it in place of the BSR arrays.
+void bsr_build_sell(Ctx& c, BSR& A, bool fp64, bool fp32);
+
 // contact term of a level over its contact node rows (crows, ncrows):
 // t = D.(J x) then, per mode,
 //   CT_SUB_RES:  y -= J^T t          (residual update)

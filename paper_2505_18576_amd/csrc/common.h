@@ -75,6 +75,13 @@ struct BSR {
   DBuf<int> rowptr, col;
   DBuf<double> val;
   DBuf<float> val32;       // FP32 copy used by the mixed-precision V-cycle
+  // Sliced-ELL copy of a 3x3 matrix for the apply phase (built by bsr_build_sell):
+  // slices of 64 block rows, each padded to its longest row.  Slot j of slice s holds
+  // the column ids at sell_col[sell_off[s] + 64 j + i] and entry (p,q) of row i's block
+  // at sell_val[9 (sell_off[s] + 64 j) + 64 (3p+q) + i]; padding has value 0.
+  DBuf<int> sell_off, sell_col;
+  DBuf<double> sell_val;
+  DBuf<float> sell_val32;
   size_t bsz() const { return size_t(br) * bc; }
 };
 

@@ -29,6 +29,8 @@ def parse():
     ap.add_argument("--cpu-sample", default="C2")
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--reps", type=int, default=30)
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for hardware counter collection, prints no JSON")
     return ap.parse_args()
 
 
@@ -69,6 +71,33 @@ def smoother_bytes(h, vbytes):
     nn, bs, nnzK = int(s[0]), int(s[1]), int(s[6])
     n = nn * bs
     return nnzK * (bs * bs * vbytes + 4) + (nn + 1) * 4 + 4 * n * vbytes
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "presmooth_sell3_f32_C5_counters.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2505_18576_amd", "csrc", "apply.hip")
+
+
+def measured_traffic():
+    """HBM bytes per pre-smooth launch from the committed FETCH_SIZE / WRITE_SIZE summary,
+    each scaled by the same counter's reading for a plain copy of known size; None when
+    the summary is missing or the kernel source changed after the counters were taken."""
+    import hashlib
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    with open(KERNEL_SRC, "rb") as f:
+        src = hashlib.sha256(f.read()).hexdigest()
+    if kv.get("kernel_source_sha256") != src:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(name, iters):
@@ -121,11 +150,28 @@ def main():
     wpath = os.path.join(ROOT, "paper_2505_18576_amd", "weights", "smoother_ip.bin")
     W = load_weights(wpath)
 
-    def solve(precision, weights):
+    def solve(precision, weights, live=False):
         h = AMGF(p.n_nodes, d["K_rowptr"], d["K_col"], d["K_val"], d["J_rowptr"], d["J_col"],
                  d["J_val"], d["D"], d["coords"], precision=precision, mlp_weights=weights)
+        if live:   # event pairs around every level-0 pre-smooth launch of this solve
+            h.profile_start(b.K_PRESMOOTH, 1000)
         x, info = h.pcg(bvec)
         return h, x, info
+
+    if args.counters:
+        # short run for rocprofv3 --pmc: one mixed+learned setup, a few pre-smooth
+        # launches, and a plain 1 GiB device copy that calibrates the byte counters
+        h = AMGF(p.n_nodes, d["K_rowptr"], d["K_col"], d["K_val"], d["J_rowptr"], d["J_col"],
+                 d["J_val"], d["D"], d["coords"], precision=b.MIXED_FP32, mlp_weights=W)
+        h.time_kernel(b.K_PRESMOOTH, 5)
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        h.close()
+        log("counter probe done")
+        return
 
     res = {}
     for mode, prec, weights in (("fp64", b.FP64, None), ("mixed", b.MIXED_FP32, None),
@@ -136,12 +182,16 @@ def main():
             h.close()
         torch.cuda.synchronize()
         times = []
+        live_n, live_ms = 0, 0.0
         for s in range(args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            h, x, info = solve(prec, weights)
+            h, x, info = solve(prec, weights, live=True)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
+            cnt, avg = h.profile_read()
+            live_ms = (live_ms * live_n + avg * cnt) / max(1, live_n + cnt)
+            live_n += cnt
             log(f"{mode} step {s}: {times[-1]:.3f}s, {info.iterations} it, "
                 f"solve {info.ms_solve:.1f} ms, rel prec res {info.rel_prec_res:.2e}, "
                 f"true res {info.rel_true_res:.2e}, levels {info.n_levels}, "
@@ -157,11 +207,13 @@ def main():
                          used_fallback=int(info.used_fallback),
                          rel_true_res=float(info.rel_true_res), n_levels=int(info.n_levels),
                          op_complexity=float(info.op_complexity),
+                         smoother_ms_live=live_ms, smoother_launches_live=live_n,
                          smoother_ms=ms_pre, smoother_bytes=smoother_bytes(h, vb),
                          vcycle_ms=ms_vc, vcycle_bytes=vcycle_bytes(h, vb), operator_ms=ms_op,
                          x=x)
         h.close()
-        log(f"{mode}: pre-smooth {ms_pre:.3f} ms, V-cycle {ms_vc:.3f} ms, operator {ms_op:.3f} ms")
+        log(f"{mode}: pre-smooth live {live_ms:.3f} ms over {live_n} launches, isolated "
+            f"{ms_pre:.3f} ms, V-cycle {ms_vc:.3f} ms, operator {ms_op:.3f} ms")
     xd = res["fp64"].pop("x")
     rel_vs_fp64 = {}
     for k in ("mixed", "mixed_learned"):
@@ -169,7 +221,7 @@ def main():
         rel_vs_fp64[k] = float(torch.linalg.norm(xk - xd) / torch.linalg.norm(xd))
 
     m = res["mixed_learned"]
-    ach = m["smoother_bytes"] / (m["smoother_ms"] * 1e-3) / 1e9
+    ach = m["smoother_bytes"] / (m["smoother_ms_live"] * 1e-3) / 1e9
     vc_gbs = m["vcycle_bytes"] / (m["vcycle_ms"] * 1e-3) / 1e9
     out = {
         "metric": "PCG+AMGF time-to-rtol1e-10 & V-cycle HBM GB/s: mixed+learned vs FP64 plain",
@@ -201,7 +253,9 @@ def main():
                    "vcycle_GBs_fp64": res["fp64"]["vcycle_bytes"]
                    / (res["fp64"]["vcycle_ms"] * 1e-3) / 1e9},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "algorithmic_bytes": m["smoother_bytes"],
+                     "launch_ms": m["smoother_ms_live"],
                      "kernel": "level-0 fused pre-smooth SpMV (FP32 values, 3x3 blocks, sliced ELL)"},
     }
     if not args.no_cpu_baseline:

@@ -192,6 +192,18 @@ amgf_status amgf_adam_step(float* W, const double* grad, float* m1, float* m2, i
 enum { AMGF_K_PRESMOOTH = 0, AMGF_K_POSTSMOOTH = 1, AMGF_K_VCYCLE = 2, AMGF_K_OPERATOR = 3 };
 amgf_status amgf_time_kernel(amgf_handle h, int32_t which, int32_t reps, void* stream,
                              double* avg_ms);
+
+/* Live timing inside solves.  After amgf_profile_start(h, which, max_launches) with
+ * which = AMGF_K_PRESMOOTH or AMGF_K_POSTSMOOTH, every launch of that level-0 kernel
+ * made by later amgf_apply / amgf_vcycle / amgf_pcg calls is bracketed by a pair of
+ * hipEvents recorded on the solve stream (the first max_launches launches; later ones
+ * are not timed).  which < 0 switches timing off.  Events are owned by the handle.
+ * amgf_profile_read waits for the recorded events, stores the number of timed launches
+ * in *count and their mean duration (milliseconds) in *avg_ms (host pointers), and
+ * clears the record.  EINVAL for a null handle or pointer, an unknown kernel or
+ * max_launches <= 0.                                                                  */
+amgf_status amgf_profile_start(amgf_handle h, int32_t which, int32_t max_launches);
+amgf_status amgf_profile_read(amgf_handle h, int32_t* count, double* avg_ms);
 amgf_status amgf_query(amgf_handle h, int32_t level, int32_t which, void* host_dst,
                        size_t bytes);
 

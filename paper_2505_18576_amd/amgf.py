@@ -24,7 +24,8 @@ MLP_NPARAM, MLP_NTOTAL = 1313, 1325
 ABI_FUNCTIONS = ["amgf_default_options", "amgf_setup", "amgf_apply", "amgf_vcycle",
                  "amgf_operator_apply", "amgf_pcg", "amgf_destroy", "amgf_status_string",
                  "amgf_last_error", "amgf_num_levels", "amgf_query", "amgf_time_kernel",
-                 "amgf_set_mlp", "amgf_mlp_loss_grad", "amgf_adam_step"]
+                 "amgf_set_mlp", "amgf_mlp_loss_grad", "amgf_adam_step",
+                 "amgf_profile_start", "amgf_profile_read"]
 K_PRESMOOTH, K_POSTSMOOTH, K_VCYCLE, K_OPERATOR = range(4)
 
 
@@ -91,6 +92,10 @@ def load_library(path=LIB_PATH):
     L.amgf_mlp_loss_grad.restype = ctypes.c_int
     L.amgf_adam_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp]
     L.amgf_adam_step.restype = ctypes.c_int
+    L.amgf_profile_start.argtypes = [vp, i32, i32]
+    L.amgf_profile_start.restype = ctypes.c_int
+    L.amgf_profile_read.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    L.amgf_profile_read.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -260,6 +265,18 @@ class AMGF:
         _check(self.L.amgf_time_kernel(self.h, which, reps, _stream(), ctypes.byref(ms)),
                "amgf_time_kernel")
         return ms.value
+
+    def profile_start(self, which, max_launches=100000):
+        """Time every later launch of a level-0 smoother kernel inside solves (hipEvents on
+        the solve stream); which < 0 switches it off."""
+        _check(self.L.amgf_profile_start(self.h, which, max_launches), "amgf_profile_start")
+
+    def profile_read(self):
+        """(number of timed launches, mean milliseconds per launch); clears the record."""
+        cnt, ms = ctypes.c_int32(), ctypes.c_double()
+        _check(self.L.amgf_profile_read(self.h, ctypes.byref(cnt), ctypes.byref(ms)),
+               "amgf_profile_read")
+        return cnt.value, ms.value
 
     def set_mlp(self, W):
         """Damping from the MLP with parameters W (1325 values), or theta = 1 for None."""

@@ -67,6 +67,16 @@ struct Handle {
   double op_complexity = 1.0;
   DBuf<float> mlpW;             // device copy of the MLP parameters (learned smoother)
   bool learned = false;
+  // live timing of one level-0 kernel class inside solves: event pairs on the solve stream
+  int prof_which = -1;
+  std::vector<hipEvent_t> prof_ev;
+  size_t prof_used = 0;
+  bool prof_open = false;
+  Handle() = default;
+  Handle(const Handle&) = delete;
+  ~Handle() {
+    for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+  }
   bool mixed() const { return opt.precision == AMGF_MIXED_FP32; }
   int64_t n() const { return int64_t(n_nodes) * 3; }
 };
@@ -307,6 +317,18 @@ static void coarse_solve(Handle& h, const double* b, double* x) {
   h.coarse.solve(h.ctx, b, x);
 }
 
+// bracket the launches of kernel class `which` (level 0) when live timing is on
+static void prof_begin(Handle& h, int which) {
+  if (h.prof_which != which || h.prof_used + 2 > h.prof_ev.size()) return;
+  AMGF_HIP(hipEventRecord(h.prof_ev[h.prof_used++], h.ctx.s));
+  h.prof_open = true;
+}
+static void prof_end(Handle& h) {
+  if (!h.prof_open) return;
+  AMGF_HIP(hipEventRecord(h.prof_ev[h.prof_used++], h.ctx.s));
+  h.prof_open = false;
+}
+
 // FP64 V(1,1) on level l: L.vb -> L.vx
 static void vcycle64(Handle& h, size_t l) {
   Ctx& c = h.ctx;
@@ -316,13 +338,17 @@ static void vcycle64(Handle& h, size_t l) {
     return;
   }
   Level& N = *h.lev[l + 1];
+  if (l == 0) prof_begin(h, AMGF_K_PRESMOOTH);
   bsr_spmv<double>(c, SPMV_PRE, L.K, L.K.val.p, nullptr, L.vr.p, L.vb.p, L.w.p, L.vx.p);
+  prof_end(h);
   contact_apply<double, double>(c, CT_SUB_RES, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.vx.p,
                                 h.t.p, L.vr.p, nullptr);
   bsr_spmv<double>(c, SPMV_Y, L.PT, L.PT.val.p, L.vr.p, N.vb.p, nullptr, nullptr, nullptr);
   vcycle64(h, l + 1);
   bsr_spmv<double>(c, SPMV_ADD, L.P, L.P.val.p, N.vx.p, L.vx.p, nullptr, nullptr, nullptr);
+  if (l == 0) prof_begin(h, AMGF_K_POSTSMOOTH);
   bsr_spmv<double>(c, SPMV_POST, L.K, L.K.val.p, L.vx.p, nullptr, L.vb.p, L.w.p, L.vxn.p);
+  prof_end(h);
   contact_apply<double, double>(c, CT_SUB_W, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.vx.p,
                                 h.t.p, L.vxn.p, L.w.p);
   std::swap(L.vx, L.vxn);
@@ -339,13 +365,17 @@ static void vcycle32(Handle& h, size_t l) {
     return;
   }
   Level& N = *h.lev[l + 1];
+  if (l == 0) prof_begin(h, AMGF_K_PRESMOOTH);
   bsr_spmv<float>(c, SPMV_PRE, L.K, L.K.val32.p, nullptr, L.fr.p, L.fb.p, L.w32.p, L.fx.p);
+  prof_end(h);
   contact_apply<float, float>(c, CT_SUB_RES, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.fx.p,
                               h.t.p, L.fr.p, nullptr);
   bsr_spmv<float>(c, SPMV_Y, L.PT, L.PT.val32.p, L.fr.p, N.fb.p, nullptr, nullptr, nullptr);
   vcycle32(h, l + 1);
   bsr_spmv<float>(c, SPMV_ADD, L.P, L.P.val32.p, N.fx.p, L.fx.p, nullptr, nullptr, nullptr);
+  if (l == 0) prof_begin(h, AMGF_K_POSTSMOOTH);
   bsr_spmv<float>(c, SPMV_POST, L.K, L.K.val32.p, L.fx.p, nullptr, L.fb.p, L.w32.p, L.fxn.p);
+  prof_end(h);
   contact_apply<float, float>(c, CT_SUB_W, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.fx.p,
                               h.t.p, L.fxn.p, L.w32.p);
   std::swap(L.fx, L.fxn);
@@ -867,6 +897,44 @@ void amgf_destroy(amgf_handle hd) {
   if (!hd) return;
   (void)hipStreamSynchronize(hd->h.ctx.s);
   delete hd;
+}
+
+amgf_status amgf_profile_start(amgf_handle hd, int32_t which, int32_t max_launches) {
+  if (!hd) return AMGF_EINVAL;
+  if (which >= 0 && (which > AMGF_K_POSTSMOOTH || max_launches <= 0)) return AMGF_EINVAL;
+  return guard([&]() -> amgf_status {
+    Handle& h = hd->h;
+    AMGF_HIP(hipStreamSynchronize(h.ctx.s));
+    for (hipEvent_t e : h.prof_ev) AMGF_HIP(hipEventDestroy(e));
+    h.prof_ev.clear();
+    h.prof_used = 0;
+    h.prof_open = false;
+    h.prof_which = which;
+    if (which < 0) return AMGF_OK;
+    h.prof_ev.resize(size_t(max_launches) * 2);
+    for (hipEvent_t& e : h.prof_ev) AMGF_HIP(hipEventCreate(&e));
+    return AMGF_OK;
+  });
+}
+
+amgf_status amgf_profile_read(amgf_handle hd, int32_t* count, double* avg_ms) {
+  if (!hd || !count || !avg_ms) return AMGF_EINVAL;
+  return guard([&]() -> amgf_status {
+    Handle& h = hd->h;
+    *count = 0;
+    *avg_ms = 0.0;
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < h.prof_used; k += 2) {
+      AMGF_HIP(hipEventSynchronize(h.prof_ev[k + 1]));
+      float ms = 0.f;
+      AMGF_HIP(hipEventElapsedTime(&ms, h.prof_ev[k], h.prof_ev[k + 1]));
+      tot += ms;
+      ++*count;
+    }
+    if (*count) *avg_ms = tot / *count;
+    h.prof_used = 0;
+    return AMGF_OK;
+  });
 }
 
 int32_t amgf_num_levels(amgf_handle hd) { return hd ? int32_t(hd->h.lev.size()) : 0; }

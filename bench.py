@@ -38,7 +38,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def vcycle_bytes(h, vbytes):
+def vcycle_bytes(h, vbytes, k0bytes=None):
     """Algorithmic HBM bytes of one V(1,1) (values of `vbytes` bytes, int32 indices).
 
     Per non-coarsest level: pre-smooth (K read, b and w read, x and r written),
@@ -56,7 +56,8 @@ def vcycle_bytes(h, vbytes):
         if l == nl - 1:
             total += 2 * (n * n // 2) * 8 + 4 * n * 8
             break
-        kbytes = nnzK * (bs * bs * vbytes + 4) + (nn + 1) * 4
+        kv = k0bytes if (l == 0 and k0bytes) else vbytes
+        kbytes = nnzK * (bs * bs * kv + 4) + (nn + 1) * 4
         pbytes = nnzP * (bs * 6 * vbytes + 4) + (nn + 1) * 4
         total += kbytes + 4 * n * vbytes            # pre-smooth
         total += pbytes + n * vbytes + n_agg * 6 * vbytes      # restrict (P^T has P's size)
@@ -65,12 +66,15 @@ def vcycle_bytes(h, vbytes):
     return total
 
 
-def smoother_bytes(h, vbytes):
+def smoother_bytes(h, vbytes, kbytes=None):
+    """Level-0 fused pre-smooth: K values (kbytes each) and int32 column ids, row
+    pointers, and b, w read and x, r written (vbytes each)."""
     from paper_2505_18576_amd import amgf as b
     s = h.query(0, b.Q_SIZES)
     nn, bs, nnzK = int(s[0]), int(s[1]), int(s[6])
     n = nn * bs
-    return nnzK * (bs * bs * vbytes + 4) + (nn + 1) * 4 + 4 * n * vbytes
+    kb = kbytes or vbytes
+    return nnzK * (bs * bs * kb + 4) + (nn + 1) * 4 + 4 * n * vbytes
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "presmooth_sell3_f32_C5_counters.txt")
@@ -175,7 +179,8 @@ def main():
 
     res = {}
     for mode, prec, weights in (("fp64", b.FP64, None), ("mixed", b.MIXED_FP32, None),
-                                ("mixed_learned", b.MIXED_FP32, W)):
+                                ("mixed_learned", b.MIXED_FP32, W),
+                                ("bf16k_learned", b.MIXED_BF16K, W)):
         for w in range(args.warmup):
             h, x, info = solve(prec, weights)
             log(f"{mode} warmup {w}: {info.iterations} it, conv {info.converged}")
@@ -198,7 +203,8 @@ def main():
                 f"op complexity {info.op_complexity:.3f}, fallback {info.used_fallback}")
             if s < args.steps - 1:
                 h.close()
-        vb = 4 if prec == b.MIXED_FP32 else 8
+        vb = 8 if prec == b.FP64 else 4
+        kb = 2 if prec == b.MIXED_BF16K else vb
         ms_pre = h.time_kernel(b.K_PRESMOOTH, args.reps)
         ms_vc = h.time_kernel(b.K_VCYCLE, max(3, args.reps // 5))
         ms_op = h.time_kernel(b.K_OPERATOR, args.reps)
@@ -208,15 +214,16 @@ def main():
                          rel_true_res=float(info.rel_true_res), n_levels=int(info.n_levels),
                          op_complexity=float(info.op_complexity),
                          smoother_ms_live=live_ms, smoother_launches_live=live_n,
-                         smoother_ms=ms_pre, smoother_bytes=smoother_bytes(h, vb),
-                         vcycle_ms=ms_vc, vcycle_bytes=vcycle_bytes(h, vb), operator_ms=ms_op,
+                         smoother_ms=ms_pre, smoother_bytes=smoother_bytes(h, vb, kb),
+                         vcycle_ms=ms_vc, vcycle_bytes=vcycle_bytes(h, vb, kb),
+                         operator_ms=ms_op,
                          x=x)
         h.close()
         log(f"{mode}: pre-smooth live {live_ms:.3f} ms over {live_n} launches, isolated "
             f"{ms_pre:.3f} ms, V-cycle {ms_vc:.3f} ms, operator {ms_op:.3f} ms")
     xd = res["fp64"].pop("x")
     rel_vs_fp64 = {}
-    for k in ("mixed", "mixed_learned"):
+    for k in ("mixed", "mixed_learned", "bf16k_learned"):
         xk = res[k].pop("x")
         rel_vs_fp64[k] = float(torch.linalg.norm(xk - xd) / torch.linalg.norm(xd))
 
@@ -241,6 +248,9 @@ def main():
                    "n": p.n, "m": p.m, "nnzb": p.nnzb,
                    "mixed_learned": dict(m),
                    "mixed_plain": dict(res["mixed"]),
+                   "bf16k_learned": dict(res["bf16k_learned"]),
+                   "speedup_bf16k_learned_vs_fp64_plain":
+                       res["fp64"]["s_per_solve"] / res["bf16k_learned"]["s_per_solve"],
                    "fp64_plain": dict(res["fp64"]),
                    "speedup_mixed_learned_vs_fp64_plain":
                        res["fp64"]["s_per_solve"] / m["s_per_solve"],

@@ -44,13 +44,17 @@ typedef enum {
   AMGF_EDEVICE = 5   /* a HIP runtime call failed                                  */
 } amgf_status;
 
-enum { AMGF_FP64 = 0, AMGF_MIXED_FP32 = 1 };          /* V-cycle arithmetic        */
+/* V-cycle arithmetic.  MIXED_BF16K is MIXED_FP32 with the level-0 stiffness values of
+ * the smoothing steps stored in BF16 (rounded to nearest even once from FP64) and
+ * widened to FP32 in registers; the second AMGF residual keeps FP32 values.         */
+enum { AMGF_FP64 = 0, AMGF_MIXED_FP32 = 1, AMGF_MIXED_BF16K = 2 };
 enum { AMGF_L1JACOBI = 0, AMGF_LEARNED = 2 };         /* smoother damping          */
 
 typedef struct {
   int32_t struct_size;        /* sizeof(amgf_options), for ABI versioning            */
-  int32_t precision;          /* AMGF_FP64 or AMGF_MIXED_FP32 (FP32 V-cycle, FP64
-                                 contact term, coarse solve, filter and outer CG)     */
+  int32_t precision;          /* AMGF_FP64, AMGF_MIXED_FP32 (FP32 V-cycle, FP64
+                                 contact term, coarse solve, filter and outer CG) or
+                                 AMGF_MIXED_BF16K                                      */
   int32_t smoother;           /* AMGF_L1JACOBI (theta = 1) or AMGF_LEARNED          */
   int32_t filter;             /* 1: AMGF (Definition 5.3); 0: plain AMG-PCG, M = B   */
   int32_t max_levels;         /* hierarchy depth cap (default 10)                    */

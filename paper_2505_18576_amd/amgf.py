@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libamgf.so")
 
 AMGF_OK, AMGF_EINVAL, AMGF_ENOTSPD, AMGF_ENOCONV, AMGF_ENOMEM, AMGF_EDEVICE = range(6)
-FP64, MIXED_FP32 = 0, 1
+FP64, MIXED_FP32, MIXED_BF16K = 0, 1, 2
 L1JACOBI, LEARNED = 0, 2
 (Q_SIZES, Q_A_ROWPTR, Q_A_COL, Q_A_VAL, Q_AGG, Q_ROOT, Q_G_ROWPTR, Q_G_COL, Q_P_ROWPTR,
  Q_P_COL, Q_P_VAL, Q_L1, Q_K_ROWPTR, Q_K_COL, Q_K_VAL, Q_OMEGA, Q_IC, Q_FEATURES,

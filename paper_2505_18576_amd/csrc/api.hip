@@ -77,7 +77,8 @@ struct Handle {
   ~Handle() {
     for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
   }
-  bool mixed() const { return opt.precision == AMGF_MIXED_FP32; }
+  bool mixed() const { return opt.precision != AMGF_FP64; }
+  bool bf16k() const { return opt.precision == AMGF_MIXED_BF16K; }
   int64_t n() const { return int64_t(n_nodes) * 3; }
 };
 
@@ -294,7 +295,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     Level& L = *h.lev[l];
     const int64_t n = L.n();
     L.vb.alloc(n); L.vx.alloc(n); L.vr.alloc(n); L.vxn.alloc(n);
-    if (l == 0) bsr_build_sell(c, L.K, true, h.mixed());
+    if (l == 0) bsr_build_sell(c, L.K, true, h.mixed(), h.bf16k());
     if (h.mixed()) {
       if (l != 0) to_fp32(c, L.K);
       if (L.P.nnzb) { to_fp32(c, L.P); to_fp32(c, L.PT); }
@@ -366,7 +367,10 @@ static void vcycle32(Handle& h, size_t l) {
   }
   Level& N = *h.lev[l + 1];
   if (l == 0) prof_begin(h, AMGF_K_PRESMOOTH);
-  bsr_spmv<float>(c, SPMV_PRE, L.K, L.K.val32.p, nullptr, L.fr.p, L.fb.p, L.w32.p, L.fx.p);
+  if (l == 0 && h.bf16k())
+    sell_spmv_bf16(c, SPMV_PRE, L.K, nullptr, L.fr.p, L.fb.p, L.w32.p, L.fx.p);
+  else
+    bsr_spmv<float>(c, SPMV_PRE, L.K, L.K.val32.p, nullptr, L.fr.p, L.fb.p, L.w32.p, L.fx.p);
   prof_end(h);
   contact_apply<float, float>(c, CT_SUB_RES, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.fx.p,
                               h.t.p, L.fr.p, nullptr);
@@ -374,7 +378,10 @@ static void vcycle32(Handle& h, size_t l) {
   vcycle32(h, l + 1);
   bsr_spmv<float>(c, SPMV_ADD, L.P, L.P.val32.p, N.fx.p, L.fx.p, nullptr, nullptr, nullptr);
   if (l == 0) prof_begin(h, AMGF_K_POSTSMOOTH);
-  bsr_spmv<float>(c, SPMV_POST, L.K, L.K.val32.p, L.fx.p, nullptr, L.fb.p, L.w32.p, L.fxn.p);
+  if (l == 0 && h.bf16k())
+    sell_spmv_bf16(c, SPMV_POST, L.K, L.fx.p, nullptr, L.fb.p, L.w32.p, L.fxn.p);
+  else
+    bsr_spmv<float>(c, SPMV_POST, L.K, L.K.val32.p, L.fx.p, nullptr, L.fb.p, L.w32.p, L.fxn.p);
   prof_end(h);
   contact_apply<float, float>(c, CT_SUB_W, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.fx.p,
                               h.t.p, L.fxn.p, L.w32.p);
@@ -828,7 +835,8 @@ amgf_status amgf_setup(const amgf_options* opts, int32_t n_nodes, const int32_t*
                  "bad sizes or null K / coords");
     AMGF_REQUIRE(m == 0 || (J_rowptr && J_col && J_val && D), AMGF_EINVAL, "null J or D");
     AMGF_REQUIRE(int64_t(n_nodes) * 6 < (int64_t(1) << 31), AMGF_EINVAL, "too many nodes");
-    AMGF_REQUIRE(h.opt.precision == AMGF_FP64 || h.opt.precision == AMGF_MIXED_FP32,
+    AMGF_REQUIRE(h.opt.precision == AMGF_FP64 || h.opt.precision == AMGF_MIXED_FP32 ||
+                     h.opt.precision == AMGF_MIXED_BF16K,
                  AMGF_EINVAL, "precision");
     AMGF_REQUIRE(h.opt.smoother == AMGF_L1JACOBI || h.opt.smoother == AMGF_LEARNED, AMGF_EINVAL,
                  "smoother");
@@ -1007,7 +1015,10 @@ amgf_status amgf_time_kernel(amgf_handle hd, int32_t which, int32_t reps, void* 
     auto launch = [&]() {
       switch (which) {
         case AMGF_K_PRESMOOTH:
-          if (h.mixed())
+          if (h.bf16k())
+            amgf::sell_spmv_bf16(c, amgf::SPMV_PRE, L.K, nullptr, L.fr.p, L.fb.p, L.w32.p,
+                                 L.fx.p);
+          else if (h.mixed())
             amgf::bsr_spmv<float>(c, amgf::SPMV_PRE, L.K, L.K.val32.p, nullptr, L.fr.p, L.fb.p,
                                   L.w32.p, L.fx.p);
           else
@@ -1015,7 +1026,10 @@ amgf_status amgf_time_kernel(amgf_handle hd, int32_t which, int32_t reps, void* 
                                    L.w.p, L.vx.p);
           break;
         case AMGF_K_POSTSMOOTH:
-          if (h.mixed())
+          if (h.bf16k())
+            amgf::sell_spmv_bf16(c, amgf::SPMV_POST, L.K, L.fx.p, nullptr, L.fb.p, L.w32.p,
+                                 L.fxn.p);
+          else if (h.mixed())
             amgf::bsr_spmv<float>(c, amgf::SPMV_POST, L.K, L.K.val32.p, L.fx.p, nullptr, L.fb.p,
                                   L.w32.p, L.fxn.p);
           else

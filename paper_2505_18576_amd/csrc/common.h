@@ -82,6 +82,9 @@ struct BSR {
   DBuf<int> sell_off, sell_col;
   DBuf<double> sell_val;
   DBuf<float> sell_val32;
+  // BF16 copy (round to nearest even): per slot, entries (0,1) (2,3) (4,5) (6,7) of the
+  // 64 rows as 4 x 64 packed pairs (uint32), then entry 8 as 64 uint16: 1152 bytes
+  DBuf<uint16_t> sell_val16;
   size_t bsz() const { return size_t(br) * bc; }
 };
 

@@ -47,19 +47,21 @@ def test_apply_fp64_tight_for_moderate_barrier():
     h.close()
 
 
-def test_apply_mixed_precision_close_to_fp64():
+@pytest.mark.parametrize("precision,tol", [(1, 1e-4), (2, 2e-2)])
+def test_apply_mixed_precision_close_to_fp64(precision, tol):
+    # FP32 values: relative rounding 6e-8 per entry; BF16 values (precision 2): 3.9e-3
     o = oracle("C1")
-    h = gpu("C1", precision=1)
+    h = gpu("C1", precision=precision)
     rng = np.random.default_rng(2)
     r = rng.standard_normal(o.n)
     e_b = rel(h.vcycle(r).cpu().numpy(), o.vcycle(r))
     e_m = rel(h.apply(r).cpu().numpy(), o.apply(r))
-    print(f"mixed vcycle rel {e_b:.2e} apply rel {e_m:.2e}")
-    assert e_b < 1e-4 and e_m < 1e-4
+    print(f"precision {precision}: vcycle rel {e_b:.2e} apply rel {e_m:.2e}")
+    assert e_b < tol and e_m < tol
     h.close()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_pcg_matches_oracle(precision):
     p = problem("C1")
     o = oracle("C1")
@@ -78,7 +80,7 @@ def test_pcg_matches_oracle(precision):
         assert abs(info.iterations - ref.iterations) <= 1
         assert err <= 1e-8
     else:
-        assert info.iterations <= ref.iterations + 5
+        assert info.iterations <= ref.iterations + (5 if precision == 1 else 10)
         assert err_S <= 1e-8
 
 

@@ -108,6 +108,12 @@ amgf_status amgf_setup(const amgf_options* opts, int32_t n_nodes,
  * FP64 device vectors (may not alias).  With filter = 0, z = B r.            */
 amgf_status amgf_apply(amgf_handle h, const double* r, double* z, void* stream);
 
+/* w_c = A_w^{-1} r_c with A_w = S[I_c, I_c], the filtering-space solve of Definition 5.3
+ * (Sec. 5.1), by the handle's nested-dissection multifrontal Cholesky factor.  r_c, w_c:
+ * n_c FP64 device vectors in the order of I_c (may not alias).  EINVAL when the handle
+ * was built with filter = 0 or has an empty filtering space.                     */
+amgf_status amgf_filter_solve(amgf_handle h, const double* r_c, double* w_c, void* stream);
+
 /* z = B r, one V-cycle of the AMG part alone (the B of Assumptions 1-2).        */
 amgf_status amgf_vcycle(amgf_handle h, const double* r, double* z, void* stream);
 

@@ -25,7 +25,7 @@ ABI_FUNCTIONS = ["amgf_default_options", "amgf_setup", "amgf_apply", "amgf_vcycl
                  "amgf_operator_apply", "amgf_pcg", "amgf_destroy", "amgf_status_string",
                  "amgf_last_error", "amgf_num_levels", "amgf_query", "amgf_time_kernel",
                  "amgf_set_mlp", "amgf_mlp_loss_grad", "amgf_adam_step",
-                 "amgf_profile_start", "amgf_profile_read"]
+                 "amgf_profile_start", "amgf_profile_read", "amgf_filter_solve"]
 K_PRESMOOTH, K_POSTSMOOTH, K_VCYCLE, K_OPERATOR = range(4)
 
 
@@ -69,7 +69,7 @@ def load_library(path=LIB_PATH):
     L.amgf_setup.argtypes = [ctypes.POINTER(Options), i32, vp, vp, vp, i32, vp, vp, vp, vp, vp,
                              vp, i32, vp, ctypes.POINTER(vp)]
     L.amgf_setup.restype = ctypes.c_int
-    for f in ("amgf_apply", "amgf_vcycle", "amgf_operator_apply"):
+    for f in ("amgf_apply", "amgf_vcycle", "amgf_operator_apply", "amgf_filter_solve"):
         getattr(L, f).argtypes = [vp, vp, vp, vp]
         getattr(L, f).restype = ctypes.c_int
     L.amgf_pcg.argtypes = [vp, vp, vp, ctypes.POINTER(SolveInfo), vp]
@@ -201,6 +201,10 @@ class AMGF:
 
     def apply(self, r):
         return self._vec_op(self.L.amgf_apply, r, "amgf_apply")
+
+    def filter_solve(self, rc):
+        """w_c = A_w^{-1} r_c on the filtering space (vectors in the order of I_c)."""
+        return self._vec_op(self.L.amgf_filter_solve, rc, "amgf_filter_solve")
 
     def vcycle(self, r):
         return self._vec_op(self.L.amgf_vcycle, r, "amgf_vcycle")

@@ -5,7 +5,7 @@
 #include <memory>
 
 #include "apply.h"
-#include "btd.h"
+#include "multifrontal.h"
 #include "dense.h"
 #include "learn.h"
 #include "setup.h"
@@ -47,13 +47,13 @@ struct Handle {
   DBuf<double> t;               // contact scratch (m)
   // coarsest solve (one dense block)
   int nc_dense = 0;
-  BTDSolver coarse;
+  MFSolver coarse;
   DBuf<double> coarse_b, coarse_x;
   // filter
   int n_c = 0;
   int filter_refine = 0;
   DBuf<int> Ic;
-  BTDSolver aw;
+  MFSolver aw;
   DBuf<double> f_r, f_w, f_res, f_dw;
   DBuf<int> aw_rp, aw_col;      // sparse A_w for refinement residuals
   DBuf<double> aw_val;
@@ -62,6 +62,7 @@ struct Handle {
   DBuf<float> zf, r2f;
   DBuf<int> ic_nodes;           // node rows holding filter DOFs
   int n_icn = 0;
+  bool ic_closed = false;
   // pcg scratch
   DBuf<double> pr, pz, pzo, pp, pq;
   double op_complexity = 1.0;
@@ -236,7 +237,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     DBuf<int> rp, cl;
     DBuf<double> vl;
     bsr_to_csr(c, LL.A, rp, cl, vl);
-    h.coarse.setup(c, h.nc_dense, rp.p, cl.p, vl.p, h.nc_dense);
+    h.coarse.setup(c, h.nc_dense, LL.b, rp.p, cl.p, vl.p);
   }
   h.coarse_b.alloc(h.nc_dense);
   h.coarse_x.alloc(h.nc_dense);
@@ -257,6 +258,11 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
       if (nodes.empty() || nodes.back() != ic[i] / 3) nodes.push_back(ic[i] / 3);
     }
     h.n_icn = int(nodes.size());
+    // node-closed I_c (all three DOFs of each node, in order) lets the filter solver order
+    // nodes instead of single DOFs
+    h.ic_closed = h.n_c == 3 * h.n_icn;
+    for (int i = 0; h.ic_closed && i < h.n_c; ++i)
+      h.ic_closed = ic[i] == 3 * nodes[i / 3] + i % 3;
     h.ic_nodes.alloc(h.n_icn);
     AMGF_HIP(hipMemcpyAsync(h.ic_nodes.p, nodes.data(), sizeof(int) * h.n_icn,
                             hipMemcpyHostToDevice, c.s));
@@ -264,7 +270,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   }
   if (o.filter && h.n_c > 0) {
     filter_csr(c, L0->A, h.Ic.p, h.n_c, h.aw_rp, h.aw_col, h.aw_val);
-    h.aw.setup(c, h.n_c, h.aw_rp.p, h.aw_col.p, h.aw_val.p, 1536);
+    h.aw.setup(c, h.n_c, h.ic_closed ? 3 : 1, h.aw_rp.p, h.aw_col.p, h.aw_val.p);
     h.f_r.alloc(h.n_c);
     h.f_w.alloc(h.n_c);
     h.f_res.alloc(h.n_c);
@@ -866,6 +872,17 @@ amgf_status amgf_apply(amgf_handle hd, const double* r, double* z, void* stream)
   });
   if (st_ != AMGF_OK) return st_;
   return AMGF_OK;
+}
+
+amgf_status amgf_filter_solve(amgf_handle hd, const double* rc, double* wc, void* stream) {
+  if (!hd || !rc || !wc) return AMGF_EINVAL;
+  return guard([&]() -> amgf_status {
+    Handle& h = hd->h;
+    AMGF_REQUIRE(h.opt.filter && h.n_c > 0, AMGF_EINVAL, "handle has no filtering space");
+    h.ctx.s = static_cast<hipStream_t>(stream);
+    amgf::filter_solve(h, rc, wc);
+    return AMGF_OK;
+  });
 }
 
 amgf_status amgf_vcycle(amgf_handle hd, const double* r, double* z, void* stream) {

@@ -6,7 +6,7 @@
 
 #include "apply.h"
 #include "multifrontal.h"
-#include "dense.h"
+#include "csr.h"
 #include "learn.h"
 #include "setup.h"
 
@@ -45,7 +45,7 @@ struct Handle {
   DBuf<double> D, coords;
   DBuf<unsigned char> dec0;
   DBuf<double> t;               // contact scratch (m)
-  // coarsest solve (one dense block)
+  // coarsest solve (multifrontal Cholesky of the coarsest operator)
   int nc_dense = 0;
   MFSolver coarse;
   DBuf<double> coarse_b, coarse_x;
@@ -230,7 +230,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     Rprev = std::move(R);
   }
   h.op_complexity = double(nzsum) / double(std::max<int64_t>(nz0, 1));
-  // ---- coarsest level: one dense block
+  // ---- coarsest level: direct multifrontal Cholesky
   Level& LL = *h.lev.back();
   h.nc_dense = int(LL.n());
   {
@@ -241,7 +241,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   }
   h.coarse_b.alloc(h.nc_dense);
   h.coarse_x.alloc(h.nc_dense);
-  // ---- filter (Sec. 5.1): A_w = S[I_c, I_c], level-set block-tridiagonal Cholesky
+  // ---- filter (Sec. 5.1): A_w = S[I_c, I_c], nested-dissection multifrontal Cholesky
   if (Ic_user && n_c_user > 0) {
     h.Ic.alloc(n_c_user);
     copy_in(c, h.Ic.p, Ic_user, sizeof(int) * size_t(n_c_user));

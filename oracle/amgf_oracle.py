@@ -453,12 +453,12 @@ def power_start(n):
     return fmix32(np.arange(n)).astype(np.float64) * 2.0 ** -32 - 0.5
 
 
-def power_estimate(Acsr, d, decoupled, iters):
+def power_estimate(Acsr, d, decoupled, iters, clip=True):
     """Spectral radius estimate of D_l1^{-1} A on the coupled DOFs.
 
     x_0 from ``power_start``; each step y = (A x) / d with decoupled entries zeroed,
     lam = ||y||_2, x = y / lam.  Returns min(1, lam) after ``iters`` steps (the l1
-    diagonal already bounds the radius by 1)."""
+    diagonal already bounds the radius by 1), or lam itself with clip=False."""
     x = power_start(Acsr.shape[0])
     x[decoupled] = 0.0
     x = x / math.sqrt(float(x @ x))
@@ -468,7 +468,7 @@ def power_estimate(Acsr, d, decoupled, iters):
         y[decoupled] = 0.0
         lam = math.sqrt(float(y @ y))
         x = y / lam
-    return min(1.0, lam)
+    return min(1.0, lam) if clip else lam
 
 
 # ======================================================================================
@@ -489,6 +489,9 @@ class OracleOptions:
     Ic: np.ndarray | None = None          # optional DOF list of the filter space
     theta: list | None = None             # per-level smoother damping (default 1)
     dense_filter_max: int = 8000
+    smoother: str = "jacobi"              # "jacobi" (l1-Jacobi) or "chebyshev"
+    sweeps: int = 1                       # smoother applications before and after
+    cheb_degree: int = 2                  # Chebyshev polynomial degree
 
 
 @dataclass
@@ -508,6 +511,7 @@ class Level:
     dead: np.ndarray = None
     decoupled: np.ndarray = None
     rho: float = 1.0
+    lam: float = 1.0                      # unclipped power estimate of rho(D_l1^{-1} A)
     omega: float = 4.0 / 3.0
 
 
@@ -561,7 +565,8 @@ class OracleAMGF:
             lev.Pt, lev.R, lev.dead = Pt, R, dead
             # O7: prolongator smoothing  P = P_t - omega D_l1^{-1} A P_t
             dec = lev.decoupled if l == 0 else np.zeros(A.nrows * br, bool)
-            lev.rho = power_estimate(Acsr, lev.d, dec, o.sa_power_iters)
+            lev.lam = power_estimate(Acsr, lev.d, dec, o.sa_power_iters, clip=False)
+            lev.rho = min(1.0, lev.lam)
             lev.omega = o.sa_omega / lev.rho
             APt = block_spgemm(A, Pt, keep_rows=agg >= 0)
             P = BlockMatrix(APt.rowptr, APt.col, APt.val.copy(), n_agg)
@@ -646,17 +651,50 @@ class OracleAMGF:
     def A_apply(self, x):
         return self.S.csr() @ x
 
+    def smooth(self, l, b, x):
+        """One smoother application on level l for A x = b (O10).
+
+        l1-Jacobi: x + w (b - A x).  Chebyshev: the degree-m Chebyshev iteration on the
+        D_l1-preconditioned system over [0.3 lam, lam], lam = min(1, 1.1 * power
+        estimate); its error propagation is T_m((theta - D^-1 A)/delta) / T_m(theta/delta)
+        with theta, delta the centre and half-width of that interval."""
+        lev = self.levels[l]
+        A = lev.A.csr()
+        if self.opts.smoother == "jacobi":
+            return x + lev.w * (b - A @ x)
+        lmax = min(1.0, 1.1 * lev.lam)
+        lmin = 0.3 * lmax
+        theta, delta = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+        sigma = theta / delta
+        dinv = 1.0 / lev.d
+        r = dinv * (b - A @ x)
+        rho = 1.0 / sigma
+        dk = r / theta
+        for k in range(self.opts.cheb_degree):
+            x = x + dk
+            if k + 1 == self.opts.cheb_degree:
+                break
+            r = r - dinv * (A @ dk)
+            rho_new = 1.0 / (2.0 * sigma - rho)
+            dk = rho_new * rho * dk + (2.0 * rho_new / delta) * r
+            rho = rho_new
+        return x
+
     def vcycle(self, b, l=0):
-        """B b: symmetric V(1,1) with l1-Jacobi smoothing from a zero initial guess."""
+        """B b: symmetric V(nu, nu) from a zero initial guess (O11): nu smoother
+        applications, coarse correction, nu smoother applications."""
         if l == self.nlev - 1:
             return sla.cho_solve(self.coarse_chol, b)
         lev = self.levels[l]
         A = lev.A.csr()
-        x = lev.w * b
+        x = np.zeros_like(b)
+        for _ in range(self.opts.sweeps):
+            x = self.smooth(l, b, x)
         r = b - A @ x
         xc = self.vcycle(lev.P.csr().T @ r, l + 1)
         x = x + lev.P.csr() @ xc
-        x = x + lev.w * (b - A @ x)
+        for _ in range(self.opts.sweeps):
+            x = self.smooth(l, b, x)
         return x
 
     def filter_solve(self, r_c):

@@ -48,7 +48,10 @@ typedef enum {
  * the smoothing steps stored in BF16 (rounded to nearest even once from FP64) and
  * widened to FP32 in registers; the second AMGF residual keeps FP32 values.         */
 enum { AMGF_FP64 = 0, AMGF_MIXED_FP32 = 1, AMGF_MIXED_BF16K = 2 };
-enum { AMGF_L1JACOBI = 0, AMGF_LEARNED = 2 };         /* smoother damping          */
+/* Smoother (Sec. 6 uses l1 smoothers; Remark 5.6): l1-Jacobi with theta = 1, Chebyshev
+ * of degree cheb_degree in D_l1^{-1} A over [0.3 lam, lam] (lam = min(1, 1.1 x the power
+ * estimate of the prolongator damping)), or l1-Jacobi with learned damping theta_i.  */
+enum { AMGF_L1JACOBI = 0, AMGF_CHEBYSHEV = 1, AMGF_LEARNED = 2 };
 
 typedef struct {
   int32_t struct_size;        /* sizeof(amgf_options), for ABI versioning            */
@@ -68,6 +71,9 @@ typedef struct {
   double max_coarse_ratio;    /* stop if n_agg > ratio * n_nodes (default 0.9)        */
   const float* mlp_weights;   /* host; 1313 MLP parameters + 12 feature normalisers,
                                  required iff smoother == AMGF_LEARNED                */
+  int32_t sweeps;             /* smoother applications before and after the coarse
+                                 correction, 1..16 (default 1: V(1,1))                */
+  int32_t cheb_degree;        /* Chebyshev degree, 1..16 (default 2)                  */
 } amgf_options;
 
 typedef struct {
@@ -173,7 +179,8 @@ int32_t amgf_num_levels(amgf_handle h);
  * not converge and sets info.used_fallback.                                          */
 
 /* Replace the damping of every smoothed level by the MLP with device parameters W
- * (1325 floats), or restore theta = 1 when W is NULL.                                  */
+ * (1325 floats), or restore theta = 1 when W is NULL.  EINVAL with W on a Chebyshev
+ * handle.                                                                              */
 amgf_status amgf_set_mlp(amgf_handle h, const float* W, void* stream);
 
 /* Training loss and gradient on an FP64 handle: for each probe e0 (device, column q of
@@ -181,7 +188,8 @@ amgf_status amgf_set_mlp(amgf_handle h, const float* W, void* stream);
  * E = I - M S and M the AMGF preconditioner with MLP damping W (device).  *loss (host)
  * = mean over probes; grad (device, 1313 doubles) = d loss / d (W1 b1 W2 b2 W3 b3),
  * obtained by reverse mode through both V-cycles and the filter correction.  The
- * handle's own damping is left unchanged.                                              */
+ * handle's own damping is left unchanged.  EINVAL unless the handle smooths with
+ * l1-Jacobi and sweeps = 1 (the reverse mode follows that V(1,1)).                     */
 amgf_status amgf_mlp_loss_grad(amgf_handle h, const float* W, int32_t k, int32_t n_probes,
                                const double* probes, double* loss, double* grad,
                                void* stream);

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libamgf.so")
 
 AMGF_OK, AMGF_EINVAL, AMGF_ENOTSPD, AMGF_ENOCONV, AMGF_ENOMEM, AMGF_EDEVICE = range(6)
 FP64, MIXED_FP32, MIXED_BF16K = 0, 1, 2
-L1JACOBI, LEARNED = 0, 2
+L1JACOBI, CHEBYSHEV, LEARNED = 0, 1, 2
 (Q_SIZES, Q_A_ROWPTR, Q_A_COL, Q_A_VAL, Q_AGG, Q_ROOT, Q_G_ROWPTR, Q_G_COL, Q_P_ROWPTR,
  Q_P_COL, Q_P_VAL, Q_L1, Q_K_ROWPTR, Q_K_COL, Q_K_VAL, Q_OMEGA, Q_IC, Q_FEATURES,
  Q_THETA) = range(19)
@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
                 ("strength_theta", ctypes.c_double), ("rtol", ctypes.c_double),
                 ("sa_omega", ctypes.c_double), ("qr_tol", ctypes.c_double),
                 ("max_coarse_ratio", ctypes.c_double),
-                ("mlp_weights", ctypes.POINTER(ctypes.c_float))]
+                ("mlp_weights", ctypes.POINTER(ctypes.c_float)),
+                ("sweeps", ctypes.c_int32), ("cheb_degree", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

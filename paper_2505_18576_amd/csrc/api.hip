@@ -34,6 +34,10 @@ struct Level {
   // V-cycle work vectors
   DBuf<double> vb, vx, vr, vxn;
   DBuf<float> fb, fx, fr, fxn;
+  // Chebyshev / multi-sweep smoothing work vectors
+  DBuf<double> vd, vt;
+  DBuf<float> fd, ft;
+  double lam = 1.0;             // unclipped power estimate of rho(D_l1^{-1} A)
   int64_t n() const { return int64_t(nn) * b; }
 };
 
@@ -80,6 +84,8 @@ struct Handle {
   }
   bool mixed() const { return opt.precision != AMGF_FP64; }
   bool bf16k() const { return opt.precision == AMGF_MIXED_BF16K; }
+  // one fused l1-Jacobi step before and after the coarse correction
+  bool plain_cycle() const { return opt.smoother != AMGF_CHEBYSHEV && opt.sweeps == 1; }
   int64_t n() const { return int64_t(n_nodes) * 3; }
 };
 
@@ -112,7 +118,7 @@ static double power_estimate(Handle& h, Level& L, const unsigned char* dec) {
     vcopy(c, y.p, x.p, n);
     vscale(c, n, 1.0 / lam, x.p);
   }
-  return std::min(1.0, lam);
+  return lam;
 }
 
 static void to_fp32(Ctx& c, BSR& A) {
@@ -200,7 +206,8 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     DBuf<unsigned char> dead;
     tentative_prolongator(c, L.b, L.nn, n_agg, moff.p, members.p, l == 0 ? h.coords.p : nullptr,
                           dec, Rprev.p, o.qr_tol, Pt, R, dead);
-    L.rho = power_estimate(h, L, dec);
+    L.lam = power_estimate(h, L, dec);
+    L.rho = std::min(1.0, L.lam);
     L.omega = o.sa_omega / L.rho;
     smooth_prolongator(c, L.A, L.agg.p, n_agg, Pt.p, L.d.p, L.omega, L.P);
     bsr_transpose(c, L.P, L.PT);
@@ -301,6 +308,11 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     Level& L = *h.lev[l];
     const int64_t n = L.n();
     L.vb.alloc(n); L.vx.alloc(n); L.vr.alloc(n); L.vxn.alloc(n);
+    if (!h.plain_cycle()) {
+      L.vd.alloc(n);
+      L.vt.alloc(n);
+      if (h.mixed()) { L.fd.alloc(n); L.ft.alloc(n); }
+    }
     if (l == 0) bsr_build_sell(c, L.K, true, h.mixed(), h.bf16k());
     if (h.mixed()) {
       if (l != 0) to_fp32(c, L.K);
@@ -336,6 +348,97 @@ static void prof_end(Handle& h) {
   h.prof_open = false;
 }
 
+// ---- smoother options: nu applications of l1-Jacobi or of the degree-m Chebyshev
+// polynomial in D_l1^{-1} A over [0.3 lam, lam], lam = min(1, 1.1 * power estimate)
+template <class T>
+struct LvBufs {
+  DBuf<T>*b, *x, *xn, *r, *d, *t;
+  const T* w;
+};
+static LvBufs<double> lv_bufs(Level& L, double) {
+  return {&L.vb, &L.vx, &L.vxn, &L.vr, &L.vd, &L.vt, L.w.p};
+}
+static LvBufs<float> lv_bufs(Level& L, float) {
+  return {&L.fb, &L.fx, &L.fxn, &L.fr, &L.fd, &L.ft, L.w32.p};
+}
+
+static const double* bsr_vals(const BSR& A, double) { return A.val.p; }
+static const float* bsr_vals(const BSR& A, float) { return A.val32.p; }
+
+// K x in the level's V-cycle precision (BF16 level-0 values in MIXED_BF16K)
+static void k_spmv(Handle& h, size_t l, int mode, const double* x, double* y, const double* b,
+                   const double* w, double* xo) {
+  Level& L = *h.lev[l];
+  bsr_spmv<double>(h.ctx, mode, L.K, L.K.val.p, x, y, b, w, xo);
+}
+static void k_spmv(Handle& h, size_t l, int mode, const float* x, float* y, const float* b,
+                   const float* w, float* xo) {
+  Level& L = *h.lev[l];
+  if (l == 0 && h.bf16k()) sell_spmv_bf16(h.ctx, mode, L.K, x, y, b, w, xo);
+  else bsr_spmv<float>(h.ctx, mode, L.K, L.K.val32.p, x, y, b, w, xo);
+}
+
+template <class T>
+static void contact(Handle& h, Level& L, int mode, const T* x, T* y, const T* w) {
+  contact_apply<T, T>(h.ctx, mode, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, x, h.t.p, y, w);
+}
+
+// one smoother application on x (x_zero: x = 0 on entry); result in *B.x
+template <class T>
+static void smooth_once(Handle& h, size_t l, bool x_zero) {
+  Ctx& c = h.ctx;
+  Level& L = *h.lev[l];
+  LvBufs<T> B = lv_bufs(L, T());
+  const int64_t n = L.n();
+  if (h.opt.smoother != AMGF_CHEBYSHEV) {
+    if (x_zero) {
+      // x = w.b (the residual written to r is not needed here)
+      k_spmv(h, l, SPMV_PRE, (const T*)nullptr, B.r->p, B.b->p, B.w, B.x->p);
+      return;
+    }
+    k_spmv(h, l, SPMV_POST, B.x->p, (T*)nullptr, B.b->p, B.w, B.xn->p);
+    contact<T>(h, L, CT_SUB_W, B.x->p, B.xn->p, B.w);
+    std::swap(*B.x, *B.xn);
+    return;
+  }
+  const double lmax = std::min(1.0, 1.1 * L.lam), lmin = 0.3 * lmax;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  const T* src = B.b->p;
+  if (!x_zero) {
+    k_spmv(h, l, SPMV_RES, B.x->p, B.r->p, B.b->p, (const T*)nullptr, (T*)nullptr);
+    contact<T>(h, L, CT_SUB_RES, B.x->p, B.r->p, (const T*)nullptr);
+    src = B.r->p;
+  }
+  cheb_start<T>(c, n, src, B.w, B.r->p, B.d->p, B.x->p, 1.0 / theta, x_zero);
+  double rho = 1.0 / sigma;
+  for (int k = 1; k < h.opt.cheb_degree; ++k) {
+    k_spmv(h, l, SPMV_Y, B.d->p, B.t->p, (const T*)nullptr, (const T*)nullptr, (T*)nullptr);
+    contact<T>(h, L, CT_ADD, B.d->p, B.t->p, (const T*)nullptr);
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    cheb_step<T>(c, n, B.t->p, B.w, B.r->p, B.d->p, B.x->p, rho_new * rho, 2.0 * rho_new / delta);
+    rho = rho_new;
+  }
+}
+
+// general V(nu, nu) on level l (not the coarsest): *B.b -> *B.x
+template <class T>
+static void vcycle_general(Handle& h, size_t l, void (*coarse)(Handle&, size_t)) {
+  Level& L = *h.lev[l];
+  Level& N = *h.lev[l + 1];
+  LvBufs<T> B = lv_bufs(L, T());
+  LvBufs<T> NB = lv_bufs(N, T());
+  for (int s = 0; s < h.opt.sweeps; ++s) smooth_once<T>(h, l, s == 0);
+  k_spmv(h, l, SPMV_RES, B.x->p, B.r->p, B.b->p, (const T*)nullptr, (T*)nullptr);
+  contact<T>(h, L, CT_SUB_RES, B.x->p, B.r->p, (const T*)nullptr);
+  bsr_spmv<T>(h.ctx, SPMV_Y, L.PT, bsr_vals(L.PT, T()), B.r->p, NB.b->p, nullptr, nullptr,
+              nullptr);
+  coarse(h, l + 1);
+  bsr_spmv<T>(h.ctx, SPMV_ADD, L.P, bsr_vals(L.P, T()), NB.x->p, B.x->p, nullptr, nullptr,
+              nullptr);
+  for (int s = 0; s < h.opt.sweeps; ++s) smooth_once<T>(h, l, false);
+}
+
 // FP64 V(1,1) on level l: L.vb -> L.vx
 static void vcycle64(Handle& h, size_t l) {
   Ctx& c = h.ctx;
@@ -344,6 +447,7 @@ static void vcycle64(Handle& h, size_t l) {
     coarse_solve(h, L.vb.p, L.vx.p);
     return;
   }
+  if (!h.plain_cycle()) return vcycle_general<double>(h, l, vcycle64);
   Level& N = *h.lev[l + 1];
   if (l == 0) prof_begin(h, AMGF_K_PRESMOOTH);
   bsr_spmv<double>(c, SPMV_PRE, L.K, L.K.val.p, nullptr, L.vr.p, L.vb.p, L.w.p, L.vx.p);
@@ -371,6 +475,7 @@ static void vcycle32(Handle& h, size_t l) {
     cast_d2f(c, h.coarse_x.p, L.fx.p, L.n());
     return;
   }
+  if (!h.plain_cycle()) return vcycle_general<float>(h, l, vcycle32);
   Level& N = *h.lev[l + 1];
   if (l == 0) prof_begin(h, AMGF_K_PRESMOOTH);
   if (l == 0 && h.bf16k())
@@ -792,6 +897,8 @@ void amgf_default_options(amgf_options* o) {
   o->struct_size = sizeof(amgf_options);
   o->precision = AMGF_FP64;
   o->smoother = AMGF_L1JACOBI;
+  o->sweeps = 1;
+  o->cheb_degree = 2;
   o->filter = 1;
   o->max_levels = 10;
   o->coarse_max_nodes = 256;
@@ -844,8 +951,12 @@ amgf_status amgf_setup(const amgf_options* opts, int32_t n_nodes, const int32_t*
     AMGF_REQUIRE(h.opt.precision == AMGF_FP64 || h.opt.precision == AMGF_MIXED_FP32 ||
                      h.opt.precision == AMGF_MIXED_BF16K,
                  AMGF_EINVAL, "precision");
-    AMGF_REQUIRE(h.opt.smoother == AMGF_L1JACOBI || h.opt.smoother == AMGF_LEARNED, AMGF_EINVAL,
-                 "smoother");
+    AMGF_REQUIRE(h.opt.smoother == AMGF_L1JACOBI || h.opt.smoother == AMGF_CHEBYSHEV ||
+                     h.opt.smoother == AMGF_LEARNED,
+                 AMGF_EINVAL, "smoother");
+    AMGF_REQUIRE(h.opt.sweeps >= 1 && h.opt.sweeps <= 16, AMGF_EINVAL, "sweeps must be 1..16");
+    AMGF_REQUIRE(h.opt.cheb_degree >= 1 && h.opt.cheb_degree <= 16, AMGF_EINVAL,
+                 "cheb_degree must be 1..16");
     AMGF_REQUIRE(h.opt.smoother != AMGF_LEARNED || h.opt.mlp_weights, AMGF_EINVAL,
                  "the learned smoother needs mlp_weights");
     AMGF_REQUIRE(h.opt.max_levels >= 1 && h.opt.max_iters >= 0 && h.opt.rtol >= 0,
@@ -970,6 +1081,8 @@ amgf_status amgf_set_mlp(amgf_handle hd, const float* W, void* stream) {
     Handle& h = hd->h;
     h.ctx.s = static_cast<hipStream_t>(stream);
     if (W) {
+      AMGF_REQUIRE(h.opt.smoother != AMGF_CHEBYSHEV, AMGF_EINVAL,
+                   "learned damping applies to the l1-Jacobi smoother");
       if (!h.mlpW.n) h.mlpW.alloc(amgf::MLP_NTOTAL);
       AMGF_HIP(hipMemcpyAsync(h.mlpW.p, W, sizeof(float) * amgf::MLP_NTOTAL,
                               hipMemcpyDeviceToDevice, h.ctx.s));
@@ -989,6 +1102,8 @@ amgf_status amgf_mlp_loss_grad(amgf_handle hd, const float* W, int32_t k, int32_
   if (!hd || !W || !probes || !loss || !grad || k < 1 || n_probes < 1) return AMGF_EINVAL;
   amgf_status st_ = guard([&]() -> amgf_status {
     Handle& h = hd->h;
+    AMGF_REQUIRE(h.plain_cycle(), AMGF_EINVAL,
+                 "the damping gradient needs the l1-Jacobi V(1,1) (sweeps = 1)");
     h.ctx.s = static_cast<hipStream_t>(stream);
     *loss = amgf::loss_grad(h, W, k, n_probes, probes, grad);
     // leave the handle's damping as it was

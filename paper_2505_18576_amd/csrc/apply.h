@@ -40,6 +40,15 @@ int nonempty_rows(Ctx& c, const int* rp, int n, DBuf<int>& rows);
 void bsr_res_rows(Ctx& c, const BSR& A, const int* rows, int nlist, const double* x,
                   const double* b, double* y);
 
+// Chebyshev smoother steps: start r = w.src, d = r/theta, x = d or x + d;
+// step r -= w.t, d = c1 d + c2 r, x += d
+template <class T>
+void cheb_start(Ctx& c, int64_t n, const T* src, const T* w, T* r, T* d, T* x, double inv_theta,
+                bool x_zero);
+template <class T>
+void cheb_step(Ctx& c, int64_t n, const T* t, const T* w, T* r, T* d, T* x, double c1,
+               double c2);
+
 // elementwise helpers
 void cast_d2f(Ctx& c, const double* a, float* b, int64_t n);
 void cast_f2d(Ctx& c, const float* a, double* b, int64_t n);

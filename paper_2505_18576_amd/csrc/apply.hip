@@ -563,7 +563,54 @@ __global__ void k_check(const double* __restrict__ v, int64_t n, int pos, int* f
   if (pos && !(x > 0.0)) atomicOr(flag, 2);
 }
 
+// Chebyshev smoother steps (elementwise):
+//   start: r = w.src; d = r * inv_theta; x = d (x_zero) or x + d
+//   step:  r -= w.t;  d = c1 d + c2 r;    x += d
+template <class T>
+__global__ void k_cheb_start(int64_t n, const T* __restrict__ src, const T* __restrict__ w,
+                             T* __restrict__ r, T* __restrict__ d, T* __restrict__ x,
+                             T inv_theta, int x_zero) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T ri = w[i] * src[i];
+  const T di = ri * inv_theta;
+  r[i] = ri;
+  d[i] = di;
+  x[i] = x_zero ? di : x[i] + di;
+}
+template <class T>
+__global__ void k_cheb_step(int64_t n, const T* __restrict__ t, const T* __restrict__ w,
+                            T* __restrict__ r, T* __restrict__ d, T* __restrict__ x, T c1,
+                            T c2) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T ri = r[i] - w[i] * t[i];
+  const T di = c1 * d[i] + c2 * ri;
+  r[i] = ri;
+  d[i] = di;
+  x[i] += di;
+}
+
 #define AMGF_L1D(n) dim3(grid_for((n), 256)), dim3(256), 0, c.s
+template <class T>
+void cheb_start(Ctx& c, int64_t n, const T* src, const T* w, T* r, T* d, T* x, double inv_theta,
+                bool x_zero) {
+  if (n) hipLaunchKernelGGL(k_cheb_start<T>, AMGF_L1D(n), n, src, w, r, d, x, T(inv_theta),
+                            int(x_zero));
+}
+template <class T>
+void cheb_step(Ctx& c, int64_t n, const T* t, const T* w, T* r, T* d, T* x, double c1,
+               double c2) {
+  if (n) hipLaunchKernelGGL(k_cheb_step<T>, AMGF_L1D(n), n, t, w, r, d, x, T(c1), T(c2));
+}
+template void cheb_start<double>(Ctx&, int64_t, const double*, const double*, double*, double*,
+                                 double*, double, bool);
+template void cheb_start<float>(Ctx&, int64_t, const float*, const float*, float*, float*,
+                                float*, double, bool);
+template void cheb_step<double>(Ctx&, int64_t, const double*, const double*, double*, double*,
+                                double*, double, double);
+template void cheb_step<float>(Ctx&, int64_t, const float*, const float*, float*, float*, float*,
+                               double, double);
 void cast_d2f(Ctx& c, const double* a, float* b, int64_t n) {
   if (n) hipLaunchKernelGGL(k_d2f, AMGF_L1D(n), a, b, n);
 }

@@ -6,6 +6,8 @@
 // reproducible; aggregation decisions on later levels are integer-only.
 #include "setup.h"
 
+#include <climits>
+
 namespace amgf {
 
 // ======================================================================================
@@ -552,51 +554,57 @@ void tentative_prolongator(Ctx& c, int br, int n_nodes, int n_agg, const int* mo
 }
 
 // ======================================================================================
-// prolongator smoothing  P = P_t - omega D_l1^{-1} A P_t   (thread per aggregated row)
+// prolongator smoothing  P = P_t - omega D_l1^{-1} A P_t
 // ======================================================================================
-template <int B>
-__global__ void k_sa_numeric(int n, const int* __restrict__ arp, const int* __restrict__ acol,
-                             const double* __restrict__ aval, const int* __restrict__ agg,
-                             const double* __restrict__ Pt, const double* __restrict__ d,
-                             double omega, const int* __restrict__ prp,
-                             const int* __restrict__ pcol, double* __restrict__ pval,
-                             int* flag) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || agg[i] < 0) return;
-  const int c0 = prp[i], c1 = prp[i + 1];
-  for (int t = arp[i]; t < arp[i + 1]; ++t) {
-    const int v = acol[t];
-    const int J = agg[v];
-    if (J < 0) continue;
-    const int s = lower_bound_i(pcol, c0, c1, J);
-    if (s >= c1 || pcol[s] != J) { atomicOr(flag, 64); continue; }
-    double* out = pval + int64_t(s) * B * 6;
-    const double* A = aval + int64_t(t) * B * B;
-    const double* Q = Pt + int64_t(v) * B * 6;
+// G lanes per aggregated row i, one lane per block (i, J) of P: the lane sums A_iv P_t,v
+// over the blocks of A's row whose column v lies in aggregate J, in ascending order, then
+// scales by -omega/d and adds P_t,i on the block of i's own aggregate.
+template <int B, int G>
+__global__ void __launch_bounds__(256) k_sa_numeric(int n, const int* __restrict__ arp,
+                                                    const int* __restrict__ acol,
+                                                    const double* __restrict__ aval,
+                                                    const int* __restrict__ agg,
+                                                    const double* __restrict__ Pt,
+                                                    const double* __restrict__ d, double omega,
+                                                    const int* __restrict__ prp,
+                                                    const int* __restrict__ pcol,
+                                                    double* __restrict__ pval) {
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int i = int(gid / G), l = int(gid % G);
+  if (i >= n) return;
+  const int ai = agg[i];
+  if (ai < 0) return;
+  for (int s = prp[i] + l; s < prp[i + 1]; s += G) {
+    const int J = pcol[s];
+    double acc[B * 6];
 #pragma unroll
-    for (int p = 0; p < B; ++p)
+    for (int e = 0; e < B * 6; ++e) acc[e] = 0.0;
+    for (int t = arp[i]; t < arp[i + 1]; ++t) {
+      const int v = acol[t];
+      if (agg[v] != J) continue;
+      const double* A = aval + int64_t(t) * B * B;
+      const double* Q = Pt + int64_t(v) * B * 6;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        double acc = 0.0;
+      for (int p = 0; p < B; ++p)
 #pragma unroll
-        for (int r = 0; r < B; ++r) acc += A[p * B + r] * Q[r * 6 + q];
-        out[p * 6 + q] += acc;
-      }
-  }
-  for (int s = c0; s < c1; ++s) {
+        for (int q = 0; q < 6; ++q) {
+          double a = 0.0;
+#pragma unroll
+          for (int r = 0; r < B; ++r) a += A[p * B + r] * Q[r * 6 + q];
+          acc[p * 6 + q] += a;
+        }
+    }
     double* out = pval + int64_t(s) * B * 6;
 #pragma unroll
     for (int p = 0; p < B; ++p) {
       const double sc = omega / d[int64_t(i) * B + p];
 #pragma unroll
-      for (int q = 0; q < 6; ++q) out[p * 6 + q] = -(out[p * 6 + q] * sc);
+      for (int q = 0; q < 6; ++q) {
+        const double v = -(acc[p * 6 + q] * sc);
+        out[p * 6 + q] = J == ai ? Pt[int64_t(i) * B * 6 + p * 6 + q] + v : v;
+      }
     }
   }
-  const int s = lower_bound_i(pcol, c0, c1, agg[i]);
-  if (s >= c1 || pcol[s] != agg[i]) { atomicOr(flag, 64); return; }
-  double* out = pval + int64_t(s) * B * 6;
-  const double* Q = Pt + int64_t(i) * B * 6;
-  for (int e = 0; e < B * 6; ++e) out[e] = Q[e] + out[e];
 }
 
 void smooth_prolongator(Ctx& c, const BSR& A, const int* agg, int n_agg, const double* Pt,
@@ -608,18 +616,15 @@ void smooth_prolongator(Ctx& c, const BSR& A, const int* agg, int n_agg, const d
   P.br = A.br;
   P.bc = 6;
   P.val.alloc(std::max<int64_t>(P.nnzb, 1) * P.bsz());
-  AMGF_HIP(hipMemsetAsync(P.val.p, 0, P.val.bytes(), c.s));
-  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  constexpr int G = 8;
+  const dim3 g(grid_for(int64_t(n) * G, 256));
   if (A.br == 3)
-    hipLaunchKernelGGL(k_sa_numeric<3>, dim3(grid_for(n, 128)), dim3(128), 0, c.s, n,
-                       A.rowptr.p, A.col.p, A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p,
-                       P.val.p, c.flag.p);
+    hipLaunchKernelGGL((k_sa_numeric<3, G>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
+                       A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p, P.val.p);
   else
-    hipLaunchKernelGGL(k_sa_numeric<6>, dim3(grid_for(n, 128)), dim3(128), 0, c.s, n,
-                       A.rowptr.p, A.col.p, A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p,
-                       P.val.p, c.flag.p);
+    hipLaunchKernelGGL((k_sa_numeric<6, G>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
+                       A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p, P.val.p);
   AMGF_LAUNCH_CHECK();
-  AMGF_REQUIRE(d2h_scalar(c.flag.p, c.s) == 0, AMGF_EDEVICE, "prolongator pattern mismatch");
 }
 
 __global__ void k_nonneg_mask(int n, const int* __restrict__ a, int* __restrict__ m) {
@@ -631,42 +636,59 @@ __global__ void k_nonneg_mask(int n, const int* __restrict__ a, int* __restrict_
 // generic BSR product C = A B, output-stationary
 // ======================================================================================
 // One wavefront per row r, one lane per output block (r, j): the lane walks A's row in
-// ascending order and finds block (k, j) of B by binary search, so each output block
-// accumulates in a fixed order (deterministic) and rows with many blocks spread over
-// the wavefront instead of serialising in one thread.
+// ascending order, so each output block accumulates in a fixed order (deterministic) and
+// rows with many blocks spread over the wavefront.  For each A block (r, k) the wavefront
+// loads the column ids of B's row k once (coalesced, up to 64 at a time) and every lane
+// finds its column j there by a binary search over lanes (shuffles, no dependent loads).
 template <int RA, int KA, int CB>
 __global__ void __launch_bounds__(256) k_spgemm_numeric(
     int nrows, const int* __restrict__ arp, const int* __restrict__ acol,
     const double* __restrict__ aval, const int* __restrict__ brp, const int* __restrict__ bcol,
     const double* __restrict__ bval, const int* __restrict__ crp, const int* __restrict__ ccol,
     double* __restrict__ cval) {
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int r = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (r >= nrows) return;
   const int t0 = arp[r], t1 = arp[r + 1];
-  for (int s = crp[r] + lane; s < crp[r + 1]; s += 64) {
-    const int j = ccol[s];
+  const int s1 = crp[r + 1];
+  for (int sb = crp[r]; sb < s1; sb += 64) {
+    const int s = sb + lane;
+    const bool act = s < s1;
+    const int j = act ? ccol[s] : INT_MAX;
     double acc[RA * CB];
 #pragma unroll
     for (int e = 0; e < RA * CB; ++e) acc[e] = 0.0;
     for (int t = t0; t < t1; ++t) {
       const int k = acol[t];
-      const int u = lower_bound_i(bcol, brp[k], brp[k + 1], j);
-      if (u >= brp[k + 1] || bcol[u] != j) continue;
-      const double* a = aval + int64_t(t) * RA * KA;
-      const double* b = bval + int64_t(u) * KA * CB;
-#pragma unroll
-      for (int p = 0; p < RA; ++p)
-#pragma unroll
-        for (int x = 0; x < KA; ++x) {
-          const double av = a[p * KA + x];
-#pragma unroll
-          for (int q = 0; q < CB; ++q) acc[p * CB + q] += av * b[x * CB + q];
+      const int b0 = brp[k], blen = brp[k + 1] - b0;
+      for (int c0 = 0; c0 < blen; c0 += 64) {
+        const int nb = min(64, blen - c0);
+        const int myc = lane < nb ? bcol[b0 + c0 + lane] : INT_MAX;
+        // pos = number of chunk columns below j (chunk columns ascending)
+        int pos = 0;
+        for (int st = 1 << (31 - __clz(nb)); st > 0; st >>= 1) {
+          const int v = __shfl(myc, min(pos + st - 1, 63), 64);
+          if (pos + st <= nb && v < j) pos += st;
         }
-    }
-    double* out = cval + int64_t(s) * RA * CB;
+        const int hit = __shfl(myc, min(pos, 63), 64);
+        if (!act || pos >= nb || hit != j) continue;
+        const double* a = aval + int64_t(t) * RA * KA;
+        const double* b = bval + int64_t(b0 + c0 + pos) * KA * CB;
 #pragma unroll
-    for (int e = 0; e < RA * CB; ++e) out[e] = acc[e];
+        for (int p = 0; p < RA; ++p)
+#pragma unroll
+          for (int x = 0; x < KA; ++x) {
+            const double av = a[p * KA + x];
+#pragma unroll
+            for (int q = 0; q < CB; ++q) acc[p * CB + q] += av * b[x * CB + q];
+          }
+      }
+    }
+    if (act) {
+      double* out = cval + int64_t(s) * RA * CB;
+#pragma unroll
+      for (int e = 0; e < RA * CB; ++e) out[e] = acc[e];
+    }
   }
 }
 

@@ -281,19 +281,22 @@ void bsr_transpose(Ctx& c, const BSR& A, BSR& T) {
 }
 
 // ======================================================================================
-// symbolic union (one 64-lane workgroup per output row, LDS hash set)
+// symbolic union (one wavefront per output row, LDS hash set)
 // ======================================================================================
-constexpr int HS = 2048;                 // hash slots per row
+// The hash table of a launch has TS slots per row (a power of two at least twice the
+// largest candidate count of any row, at most HS); rows with up to 512 slots share a
+// 256-thread workgroup four at a time, larger tables get one wavefront per workgroup.
+constexpr int HS = 2048;                 // largest hash table per row
 constexpr int HS_MAX_UNIQUE = 1536;      // capacity before the row is rejected
 
 __device__ __forceinline__ void hs_insert(int* table, int* list, int* cnt, int key,
-                                          bool fill, int* flag, unsigned mask) {
+                                          bool fill, int* flag, unsigned mask, int cap) {
   unsigned h = (unsigned(key) * 2654435761u) & mask;
   for (unsigned probe = 0; probe <= mask; ++probe) {
     const int old = atomicCAS(&table[h], -1, key);
     if (old == -1) {
       const int pos = atomicAdd(cnt, 1);
-      if (pos < HS_MAX_UNIQUE) {
+      if (pos < cap) {
         if (fill) list[pos] = key;
       } else {
         atomicOr(flag, 2);
@@ -306,58 +309,91 @@ __device__ __forceinline__ void hs_insert(int* table, int* list, int* cnt, int k
   atomicOr(flag, 2);
 }
 
-__global__ void __launch_bounds__(64) k_union(int nrows, const int* __restrict__ rp1,
-                                              const int* __restrict__ col1,
-                                              const int* __restrict__ rp2,
-                                              const int* __restrict__ col2,
-                                              const int* __restrict__ map, int exclude_diag,
-                                              const int* __restrict__ row_mask, int fill,
-                                              int* __restrict__ counts,
-                                              const int* __restrict__ rowptr,
-                                              int* __restrict__ outcol, int* flag) {
-  __shared__ int table[HS];
-  __shared__ int list[HS_MAX_UNIQUE];
-  __shared__ int cnt;
-  const int r = blockIdx.x;
+__global__ void k_max_int(const int* __restrict__ v, int n, int* __restrict__ mx) {
+  int m = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    m = max(m, v[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(mx, m);
+}
+
+// largest entry of a non-negative int array (0 when empty); waits for the result
+static int max_value(Ctx& c, const int* v, int n) {
+  DBuf<int> mx(1);
+  AMGF_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), c.s));
+  if (n > 0)
+    hipLaunchKernelGGL(k_max_int, dim3(std::min<unsigned>(grid_for(n, 256), 1024)), dim3(256), 0,
+                       c.s, v, n, mx.p);
+  AMGF_LAUNCH_CHECK();
+  return d2h_scalar(mx.p, c.s);
+}
+
+// candidate count of each row (an upper bound of its union size)
+__global__ void k_union_bound(int nrows, const int* __restrict__ rp1,
+                              const int* __restrict__ col1, const int* __restrict__ rp2,
+                              const int* __restrict__ row_mask, int* __restrict__ bound) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int b = 0;
+  if (!row_mask || row_mask[r])
+    for (int t = rp1[r]; t < rp1[r + 1]; ++t) b += rp2 ? rp2[col1[t] + 1] - rp2[col1[t]] : 1;
+  bound[r] = b;
+}
+
+__global__ void __launch_bounds__(256) k_union(int nrows, int ts, int cap,
+                                               const int* __restrict__ rp1,
+                                               const int* __restrict__ col1,
+                                               const int* __restrict__ rp2,
+                                               const int* __restrict__ col2,
+                                               const int* __restrict__ map, int exclude_diag,
+                                               const int* __restrict__ row_mask, int fill,
+                                               int* __restrict__ counts,
+                                               const int* __restrict__ rowptr,
+                                               int* __restrict__ outcol, int* flag) {
+  extern __shared__ int lds[];
+  __shared__ int cnts[4];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = blockIdx.x * (blockDim.x >> 6) + wv;
+  int* table = lds + wv * (ts + cap);
+  int* list = table + ts;
+  int* cnt = &cnts[wv];
   if (r >= nrows) return;
   if ((row_mask && !row_mask[r]) || rp1[r] == rp1[r + 1]) {
-    if (!fill && threadIdx.x == 0) counts[r] = 0;
+    if (!fill && lane == 0) counts[r] = 0;
     return;
   }
-  // table size: next power of two >= 2 x (number of candidates), at most HS
-  int bound = 0;
-  for (int t = rp1[r] + threadIdx.x; t < rp1[r + 1]; t += 64)
-    bound += rp2 ? rp2[col1[t] + 1] - rp2[col1[t]] : 1;
-  bound = wave_sum(bound);
-  unsigned ts = 64;
-  while (ts < 2u * unsigned(bound) && ts < unsigned(HS)) ts <<= 1;
-  const unsigned mask = ts - 1;
-  for (int i = threadIdx.x; i < int(ts); i += 64) table[i] = -1;
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
-  for (int t = rp1[r] + threadIdx.x; t < rp1[r + 1]; t += 64) {
+  const unsigned mask = unsigned(ts) - 1;
+  for (int i = lane; i < ts; i += 64) table[i] = -1;
+  if (lane == 0) *cnt = 0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  for (int t = rp1[r] + lane; t < rp1[r + 1]; t += 64) {
     const int mid = col1[t];
     if (rp2) {
       for (int u = rp2[mid]; u < rp2[mid + 1]; ++u) {
         int cand = col2[u];
         if (map) cand = map[cand];
         if (cand < 0 || (exclude_diag && cand == r)) continue;
-        hs_insert(table, list, &cnt, cand, fill, flag, mask);
+        hs_insert(table, list, cnt, cand, fill, flag, mask, cap);
       }
     } else {
       int cand = map ? map[mid] : mid;
       if (cand < 0 || (exclude_diag && cand == r)) continue;
-      hs_insert(table, list, &cnt, cand, fill, flag, mask);
+      hs_insert(table, list, cnt, cand, fill, flag, mask, cap);
     }
   }
-  __syncthreads();
-  const int n = min(cnt, HS_MAX_UNIQUE);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  const int n = min(*cnt, cap);
   if (!fill) {
-    if (threadIdx.x == 0) counts[r] = n;
+    if (lane == 0) counts[r] = n;
     return;
   }
   const int base = rowptr[r];
-  for (int j = threadIdx.x; j < n; j += 64) {
+  for (int j = lane; j < n; j += 64) {
     const int v = list[j];
     int rank = 0;
     for (int i = 0; i < n; ++i) rank += list[i] < v;
@@ -373,19 +409,32 @@ void union_symbolic(Ctx& c, int nrows, int ncols, const int* rp1, const int* col
   DBuf<int> counts(std::max(nrows, 1));
   C.rowptr.alloc(size_t(nrows) + 1);
   AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
-  if (nrows)
-    hipLaunchKernelGGL(k_union, dim3(nrows), dim3(64), 0, c.s, nrows, rp1, col1, rp2, col2,
-                       map, int(exclude_diag), row_mask, 0, counts.p, nullptr, nullptr,
-                       c.flag.p);
+  if (nrows == 0) {
+    C.nnzb = scan_exclusive(c, counts.p, C.rowptr.p, 0);
+    C.col.alloc(1);
+    return;
+  }
+  // table size from the largest candidate count
+  hipLaunchKernelGGL(k_union_bound, dim3(grid_for(nrows, 256)), dim3(256), 0, c.s, nrows, rp1,
+                     col1, rp2, row_mask, counts.p);
+  AMGF_LAUNCH_CHECK();
+  const int maxb = max_value(c, counts.p, nrows);
+  int ts = 64;
+  while (ts < 2 * maxb && ts < HS) ts <<= 1;
+  const int cap = std::min(HS_MAX_UNIQUE, ts);
+  const int wpg = ts <= 512 ? 4 : 1;                    // rows (wavefronts) per workgroup
+  const size_t lds = size_t(wpg) * (ts + cap) * sizeof(int);
+  const dim3 g((nrows + wpg - 1) / wpg), b(64 * wpg);
+  hipLaunchKernelGGL(k_union, g, b, lds, c.s, nrows, ts, cap, rp1, col1, rp2, col2, map,
+                     int(exclude_diag), row_mask, 0, counts.p, nullptr, nullptr, c.flag.p);
   AMGF_LAUNCH_CHECK();
   int fl = d2h_scalar(c.flag.p, c.s);
   AMGF_REQUIRE(fl == 0, AMGF_ENOMEM, "symbolic product row exceeds the union capacity");
   C.nnzb = scan_exclusive(c, counts.p, C.rowptr.p, nrows);
   C.col.alloc(std::max<int64_t>(C.nnzb, 1));
-  if (nrows && C.nnzb)
-    hipLaunchKernelGGL(k_union, dim3(nrows), dim3(64), 0, c.s, nrows, rp1, col1, rp2, col2,
-                       map, int(exclude_diag), row_mask, 1, nullptr, C.rowptr.p, C.col.p,
-                       c.flag.p);
+  if (C.nnzb)
+    hipLaunchKernelGGL(k_union, g, b, lds, c.s, nrows, ts, cap, rp1, col1, rp2, col2, map,
+                       int(exclude_diag), row_mask, 1, nullptr, C.rowptr.p, C.col.p, c.flag.p);
   AMGF_LAUNCH_CHECK();
 }
 

@@ -19,6 +19,8 @@ struct Level {
   BSR J, JT;                    // contact Jacobian (m x nn, 1 x b) and transpose
   DBuf<int> crows;              // node rows with a contact term (nonempty J^T rows)
   int ncrows = 0;
+  DBuf<int> ccrows;             // nonempty rows of C (levels >= 1)
+  int nccrows = 0;
   BSR P, PT;                    // prolongator to the next level and its transpose
   BSR C;                        // contact term J^T D J of this level (interface rows only)
   Graph G;                      // aggregation graph
@@ -231,6 +233,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
       spgemm(c, Lc.C, Lc.P, CP);
       spgemm(c, Lc.PT, CP, N.C);
       bsr_add(c, N.K, N.C, N.A);
+      N.nccrows = nonempty_rows(c, N.C.rowptr.p, N.nn, N.ccrows);
     }
     nzsum += N.A.nnzb * 36;
     coarse_graph(c, Lc.G, Lc.agg.p, n_agg, moff.p, members.p, Gnext);
@@ -336,6 +339,17 @@ static void coarse_solve(Handle& h, const double* b, double* x) {
   h.coarse.solve(h.ctx, b, x);
 }
 
+// Contact term of a level inside the V-cycle: through J and D on level 0 (the fine
+// interface, where the assembled block would be larger than J), through the assembled
+// Galerkin block C = J^T D J on coarser levels (one kernel instead of two).
+template <class T>
+static void level_contact(Handle& h, Level& L, int mode, const T* x, T* y, const T* w) {
+  if (&L == h.lev[0].get())
+    contact_apply<T, T>(h.ctx, mode, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, x, h.t.p, y, w);
+  else
+    contact_cmat<T, T>(h.ctx, mode, L.C, L.ccrows.p, L.nccrows, x, y, w);
+}
+
 // bracket the launches of kernel class `which` (level 0) when live timing is on
 static void prof_begin(Handle& h, int which) {
   if (h.prof_which != which || h.prof_used + 2 > h.prof_ev.size()) return;
@@ -380,7 +394,7 @@ static void k_spmv(Handle& h, size_t l, int mode, const float* x, float* y, cons
 
 template <class T>
 static void contact(Handle& h, Level& L, int mode, const T* x, T* y, const T* w) {
-  contact_apply<T, T>(h.ctx, mode, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, x, h.t.p, y, w);
+  level_contact<T>(h, L, mode, x, y, w);
 }
 
 // one smoother application on x (x_zero: x = 0 on entry); result in *B.x
@@ -452,16 +466,14 @@ static void vcycle64(Handle& h, size_t l) {
   if (l == 0) prof_begin(h, AMGF_K_PRESMOOTH);
   bsr_spmv<double>(c, SPMV_PRE, L.K, L.K.val.p, nullptr, L.vr.p, L.vb.p, L.w.p, L.vx.p);
   prof_end(h);
-  contact_apply<double, double>(c, CT_SUB_RES, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.vx.p,
-                                h.t.p, L.vr.p, nullptr);
+  level_contact<double>(h, L, CT_SUB_RES, L.vx.p, L.vr.p, nullptr);
   bsr_spmv<double>(c, SPMV_Y, L.PT, L.PT.val.p, L.vr.p, N.vb.p, nullptr, nullptr, nullptr);
   vcycle64(h, l + 1);
   bsr_spmv<double>(c, SPMV_ADD, L.P, L.P.val.p, N.vx.p, L.vx.p, nullptr, nullptr, nullptr);
   if (l == 0) prof_begin(h, AMGF_K_POSTSMOOTH);
   bsr_spmv<double>(c, SPMV_POST, L.K, L.K.val.p, L.vx.p, nullptr, L.vb.p, L.w.p, L.vxn.p);
   prof_end(h);
-  contact_apply<double, double>(c, CT_SUB_W, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.vx.p,
-                                h.t.p, L.vxn.p, L.w.p);
+  level_contact<double>(h, L, CT_SUB_W, L.vx.p, L.vxn.p, L.w.p);
   std::swap(L.vx, L.vxn);
 }
 
@@ -483,8 +495,7 @@ static void vcycle32(Handle& h, size_t l) {
   else
     bsr_spmv<float>(c, SPMV_PRE, L.K, L.K.val32.p, nullptr, L.fr.p, L.fb.p, L.w32.p, L.fx.p);
   prof_end(h);
-  contact_apply<float, float>(c, CT_SUB_RES, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.fx.p,
-                              h.t.p, L.fr.p, nullptr);
+  level_contact<float>(h, L, CT_SUB_RES, L.fx.p, L.fr.p, nullptr);
   bsr_spmv<float>(c, SPMV_Y, L.PT, L.PT.val32.p, L.fr.p, N.fb.p, nullptr, nullptr, nullptr);
   vcycle32(h, l + 1);
   bsr_spmv<float>(c, SPMV_ADD, L.P, L.P.val32.p, N.fx.p, L.fx.p, nullptr, nullptr, nullptr);
@@ -494,8 +505,7 @@ static void vcycle32(Handle& h, size_t l) {
   else
     bsr_spmv<float>(c, SPMV_POST, L.K, L.K.val32.p, L.fx.p, nullptr, L.fb.p, L.w32.p, L.fxn.p);
   prof_end(h);
-  contact_apply<float, float>(c, CT_SUB_W, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, L.fx.p,
-                              h.t.p, L.fxn.p, L.w32.p);
+  level_contact<float>(h, L, CT_SUB_W, L.fx.p, L.fxn.p, L.w32.p);
   std::swap(L.fx, L.fxn);
 }
 

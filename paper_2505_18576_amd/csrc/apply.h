@@ -34,6 +34,11 @@ enum ContactMode { CT_SUB_RES = 0, CT_SUB_W = 1, CT_ADD = 2 };
 template <class TX, class TY>
 void contact_apply(Ctx& c, int mode, const BSR& J, const BSR& JT, const int* crows, int ncrows,
                    const double* D, const TX* x, double* t, TY* y, const TY* w);
+// the same three modes with the assembled contact block C of a coarse level (6x6 FP64
+// BSR) applied to its listed nonempty rows
+template <class TX, class TY>
+void contact_cmat(Ctx& c, int mode, const BSR& C, const int* rows, int nrows, const TX* x,
+                  TY* y, const TY* w);
 // indices of the nonempty rows of a CSR pattern
 int nonempty_rows(Ctx& c, const int* rp, int n, DBuf<int>& rows);
 // y = b - A x on the listed block rows only (FP64, 3x3 blocks)

@@ -483,6 +483,69 @@ template void contact_apply<double, float>(Ctx&, int, const BSR&, const BSR&, co
                                            const double*, const double*, double*, float*,
                                            const float*);
 
+// Coarse-level contact term from its assembled block C = J^T D J (FP64 BSR, B x B
+// blocks): one wavefront per listed row, lanes over the row's blocks, then y (op)= C x.
+template <int B, class TX, class TY, int MODE>
+__global__ void __launch_bounds__(256) k_contact_c(int nrows, const int* __restrict__ rows,
+                                                   const int* __restrict__ rp,
+                                                   const int* __restrict__ col,
+                                                   const double* __restrict__ val,
+                                                   const TX* __restrict__ x,
+                                                   TY* __restrict__ y,
+                                                   const TY* __restrict__ w) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= nrows) return;
+  const int a = rows[i];
+  double acc[B];
+#pragma unroll
+  for (int p = 0; p < B; ++p) acc[p] = 0.0;
+  for (int k = rp[a] + lane; k < rp[a + 1]; k += 64) {
+    const double* v = val + int64_t(k) * B * B;
+    const int64_t base = int64_t(col[k]) * B;
+    double xq[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) xq[q] = double(x[base + q]);
+#pragma unroll
+    for (int p = 0; p < B; ++p)
+#pragma unroll
+      for (int q = 0; q < B; ++q) acc[p] += v[p * B + q] * xq[q];
+  }
+#pragma unroll
+  for (int p = 0; p < B; ++p) acc[p] = wave_sum(acc[p]);
+  if (lane >= B) return;
+  double cv = 0.0;
+#pragma unroll
+  for (int p = 0; p < B; ++p)
+    if (lane == p) cv = acc[p];
+  const int64_t ix = int64_t(a) * B + lane;
+  if (MODE == CT_SUB_RES) y[ix] = TY(double(y[ix]) - cv);
+  else if (MODE == CT_SUB_W) y[ix] = TY(double(y[ix]) - double(w[ix]) * cv);
+  else y[ix] = TY(double(y[ix]) + cv);
+}
+
+template <class TX, class TY>
+void contact_cmat(Ctx& c, int mode, const BSR& C, const int* rows, int nrows, const TX* x,
+                  TY* y, const TY* w) {
+  if (nrows == 0 || C.nnzb == 0) return;
+  AMGF_REQUIRE(C.br == 6 && C.bc == 6, AMGF_EINVAL, "coarse contact block size");
+  const dim3 g(grid_for(nrows, 4)), blk(256);
+  if (mode == CT_SUB_RES)
+    hipLaunchKernelGGL((k_contact_c<6, TX, TY, CT_SUB_RES>), g, blk, 0, c.s, nrows, rows,
+                       C.rowptr.p, C.col.p, C.val.p, x, y, w);
+  else if (mode == CT_SUB_W)
+    hipLaunchKernelGGL((k_contact_c<6, TX, TY, CT_SUB_W>), g, blk, 0, c.s, nrows, rows,
+                       C.rowptr.p, C.col.p, C.val.p, x, y, w);
+  else
+    hipLaunchKernelGGL((k_contact_c<6, TX, TY, CT_ADD>), g, blk, 0, c.s, nrows, rows,
+                       C.rowptr.p, C.col.p, C.val.p, x, y, w);
+  AMGF_LAUNCH_CHECK();
+}
+template void contact_cmat<double, double>(Ctx&, int, const BSR&, const int*, int, const double*,
+                                           double*, const double*);
+template void contact_cmat<float, float>(Ctx&, int, const BSR&, const int*, int, const float*,
+                                         float*, const float*);
+
 // nonempty rows of a CSR (compact list)
 __global__ void k_nonempty_flag(int n, const int* __restrict__ rp, int* __restrict__ f) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

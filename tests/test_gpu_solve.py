@@ -117,3 +117,25 @@ def test_pcg_run_to_run_bitwise():
     assert i1.iterations == i2.iterations
     assert np.array_equal(x1.cpu().numpy().view(np.uint64), x2.cpu().numpy().view(np.uint64))
     h.close()
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(precision=1), dict(smoother=1)])
+def test_three_level_vcycle_and_apply_match_oracle(kw):
+    """C2 has a smoothed coarse level between level 0 and the coarsest one, so its contact
+    term goes through the assembled coarse block C = J^T D J."""
+    oo = {"smoother": "chebyshev"} if kw.get("smoother") == 1 else {}
+    o = oracle("C2", **oo)
+    h = gpu("C2", **kw)
+    assert h.n_levels >= 3 and o.nlev == h.n_levels
+    rng = np.random.default_rng(12)
+    r = rng.standard_normal(o.n)
+    e_b = rel(h.vcycle(r).cpu().numpy(), o.vcycle(r))
+    e_m = rel(h.apply(r).cpu().numpy(), o.apply(r))
+    print(f"C2 {kw}: levels {h.n_levels}, vcycle rel {e_b:.2e}, apply rel {e_m:.2e}")
+    tol = 1e-4 if kw.get("precision") else 1e-10
+    assert e_b <= tol
+    # the residual r - A z inside M cancels on contact rows: FP64 error about u * D_max |z|
+    u = np.finfo(np.float64).eps / 2
+    dmax = float(problem("C2").D.max())
+    assert e_m <= max(1e-4 if kw.get("precision") else 0.0, 10 * u * dmax)
+    h.close()

@@ -78,13 +78,14 @@ def smoother_bytes(h, vbytes, kbytes=None):
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "presmooth_sell3_f32_C5_counters.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2505_18576_amd", "csrc", "apply.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2505_18576_amd", "csrc", "sell.hip")
 
 
 def measured_traffic():
     """HBM bytes per pre-smooth launch from the committed FETCH_SIZE / WRITE_SIZE summary,
     each scaled by the same counter's reading for a plain copy of known size; None when
-    the summary is missing or the kernel source changed after the counters were taken."""
+    the summary is missing or the kernels' source (sell.hip) changed after the counters
+    were taken."""
     import hashlib
     if not os.path.exists(COUNTERS):
         return None

@@ -21,6 +21,10 @@ void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, co
 // Build the sliced-ELL copy (FP64 values when fp64, FP32 values when fp32) of a 3x3
 // BSR matrix; bsr_spmv then reads it in place of the BSR arrays.
 void bsr_build_sell(Ctx& c, BSR& A, bool fp64, bool fp32, bool bf16 = false);
+// SpMV modes on a sliced copy with T values (the dispatch of bsr_spmv uses it)
+template <class T>
+void sell3_spmv(Ctx& c, int mode, const BSR& A, const T* sval, const T* x, T* y, const T* b,
+                const T* w, T* xo);
 // SpMV modes on the BF16 sliced copy, FP32 vectors and FP32 accumulation
 void sell_spmv_bf16(Ctx& c, int mode, const BSR& A, const float* x, float* y, const float* b,
                     const float* w, float* xo);

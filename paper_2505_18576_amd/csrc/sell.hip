@@ -1,0 +1,256 @@
+// Sliced-ELL copies of the level-0 stiffness and their SpMV kernels (FP64, FP32 and
+// BF16 values): the V-cycle's smoothing steps and the CG operator spend most of the
+// solve here.
+#include <climits>
+
+#include "apply.h"
+
+namespace amgf {
+
+// ======================================================================================
+// Sliced-ELL SpMV for 3x3 blocks: one wave per slice of 64 block rows, lane i owns row
+// 64 s + i.  For every slot the wave reads 64 column ids (256 B), 9 x 64 values
+// (contiguous) and the three x entries of each column; neighbouring rows of a structured
+// mesh have neighbouring columns, so the x reads coalesce too.  No cross-lane reduction.
+// ======================================================================================
+template <class T, int MODE>
+__global__ void __launch_bounds__(256) k_sell3(int nrows, const int* __restrict__ off,
+                                               const int* __restrict__ scol,
+                                               const T* __restrict__ sval,
+                                               const T* __restrict__ x, T* __restrict__ y,
+                                               const T* __restrict__ b,
+                                               const T* __restrict__ w, T* __restrict__ xo) {
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int i = threadIdx.x & 63;
+  if (int64_t(s) * 64 >= nrows) return;
+  const int o0 = off[s];
+  const int len = (off[s + 1] - o0) >> 6;
+  const int* cp = scol + o0 + i;
+  const T* vp = sval + int64_t(o0) * 9 + i;
+  T a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll 3
+  for (int j = 0; j < len; ++j) {
+    const int64_t cc = int64_t(cp[j * 64]) * 3;
+    T x0, x1, x2;
+    if (MODE == SPMV_PRE) {
+      x0 = w[cc] * b[cc];
+      x1 = w[cc + 1] * b[cc + 1];
+      x2 = w[cc + 2] * b[cc + 2];
+    } else {
+      x0 = x[cc];
+      x1 = x[cc + 1];
+      x2 = x[cc + 2];
+    }
+    const T* v = vp + int64_t(j) * 576;
+    a0 += v[0] * x0 + v[64] * x1 + v[128] * x2;
+    a1 += v[192] * x0 + v[256] * x1 + v[320] * x2;
+    a2 += v[384] * x0 + v[448] * x1 + v[512] * x2;
+  }
+  const int r = s * 64 + i;
+  if (r >= nrows) return;
+  const T ax[3] = {a0, a1, a2};
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const int64_t k = int64_t(r) * 3 + p;
+    if (MODE == SPMV_Y) y[k] = ax[p];
+    else if (MODE == SPMV_ADD) y[k] += ax[p];
+    else if (MODE == SPMV_PRE) {
+      const T bk = b[k];
+      xo[k] = w[k] * bk;
+      y[k] = bk - ax[p];
+    } else if (MODE == SPMV_POST) {
+      xo[k] = x[k] + w[k] * (b[k] - ax[p]);
+    } else {
+      y[k] = b[k] - ax[p];
+    }
+  }
+}
+
+__device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_sell3_bf16(int nrows, const int* __restrict__ off,
+                                                    const int* __restrict__ scol,
+                                                    const uint16_t* __restrict__ sval,
+                                                    const float* __restrict__ x,
+                                                    float* __restrict__ y,
+                                                    const float* __restrict__ b,
+                                                    const float* __restrict__ w,
+                                                    float* __restrict__ xo) {
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int i = threadIdx.x & 63;
+  if (int64_t(s) * 64 >= nrows) return;
+  const int o0 = off[s];
+  const int len = (off[s + 1] - o0) >> 6;
+  const int* cp = scol + o0 + i;
+  const uint16_t* vs = sval + int64_t(o0) * 9;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll 3
+  for (int j = 0; j < len; ++j) {
+    const int64_t cc = int64_t(cp[j * 64]) * 3;
+    float x0, x1, x2;
+    if (MODE == SPMV_PRE) {
+      x0 = w[cc] * b[cc];
+      x1 = w[cc + 1] * b[cc + 1];
+      x2 = w[cc + 2] * b[cc + 2];
+    } else {
+      x0 = x[cc];
+      x1 = x[cc + 1];
+      x2 = x[cc + 2];
+    }
+    const uint16_t* slot = vs + int64_t(j) * 576;
+    const uint32_t* pr = reinterpret_cast<const uint32_t*>(slot) + i;
+    const uint32_t e01 = pr[0], e23 = pr[64], e45 = pr[128], e67 = pr[192];
+    const float e8 = __uint_as_float(uint32_t(slot[512 + i]) << 16);
+    a0 += bf16_lo(e01) * x0 + bf16_hi(e01) * x1 + bf16_lo(e23) * x2;
+    a1 += bf16_hi(e23) * x0 + bf16_lo(e45) * x1 + bf16_hi(e45) * x2;
+    a2 += bf16_lo(e67) * x0 + bf16_hi(e67) * x1 + e8 * x2;
+  }
+  const int r = s * 64 + i;
+  if (r >= nrows) return;
+  const float ax[3] = {a0, a1, a2};
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const int64_t k = int64_t(r) * 3 + p;
+    if (MODE == SPMV_Y) y[k] = ax[p];
+    else if (MODE == SPMV_ADD) y[k] += ax[p];
+    else if (MODE == SPMV_PRE) {
+      const float bk = b[k];
+      xo[k] = w[k] * bk;
+      y[k] = bk - ax[p];
+    } else if (MODE == SPMV_POST) {
+      xo[k] = x[k] + w[k] * (b[k] - ax[p]);
+    } else {
+      y[k] = b[k] - ax[p];
+    }
+  }
+}
+
+// FP64 -> BF16 with one rounding to nearest even: truncate to FP32, mark inexactness in
+// the last bit (round to odd, 16 spare bits), then round the FP32 bits to BF16.
+__device__ __forceinline__ uint16_t bf16_rne(double v) {
+  float f = __double2float_rz(v);
+  uint32_t u = __float_as_uint(f);
+  if (double(f) != v) u |= 1u;
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+__global__ void k_sell_len(int nrows, int nslices, const int* __restrict__ rp,
+                           int* __restrict__ len) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > nslices) return;
+  if (s == nslices) { len[s] = 0; return; }
+  int m = 0;
+  const int r1 = min(nrows, (s + 1) * 64);
+  for (int r = s * 64; r < r1; ++r) m = max(m, rp[r + 1] - rp[r]);
+  len[s] = m * 64;
+}
+
+// one wave per slice; lane i copies row 64 s + i slot by slot
+__global__ void __launch_bounds__(64) k_sell_fill(int nrows, const int* __restrict__ rp,
+                                                  const int* __restrict__ col,
+                                                  const double* __restrict__ val,
+                                                  const int* __restrict__ off,
+                                                  int* __restrict__ scol,
+                                                  double* __restrict__ sv,
+                                                  float* __restrict__ sv32,
+                                                  uint16_t* __restrict__ sv16) {
+  const int s = blockIdx.x, i = threadIdx.x;
+  const int r = s * 64 + i;
+  const int o0 = off[s], len = (off[s + 1] - o0) >> 6;
+  const int rr = min(r, nrows - 1);
+  const int j0 = r < nrows ? rp[r] : 0, n = r < nrows ? rp[r + 1] - j0 : 0;
+  for (int j = 0; j < len; ++j) {
+    const int64_t slot = int64_t(o0) + int64_t(j) * 64;
+    scol[slot + i] = j < n ? col[j0 + j] : rr;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      const double v = j < n ? val[int64_t(j0 + j) * 9 + e] : 0.0;
+      const int64_t k = slot * 9 + e * 64 + i;
+      if (sv) sv[k] = v;
+      if (sv32) sv32[k] = float(v);
+      if (sv16) {
+        // pairs (2q, 2q+1) packed in uint32 q of the slot, entry 8 after the pairs
+        const int64_t e16 = e < 8 ? slot * 9 + (e >> 1) * 128 + 2 * i + (e & 1)
+                                  : slot * 9 + 512 + i;
+        sv16[e16] = bf16_rne(v);
+      }
+    }
+  }
+}
+
+void bsr_build_sell(Ctx& c, BSR& A, bool fp64, bool fp32, bool bf16) {
+  AMGF_REQUIRE(A.br == 3 && A.bc == 3, AMGF_EINVAL, "sliced ELL needs 3x3 blocks");
+  if (A.nrows == 0) return;
+  const int ns = (A.nrows + 63) / 64;
+  DBuf<int> len(ns + 1);
+  hipLaunchKernelGGL(k_sell_len, dim3(grid_for(ns + 1, 256)), dim3(256), 0, c.s, A.nrows, ns,
+                     A.rowptr.p, len.p);
+  AMGF_LAUNCH_CHECK();
+  A.sell_off.alloc(ns + 2);
+  const int total = scan_exclusive(c, len.p, A.sell_off.p, ns + 1);
+  A.sell_col.alloc(size_t(total));
+  if (fp64) A.sell_val.alloc(size_t(total) * 9);
+  if (fp32) A.sell_val32.alloc(size_t(total) * 9);
+  if (bf16) A.sell_val16.alloc(size_t(total) * 9);
+  hipLaunchKernelGGL(k_sell_fill, dim3(ns), dim3(64), 0, c.s, A.nrows, A.rowptr.p, A.col.p,
+                     A.val.p, A.sell_off.p, A.sell_col.p, A.sell_val.p, A.sell_val32.p,
+                     A.sell_val16.p);
+  AMGF_LAUNCH_CHECK();
+}
+
+template <class T>
+void sell3_spmv(Ctx& c, int mode, const BSR& A, const T* sval, const T* x, T* y, const T* b,
+                const T* w, T* xo) {
+  const int ns = (A.nrows + 63) / 64;
+  const dim3 g((ns + 3) / 4), blk(256);
+  switch (mode) {
+#define AMGF_MODE(MD)                                                                        \
+  case MD:                                                                                   \
+    hipLaunchKernelGGL((k_sell3<T, MD>), g, blk, 0, c.s, A.nrows, A.sell_off.p, A.sell_col.p, \
+                       sval, x, y, b, w, xo);                                                \
+    break;
+    AMGF_MODE(SPMV_Y)
+    AMGF_MODE(SPMV_ADD)
+    AMGF_MODE(SPMV_PRE)
+    AMGF_MODE(SPMV_POST)
+    AMGF_MODE(SPMV_RES)
+#undef AMGF_MODE
+    default:
+      throw Error(AMGF_EINVAL, "spmv mode");
+  }
+  AMGF_LAUNCH_CHECK();
+}
+
+template void sell3_spmv<double>(Ctx&, int, const BSR&, const double*, const double*, double*,
+                                 const double*, const double*, double*);
+template void sell3_spmv<float>(Ctx&, int, const BSR&, const float*, const float*, float*,
+                                const float*, const float*, float*);
+
+void sell_spmv_bf16(Ctx& c, int mode, const BSR& A, const float* x, float* y, const float* b,
+                    const float* w, float* xo) {
+  AMGF_REQUIRE(A.sell_val16.p, AMGF_EINVAL, "no BF16 sliced copy");
+  if (A.nrows == 0) return;
+  const int ns = (A.nrows + 63) / 64;
+  const dim3 g((ns + 3) / 4), blk(256);
+  switch (mode) {
+#define AMGF_MODE(MD)                                                                        \
+  case MD:                                                                                   \
+    hipLaunchKernelGGL((k_sell3_bf16<MD>), g, blk, 0, c.s, A.nrows, A.sell_off.p,            \
+                       A.sell_col.p, A.sell_val16.p, x, y, b, w, xo);                        \
+    break;
+    AMGF_MODE(SPMV_Y)
+    AMGF_MODE(SPMV_ADD)
+    AMGF_MODE(SPMV_PRE)
+    AMGF_MODE(SPMV_POST)
+    AMGF_MODE(SPMV_RES)
+#undef AMGF_MODE
+    default:
+      throw Error(AMGF_EINVAL, "spmv mode");
+  }
+  AMGF_LAUNCH_CHECK();
+}
+
+}  // namespace amgf

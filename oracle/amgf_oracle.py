@@ -594,6 +594,36 @@ class OracleAMGF:
         self.coarse_chol = sla.cho_factor(self.coarse_dense, lower=True)
         self._setup_filter()
 
+    # ---------------------------------------------------------------- new barrier diagonal
+    def update_D(self, D):
+        """Numeric re-setup for a new interior-point step (same K and J, new D).
+
+        The aggregates, prolongators P_l, coarse stiffness K_{l+1} = P_l^T K_l P_l and coarse
+        Jacobians J_{l+1} = J_l P_l are kept; the operators A_l = K_l + J_l^T D J_l, their l1
+        norms, the smoother weights, the spectral estimates, the coarsest factor and the
+        filter factor are recomputed for the new D.  A_{l+1} = P_l^T A_l P_l still holds, so
+        B stays a Galerkin V-cycle and M the AMGF operator of Definition 5.3 for the new
+        Schur complement."""
+        o = self.opts
+        self.D = np.asarray(D, np.float64)
+        for l, lev in enumerate(self.levels):
+            if l == 0:
+                lev.A = schur_operator(self.K0, self.J0, self.D)
+                self.S = lev.A
+            else:
+                lev.A = block_add(lev.K, contact_product(lev.J, self.D))
+            Acsr = lev.A.csr()
+            lev.d = np.asarray(abs(Acsr).sum(axis=1)).ravel()
+            th = 1.0 if o.theta is None else np.asarray(o.theta[l], float)
+            lev.w = th / lev.d
+            if l + 1 < self.nlev:
+                dec = lev.decoupled if l == 0 else np.zeros(lev.A.nrows * lev.A.br, bool)
+                lev.lam = power_estimate(Acsr, lev.d, dec, o.sa_power_iters, clip=False)
+        last = self.levels[-1]
+        self.coarse_dense = last.A.todense()
+        self.coarse_chol = sla.cho_factor(self.coarse_dense, lower=True)
+        self._setup_filter()
+
     # ---------------------------------------------------------------- level-0 helpers
     def _decoupled_dofs(self, Acsr):
         """DOFs whose row has no nonzero off-diagonal entry (e.g. Dirichlet DOFs)."""

@@ -114,6 +114,15 @@ amgf_status amgf_setup(const amgf_options* opts, int32_t n_nodes,
  * FP64 device vectors (may not alias).  With filter = 0, z = B r.            */
 amgf_status amgf_apply(amgf_handle h, const double* r, double* z, void* stream);
 
+/* New interior-point step: replace the barrier diagonal D (m FP64 values > 0, device,
+ * copied) while K and J stay (Sec. 3, the Newton systems of one IP solve differ in D
+ * only).  Numeric re-setup: the aggregates, prolongators, coarse stiffness and coarse
+ * Jacobians are kept; A_l = K_l + J_l^T D J_l, the l1 norms, smoother weights (and learned
+ * damping), spectral estimates, the coarsest factor and the filter factor are rebuilt, so
+ * every A_{l+1} = P_l^T A_l P_l still holds.  EINVAL for D <= 0 or non-finite entries
+ * (the handle is unchanged then); ENOTSPD if a factor loses definiteness.             */
+amgf_status amgf_update_D(amgf_handle h, const double* D, void* stream);
+
 /* w_c = A_w^{-1} r_c with A_w = S[I_c, I_c], the filtering-space solve of Definition 5.3
  * (Sec. 5.1), by the handle's nested-dissection multifrontal Cholesky factor.  r_c, w_c:
  * n_c FP64 device vectors in the order of I_c (may not alias).  EINVAL when the handle

@@ -25,7 +25,8 @@ ABI_FUNCTIONS = ["amgf_default_options", "amgf_setup", "amgf_apply", "amgf_vcycl
                  "amgf_operator_apply", "amgf_pcg", "amgf_destroy", "amgf_status_string",
                  "amgf_last_error", "amgf_num_levels", "amgf_query", "amgf_time_kernel",
                  "amgf_set_mlp", "amgf_mlp_loss_grad", "amgf_adam_step",
-                 "amgf_profile_start", "amgf_profile_read", "amgf_filter_solve"]
+                 "amgf_profile_start", "amgf_profile_read", "amgf_filter_solve",
+                 "amgf_update_D"]
 K_PRESMOOTH, K_POSTSMOOTH, K_VCYCLE, K_OPERATOR = range(4)
 
 
@@ -93,6 +94,8 @@ def load_library(path=LIB_PATH):
     L.amgf_mlp_loss_grad.restype = ctypes.c_int
     L.amgf_adam_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp]
     L.amgf_adam_step.restype = ctypes.c_int
+    L.amgf_update_D.argtypes = [vp, vp, vp]
+    L.amgf_update_D.restype = ctypes.c_int
     L.amgf_profile_start.argtypes = [vp, i32, i32]
     L.amgf_profile_start.restype = ctypes.c_int
     L.amgf_profile_read.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
@@ -202,6 +205,13 @@ class AMGF:
 
     def apply(self, r):
         return self._vec_op(self.L.amgf_apply, r, "amgf_apply")
+
+    def update_D(self, D):
+        """New interior-point step: same K and J, new barrier diagonal D (m values > 0)."""
+        torch = _torch()
+        Dd = _dev(D, torch.float64)
+        _check(self.L.amgf_update_D(self.h, _ptr(Dd), _stream()), "amgf_update_D")
+        torch.cuda.synchronize()
 
     def filter_solve(self, rc):
         """w_c = A_w^{-1} r_c on the filtering space (vectors in the order of I_c)."""

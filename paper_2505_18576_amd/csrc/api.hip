@@ -130,6 +130,40 @@ static void to_fp32(Ctx& c, BSR& A) {
 }
 
 // ------------------------------------------------------------------------------------
+// setup pieces shared with the numeric re-setup of a new barrier diagonal
+// ------------------------------------------------------------------------------------
+// direct factor of the coarsest operator
+static void factor_coarsest(Handle& h) {
+  Level& LL = *h.lev.back();
+  DBuf<int> rp, cl;
+  DBuf<double> vl;
+  bsr_to_csr(h.ctx, LL.A, rp, cl, vl);
+  h.coarse.setup(h.ctx, int(LL.n()), LL.b, rp.p, cl.p, vl.p);
+}
+
+// A_w = S[I_c, I_c] and its factor
+static void factor_filter(Handle& h) {
+  Level& L0 = *h.lev[0];
+  filter_csr(h.ctx, L0.A, h.Ic.p, h.n_c, h.aw_rp, h.aw_col, h.aw_val);
+  h.aw.setup(h.ctx, h.n_c, h.ic_closed ? 3 : 1, h.aw_rp.p, h.aw_col.p, h.aw_val.p);
+}
+
+// features of every smoothed level and, with learned damping, w = theta/d from the MLP
+static void features_and_damping(Handle& h) {
+  Ctx& c = h.ctx;
+  const int nlev = int(h.lev.size());
+  for (int l = 0; l + 1 < nlev; ++l) {
+    Level& L = *h.lev[l];
+    L.F.alloc(size_t(6) * L.n());
+    L.theta.alloc(L.n());
+    level_features(c, L.b, L.nn, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.d.p, L.JT.rowptr.p,
+                   L.JT.col.p, L.JT.val.p, h.D.p, nlev > 1 ? double(l) / double(nlev - 1) : 0.0,
+                   L.F.p);
+    if (h.learned) mlp_theta(c, L.n(), h.mlpW.p, L.F.p, L.d.p, L.theta.p, L.w.p);
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // setup
 // ------------------------------------------------------------------------------------
 static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, const double* K_val,
@@ -243,12 +277,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   // ---- coarsest level: direct multifrontal Cholesky
   Level& LL = *h.lev.back();
   h.nc_dense = int(LL.n());
-  {
-    DBuf<int> rp, cl;
-    DBuf<double> vl;
-    bsr_to_csr(c, LL.A, rp, cl, vl);
-    h.coarse.setup(c, h.nc_dense, LL.b, rp.p, cl.p, vl.p);
-  }
+  factor_coarsest(h);
   h.coarse_b.alloc(h.nc_dense);
   h.coarse_x.alloc(h.nc_dense);
   // ---- filter (Sec. 5.1): A_w = S[I_c, I_c], nested-dissection multifrontal Cholesky
@@ -279,33 +308,20 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     AMGF_HIP(hipStreamSynchronize(c.s));
   }
   if (o.filter && h.n_c > 0) {
-    filter_csr(c, L0->A, h.Ic.p, h.n_c, h.aw_rp, h.aw_col, h.aw_val);
-    h.aw.setup(c, h.n_c, h.ic_closed ? 3 : 1, h.aw_rp.p, h.aw_col.p, h.aw_val.p);
+    factor_filter(h);
     h.f_r.alloc(h.n_c);
     h.f_w.alloc(h.n_c);
     h.f_res.alloc(h.n_c);
     h.f_dw.alloc(h.n_c);
   }
   // ---- learned-smoother features of the smoothed levels
-  const int nlev = int(h.lev.size());
-  for (int l = 0; l + 1 < nlev; ++l) {
-    Level& L = *h.lev[l];
-    L.F.alloc(size_t(6) * L.n());
-    L.theta.alloc(L.n());
-    level_features(c, L.b, L.nn, L.A.rowptr.p, L.A.col.p, L.A.val.p, L.d.p, L.JT.rowptr.p,
-                   L.JT.col.p, L.JT.val.p, h.D.p, nlev > 1 ? double(l) / double(nlev - 1) : 0.0,
-                   L.F.p);
-  }
   if (o.smoother == AMGF_LEARNED) {
     h.mlpW.alloc(MLP_NTOTAL);
     AMGF_HIP(hipMemcpyAsync(h.mlpW.p, o.mlp_weights, sizeof(float) * MLP_NTOTAL,
                             hipMemcpyHostToDevice, c.s));
     h.learned = true;
-    for (int l = 0; l + 1 < nlev; ++l) {
-      Level& L = *h.lev[l];
-      mlp_theta(c, L.n(), h.mlpW.p, L.F.p, L.d.p, L.theta.p, L.w.p);
-    }
   }
+  features_and_damping(h);
   // ---- precision copies and work vectors
   for (size_t l = 0; l < h.lev.size(); ++l) {
     Level& L = *h.lev[l];
@@ -329,6 +345,46 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   h.z1.alloc(n); h.ra.alloc(n); h.r2.alloc(n); h.z3.alloc(n);
   if (h.mixed()) { h.zf.alloc(n); h.r2f.alloc(n); }
   h.pr.alloc(n); h.pz.alloc(n); h.pzo.alloc(n); h.pp.alloc(n); h.pq.alloc(n);
+  AMGF_HIP(hipStreamSynchronize(c.s));
+}
+
+// ------------------------------------------------------------------------------------
+// numeric re-setup for a new barrier diagonal (same K, J; aggregates and P kept)
+// ------------------------------------------------------------------------------------
+static void update_D(Handle& h, const double* D) {
+  Ctx& c = h.ctx;
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  if (h.m > 0) check_values(c, D, h.m, true, c.flag.p);
+  const int fl = d2h_scalar(c.flag.p, c.s);
+  AMGF_REQUIRE(fl == 0, AMGF_EINVAL, (fl & 2) ? "D must be positive" : "non-finite value in D");
+  copy_in(c, h.D.p, D, sizeof(double) * size_t(h.m));
+  const size_t nlev = h.lev.size();
+  for (size_t l = 0; l < nlev; ++l) {
+    Level& L = *h.lev[l];
+    if (l == 0) {
+      L.C = BSR();
+      contact_operator(c, L.J, L.JT, h.D.p, L.C);
+    } else {
+      Level& U = *h.lev[l - 1];
+      BSR CP;
+      spgemm(c, U.C, U.P, CP);
+      L.C = BSR();
+      spgemm(c, U.PT, CP, L.C);
+    }
+    L.A = BSR();
+    bsr_add(c, L.K, L.C, L.A);
+    l1_norms(c, L.A, L.d);
+    weights_from_l1(c, L.n(), L.d.p, nullptr, L.w.p);
+    if (l + 1 < nlev) L.lam = power_estimate(h, L, l == 0 ? h.dec0.p : nullptr);
+  }
+  factor_coarsest(h);
+  if (h.opt.filter && h.n_c > 0) factor_filter(h);
+  features_and_damping(h);
+  if (h.mixed())
+    for (size_t l = 0; l < nlev; ++l) {
+      Level& L = *h.lev[l];
+      cast_d2f(c, L.w.p, L.w32.p, L.n());
+    }
   AMGF_HIP(hipStreamSynchronize(c.s));
 }
 
@@ -993,6 +1049,15 @@ amgf_status amgf_apply(amgf_handle hd, const double* r, double* z, void* stream)
   });
   if (st_ != AMGF_OK) return st_;
   return AMGF_OK;
+}
+
+amgf_status amgf_update_D(amgf_handle hd, const double* D, void* stream) {
+  if (!hd || (!D && hd->h.m > 0)) return AMGF_EINVAL;
+  return guard([&]() -> amgf_status {
+    hd->h.ctx.s = static_cast<hipStream_t>(stream);
+    amgf::update_D(hd->h, D);
+    return AMGF_OK;
+  });
 }
 
 amgf_status amgf_filter_solve(amgf_handle hd, const double* rc, double* wc, void* stream) {

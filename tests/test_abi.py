@@ -11,7 +11,7 @@ HEADER = os.path.join(ROOT, "include", "amgf.h")
 def _declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"\b(amgf_[a-z_0-9]+)\s*\(", src)
+    names = re.findall(r"\b(amgf_[A-Za-z_0-9]+)\s*\(", src)
     return sorted(set(names))
 
 

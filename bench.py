@@ -199,6 +199,7 @@ def main():
             live_ms = (live_ms * live_n + avg * cnt) / max(1, live_n + cnt)
             live_n += cnt
             log(f"{mode} step {s}: {times[-1]:.3f}s, {info.iterations} it, "
+                f"setup {info.ms_setup_amg:.1f} + {info.ms_setup_filter:.1f} ms, "
                 f"solve {info.ms_solve:.1f} ms, rel prec res {info.rel_prec_res:.2e}, "
                 f"true res {info.rel_true_res:.2e}, levels {info.n_levels}, "
                 f"op complexity {info.op_complexity:.3f}, fallback {info.used_fallback}")
@@ -212,6 +213,8 @@ def main():
         res[mode] = dict(s_per_solve=float(np.mean(times)), iterations=int(info.iterations),
                          converged=bool(info.converged), ms_solve=float(info.ms_solve),
                          used_fallback=int(info.used_fallback),
+                         ms_setup_amg=float(info.ms_setup_amg),
+                         ms_setup_filter=float(info.ms_setup_filter),
                          rel_true_res=float(info.rel_true_res), n_levels=int(info.n_levels),
                          op_complexity=float(info.op_complexity),
                          smoother_ms_live=live_ms, smoother_launches_live=live_n,

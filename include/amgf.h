@@ -86,6 +86,9 @@ typedef struct {
   double op_complexity;       /* sum of level nonzeros / level-0 nonzeros             */
   float ms_solve;             /* wall time of amgf_pcg (hipEvents)                    */
   int32_t used_fallback;      /* learned smoother fell back to theta = 1              */
+  float ms_setup_amg;         /* host wall time of the last amgf_setup / amgf_update_D:
+                                 hierarchy, smoother data and coarsest factor          */
+  float ms_setup_filter;      /* ... and of the filtering space and its factor        */
 } amgf_solve_info;
 
 /* Fill `o` with the defaults listed above. */

@@ -47,7 +47,8 @@ class SolveInfo(ctypes.Structure):
                 ("n_levels", ctypes.c_int32), ("n_c", ctypes.c_int32),
                 ("rel_prec_res", ctypes.c_double), ("rel_true_res", ctypes.c_double),
                 ("op_complexity", ctypes.c_double), ("ms_solve", ctypes.c_float),
-                ("used_fallback", ctypes.c_int32)]
+                ("used_fallback", ctypes.c_int32), ("ms_setup_amg", ctypes.c_float),
+                ("ms_setup_filter", ctypes.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -74,6 +74,7 @@ struct Handle {
   double op_complexity = 1.0;
   DBuf<float> mlpW;             // device copy of the MLP parameters (learned smoother)
   bool learned = false;
+  double ms_setup_amg = 0.0, ms_setup_filter = 0.0;   // host wall times of the last setup
   // live timing of one level-0 kernel class inside solves: event pairs on the solve stream
   int prof_which = -1;
   std::vector<hipEvent_t> prof_ev;
@@ -172,6 +173,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   Ctx& c = h.ctx;
   const amgf_options& o = h.opt;
   const int nn = h.n_nodes, m = h.m;
+  const auto t_start = std::chrono::steady_clock::now();
   // ---- input checks
   std::vector<int> rp_host = d2h(K_rowptr, 2, c.s);
   AMGF_REQUIRE(rp_host[0] == 0, AMGF_EINVAL, "K_rowptr[0] must be 0");
@@ -281,6 +283,8 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   h.coarse_b.alloc(h.nc_dense);
   h.coarse_x.alloc(h.nc_dense);
   // ---- filter (Sec. 5.1): A_w = S[I_c, I_c], nested-dissection multifrontal Cholesky
+  AMGF_HIP(hipStreamSynchronize(c.s));
+  const auto t_filter = std::chrono::steady_clock::now();
   if (Ic_user && n_c_user > 0) {
     h.Ic.alloc(n_c_user);
     copy_in(c, h.Ic.p, Ic_user, sizeof(int) * size_t(n_c_user));
@@ -314,6 +318,8 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     h.f_res.alloc(h.n_c);
     h.f_dw.alloc(h.n_c);
   }
+  AMGF_HIP(hipStreamSynchronize(c.s));
+  const auto t_filter_end = std::chrono::steady_clock::now();
   // ---- learned-smoother features of the smoothed levels
   if (o.smoother == AMGF_LEARNED) {
     h.mlpW.alloc(MLP_NTOTAL);
@@ -346,6 +352,10 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   if (h.mixed()) { h.zf.alloc(n); h.r2f.alloc(n); }
   h.pr.alloc(n); h.pz.alloc(n); h.pzo.alloc(n); h.pp.alloc(n); h.pq.alloc(n);
   AMGF_HIP(hipStreamSynchronize(c.s));
+  const auto t_end = std::chrono::steady_clock::now();
+  using ms = std::chrono::duration<double, std::milli>;
+  h.ms_setup_filter = ms(t_filter_end - t_filter).count();
+  h.ms_setup_amg = ms(t_filter - t_start).count() + ms(t_end - t_filter_end).count();
 }
 
 // ------------------------------------------------------------------------------------
@@ -358,6 +368,7 @@ static void update_D(Handle& h, const double* D) {
   const int fl = d2h_scalar(c.flag.p, c.s);
   AMGF_REQUIRE(fl == 0, AMGF_EINVAL, (fl & 2) ? "D must be positive" : "non-finite value in D");
   copy_in(c, h.D.p, D, sizeof(double) * size_t(h.m));
+  const auto t_start = std::chrono::steady_clock::now();
   const size_t nlev = h.lev.size();
   for (size_t l = 0; l < nlev; ++l) {
     Level& L = *h.lev[l];
@@ -378,7 +389,11 @@ static void update_D(Handle& h, const double* D) {
     if (l + 1 < nlev) L.lam = power_estimate(h, L, l == 0 ? h.dec0.p : nullptr);
   }
   factor_coarsest(h);
+  AMGF_HIP(hipStreamSynchronize(c.s));
+  const auto t_filter = std::chrono::steady_clock::now();
   if (h.opt.filter && h.n_c > 0) factor_filter(h);
+  AMGF_HIP(hipStreamSynchronize(c.s));
+  const auto t_filter_end = std::chrono::steady_clock::now();
   features_and_damping(h);
   if (h.mixed())
     for (size_t l = 0; l < nlev; ++l) {
@@ -386,6 +401,10 @@ static void update_D(Handle& h, const double* D) {
       cast_d2f(c, L.w.p, L.w32.p, L.n());
     }
   AMGF_HIP(hipStreamSynchronize(c.s));
+  const auto t_end = std::chrono::steady_clock::now();
+  using ms = std::chrono::duration<double, std::milli>;
+  h.ms_setup_filter = ms(t_filter_end - t_filter).count();
+  h.ms_setup_amg = ms(t_filter - t_start).count() + ms(t_end - t_filter_end).count();
 }
 
 // ------------------------------------------------------------------------------------
@@ -927,6 +946,8 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
     info->op_complexity = h.op_complexity;
     info->ms_solve = ms;
     info->used_fallback = 0;
+    info->ms_setup_amg = float(h.ms_setup_amg);
+    info->ms_setup_filter = float(h.ms_setup_filter);
   }
   if (st != AMGF_OK) return st;
   return conv ? AMGF_OK : AMGF_ENOCONV;

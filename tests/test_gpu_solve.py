@@ -76,6 +76,7 @@ def test_pcg_matches_oracle(precision):
     print(f"precision {precision}: gpu {info.iterations} it, oracle {ref.iterations} it, "
           f"rel err {err:.2e}, S-norm {err_S:.2e}, true res {info.rel_true_res:.2e}")
     assert info.converged and info.rel_prec_res <= 1e-10
+    assert info.ms_setup_amg > 0 and info.ms_setup_filter > 0 and info.ms_solve > 0
     if precision == 0:
         assert abs(info.iterations - ref.iterations) <= 1
         assert err <= 1e-8

@@ -111,8 +111,16 @@ static double power_estimate(Handle& h, Level& L, const unsigned char* dec) {
   dots(c, n, 1, xs, xs, &nrm);
   vscale(c, n, 1.0 / std::sqrt(nrm), x.p);
   double lam = 1.0;
+  const bool fine = &L == h.lev[0].get();
   for (int it = 0; it < h.opt.sa_power_iters; ++it) {
-    bsr_spmv<double>(c, SPMV_Y, L.A, L.A.val.p, x.p, y.p, nullptr, nullptr, nullptr);
+    if (fine) {
+      // level 0: sliced stiffness plus the contact term through J (same operator as A)
+      bsr_spmv<double>(c, SPMV_Y, L.K, L.K.val.p, x.p, y.p, nullptr, nullptr, nullptr);
+      contact_apply<double, double>(c, CT_ADD, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, x.p,
+                                    h.t.p, y.p, nullptr);
+    } else {
+      bsr_spmv<double>(c, SPMV_Y, L.A, L.A.val.p, x.p, y.p, nullptr, nullptr, nullptr);
+    }
     scale_div_zero(c, n, y.p, L.d.p, dec);
     const double* ys[1] = {y.p};
     dots(c, n, 1, ys, ys, &nrm);
@@ -212,6 +220,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   h.coords.alloc(size_t(nn) * 3);
   copy_in(c, h.coords.p, coords, sizeof(double) * size_t(nn) * 3);
   h.t.alloc(std::max(m, 1));
+  bsr_build_sell(c, K, true, h.mixed(), h.bf16k());     // apply copies of K (level 0)
   j_to_node_blocks(c, m, nn, J_rowptr, J_col, J_val, L0->J);
   bsr_transpose(c, L0->J, L0->JT);
   L0->ncrows = nonempty_rows(c, L0->JT.rowptr.p, nn, L0->crows);
@@ -338,7 +347,6 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
       L.vt.alloc(n);
       if (h.mixed()) { L.fd.alloc(n); L.ft.alloc(n); }
     }
-    if (l == 0) bsr_build_sell(c, L.K, true, h.mixed(), h.bf16k());
     if (h.mixed()) {
       if (l != 0) to_fp32(c, L.K);
       if (L.P.nnzb) { to_fp32(c, L.P); to_fp32(c, L.PT); }

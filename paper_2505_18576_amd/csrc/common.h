@@ -165,7 +165,7 @@ void expand_rows(Ctx& c, const int* rowptr, int nrows, int* rows);
 // Deterministic grouping: for keys[i] in [0, nkeys) (negative keys skipped),
 // offsets[nkeys+1] and perm[] listing the indices i of each key in ascending order.
 void group_by_key(Ctx& c, const int* keys, int n, int nkeys, DBuf<int>& offsets,
-                  DBuf<int>& perm);
+                  DBuf<int>& perm, bool sorted = true);
 // Transpose a BSR matrix (blocks transposed too).  Deterministic.
 void bsr_transpose(Ctx& c, const BSR& A, BSR& T);
 // Symbolic union: row r of C collects map(col2[u]) for u in rows col1[t] of the inner

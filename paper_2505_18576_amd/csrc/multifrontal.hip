@@ -130,7 +130,14 @@ __global__ void __launch_bounds__(256) k_mf_split(int tb, int force_leaf,
   bool leaf = force_leaf || np <= MF_LEAF;
   int mode = 0, m = 0;
   if (!leaf) {
-    mf_bfs(p, nodes[0], nodes, np, grp, gcol, part, lvl, qa + o, qb + o, sh);
+    // first search from the part's smallest node id (members arrive in any order)
+    if (tid == 0) far = INT_MAX;
+    __syncthreads();
+    for (int i = tid; i < np; i += blockDim.x) atomicMin(&far, nodes[i]);
+    __syncthreads();
+    const int start = far;
+    __syncthreads();
+    mf_bfs(p, start, nodes, np, grp, gcol, part, lvl, qa + o, qb + o, sh);
     const int L1 = sh[0];
     if (tid == 0) far = INT_MAX;
     __syncthreads();
@@ -774,7 +781,7 @@ void MFSolver::setup(Ctx& c, int n_, int bs_, const int* rp, const int* col,
   while (np > 0) {
     AMGF_REQUIRE(d < MF_MAXD && tb + np <= cap, AMGF_ENOMEM, "multifrontal: ordering depth");
     DBuf<int> poff, pperm;
-    group_by_key(c, part.p, nn, np, poff, pperm);
+    group_by_key(c, part.p, nn, np, poff, pperm, false);   // order within a part unused
     DBuf<int> pinfo(size_t(np) + 1), rank(size_t(np) + 1);
     hipLaunchKernelGGL(k_mf_split, dim3(np), dim3(256), 0, c.s, tb, int(d == MF_MAXD - 1),
                        poff.p, pperm.p, grp.p, gcol.p, part.p, npart.p, lvl.p, qa.p, qb.p,

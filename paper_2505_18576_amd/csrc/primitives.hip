@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(1024) k_bitonic_segments(const int* __restrict
 }
 
 void group_by_key(Ctx& c, const int* keys, int n, int nkeys, DBuf<int>& offsets,
-                  DBuf<int>& perm) {
+                  DBuf<int>& perm, bool sorted) {
   offsets.alloc(size_t(nkeys) + 1);
   DBuf<int> counts(std::max(nkeys, 1));
   AMGF_HIP(hipMemsetAsync(counts.p, 0, counts.bytes(), c.s));
@@ -209,6 +209,13 @@ void group_by_key(Ctx& c, const int* keys, int n, int nkeys, DBuf<int>& offsets,
   perm.alloc(std::max(total, 1));
   if (total == 0) return;
   AMGF_HIP(hipMemsetAsync(counts.p, 0, counts.bytes(), c.s));
+  if (!sorted) {
+    // members of each key in arrival order (callers that only iterate over them)
+    hipLaunchKernelGGL(k_fill_keys, dim3(grid_for(n, 256)), dim3(256), 0, c.s, keys, n,
+                       offsets.p, counts.p, perm.p);
+    AMGF_LAUNCH_CHECK();
+    return;
+  }
   DBuf<int> tmp(total);
   hipLaunchKernelGGL(k_fill_keys, dim3(grid_for(n, 256)), dim3(256), 0, c.s, keys, n,
                      offsets.p, counts.p, tmp.p);

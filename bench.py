@@ -77,6 +77,24 @@ def smoother_bytes(h, vbytes, kbytes=None):
     return nnzK * (bs * bs * kb + 4) + (nn + 1) * 4 + 4 * n * vbytes
 
 
+def paper_table1():
+    """The paper's two-block runs by number of contact constraints m (Table 1: average
+    AMGF-PCG iterations over the IP steps and the theoretical bound), measured with
+    BoomerAMG + l1-Gauss-Seidel and MUMPS under MPI on CPUs (model not stated) on its own
+    meshes and barrier diagonals: context for the iteration counts, not a target."""
+    out = {}
+    with open(os.path.join(ROOT, "tests", "golden", "table1_two_block.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            mesh, n, nc, m, kip, kamgf, bound = (int(v) for v in line.split())
+            out[m] = {"mesh": mesh, "n": n, "avg_iterations": kamgf, "iteration_bound": bound,
+                      "hardware": "MPI CPU runs, processor model not stated",
+                      "precision": "FP64 presumed",
+                      "source": "Table 1 (two-block contact); different meshes and D"}
+    return out
+
+
 COUNTERS = os.path.join(ROOT, "profiles", "presmooth_sell3_f32_C5_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2505_18576_amd", "csrc", "sell.hip")
 
@@ -261,6 +279,7 @@ def main():
                    "speedup_mixed_plain_vs_fp64_plain":
                        res["fp64"]["s_per_solve"] / res["mixed"]["s_per_solve"],
                    "rel_diff_vs_fp64_solution": rel_vs_fp64,
+                   "paper_context": paper_table1().get(p.m),
                    "learned_weights": "paper_2505_18576_amd/weights/smoother_ip.bin "
                                       "(trained on interior-point steps 1-10, N=32)",
                    "vcycle_GBs_mixed": vc_gbs,

@@ -57,11 +57,10 @@ struct Handle {
   DBuf<double> coarse_b, coarse_x;
   // filter
   int n_c = 0;
-  int filter_refine = 0;
   DBuf<int> Ic;
   MFSolver aw;
-  DBuf<double> f_r, f_w, f_res, f_dw;
-  DBuf<int> aw_rp, aw_col;      // sparse A_w for refinement residuals
+  DBuf<double> f_r, f_w;
+  DBuf<int> aw_rp, aw_col;      // A_w = S[I_c, I_c] as scalar CSR (input of its factor)
   DBuf<double> aw_val;
   // apply scratch
   DBuf<double> z1, ra, r2, z3;
@@ -324,8 +323,6 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     factor_filter(h);
     h.f_r.alloc(h.n_c);
     h.f_w.alloc(h.n_c);
-    h.f_res.alloc(h.n_c);
-    h.f_dw.alloc(h.n_c);
   }
   AMGF_HIP(hipStreamSynchronize(c.s));
   const auto t_filter_end = std::chrono::steady_clock::now();
@@ -623,16 +620,9 @@ static void operator_apply(Handle& h, const double* x, double* y, const double* 
   }
 }
 
-// w = A_w^{-1} r: solve with the factored inverse, then refinement steps with the
-// sparse A_w residual (restores the accuracy the explicit inverse gives up)
+// w = A_w^{-1} r with the multifrontal factor of the filter matrix
 static void filter_solve(Handle& h, const double* r, double* w) {
-  Ctx& c = h.ctx;
-  h.aw.solve(c, r, w);
-  for (int it = 0; it < h.filter_refine; ++it) {
-    csr_residual(c, h.n_c, h.aw_rp.p, h.aw_col.p, h.aw_val.p, w, r, h.f_res.p);
-    h.aw.solve(c, h.f_res.p, h.f_dw.p);
-    axpby(c, h.n_c, 1.0, h.f_dw.p, 1.0, w);
-  }
+  h.aw.solve(h.ctx, r, w);
 }
 
 // z = M r, Definition 5.3:  z1 = B r;  z2 = z1 + P A_w^{-1} P^T (r - A z1);

@@ -9,8 +9,5 @@ void filter_csr(Ctx& c, const BSR& S, const int* Ic, int nc, DBuf<int>& rp, DBuf
                 DBuf<double>& val);
 // square BSR -> scalar CSR (rows ordered block row by block row, columns ascending)
 void bsr_to_csr(Ctx& c, const BSR& A, DBuf<int>& rp, DBuf<int>& col, DBuf<double>& val);
-// res = r - A w (scalar CSR)
-void csr_residual(Ctx& c, int n, const int* rp, const int* col, const double* val,
-                  const double* w, const double* r, double* res);
 
 }  // namespace amgf

@@ -1,5 +1,5 @@
 // Scalar CSR views used by the direct solvers: A_w = S[I_c, I_c] of the filter and the
-// coarsest level's operator, plus a CSR residual for iterative refinement.
+// coarsest level's operator.
 #include "csr.h"
 
 namespace amgf {
@@ -46,24 +46,6 @@ void filter_csr(Ctx& c, const BSR& S, const int* Ic, int nc, DBuf<int>& rp, DBuf
   val.alloc(std::max(nnz, 1));
   hipLaunchKernelGGL(k_aw_csr, dim3(grid_for(nc, 128)), dim3(128), 0, c.s, nc, 1, Ic, pos.p,
                      S.rowptr.p, S.col.p, S.val.p, nullptr, rp.p, col.p, val.p);
-  AMGF_LAUNCH_CHECK();
-}
-
-// res = r - A w for a scalar CSR A (one thread per row)
-__global__ void k_csr_residual(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                               const double* __restrict__ val, const double* __restrict__ w,
-                               const double* __restrict__ r, double* __restrict__ res) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) s += val[k] * w[col[k]];
-  res[i] = r[i] - s;
-}
-
-void csr_residual(Ctx& c, int n, const int* rp, const int* col, const double* val,
-                  const double* w, const double* r, double* res) {
-  if (n) hipLaunchKernelGGL(k_csr_residual, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, rp, col,
-                            val, w, r, res);
   AMGF_LAUNCH_CHECK();
 }
 

@@ -70,6 +70,7 @@ struct Handle {
   bool ic_closed = false;
   // pcg scratch
   DBuf<double> pr, pz, pzo, pp, pq;
+  DBuf<double> pcg_s;           // device scalars of one CG iteration: p.q, r.z, r.z_old
   double op_complexity = 1.0;
   DBuf<float> mlpW;             // device copy of the MLP parameters (learned smoother)
   bool learned = false;
@@ -897,24 +898,30 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
   bool conv = rz0 == 0.0;
   double rel = conv ? 0.0 : 1.0;
   amgf_status st = AMGF_OK;
+  // scalars stay on the device within an iteration (p.q feeds the x, r update directly);
+  // the host reads p.q, r.z and r.z_old once per iteration for the stopping rule and beta
+  if (h.pcg_s.n == 0) h.pcg_s.alloc(4);
   while (!conv && it < h.opt.max_iters) {
     operator_apply(h, h.pp.p, h.pq.p, nullptr);       // q = A p
-    double pq;
     {
       const double* xs[1] = {h.pp.p};
       const double* ys[1] = {h.pq.p};
-      dots(c, n, 1, xs, ys, &pq);
+      dots_device(c, n, 1, xs, ys, h.pcg_s.p);
     }
-    if (!(pq > 0.0)) { st = AMGF_ENOTSPD; break; }
-    const double alpha = rz / pq;
-    pcg_update_xr(c, n, alpha, h.pp.p, h.pq.p, x, h.pr.p);
+    pcg_update_xr_dev(c, n, rz, h.pcg_s.p, h.pp.p, h.pq.p, x, h.pr.p);
     std::swap(h.pz, h.pzo);
     amgf_apply_impl(h, h.pr.p, h.pz.p);
     {
       const double* xs[2] = {h.pr.p, h.pr.p};
       const double* ys[2] = {h.pz.p, h.pzo.p};
-      dots(c, n, 2, xs, ys, d2);
+      dots_device(c, n, 2, xs, ys, h.pcg_s.p + 1);
     }
+    double s3[3];
+    AMGF_HIP(hipMemcpyAsync(s3, h.pcg_s.p, 3 * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    AMGF_HIP(hipStreamSynchronize(c.s));
+    if (!(s3[0] > 0.0)) { st = AMGF_ENOTSPD; break; }  // p.q <= 0: not SPD
+    d2[0] = s3[1];
+    d2[1] = s3[2];
     ++it;
     rel = std::sqrt(std::fabs(d2[0]) / rz0);
     if (!std::isfinite(rel)) { st = AMGF_ENOTSPD; break; }

@@ -75,9 +75,16 @@ void vscale(Ctx& c, int64_t n, double s, double* x);
 void dots(Ctx& c, int64_t n, int nd, const double* const* xs, const double* const* ys,
           double* out_host);
 
+// the same sums left in device memory (out_dev[0 .. nd-1]), stream-ordered, no wait
+void dots_device(Ctx& c, int64_t n, int nd, const double* const* xs, const double* const* ys,
+                 double* out_dev);
+
 // PCG updates
 void pcg_update_xr(Ctx& c, int64_t n, double alpha, const double* p, const double* q, double* x,
                    double* r);
+// x += a p, r -= a q with a = rz / pq[0] (pq in device memory)
+void pcg_update_xr_dev(Ctx& c, int64_t n, double rz, const double* pq, const double* p,
+                       const double* q, double* x, double* r);
 void pcg_update_p(Ctx& c, int64_t n, double beta, const double* z, double* p);
 
 // input validation: flag bit 1 non-finite, bit 2 non-positive

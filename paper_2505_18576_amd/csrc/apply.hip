@@ -360,6 +360,13 @@ AMGF_ELEMWISE(k_xr, (int64_t n, double al, const double* __restrict__ p,
                      double* __restrict__ r),
               x[i] += al * p[i];
               r[i] -= al * q[i])
+// alpha = rz / (p.q) with p.q read from device memory (no host round trip)
+AMGF_ELEMWISE(k_xr_dev, (int64_t n, double rz, const double* __restrict__ pq,
+                         const double* __restrict__ p, const double* __restrict__ q,
+                         double* __restrict__ x, double* __restrict__ r),
+              const double al = rz / pq[0];
+              x[i] += al * p[i];
+              r[i] -= al * q[i])
 AMGF_ELEMWISE(k_pupd, (int64_t n, double be, const double* __restrict__ z, double* __restrict__ p),
               p[i] = z[i] + be * p[i])
 AMGF_ELEMWISE(k_power_start, (int64_t n, double* __restrict__ x,
@@ -470,6 +477,10 @@ void pcg_update_xr(Ctx& c, int64_t n, double alpha, const double* p, const doubl
                    double* r) {
   if (n) hipLaunchKernelGGL(k_xr, AMGF_L1D(n), n, alpha, p, q, x, r);
 }
+void pcg_update_xr_dev(Ctx& c, int64_t n, double rz, const double* pq, const double* p,
+                       const double* q, double* x, double* r) {
+  if (n) hipLaunchKernelGGL(k_xr_dev, AMGF_L1D(n), n, rz, pq, p, q, x, r);
+}
 void pcg_update_p(Ctx& c, int64_t n, double beta, const double* z, double* p) {
   if (n) hipLaunchKernelGGL(k_pupd, AMGF_L1D(n), n, beta, z, p);
 }
@@ -522,6 +533,20 @@ __global__ void __launch_bounds__(256) k_dot_final(int nd, const double* __restr
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) out[d] = s;
   }
+}
+
+void dots_device(Ctx& c, int64_t n, int nd, const double* const* xs, const double* const* ys,
+                 double* out_dev) {
+  AMGF_REQUIRE(nd >= 1 && nd <= DOT_MAX, AMGF_EINVAL, "dots count");
+  if (c.dot.n == 0) c.dot.alloc(size_t(DOT_MAX) * DOT_BLOCKS + DOT_MAX);
+  DotArgs a{};
+  for (int d = 0; d < nd; ++d) {
+    a.x[d] = xs[d];
+    a.y[d] = ys[d];
+  }
+  hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, nd, a, c.dot.p);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, c.s, nd, c.dot.p, out_dev);
+  AMGF_LAUNCH_CHECK();
 }
 
 void dots(Ctx& c, int64_t n, int nd, const double* const* xs, const double* const* ys,

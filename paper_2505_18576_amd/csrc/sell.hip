@@ -148,36 +148,59 @@ __global__ void k_sell_len(int nrows, int nslices, const int* __restrict__ rp,
   len[s] = m * 64;
 }
 
-// one wave per slice; lane i copies row 64 s + i slot by slot
-__global__ void __launch_bounds__(64) k_sell_fill(int nrows, const int* __restrict__ rp,
-                                                  const int* __restrict__ col,
-                                                  const double* __restrict__ val,
-                                                  const int* __restrict__ off,
-                                                  int* __restrict__ scol,
-                                                  double* __restrict__ sv,
-                                                  float* __restrict__ sv32,
-                                                  uint16_t* __restrict__ sv16) {
-  const int s = blockIdx.x, i = threadIdx.x;
-  const int r = s * 64 + i;
+// One workgroup per slice.  Eight slots at a time: the 64 rows' runs of 8 blocks are read
+// in BSR order (each run is contiguous) into LDS, then written slot by slot in the sliced
+// layout, so both the reads and the writes are coalesced.
+constexpr int FILL_SLOTS = 8;
+__global__ void __launch_bounds__(256) k_sell_fill(int nrows, const int* __restrict__ rp,
+                                                   const int* __restrict__ col,
+                                                   const double* __restrict__ val,
+                                                   const int* __restrict__ off,
+                                                   int* __restrict__ scol,
+                                                   double* __restrict__ sv,
+                                                   float* __restrict__ sv32,
+                                                   uint16_t* __restrict__ sv16) {
+  __shared__ double stage[FILL_SLOTS][9][65];
+  __shared__ int cstage[FILL_SLOTS][64];
+  __shared__ int rpo[65];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const int r0 = s * 64;
+  for (int t = tid; t <= 64; t += 256) rpo[t] = rp[min(r0 + t, nrows)];
+  __syncthreads();
   const int o0 = off[s], len = (off[s + 1] - o0) >> 6;
-  const int rr = min(r, nrows - 1);
-  const int j0 = r < nrows ? rp[r] : 0, n = r < nrows ? rp[r + 1] - j0 : 0;
-  for (int j = 0; j < len; ++j) {
-    const int64_t slot = int64_t(o0) + int64_t(j) * 64;
-    scol[slot + i] = j < n ? col[j0 + j] : rr;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-      const double v = j < n ? val[int64_t(j0 + j) * 9 + e] : 0.0;
-      const int64_t k = slot * 9 + e * 64 + i;
-      if (sv) sv[k] = v;
-      if (sv32) sv32[k] = float(v);
+  for (int j0 = 0; j0 < len; j0 += FILL_SLOTS) {
+    for (int e = tid; e < 64 * FILL_SLOTS * 9; e += 256) {
+      const int i = e / (FILL_SLOTS * 9), rem = e % (FILL_SLOTS * 9);
+      const int jj = rem / 9, q = rem % 9, j = j0 + jj;
+      const int rl = rpo[i + 1] - rpo[i];
+      stage[jj][q][i] = j < rl ? val[int64_t(rpo[i] + j) * 9 + q] : 0.0;
+    }
+    for (int e = tid; e < 64 * FILL_SLOTS; e += 256) {
+      const int i = e / FILL_SLOTS, jj = e % FILL_SLOTS, j = j0 + jj;
+      const int rl = rpo[i + 1] - rpo[i];
+      cstage[jj][i] = j < rl ? col[rpo[i] + j] : min(r0 + i, nrows - 1);
+    }
+    __syncthreads();
+    const int nslot = min(FILL_SLOTS, len - j0);
+    for (int e = tid; e < nslot * 64; e += 256) {
+      const int jj = e >> 6, i = e & 63;
+      scol[int64_t(o0) + int64_t(j0 + jj) * 64 + i] = cstage[jj][i];
+    }
+    for (int e = tid; e < nslot * 576; e += 256) {
+      const int jj = e / 576, pos = e % 576;
+      const int64_t base = (int64_t(o0) + int64_t(j0 + jj) * 64) * 9;
+      const int q = pos >> 6, i = pos & 63;
+      const double v = stage[jj][q][i];
+      if (sv) sv[base + pos] = v;
+      if (sv32) sv32[base + pos] = float(v);
       if (sv16) {
         // pairs (2q, 2q+1) packed in uint32 q of the slot, entry 8 after the pairs
-        const int64_t e16 = e < 8 ? slot * 9 + (e >> 1) * 128 + 2 * i + (e & 1)
-                                  : slot * 9 + 512 + i;
-        sv16[e16] = bf16_rne(v);
+        const int qq = pos < 512 ? 2 * (pos >> 7) + (pos & 1) : 8;
+        const int ii = pos < 512 ? (pos & 127) >> 1 : pos - 512;
+        sv16[base + pos] = bf16_rne(stage[jj][qq][ii]);
       }
     }
+    __syncthreads();
   }
 }
 
@@ -195,7 +218,7 @@ void bsr_build_sell(Ctx& c, BSR& A, bool fp64, bool fp32, bool bf16) {
   if (fp64) A.sell_val.alloc(size_t(total) * 9);
   if (fp32) A.sell_val32.alloc(size_t(total) * 9);
   if (bf16) A.sell_val16.alloc(size_t(total) * 9);
-  hipLaunchKernelGGL(k_sell_fill, dim3(ns), dim3(64), 0, c.s, A.nrows, A.rowptr.p, A.col.p,
+  hipLaunchKernelGGL(k_sell_fill, dim3(ns), dim3(256), 0, c.s, A.nrows, A.rowptr.p, A.col.p,
                      A.val.p, A.sell_off.p, A.sell_col.p, A.sell_val.p, A.sell_val32.p,
                      A.sell_val16.p);
   AMGF_LAUNCH_CHECK();

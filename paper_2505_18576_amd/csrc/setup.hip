@@ -232,35 +232,42 @@ void strength_graph(Ctx& c, const BSR& A, double theta, Graph& G) {
 }
 
 // DOF i of node a is decoupled when every off-diagonal entry of its row is 0.
-template <int B>
-__global__ void k_decoupled(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                            const double* __restrict__ val, unsigned char* __restrict__ dec) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= n) return;
-  bool coupled[B];
-#pragma unroll
-  for (int p = 0; p < B; ++p) coupled[p] = false;
-  for (int k = rp[a]; k < rp[a + 1]; ++k) {
-    const int b = col[k];
-    const double* v = val + int64_t(k) * B * B;
-#pragma unroll
-    for (int p = 0; p < B; ++p)
-#pragma unroll
-      for (int q = 0; q < B; ++q)
-        if ((b != a || q != p) && v[p * B + q] != 0.0) coupled[p] = true;
+// G lanes per block row read its B x B blocks entry by entry (coalesced); each lane keeps
+// a bit per row p of the block row that has an off-diagonal nonzero, OR-reduced over the
+// group.
+template <int B, int G>
+__global__ void __launch_bounds__(256) k_decoupled(int n, const int* __restrict__ rp,
+                                                   const int* __restrict__ col,
+                                                   const double* __restrict__ val,
+                                                   unsigned char* __restrict__ dec) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = t / G, g = t % G;
+  unsigned mask = 0;
+  if (a < n) {
+    const int k0 = rp[a], ne = (rp[a + 1] - k0) * B * B;
+    const double* v = val + int64_t(k0) * B * B;
+    for (int e = g; e < ne; e += G) {
+      if (v[e] == 0.0) continue;
+      const int kb = e / (B * B), rem = e - kb * B * B;
+      const int p = rem / B, q = rem - p * B;
+      if (col[k0 + kb] != a || p != q) mask |= 1u << p;
+    }
   }
 #pragma unroll
-  for (int p = 0; p < B; ++p) dec[int64_t(a) * B + p] = coupled[p] ? 0 : 1;
+  for (int o = G / 2; o > 0; o >>= 1) mask |= __shfl_xor(mask, o);
+  if (a < n && g < B) dec[int64_t(a) * B + g] = (mask >> g) & 1u ? 0 : 1;
 }
 
 void decoupled_dofs(Ctx& c, const BSR& A, DBuf<unsigned char>& dec) {
   dec.alloc(size_t(A.nrows) * A.br);
   AMGF_REQUIRE(A.br == 3 || A.br == 6, AMGF_EINVAL, "block size");
   if (A.br == 3)
-    hipLaunchKernelGGL(k_decoupled<3>, dim3(grid_for(A.nrows, 256)), dim3(256), 0, c.s,
+    hipLaunchKernelGGL((k_decoupled<3, 16>), dim3(grid_for(int64_t(A.nrows) * 16, 256)),
+                       dim3(256), 0, c.s,
                        A.nrows, A.rowptr.p, A.col.p, A.val.p, dec.p);
   else
-    hipLaunchKernelGGL(k_decoupled<6>, dim3(grid_for(A.nrows, 256)), dim3(256), 0, c.s,
+    hipLaunchKernelGGL((k_decoupled<6, 16>), dim3(grid_for(int64_t(A.nrows) * 16, 256)),
+                       dim3(256), 0, c.s,
                        A.nrows, A.rowptr.p, A.col.p, A.val.p, dec.p);
   AMGF_LAUNCH_CHECK();
 }

@@ -15,8 +15,8 @@
  *  - The caller owns every pointer it passes; the library never frees them.
  *    amgf_setup copies what it keeps (stream-ordered on `stream`) and returns once
  *    the copies are enqueued; inputs must stay valid until `stream` reaches that point.
- *  - The handle owns all hierarchy memory (allocated with hipMalloc) and releases it
- *    in amgf_destroy.
+ *  - The handle owns all hierarchy memory and releases it in amgf_destroy.  It comes
+ *    from hipMalloc, or from the caller's amgf_allocator (amgf_options.allocator).
  *  - `stream` is a hipStream_t (NULL = the default stream).  Every call runs on it.
  *  - Every entry point returns an amgf_status; nothing throws across the ABI.  On an
  *    error the output arrays are unspecified; amgf_last_error() gives a message.
@@ -53,6 +53,24 @@ enum { AMGF_FP64 = 0, AMGF_MIXED_FP32 = 1, AMGF_MIXED_BF16K = 2 };
  * estimate of the prolongator damping)), or l1-Jacobi with learned damping theta_i.  */
 enum { AMGF_L1JACOBI = 0, AMGF_CHEBYSHEV = 1, AMGF_LEARNED = 2 };
 
+/* Device memory supplied by the caller (e.g. a framework's caching allocator), used for
+ * every buffer the library allocates, persistent or temporary.  Both functions NULL:
+ * hipMalloc / hipFree.
+ *  alloc(bytes, stream, ctx): `bytes` > 0 of device memory on the current device,
+ *      256-byte aligned, usable by work queued on `stream` (the stream of the entry
+ *      point that allocates); NULL on failure (the call then returns AMGF_ENOMEM).
+ *  free(ptr, stream, ctx): returns a block with the stream it was allocated on.  It may
+ *      be called while work on that stream that reads `ptr` is still queued: the
+ *      allocator must order reuse after it (as hipFreeAsync and stream-ordered caching
+ *      allocators do).  amgf_destroy synchronises the handle's last stream first.
+ * The callbacks are called from the thread of the entry point, never concurrently for
+ * one handle, and must not call into the library.                                      */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* ptr, void* stream, void* ctx);
+  void* ctx;
+} amgf_allocator;
+
 typedef struct {
   int32_t struct_size;        /* sizeof(amgf_options), for ABI versioning            */
   int32_t precision;          /* AMGF_FP64, AMGF_MIXED_FP32 (FP32 V-cycle, FP64
@@ -74,6 +92,7 @@ typedef struct {
   int32_t sweeps;             /* smoother applications before and after the coarse
                                  correction, 1..16 (default 1: V(1,1))                */
   int32_t cheb_degree;        /* Chebyshev degree, 1..16 (default 2)                  */
+  amgf_allocator allocator;   /* device memory source (default: both NULL, hipMalloc) */
 } amgf_options;
 
 typedef struct {
@@ -236,6 +255,68 @@ amgf_status amgf_profile_start(amgf_handle h, int32_t which, int32_t max_launche
 amgf_status amgf_profile_read(amgf_handle h, int32_t* count, double* avg_ms);
 amgf_status amgf_query(amgf_handle h, int32_t level, int32_t which, void* host_dst,
                        size_t bytes);
+
+/* ---------------- interior-point driver for the contact QP ----------------------------
+ * Solves  minimise 1/2 u^T K u - f^T u  subject to  J u + g0 >= 0  with the handle's K and
+ * J, by the interior-point Newton method outlined in Sec. 3: slacks s, multipliers lam of
+ * J u + g0 - s = 0 and duals z of s >= 0; every Newton step is the condensed system
+ * A u^ = b, A = K + J^T D J with D = z / s, solved by amgf_update_D + amgf_pcg (AMGF-PCG),
+ * and s^, lam^, z^ are recovered from u^.  Barrier subproblem residuals (unit weights):
+ * r_u = K u - f + J^T lam, r_s = -lam - z, r_lam = J u + g0 - s, r_z = s z - mu; optimality
+ * error e(mu) = max(||r_u||_2 / s_d, ||r_s||_2 / s_d, ||r_lam||_inf, ||r_z||_inf / s_c) with
+ * the scalings s_d = max(s_max, (|lam|_1 + |z|_1) / 2m) / s_max, s_c = max(s_max,
+ * |z|_1 / m) / s_max.  mu decreases to max(tol / 10, min(kappa_mu mu, mu^theta_mu)) once
+ * e(mu) < kappa_eps mu; steps are cut back by the fraction-to-the-boundary rule with
+ * tau = max(tau_min, 1 - mu) (separate lengths for the primal variables and z); the run
+ * stops when e(0) < tol.  The first iterate is s = max(J u + g0, s_init), z = mu0 / s,
+ * lam = -z.  Where the paper defers to its IP reference (Wachter and Biegler 2006) the
+ * defaults of that method are used.                                                     */
+typedef struct {
+  int32_t struct_size;        /* sizeof(amgf_ip_options)                              */
+  int32_t max_steps;          /* Newton steps (default 200)                           */
+  double tol;                 /* tol_IP (default 1e-6, Sec. 4)                        */
+  double mu0;                 /* initial barrier parameter (0.1)                      */
+  double kappa_eps;           /* subproblem tolerance factor (10, Sec. 3)             */
+  double kappa_mu;            /* barrier decrease factor (0.2)                        */
+  double theta_mu;            /* superlinear barrier decrease exponent (1.5)          */
+  double tau_min;             /* fraction-to-the-boundary floor (0.99)                */
+  double s_max;               /* optimality-error scaling constant (100, Sec. 3)      */
+  double s_init;              /* floor of the first slacks (1e-2)                     */
+  double switch_ratio;        /* 0: every solve uses the handle's preconditioner.  > 0
+                                 (handle built with filter = 1): plain AMG-PCG while
+                                 D_max / D_min < switch_ratio, AMGF from the first step
+                                 that reaches it on (Sec. 7 suggests such a switch)    */
+} amgf_ip_options;
+
+typedef struct {
+  double mu;                  /* barrier parameter of the step                        */
+  double e_opt;               /* optimality error e(0) before the step                */
+  double e_opt_mu;            /* e(mu)                                                 */
+  double alpha_p, alpha_d;    /* step lengths (s, u, lam) and (z)                     */
+  double D_min, D_max;        /* range of the barrier diagonal D = z / s              */
+  int32_t pcg_iterations;     /* CG iterations of the Newton solve                    */
+  int32_t pcg_converged;      /* 0 when the solve stopped at max_iters (the step then
+                                 uses the last CG iterate)                             */
+  int32_t filter_on;          /* 1 when the solve used AMGF, 0 for plain AMG          */
+  int32_t pad;
+  float ms_update;            /* host wall time of the numeric re-setup for D         */
+  float ms_solve;             /* device time of the CG solve                           */
+} amgf_ip_step;
+
+/* Fill `o` with the defaults listed above. */
+void amgf_ip_default_options(amgf_ip_options* o);
+
+/* Run the driver.  f (n), g0 (m): device inputs.  u (n, device): initial point in,
+ * solution out.  s, lam, z (m, device): outputs.  steps: host array of max_records
+ * records (may be NULL), the first min(steps taken, max_records) are filled.  *n_steps and
+ * *converged (host) receive the number of Newton steps and whether e(0) < tol was reached.
+ * The handle's D is left at the last step's z / s.  EINVAL for m = 0, bad options or
+ * switch_ratio > 0 on a handle without filter; ENOTSPD if a solve breaks down; other CG
+ * non-convergence is recorded per step and not an error.                             */
+amgf_status amgf_ip_solve(amgf_handle h, const double* f, const double* g0, double* u,
+                          double* s, double* lam, double* z, const amgf_ip_options* opts,
+                          amgf_ip_step* steps, int32_t max_records, int32_t* n_steps,
+                          int32_t* converged, void* stream);
 
 #ifdef __cplusplus
 }

@@ -26,8 +26,46 @@ ABI_FUNCTIONS = ["amgf_default_options", "amgf_setup", "amgf_apply", "amgf_vcycl
                  "amgf_last_error", "amgf_num_levels", "amgf_query", "amgf_time_kernel",
                  "amgf_set_mlp", "amgf_mlp_loss_grad", "amgf_adam_step",
                  "amgf_profile_start", "amgf_profile_read", "amgf_filter_solve",
-                 "amgf_update_D"]
+                 "amgf_update_D", "amgf_ip_default_options", "amgf_ip_solve"]
 K_PRESMOOTH, K_POSTSMOOTH, K_VCYCLE, K_OPERATOR = range(4)
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """amgf_allocator backed by PyTorch's caching allocator on the current device.
+
+    Blocks are taken on the stream the library passes and returned with
+    ``caching_allocator_delete``; ``live`` counts the blocks the library holds."""
+
+    def __init__(self):
+        torch = _torch()
+        self._torch = torch
+        self.device = torch.cuda.current_device()
+        self.live, self.n_alloc, self.fail_after = 0, 0, None
+        self._a, self._f = ALLOC_FN(self._alloc), FREE_FN(self._free)
+        self.struct = Allocator(self._a, self._f, None)
+
+    def _alloc(self, nbytes, stream, ctx):
+        if self.fail_after is not None and self.n_alloc >= self.fail_after:
+            return None
+        try:
+            ptr = self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream or 0)
+        except Exception:
+            return None
+        self.live += 1
+        self.n_alloc += 1
+        return ptr
+
+    def _free(self, ptr, stream, ctx):
+        self._torch.cuda.caching_allocator_delete(ptr)
+        self.live -= 1
 
 
 class Options(ctypes.Structure):
@@ -39,7 +77,8 @@ class Options(ctypes.Structure):
                 ("sa_omega", ctypes.c_double), ("qr_tol", ctypes.c_double),
                 ("max_coarse_ratio", ctypes.c_double),
                 ("mlp_weights", ctypes.POINTER(ctypes.c_float)),
-                ("sweeps", ctypes.c_int32), ("cheb_degree", ctypes.c_int32)]
+                ("sweeps", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
+                ("allocator", Allocator)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -52,6 +91,28 @@ class SolveInfo(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class IPOptions(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("max_steps", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("mu0", ctypes.c_double),
+                ("kappa_eps", ctypes.c_double), ("kappa_mu", ctypes.c_double),
+                ("theta_mu", ctypes.c_double), ("tau_min", ctypes.c_double),
+                ("s_max", ctypes.c_double), ("s_init", ctypes.c_double),
+                ("switch_ratio", ctypes.c_double)]
+
+
+class IPStep(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("e_opt", ctypes.c_double),
+                ("e_opt_mu", ctypes.c_double), ("alpha_p", ctypes.c_double),
+                ("alpha_d", ctypes.c_double), ("D_min", ctypes.c_double),
+                ("D_max", ctypes.c_double), ("pcg_iterations", ctypes.c_int32),
+                ("pcg_converged", ctypes.c_int32), ("filter_on", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("ms_update", ctypes.c_float),
+                ("ms_solve", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
 _lib = None
@@ -101,6 +162,12 @@ def load_library(path=LIB_PATH):
     L.amgf_profile_start.restype = ctypes.c_int
     L.amgf_profile_read.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.amgf_profile_read.restype = ctypes.c_int
+    L.amgf_ip_default_options.argtypes = [ctypes.POINTER(IPOptions)]
+    L.amgf_ip_default_options.restype = None
+    L.amgf_ip_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(IPOptions),
+                                ctypes.POINTER(IPStep), i32, ctypes.POINTER(i32),
+                                ctypes.POINTER(i32), vp]
+    L.amgf_ip_solve.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -122,6 +189,17 @@ def default_options(**kw):
     L = load_library()
     o = Options()
     L.amgf_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def ip_default_options(**kw):
+    L = load_library()
+    o = IPOptions()
+    L.amgf_ip_default_options(ctypes.byref(o))
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
@@ -162,10 +240,14 @@ class AMGF:
     """
 
     def __init__(self, n_nodes, K_rowptr, K_col, K_val, J_rowptr, J_col, J_val, D, coords,
-                 Ic=None, options=None, mlp_weights=None, **kw):
+                 Ic=None, options=None, mlp_weights=None, allocator=None, **kw):
         torch = _torch()
         self.L = load_library()
         self.options = options if options is not None else default_options(**kw)
+        # allocator: None (hipMalloc), "torch", or a TorchAllocator; kept alive with the handle
+        self.allocator = TorchAllocator() if allocator == "torch" else allocator
+        if self.allocator is not None:
+            self.options.allocator = self.allocator.struct
         self._w = None
         if mlp_weights is not None:
             self._w = np.ascontiguousarray(mlp_weights, dtype=np.float32)
@@ -234,6 +316,29 @@ class AMGF:
             return x, info
         _check(st, "amgf_pcg")
         return x, info
+
+    def ip_solve(self, f, g0, u0=None, **opts):
+        """Interior-point solve of min 1/2 u^T K u - f^T u s.t. J u + g0 >= 0 with this
+        handle's K and J (amgf_ip_solve).  Returns (u, s, lam, z, steps, converged), the
+        vectors as device tensors and ``steps`` a list of per-Newton-step dicts."""
+        torch = _torch()
+        o = ip_default_options(**opts)
+        fd = _dev(f, torch.float64).reshape(-1)
+        gd = _dev(g0, torch.float64).reshape(-1)
+        if fd.numel() != self.n or gd.numel() != self.m:
+            raise ValueError(f"f needs {self.n} values and g0 {self.m}")
+        u = torch.zeros_like(fd) if u0 is None else _dev(u0, torch.float64).clone()
+        if u.numel() != self.n:
+            raise ValueError(f"u0 needs {self.n} values")
+        s, lam, z = (torch.empty(self.m, dtype=torch.float64, device="cuda") for _ in range(3))
+        rec = (IPStep * max(o.max_steps, 1))()
+        ns, conv = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.L.amgf_ip_solve(self.h, _ptr(fd), _ptr(gd), _ptr(u), _ptr(s), _ptr(lam),
+                                    _ptr(z), ctypes.byref(o), rec, len(rec), ctypes.byref(ns),
+                                    ctypes.byref(conv), _stream()), "amgf_ip_solve")
+        torch.cuda.synchronize()
+        steps = [rec[i].as_dict() for i in range(min(ns.value, len(rec)))]
+        return u, s, lam, z, steps, bool(conv.value)
 
     @property
     def n_levels(self):

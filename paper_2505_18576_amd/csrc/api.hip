@@ -9,6 +9,7 @@
 #include "csr.h"
 #include "learn.h"
 #include "setup.h"
+#include "ip.h"
 
 namespace amgf {
 
@@ -80,6 +81,11 @@ struct Handle {
   std::vector<hipEvent_t> prof_ev;
   size_t prof_used = 0;
   bool prof_open = false;
+  AllocSrc mem;                 // the caller's allocator and the stream of the running call
+  // plain AMG-PCG on a filter handle (the switching interior-point driver); the filter
+  // factor is not refreshed while suspended
+  bool filter_suspended = false;
+  DBuf<double> ip_red;          // device results of the driver's reductions
   Handle() = default;
   Handle(const Handle&) = delete;
   ~Handle() {
@@ -90,6 +96,12 @@ struct Handle {
   // one fused l1-Jacobi step before and after the coarse correction
   bool plain_cycle() const { return opt.smoother != AMGF_CHEBYSHEV && opt.sweeps == 1; }
   int64_t n() const { return int64_t(n_nodes) * 3; }
+  // the stream of the running entry point: kernels are queued on it, and buffers allocated
+  // during the call come from the handle's allocator with it
+  void bind(void* stream) {
+    ctx.s = static_cast<hipStream_t>(stream);
+    mem.s = ctx.s;
+  }
 };
 
 static thread_local std::string g_last_error;
@@ -397,7 +409,7 @@ static void update_D(Handle& h, const double* D) {
   factor_coarsest(h);
   AMGF_HIP(hipStreamSynchronize(c.s));
   const auto t_filter = std::chrono::steady_clock::now();
-  if (h.opt.filter && h.n_c > 0) factor_filter(h);
+  if (h.opt.filter && h.n_c > 0 && !h.filter_suspended) factor_filter(h);
   AMGF_HIP(hipStreamSynchronize(c.s));
   const auto t_filter_end = std::chrono::steady_clock::now();
   features_and_damping(h);
@@ -633,7 +645,7 @@ static void filter_solve(Handle& h, const double* r, double* w) {
 static void amgf_apply_impl(Handle& h, const double* r, double* z) {
   Ctx& c = h.ctx;
   const int64_t n = h.n();
-  if (!h.opt.filter) {
+  if (!h.opt.filter || h.filter_suspended) {
     vcycle(h, r, z);
     return;
   }
@@ -958,6 +970,107 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
   return conv ? AMGF_OK : AMGF_ENOCONV;
 }
 
+// ------------------------------------------------------------------------------------
+// interior-point driver for the contact QP (Sec. 3): Newton steps on the barrier
+// subproblems, each solved through the condensed system with AMGF-PCG
+// ------------------------------------------------------------------------------------
+static double ip_error(const amgf_ip_options& o, int m, double ru_norm, const double* q) {
+  // q: sum r_s^2, max |r_lam|, max |r_z|, sum |lam|, sum |z|
+  const double mm = std::max(m, 1);
+  const double s_d = std::max(o.s_max, (q[3] + q[4]) / (2.0 * mm)) / o.s_max;
+  const double s_c = std::max(o.s_max, q[4] / mm) / o.s_max;
+  return std::max(std::max(ru_norm / s_d, std::sqrt(q[0]) / s_d), std::max(q[1], q[2] / s_c));
+}
+
+static void ip_solve(Handle& h, const double* f, const double* g0, double* u, double* s,
+                     double* lam, double* z, const amgf_ip_options& o, amgf_ip_step* rec,
+                     int max_rec, int* n_steps, int* converged) {
+  Ctx& c = h.ctx;
+  Level& L0 = *h.lev[0];
+  const int64_t n = h.n();
+  const int m = h.m;
+  DBuf<double> ru(n), y(n), bb(n), uh(n);
+  DBuf<double> rl(m), rs(m), t(m), Dn(m), sh(m), lh(m), zh(m);
+  if (h.ip_red.n == 0) h.ip_red.alloc(8);
+  double mu = o.mu0;
+  ip_init(c, L0.J, u, g0, mu, o.s_init, s, lam, z);
+  bool filter_switched = false;
+  *n_steps = 0;
+  *converged = 0;
+  for (int step = 0; step < o.max_steps; ++step) {
+    // r_u = K u - f + J^T lam;  r_lam, r_s
+    bsr_spmv<double>(c, SPMV_RES, L0.K, L0.K.val.p, u, y.p, f, nullptr, nullptr);
+    vcopy(c, y.p, ru.p, n);
+    vscale(c, n, -1.0, ru.p);
+    ip_jt_add(c, L0.JT, L0.crows.p, L0.ncrows, lam, ru.p);
+    ip_m_residuals(c, L0.J, u, g0, s, lam, z, rl.p, rs.p);
+    double nr2;
+    const double* xs[1] = {ru.p};
+    dots(c, n, 1, xs, xs, &nr2);
+    const double ru_norm = std::sqrt(nr2);
+    double q[7];
+    ip_m_norms(c, m, rs.p, rl.p, s, lam, z, 0.0, h.ip_red.p, q);
+    const double e0 = ip_error(o, m, ru_norm, q);
+    if (e0 < o.tol) {
+      *converged = 1;
+      break;
+    }
+    double e_mu;
+    for (;;) {       // the barrier subproblem is solved: decrease mu, possibly repeatedly
+      ip_m_norms(c, m, rs.p, rl.p, s, lam, z, mu, h.ip_red.p, q);
+      e_mu = ip_error(o, m, ru_norm, q);
+      if (e_mu >= o.kappa_eps * mu || mu <= o.tol / 10) break;
+      mu = std::max(o.tol / 10, std::min(o.kappa_mu * mu, std::pow(mu, o.theta_mu)));
+    }
+    const double D_min = q[5], D_max = q[6];
+    // D = z / s and the condensed right-hand side b = -r_u + J^T (D b_lam + b_s)
+    ip_rhs_m(c, m, s, z, rs.p, rl.p, mu, Dn.p, t.p);
+    if (o.switch_ratio > 0 && !filter_switched && D_max >= o.switch_ratio * D_min)
+      filter_switched = true;
+    h.filter_suspended = o.switch_ratio > 0 && !filter_switched;
+    const auto t0 = std::chrono::steady_clock::now();
+    update_D(h, Dn.p);
+    AMGF_HIP(hipStreamSynchronize(c.s));
+    const auto t1 = std::chrono::steady_clock::now();
+    vcopy(c, ru.p, bb.p, n);
+    vscale(c, n, -1.0, bb.p);
+    ip_jt_add(c, L0.JT, L0.crows.p, L0.ncrows, t.p, bb.p);
+    AMGF_HIP(hipMemsetAsync(uh.p, 0, sizeof(double) * size_t(n), c.s));
+    amgf_solve_info info{};
+    const amgf_status st = pcg_impl(h, bb.p, uh.p, &info);
+    AMGF_REQUIRE(st == AMGF_OK || st == AMGF_ENOCONV, st, "Newton solve failed");
+    // recovery and step lengths, then the update
+    const double tau = std::max(o.tau_min, 1.0 - mu);
+    double alpha[2];
+    ip_recover(c, L0.J, uh.p, s, z, Dn.p, rs.p, rl.p, mu, tau, sh.p, lh.p, zh.p, h.ip_red.p,
+               alpha);
+    axpby(c, n, alpha[0], uh.p, 1.0, u);
+    ip_update_m(c, m, alpha[0], alpha[1], sh.p, lh.p, zh.p, s, lam, z);
+    if (step < max_rec && rec) {
+      amgf_ip_step& r = rec[step];
+      r.mu = mu;
+      r.e_opt = e0;
+      r.e_opt_mu = e_mu;
+      r.alpha_p = alpha[0];
+      r.alpha_d = alpha[1];
+      r.D_min = D_min;
+      r.D_max = D_max;
+      r.pcg_iterations = info.iterations;
+      r.pcg_converged = info.converged;
+      r.filter_on = (h.opt.filter && !h.filter_suspended) ? 1 : 0;
+      r.pad = 0;
+      r.ms_update = float(std::chrono::duration<double, std::milli>(t1 - t0).count());
+      r.ms_solve = info.ms_solve;
+    }
+    *n_steps = step + 1;
+  }
+  AMGF_HIP(hipStreamSynchronize(c.s));
+  if (h.filter_suspended) {       // leave a consistent filter factor for the last D
+    h.filter_suspended = false;
+    if (h.opt.filter && h.n_c > 0) factor_filter(h);
+  }
+}
+
 }  // namespace amgf
 
 // ======================================================================================
@@ -1054,7 +1167,11 @@ amgf_status amgf_setup(const amgf_options* opts, int32_t n_nodes, const int32_t*
     AMGF_REQUIRE(h.opt.max_levels >= 1 && h.opt.max_iters >= 0 && h.opt.rtol >= 0,
                  AMGF_EINVAL, "options");
     AMGF_REQUIRE(n_c >= 0 && (n_c == 0 || Ic), AMGF_EINVAL, "Ic");
-    h.ctx.s = static_cast<hipStream_t>(stream);
+    AMGF_REQUIRE(!h.opt.allocator.alloc == !h.opt.allocator.free, AMGF_EINVAL,
+                 "amgf_allocator needs both alloc and free, or neither");
+    h.mem.a = h.opt.allocator;
+    h.bind(stream);
+    amgf::AllocScope scope_(&h.mem);
     h.ctx.flag.alloc(1);
     h.n_nodes = n_nodes;
     h.m = m;
@@ -1066,10 +1183,61 @@ amgf_status amgf_setup(const amgf_options* opts, int32_t n_nodes, const int32_t*
   return AMGF_OK;
 }
 
+void amgf_ip_default_options(amgf_ip_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(amgf_ip_options);
+  o->max_steps = 200;
+  o->tol = 1e-6;
+  o->mu0 = 0.1;
+  o->kappa_eps = 10.0;
+  o->kappa_mu = 0.2;
+  o->theta_mu = 1.5;
+  o->tau_min = 0.99;
+  o->s_max = 100.0;
+  o->s_init = 1e-2;
+  o->switch_ratio = 0.0;
+}
+
+amgf_status amgf_ip_solve(amgf_handle hd, const double* f, const double* g0, double* u,
+                          double* s, double* lam, double* z, const amgf_ip_options* opts,
+                          amgf_ip_step* steps, int32_t max_records, int32_t* n_steps,
+                          int32_t* converged, void* stream) {
+  if (!hd || !f || !g0 || !u || !s || !lam || !z || !n_steps || !converged || max_records < 0)
+    return AMGF_EINVAL;
+  return guard([&]() -> amgf_status {
+    Handle& h = hd->h;
+    amgf_ip_options o;
+    if (opts) {
+      AMGF_REQUIRE(opts->struct_size == int32_t(sizeof(amgf_ip_options)), AMGF_EINVAL,
+                   "amgf_ip_options.struct_size mismatch");
+      o = *opts;
+    } else {
+      amgf_ip_default_options(&o);
+    }
+    AMGF_REQUIRE(h.m > 0, AMGF_EINVAL, "the interior-point driver needs contact constraints");
+    AMGF_REQUIRE(o.max_steps >= 0 && o.tol > 0 && o.mu0 > 0 && o.kappa_eps > 0 &&
+                     o.kappa_mu > 0 && o.kappa_mu < 1 && o.theta_mu > 1 && o.tau_min > 0 &&
+                     o.tau_min < 1 && o.s_max > 0 && o.s_init > 0 && o.switch_ratio >= 0,
+                 AMGF_EINVAL, "interior-point options");
+    AMGF_REQUIRE(o.switch_ratio == 0 || (h.opt.filter && h.n_c > 0), AMGF_EINVAL,
+                 "switching to AMGF needs a handle built with the filter");
+    h.bind(stream);
+    amgf::AllocScope scope_(&h.mem);
+    try {
+      amgf::ip_solve(h, f, g0, u, s, lam, z, o, steps, max_records, n_steps, converged);
+    } catch (...) {
+      h.filter_suspended = false;
+      throw;
+    }
+    return AMGF_OK;
+  });
+}
+
 amgf_status amgf_apply(amgf_handle hd, const double* r, double* z, void* stream) {
   if (!hd || !r || !z) return AMGF_EINVAL;
   amgf_status st_ = guard([&]() -> amgf_status {
-    hd->h.ctx.s = static_cast<hipStream_t>(stream);
+    hd->h.bind(stream);
+    amgf::AllocScope scope_(&hd->h.mem);
     amgf::amgf_apply_impl(hd->h, r, z);
     return AMGF_OK;
   });
@@ -1080,7 +1248,8 @@ amgf_status amgf_apply(amgf_handle hd, const double* r, double* z, void* stream)
 amgf_status amgf_update_D(amgf_handle hd, const double* D, void* stream) {
   if (!hd || (!D && hd->h.m > 0)) return AMGF_EINVAL;
   return guard([&]() -> amgf_status {
-    hd->h.ctx.s = static_cast<hipStream_t>(stream);
+    hd->h.bind(stream);
+    amgf::AllocScope scope_(&hd->h.mem);
     amgf::update_D(hd->h, D);
     return AMGF_OK;
   });
@@ -1091,7 +1260,8 @@ amgf_status amgf_filter_solve(amgf_handle hd, const double* rc, double* wc, void
   return guard([&]() -> amgf_status {
     Handle& h = hd->h;
     AMGF_REQUIRE(h.opt.filter && h.n_c > 0, AMGF_EINVAL, "handle has no filtering space");
-    h.ctx.s = static_cast<hipStream_t>(stream);
+    h.bind(stream);
+    amgf::AllocScope scope_(&h.mem);
     amgf::filter_solve(h, rc, wc);
     return AMGF_OK;
   });
@@ -1100,7 +1270,8 @@ amgf_status amgf_filter_solve(amgf_handle hd, const double* rc, double* wc, void
 amgf_status amgf_vcycle(amgf_handle hd, const double* r, double* z, void* stream) {
   if (!hd || !r || !z) return AMGF_EINVAL;
   amgf_status st_ = guard([&]() -> amgf_status {
-    hd->h.ctx.s = static_cast<hipStream_t>(stream);
+    hd->h.bind(stream);
+    amgf::AllocScope scope_(&hd->h.mem);
     amgf::vcycle(hd->h, r, z);
     return AMGF_OK;
   });
@@ -1111,7 +1282,8 @@ amgf_status amgf_vcycle(amgf_handle hd, const double* r, double* z, void* stream
 amgf_status amgf_operator_apply(amgf_handle hd, const double* x, double* y, void* stream) {
   if (!hd || !x || !y) return AMGF_EINVAL;
   amgf_status st_ = guard([&]() -> amgf_status {
-    hd->h.ctx.s = static_cast<hipStream_t>(stream);
+    hd->h.bind(stream);
+    amgf::AllocScope scope_(&hd->h.mem);
     amgf::operator_apply(hd->h, x, y, nullptr);
     return AMGF_OK;
   });
@@ -1123,7 +1295,8 @@ amgf_status amgf_pcg(amgf_handle hd, const double* b, double* x, amgf_solve_info
                      void* stream) {
   if (!hd || !b || !x) return AMGF_EINVAL;
   amgf_status st_ = guard([&]() -> amgf_status {
-    hd->h.ctx.s = static_cast<hipStream_t>(stream);
+    hd->h.bind(stream);
+    amgf::AllocScope scope_(&hd->h.mem);
     return amgf::pcg_impl(hd->h, b, x, info);
   });
   if (st_ != AMGF_OK) return st_;
@@ -1180,7 +1353,8 @@ amgf_status amgf_set_mlp(amgf_handle hd, const float* W, void* stream) {
   if (!hd) return AMGF_EINVAL;
   amgf_status st_ = guard([&]() -> amgf_status {
     Handle& h = hd->h;
-    h.ctx.s = static_cast<hipStream_t>(stream);
+    h.bind(stream);
+    amgf::AllocScope scope_(&h.mem);
     if (W) {
       AMGF_REQUIRE(h.opt.smoother != AMGF_CHEBYSHEV, AMGF_EINVAL,
                    "learned damping applies to the l1-Jacobi smoother");
@@ -1205,7 +1379,8 @@ amgf_status amgf_mlp_loss_grad(amgf_handle hd, const float* W, int32_t k, int32_
     Handle& h = hd->h;
     AMGF_REQUIRE(h.plain_cycle(), AMGF_EINVAL,
                  "the damping gradient needs the l1-Jacobi V(1,1) (sweeps = 1)");
-    h.ctx.s = static_cast<hipStream_t>(stream);
+    h.bind(stream);
+    amgf::AllocScope scope_(&h.mem);
     *loss = amgf::loss_grad(h, W, k, n_probes, probes, grad);
     // leave the handle's damping as it was
     amgf::set_damping(h, h.learned ? h.mlpW.p : nullptr);
@@ -1232,7 +1407,8 @@ amgf_status amgf_time_kernel(amgf_handle hd, int32_t which, int32_t reps, void* 
   amgf_status st_ = guard([&]() -> amgf_status {
     Handle& h = hd->h;
     amgf::Ctx& c = h.ctx;
-    c.s = static_cast<hipStream_t>(stream);
+    h.bind(stream);
+    amgf::AllocScope scope_(&h.mem);
     amgf::Level& L = *h.lev[0];
     const int64_t n = h.n();
     AMGF_REQUIRE(h.lev.size() > 1 || which >= AMGF_K_VCYCLE, AMGF_EINVAL,

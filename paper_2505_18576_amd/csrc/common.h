@@ -40,29 +40,80 @@ struct Error : std::runtime_error {
 // ------------------------------------------------------------------------------------
 // device buffers (owned by the handle)
 // ------------------------------------------------------------------------------------
+// Where device buffers come from: hipMalloc, or the caller's amgf_allocator that the
+// running entry point installed (AllocScope).  A buffer gives its memory back to the source
+// it came from, with the stream it was allocated on.
+struct AllocSrc {
+  amgf_allocator a{};
+  hipStream_t s = nullptr;
+};
+inline thread_local const AllocSrc* g_alloc = nullptr;
+struct AllocScope {
+  const AllocSrc* prev;
+  explicit AllocScope(const AllocSrc* a) : prev(g_alloc) { g_alloc = a; }
+  ~AllocScope() { g_alloc = prev; }
+  AllocScope(const AllocScope&) = delete;
+  AllocScope& operator=(const AllocScope&) = delete;
+};
+
 template <class T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
+  amgf_allocator src{};          // null alloc: the block came from hipMalloc
+  hipStream_t src_s = nullptr;
   DBuf() = default;
   explicit DBuf(size_t count) { alloc(count); }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), src(o.src), src_s(o.src_s) {
+    o.p = nullptr;
+    o.n = 0;
+  }
   DBuf& operator=(DBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      src = o.src;
+      src_s = o.src_s;
+      o.p = nullptr;
+      o.n = 0;
+    }
     return *this;
   }
   ~DBuf() { release(); }
   void alloc(size_t count) {
     release();
+    if (!count) return;
+    const size_t bytes = count * sizeof(T);
+    if (g_alloc && g_alloc->a.alloc) {
+      void* q = g_alloc->a.alloc(bytes, g_alloc->s, g_alloc->a.ctx);
+      if (!q) throw Error(AMGF_ENOMEM, "amgf_allocator.alloc returned NULL");
+      src = g_alloc->a;
+      src_s = g_alloc->s;
+      p = static_cast<T*>(q);
+      n = count;
+      if (reinterpret_cast<uintptr_t>(q) % 256) {
+        release();
+        throw Error(AMGF_EINVAL, "amgf_allocator.alloc returned a block not 256-byte aligned");
+      }
+      return;
+    }
+    AMGF_HIP(hipMalloc(&p, bytes));
     n = count;
-    if (count) AMGF_HIP(hipMalloc(&p, count * sizeof(T)));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (src.alloc)
+        src.free(p, src_s, src.ctx);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
     n = 0;
+    src = amgf_allocator{};
+    src_s = nullptr;
   }
   size_t bytes() const { return n * sizeof(T); }
   operator T*() const { return p; }

@@ -63,3 +63,30 @@ def test_binding_refuses_to_run_without_gpu():
     from paper_2505_18576_amd import AMGF
     with pytest.raises(RuntimeError, match="GPU"):
         AMGF.from_problem(make_config("C1"))
+
+
+def test_allocator_needs_both_callbacks(lib):
+    """An amgf_allocator with alloc but no free is refused before any device work."""
+    import ctypes
+    from paper_2505_18576_amd import amgf as b
+    o = b.default_options()
+    keep = b.ALLOC_FN(lambda nbytes, stream, ctx: None)
+    o.allocator.alloc = keep
+    fake = ctypes.c_void_p(256)
+    h = ctypes.c_void_p()
+    st = lib.amgf_setup(ctypes.byref(o), 8, fake, fake, fake, 0, None, None, None, None, fake,
+                        None, 0, None, ctypes.byref(h))
+    assert st == b.AMGF_EINVAL and not h.value
+    assert b"alloc and free" in lib.amgf_last_error()
+
+
+def test_ip_options_defaults(lib):
+    import ctypes
+    from paper_2505_18576_amd import amgf as b
+    o = b.ip_default_options()
+    assert o.struct_size == ctypes.sizeof(b.IPOptions)
+    assert (o.max_steps, o.tol, o.mu0, o.kappa_eps, o.s_max) == (200, 1e-6, 0.1, 10.0, 100.0)
+    assert ctypes.sizeof(b.IPStep) == 7 * 8 + 4 * 4 + 2 * 4
+    n, c = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.amgf_ip_solve(None, None, None, None, None, None, None, None, None, 0,
+                             ctypes.byref(n), ctypes.byref(c), None) == b.AMGF_EINVAL

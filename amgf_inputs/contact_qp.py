@@ -1,0 +1,36 @@
+"""Load vector and initial gap of the two-body contact problem that the interior-point
+driver solves: a uniform downward pressure on the top face of the top body (whose top face
+is on rollers, so the body is held up by contact alone) and a curved initial gap between
+the bodies, so that part of the interface closes and part stays open.
+
+Data only: the optimisation itself lives in the GPU library and, independently, in the
+CPU oracle.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def contact_load_and_gap(p, pressure=0.05, gap0=0.0, curvature=0.2):
+    """f (n) and g0 (m) for a problem from ``make_two_block``.
+
+    f: nodal forces -pressure * (lattice area of the node) in z on the top face of the
+    top body (interior nodes 1/N^2, edge nodes half, corner nodes a quarter).
+    g0: initial normal gap of constraint k, the non-mortar node at (x, y) on the
+    interface: gap0 + curvature * ((x - 1/2)^2 + (y - 1/2)^2).
+    """
+    N = p.N
+    n1 = N + 1
+    nb = n1 ** 3
+    w = np.ones(n1)
+    w[0] = w[-1] = 0.5
+    area = np.outer(w, w).ravel() / N ** 2              # index i + n1 * j
+    top_face = nb + N * n1 * n1 + np.arange(n1 * n1)
+    f = np.zeros(p.n)
+    f[3 * top_face + 2] = -pressure * area
+    r = np.arange(n1 * n1)
+    x = (r % n1) / N
+    y = (r // n1) / N
+    g0v = gap0 + curvature * ((x - 0.5) ** 2 + (y - 0.5) ** 2)
+    assert g0v.shape == (p.m,)
+    return f, g0v

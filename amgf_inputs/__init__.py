@@ -14,5 +14,5 @@ from .twoblock import (  # noqa: F401
     CONFIGS,
     make_config,
 )
-from .contact_qp import contact_load_and_gap  # noqa: F401
+from .contact_qp import contact_load_and_gap, lumped_masses  # noqa: F401
 from . import learning  # noqa: F401

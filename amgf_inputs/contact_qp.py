@@ -34,3 +34,18 @@ def contact_load_and_gap(p, pressure=0.05, gap0=0.0, curvature=0.2):
     g0v = gap0 + curvature * ((x - 0.5) ** 2 + (y - 0.5) ** 2)
     assert g0v.shape == (p.m,)
     return f, g0v
+
+
+def lumped_masses(p):
+    """Diagonal lumped masses of the lattice: Ms (m) the interface area of each constraint's
+    non-mortar node, Mu (n) the volume of each node, repeated for its three DOFs (interior
+    weights 1/N^2 and 1/N^3, halved once per boundary the node lies on)."""
+    N = p.N
+    n1 = N + 1
+    w = np.ones(n1)
+    w[0] = w[-1] = 0.5
+    Ms = np.outer(w, w).ravel() / N ** 2
+    vol = (w[:, None, None] * w[None, :, None] * w[None, None, :]).ravel() / N ** 3
+    Mu = np.repeat(np.concatenate([vol, vol]), 3)
+    assert Ms.shape == (p.m,) and Mu.shape == (p.n,)
+    return Ms, Mu

@@ -31,6 +31,12 @@ def parse():
     ap.add_argument("--reps", type=int, default=30)
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware counter collection, prints no JSON")
+    ap.add_argument("--ip", action="store_true",
+                    help="time the interior-point driver on the contact QP instead (AMGF, "
+                         "plain AMG and the AMG-to-AMGF switch); prints its own JSON line")
+    ap.add_argument("--ip-N", type=int, default=32)
+    ap.add_argument("--ip-tol", type=float, default=1e-6)
+    ap.add_argument("--ip-switch", type=float, default=1e6)
     return ap.parse_args()
 
 
@@ -140,12 +146,71 @@ def cpu_baseline(name, iters):
     return p.n, t1 - t0, (t2 - t1) / iters
 
 
+def ip_bench(args):
+    """Interior-point solve of the two-body contact QP (pressure on the top face, curved
+    initial gap) with the Newton systems solved by AMGF-PCG, plain AMG-PCG (capped at 5000
+    iterations, as in Sec. 7), and AMG switching to AMGF once D_max/D_min reaches
+    --ip-switch.  FP32 V-cycle, l1-Jacobi, inside FP64 CG for all three."""
+    import numpy as np
+    import torch
+    from amgf_inputs import contact_load_and_gap, lumped_masses, make_two_block
+    from paper_2505_18576_amd import AMGF
+    from paper_2505_18576_amd import amgf as b
+    p = make_two_block(args.ip_N)
+    f, g0 = contact_load_and_gap(p)
+    Ms, Mu = lumped_masses(p)
+    log(f"contact QP N={args.ip_N}: n={p.n} m={p.m}")
+    runs = {}
+    for name, kw, sw in (("amgf", dict(filter=1), 0.0), ("amg", dict(filter=0), 0.0),
+                         ("switch", dict(filter=1), args.ip_switch)):
+        for rep in range(args.warmup + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = AMGF.from_problem(p, precision=b.MIXED_FP32, max_iters=5000, **kw)
+            u, s, lam, z, steps, conv = h.ip_solve(f, g0, Ms=Ms, Mu=Mu, tol=args.ip_tol,
+                                                   switch_ratio=sw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            h.close()
+            its = [st["pcg_iterations"] for st in steps]
+            log(f"{name} {'warmup' if rep < args.warmup else 'timed'}: {dt:.2f}s, "
+                f"{len(steps)} Newton steps, converged {conv}, PCG its {its}")
+        runs[name] = dict(
+            seconds=dt, newton_steps=len(steps), converged=conv, pcg_iterations=its,
+            pcg_total=int(sum(its)), ms_update=float(sum(st["ms_update"] for st in steps)),
+            ms_solve=float(sum(st["ms_solve"] for st in steps)),
+            capped_solves=int(sum(1 for st in steps if not st["pcg_converged"])),
+            filter_on=[st["filter_on"] for st in steps],
+            D_ratio_last=steps[-1]["D_max"] / steps[-1]["D_min"] if steps else None,
+            u=u)
+    ua = runs["amgf"].pop("u")
+    for k in ("amg", "switch"):
+        uk = runs[k].pop("u")
+        runs[k]["rel_diff_u_vs_amgf"] = float(torch.linalg.norm(uk - ua) / torch.linalg.norm(ua))
+    out = {
+        "metric": "interior-point contact solve time to tol_IP (AMGF-PCG Newton solves)",
+        "value": runs["amgf"]["seconds"], "unit": "s", "n_gpus": 1, "steps": 1,
+        "warmup": args.warmup, "ms_per_step": 1e3 * runs["amgf"]["seconds"],
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f32 V-cycle / f64 CG and IP", "data": "synthetic",
+        "config": {"workload": f"two-body contact QP N={args.ip_N}: n={p.n}, m={p.m}, "
+                               f"tol_IP {args.ip_tol}",
+                   "amgf": runs["amgf"], "amg": runs["amg"], "switch": runs["switch"],
+                   "switch_ratio": args.ip_switch,
+                   "speedup_amgf_vs_amg": runs["amg"]["seconds"] / runs["amgf"]["seconds"],
+                   "speedup_switch_vs_amgf": runs["amgf"]["seconds"] / runs["switch"]["seconds"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the solver is a "
               "single-GPU build and has no multi-GPU path to time.", file=sys.stderr)
         sys.exit(2)
+    if args.ip:
+        return ip_bench(args)
     import numpy as np
     import torch
     from amgf_inputs import make_config

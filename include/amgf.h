@@ -259,17 +259,18 @@ amgf_status amgf_query(amgf_handle h, int32_t level, int32_t which, void* host_d
 /* ---------------- interior-point driver for the contact QP ----------------------------
  * Solves  minimise 1/2 u^T K u - f^T u  subject to  J u + g0 >= 0  with the handle's K and
  * J, by the interior-point Newton method outlined in Sec. 3: slacks s, multipliers lam of
- * J u + g0 - s = 0 and duals z of s >= 0; every Newton step is the condensed system
- * A u^ = b, A = K + J^T D J with D = z / s, solved by amgf_update_D + amgf_pcg (AMGF-PCG),
- * and s^, lam^, z^ are recovered from u^.  Barrier subproblem residuals (unit weights):
- * r_u = K u - f + J^T lam, r_s = -lam - z, r_lam = J u + g0 - s, r_z = s z - mu; optimality
- * error e(mu) = max(||r_u||_2 / s_d, ||r_s||_2 / s_d, ||r_lam||_inf, ||r_z||_inf / s_c) with
- * the scalings s_d = max(s_max, (|lam|_1 + |z|_1) / 2m) / s_max, s_c = max(s_max,
- * |z|_1 / m) / s_max.  mu decreases to max(tol / 10, min(kappa_mu mu, mu^theta_mu)) once
+ * J u + g0 - s = 0 and duals z = mu / s, the barrier weighted by the diagonal lumped slack
+ * mass M_s; every Newton step is the condensed system A u^ = b, A = K + J^T D J with
+ * D = M_s z / s, solved by amgf_update_D + amgf_pcg (AMGF-PCG), and s^, lam^, z^ are
+ * recovered from u^.  Barrier subproblem residuals: r_u = K u - f + J^T lam,
+ * r_s = -lam - M_s z, r_lam = J u + g0 - s, r_z = s z - mu; optimality error
+ * e(mu) = max(||r_u||_{M_u^-1} / s_d, ||r_s||_{M_s^-1} / s_d, ||r_lam||_inf,
+ * ||r_z||_inf / s_c) with M_u the lumped displacement mass and the scalings
+ * s_d = max(s_max, (|lam|_1 + |z|_1) / 2m) / s_max, s_c = max(s_max, |z|_1 / m) / s_max.  mu decreases to max(tol / 10, min(kappa_mu mu, mu^theta_mu)) once
  * e(mu) < kappa_eps mu; steps are cut back by the fraction-to-the-boundary rule with
  * tau = max(tau_min, 1 - mu) (separate lengths for the primal variables and z); the run
  * stops when e(0) < tol.  The first iterate is s = max(J u + g0, s_init), z = mu0 / s,
- * lam = -z.  Where the paper defers to its IP reference (Wachter and Biegler 2006) the
+ * lam = -M_s z.  Where the paper defers to its IP reference (Wachter and Biegler 2006) the
  * defaults of that method are used.                                                     */
 typedef struct {
   int32_t struct_size;        /* sizeof(amgf_ip_options)                              */
@@ -293,7 +294,7 @@ typedef struct {
   double e_opt;               /* optimality error e(0) before the step                */
   double e_opt_mu;            /* e(mu)                                                 */
   double alpha_p, alpha_d;    /* step lengths (s, u, lam) and (z)                     */
-  double D_min, D_max;        /* range of the barrier diagonal D = z / s              */
+  double D_min, D_max;        /* range of the barrier diagonal D = M_s z / s          */
   int32_t pcg_iterations;     /* CG iterations of the Newton solve                    */
   int32_t pcg_converged;      /* 0 when the solve stopped at max_iters (the step then
                                  uses the last CG iterate)                             */
@@ -306,17 +307,19 @@ typedef struct {
 /* Fill `o` with the defaults listed above. */
 void amgf_ip_default_options(amgf_ip_options* o);
 
-/* Run the driver.  f (n), g0 (m): device inputs.  u (n, device): initial point in,
+/* Run the driver.  f (n), g0 (m): device inputs.  Ms (m) and Mu (n): device lumped
+ * masses, positive, or NULL for ones.  u (n, device): initial point in,
  * solution out.  s, lam, z (m, device): outputs.  steps: host array of max_records
  * records (may be NULL), the first min(steps taken, max_records) are filled.  *n_steps and
  * *converged (host) receive the number of Newton steps and whether e(0) < tol was reached.
- * The handle's D is left at the last step's z / s.  EINVAL for m = 0, bad options or
+ * The handle's D is left at the last step's M_s z / s.  EINVAL for m = 0, bad options or
  * switch_ratio > 0 on a handle without filter; ENOTSPD if a solve breaks down; other CG
  * non-convergence is recorded per step and not an error.                             */
-amgf_status amgf_ip_solve(amgf_handle h, const double* f, const double* g0, double* u,
-                          double* s, double* lam, double* z, const amgf_ip_options* opts,
-                          amgf_ip_step* steps, int32_t max_records, int32_t* n_steps,
-                          int32_t* converged, void* stream);
+amgf_status amgf_ip_solve(amgf_handle h, const double* f, const double* g0, const double* Ms,
+                          const double* Mu, double* u, double* s, double* lam, double* z,
+                          const amgf_ip_options* opts, amgf_ip_step* steps,
+                          int32_t max_records, int32_t* n_steps, int32_t* converged,
+                          void* stream);
 
 #ifdef __cplusplus
 }

@@ -164,7 +164,7 @@ def load_library(path=LIB_PATH):
     L.amgf_profile_read.restype = ctypes.c_int
     L.amgf_ip_default_options.argtypes = [ctypes.POINTER(IPOptions)]
     L.amgf_ip_default_options.restype = None
-    L.amgf_ip_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(IPOptions),
+    L.amgf_ip_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(IPOptions),
                                 ctypes.POINTER(IPStep), i32, ctypes.POINTER(i32),
                                 ctypes.POINTER(i32), vp]
     L.amgf_ip_solve.restype = ctypes.c_int
@@ -317,9 +317,10 @@ class AMGF:
         _check(st, "amgf_pcg")
         return x, info
 
-    def ip_solve(self, f, g0, u0=None, **opts):
+    def ip_solve(self, f, g0, u0=None, Ms=None, Mu=None, **opts):
         """Interior-point solve of min 1/2 u^T K u - f^T u s.t. J u + g0 >= 0 with this
-        handle's K and J (amgf_ip_solve).  Returns (u, s, lam, z, steps, converged), the
+        handle's K and J (amgf_ip_solve); Ms (m) and Mu (n) are the lumped slack and
+        displacement masses (default ones).  Returns (u, s, lam, z, steps, converged), the
         vectors as device tensors and ``steps`` a list of per-Newton-step dicts."""
         torch = _torch()
         o = ip_default_options(**opts)
@@ -330,10 +331,16 @@ class AMGF:
         u = torch.zeros_like(fd) if u0 is None else _dev(u0, torch.float64).clone()
         if u.numel() != self.n:
             raise ValueError(f"u0 needs {self.n} values")
+        msd = None if Ms is None else _dev(Ms, torch.float64).reshape(-1)
+        mud = None if Mu is None else _dev(Mu, torch.float64).reshape(-1)
+        if (msd is not None and msd.numel() != self.m) or (mud is not None and
+                                                           mud.numel() != self.n):
+            raise ValueError(f"Ms needs {self.m} values and Mu {self.n}")
         s, lam, z = (torch.empty(self.m, dtype=torch.float64, device="cuda") for _ in range(3))
         rec = (IPStep * max(o.max_steps, 1))()
         ns, conv = ctypes.c_int32(), ctypes.c_int32()
-        _check(self.L.amgf_ip_solve(self.h, _ptr(fd), _ptr(gd), _ptr(u), _ptr(s), _ptr(lam),
+        _check(self.L.amgf_ip_solve(self.h, _ptr(fd), _ptr(gd), _ptr(msd), _ptr(mud), _ptr(u),
+                                    _ptr(s), _ptr(lam),
                                     _ptr(z), ctypes.byref(o), rec, len(rec), ctypes.byref(ns),
                                     ctypes.byref(conv), _stream()), "amgf_ip_solve")
         torch.cuda.synchronize()

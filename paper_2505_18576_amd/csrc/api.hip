@@ -982,9 +982,10 @@ static double ip_error(const amgf_ip_options& o, int m, double ru_norm, const do
   return std::max(std::max(ru_norm / s_d, std::sqrt(q[0]) / s_d), std::max(q[1], q[2] / s_c));
 }
 
-static void ip_solve(Handle& h, const double* f, const double* g0, double* u, double* s,
-                     double* lam, double* z, const amgf_ip_options& o, amgf_ip_step* rec,
-                     int max_rec, int* n_steps, int* converged) {
+static void ip_solve(Handle& h, const double* f, const double* g0, const double* Ms,
+                     const double* Mu, double* u, double* s, double* lam, double* z,
+                     const amgf_ip_options& o, amgf_ip_step* rec, int max_rec, int* n_steps,
+                     int* converged) {
   Ctx& c = h.ctx;
   Level& L0 = *h.lev[0];
   const int64_t n = h.n();
@@ -993,7 +994,7 @@ static void ip_solve(Handle& h, const double* f, const double* g0, double* u, do
   DBuf<double> rl(m), rs(m), t(m), Dn(m), sh(m), lh(m), zh(m);
   if (h.ip_red.n == 0) h.ip_red.alloc(8);
   double mu = o.mu0;
-  ip_init(c, L0.J, u, g0, mu, o.s_init, s, lam, z);
+  ip_init(c, L0.J, u, g0, Ms, mu, o.s_init, s, lam, z);
   bool filter_switched = false;
   *n_steps = 0;
   *converged = 0;
@@ -1003,13 +1004,15 @@ static void ip_solve(Handle& h, const double* f, const double* g0, double* u, do
     vcopy(c, y.p, ru.p, n);
     vscale(c, n, -1.0, ru.p);
     ip_jt_add(c, L0.JT, L0.crows.p, L0.ncrows, lam, ru.p);
-    ip_m_residuals(c, L0.J, u, g0, s, lam, z, rl.p, rs.p);
-    double nr2;
+    ip_m_residuals(c, L0.J, u, g0, Ms, s, lam, z, rl.p, rs.p);
+    double nr2;     // ||r_u||^2 in the M_u^{-1} norm
     const double* xs[1] = {ru.p};
-    dots(c, n, 1, xs, xs, &nr2);
+    if (Mu) ip_div(c, n, ru.p, Mu, y.p);
+    const double* ys[1] = {Mu ? y.p : ru.p};
+    dots(c, n, 1, xs, ys, &nr2);
     const double ru_norm = std::sqrt(nr2);
     double q[7];
-    ip_m_norms(c, m, rs.p, rl.p, s, lam, z, 0.0, h.ip_red.p, q);
+    ip_m_norms(c, m, rs.p, rl.p, s, lam, z, Ms, 0.0, h.ip_red.p, q);
     const double e0 = ip_error(o, m, ru_norm, q);
     if (e0 < o.tol) {
       *converged = 1;
@@ -1017,14 +1020,14 @@ static void ip_solve(Handle& h, const double* f, const double* g0, double* u, do
     }
     double e_mu;
     for (;;) {       // the barrier subproblem is solved: decrease mu, possibly repeatedly
-      ip_m_norms(c, m, rs.p, rl.p, s, lam, z, mu, h.ip_red.p, q);
+      ip_m_norms(c, m, rs.p, rl.p, s, lam, z, Ms, mu, h.ip_red.p, q);
       e_mu = ip_error(o, m, ru_norm, q);
       if (e_mu >= o.kappa_eps * mu || mu <= o.tol / 10) break;
       mu = std::max(o.tol / 10, std::min(o.kappa_mu * mu, std::pow(mu, o.theta_mu)));
     }
     const double D_min = q[5], D_max = q[6];
-    // D = z / s and the condensed right-hand side b = -r_u + J^T (D b_lam + b_s)
-    ip_rhs_m(c, m, s, z, rs.p, rl.p, mu, Dn.p, t.p);
+    // D = M_s z / s and the condensed right-hand side b = -r_u + J^T (D b_lam + b_s)
+    ip_rhs_m(c, m, s, z, Ms, rs.p, rl.p, mu, Dn.p, t.p);
     if (o.switch_ratio > 0 && !filter_switched && D_max >= o.switch_ratio * D_min)
       filter_switched = true;
     h.filter_suspended = o.switch_ratio > 0 && !filter_switched;
@@ -1042,8 +1045,8 @@ static void ip_solve(Handle& h, const double* f, const double* g0, double* u, do
     // recovery and step lengths, then the update
     const double tau = std::max(o.tau_min, 1.0 - mu);
     double alpha[2];
-    ip_recover(c, L0.J, uh.p, s, z, Dn.p, rs.p, rl.p, mu, tau, sh.p, lh.p, zh.p, h.ip_red.p,
-               alpha);
+    ip_recover(c, L0.J, uh.p, s, z, Dn.p, Ms, rs.p, rl.p, mu, tau, sh.p, lh.p, zh.p,
+               h.ip_red.p, alpha);
     axpby(c, n, alpha[0], uh.p, 1.0, u);
     ip_update_m(c, m, alpha[0], alpha[1], sh.p, lh.p, zh.p, s, lam, z);
     if (step < max_rec && rec) {
@@ -1198,10 +1201,11 @@ void amgf_ip_default_options(amgf_ip_options* o) {
   o->switch_ratio = 0.0;
 }
 
-amgf_status amgf_ip_solve(amgf_handle hd, const double* f, const double* g0, double* u,
-                          double* s, double* lam, double* z, const amgf_ip_options* opts,
-                          amgf_ip_step* steps, int32_t max_records, int32_t* n_steps,
-                          int32_t* converged, void* stream) {
+amgf_status amgf_ip_solve(amgf_handle hd, const double* f, const double* g0, const double* Ms,
+                          const double* Mu, double* u, double* s, double* lam, double* z,
+                          const amgf_ip_options* opts, amgf_ip_step* steps,
+                          int32_t max_records, int32_t* n_steps, int32_t* converged,
+                          void* stream) {
   if (!hd || !f || !g0 || !u || !s || !lam || !z || !n_steps || !converged || max_records < 0)
     return AMGF_EINVAL;
   return guard([&]() -> amgf_status {
@@ -1223,8 +1227,16 @@ amgf_status amgf_ip_solve(amgf_handle hd, const double* f, const double* g0, dou
                  "switching to AMGF needs a handle built with the filter");
     h.bind(stream);
     amgf::AllocScope scope_(&h.mem);
+    if (Ms || Mu) {
+      AMGF_HIP(hipMemsetAsync(h.ctx.flag.p, 0, sizeof(int), h.ctx.s));
+      if (Ms) amgf::check_values(h.ctx, Ms, h.m, true, h.ctx.flag.p);
+      if (Mu) amgf::check_values(h.ctx, Mu, h.n(), true, h.ctx.flag.p);
+      AMGF_REQUIRE(amgf::d2h_scalar(h.ctx.flag.p, h.ctx.s) == 0, AMGF_EINVAL,
+                   "lumped masses must be finite and positive");
+    }
     try {
-      amgf::ip_solve(h, f, g0, u, s, lam, z, o, steps, max_records, n_steps, converged);
+      amgf::ip_solve(h, f, g0, Ms, Mu, u, s, lam, z, o, steps, max_records, n_steps,
+                     converged);
     } catch (...) {
       h.filter_suspended = false;
       throw;

@@ -28,16 +28,16 @@ __device__ __forceinline__ double jrow(const int* __restrict__ rp, const int* __
 
 __global__ void k_ip_init(int m, const int* __restrict__ rp, const int* __restrict__ col,
                           const double* __restrict__ val, const double* __restrict__ u,
-                          const double* __restrict__ g0, double mu, double s_init,
-                          double* __restrict__ s, double* __restrict__ lam,
-                          double* __restrict__ z) {
+                          const double* __restrict__ g0, const double* __restrict__ Ms,
+                          double mu, double s_init, double* __restrict__ s,
+                          double* __restrict__ lam, double* __restrict__ z) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
   const double sk = fmax(jrow(rp, col, val, u, k) + g0[k], s_init);
   const double zk = mu / sk;
   s[k] = sk;
   z[k] = zk;
-  lam[k] = -zk;
+  lam[k] = -(Ms ? Ms[k] : 1.0) * zk;
 }
 
 // one wavefront per listed node row: y_a += sum_k JT(a, k) v_k
@@ -67,13 +67,20 @@ __global__ void __launch_bounds__(256) k_ip_jt_add(int nrows, const int* __restr
 
 __global__ void k_ip_m_residuals(int m, const int* __restrict__ rp, const int* __restrict__ col,
                                  const double* __restrict__ val, const double* __restrict__ u,
-                                 const double* __restrict__ g0, const double* __restrict__ s,
-                                 const double* __restrict__ lam, const double* __restrict__ z,
-                                 double* __restrict__ r_lam, double* __restrict__ r_s) {
+                                 const double* __restrict__ g0, const double* __restrict__ Ms,
+                                 const double* __restrict__ s, const double* __restrict__ lam,
+                                 const double* __restrict__ z, double* __restrict__ r_lam,
+                                 double* __restrict__ r_s) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
   r_lam[k] = jrow(rp, col, val, u, k) + g0[k] - s[k];
-  r_s[k] = -lam[k] - z[k];
+  r_s[k] = -lam[k] - (Ms ? Ms[k] : 1.0) * z[k];
+}
+
+__global__ void k_ip_div(int64_t n, const double* __restrict__ a, const double* __restrict__ d,
+                         double* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a[i] / d[i];
 }
 
 // tree reduction of one value per thread over the workgroup; op 0 sum, 1 max, 2 min
@@ -97,16 +104,17 @@ __device__ double block_reduce(double v, double* sh) {
 __global__ void __launch_bounds__(RED_THREADS) k_ip_m_norms(
     int m, const double* __restrict__ r_s, const double* __restrict__ r_lam,
     const double* __restrict__ s, const double* __restrict__ lam, const double* __restrict__ z,
-    double mu, double* __restrict__ out) {
+    const double* __restrict__ Ms, double mu, double* __restrict__ out) {
   __shared__ double sh[RED_THREADS];
   double q[7] = {0.0, 0.0, 0.0, 0.0, 0.0, DBL_MAX, 0.0};
   for (int k = threadIdx.x; k < m; k += RED_THREADS) {
-    q[0] += r_s[k] * r_s[k];
+    const double ms = Ms ? Ms[k] : 1.0;
+    q[0] += r_s[k] * r_s[k] / ms;
     q[1] = fmax(q[1], fabs(r_lam[k]));
     q[2] = fmax(q[2], fabs(s[k] * z[k] - mu));
     q[3] += fabs(lam[k]);
     q[4] += fabs(z[k]);
-    const double d = z[k] / s[k];
+    const double d = ms * z[k] / s[k];
     q[5] = fmin(q[5], d);
     q[6] = fmax(q[6], d);
   }
@@ -129,13 +137,15 @@ __global__ void __launch_bounds__(RED_THREADS) k_ip_m_norms(
 }
 
 __global__ void k_ip_rhs_m(int m, const double* __restrict__ s, const double* __restrict__ z,
-                           const double* __restrict__ r_s, const double* __restrict__ r_lam,
-                           double mu, double* __restrict__ D, double* __restrict__ t) {
+                           const double* __restrict__ Ms, const double* __restrict__ r_s,
+                           const double* __restrict__ r_lam, double mu, double* __restrict__ D,
+                           double* __restrict__ t) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
-  const double d = z[k] / s[k];
+  const double ms = Ms ? Ms[k] : 1.0;
+  const double d = ms * z[k] / s[k];
   const double b_lam = -r_lam[k];
-  const double b_s = -(r_s[k] + (s[k] * z[k] - mu) / s[k]);
+  const double b_s = -(r_s[k] + ms * (s[k] * z[k] - mu) / s[k]);
   D[k] = d;
   t[k] = d * b_lam + b_s;
 }
@@ -144,7 +154,8 @@ __global__ void __launch_bounds__(RED_THREADS) k_ip_recover(
     int m, const int* __restrict__ rp, const int* __restrict__ col,
     const double* __restrict__ val, const double* __restrict__ uh,
     const double* __restrict__ s, const double* __restrict__ z, const double* __restrict__ D,
-    const double* __restrict__ r_s, const double* __restrict__ r_lam, double mu, double tau,
+    const double* __restrict__ Ms, const double* __restrict__ r_s,
+    const double* __restrict__ r_lam, double mu, double tau,
     double* __restrict__ sh_out, double* __restrict__ lh_out, double* __restrict__ zh_out,
     double* __restrict__ out) {
   __shared__ double sh[RED_THREADS];
@@ -152,7 +163,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_ip_recover(
   for (int k = threadIdx.x; k < m; k += RED_THREADS) {
     const double b_lam = -r_lam[k];
     const double r_z = s[k] * z[k] - mu;
-    const double b_s = -(r_s[k] + r_z / s[k]);
+    const double b_s = -(r_s[k] + (Ms ? Ms[k] : 1.0) * r_z / s[k]);
     const double s_h = jrow(rp, col, val, uh, k) - b_lam;
     const double l_h = D[k] * s_h - b_s;
     const double z_h = -(r_z + z[k] * s_h) / s[k];
@@ -187,13 +198,13 @@ void require_j(const BSR& J) {
 
 }  // namespace
 
-void ip_init(Ctx& c, const BSR& J, const double* u, const double* g0, double mu, double s_init,
-             double* s, double* lam, double* z) {
+void ip_init(Ctx& c, const BSR& J, const double* u, const double* g0, const double* Ms,
+             double mu, double s_init, double* s, double* lam, double* z) {
   require_j(J);
   const int m = J.nrows;
   if (!m) return;
   hipLaunchKernelGGL(k_ip_init, dim3(grid_for(m, 256)), dim3(256), 0, c.s, m, J.rowptr.p,
-                     J.col.p, J.val.p, u, g0, mu, s_init, s, lam, z);
+                     J.col.p, J.val.p, u, g0, Ms, mu, s_init, s, lam, z);
   AMGF_LAUNCH_CHECK();
 }
 
@@ -205,39 +216,48 @@ void ip_jt_add(Ctx& c, const BSR& JT, const int* crows, int ncrows, const double
   AMGF_LAUNCH_CHECK();
 }
 
-void ip_m_residuals(Ctx& c, const BSR& J, const double* u, const double* g0, const double* s,
-                    const double* lam, const double* z, double* r_lam, double* r_s) {
+void ip_m_residuals(Ctx& c, const BSR& J, const double* u, const double* g0, const double* Ms,
+                    const double* s, const double* lam, const double* z, double* r_lam,
+                    double* r_s) {
   require_j(J);
   const int m = J.nrows;
   if (!m) return;
   hipLaunchKernelGGL(k_ip_m_residuals, dim3(grid_for(m, 256)), dim3(256), 0, c.s, m,
-                     J.rowptr.p, J.col.p, J.val.p, u, g0, s, lam, z, r_lam, r_s);
+                     J.rowptr.p, J.col.p, J.val.p, u, g0, Ms, s, lam, z, r_lam, r_s);
+  AMGF_LAUNCH_CHECK();
+}
+
+void ip_div(Ctx& c, int64_t n, const double* a, const double* d, double* y) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_ip_div, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, a, d, y);
   AMGF_LAUNCH_CHECK();
 }
 
 void ip_m_norms(Ctx& c, int m, const double* r_s, const double* r_lam, const double* s,
-                const double* lam, const double* z, double mu, double* dev, double* out) {
+                const double* lam, const double* z, const double* Ms, double mu, double* dev,
+                double* out) {
   hipLaunchKernelGGL(k_ip_m_norms, dim3(1), dim3(RED_THREADS), 0, c.s, m, r_s, r_lam, s, lam,
-                     z, mu, dev);
+                     z, Ms, mu, dev);
   AMGF_LAUNCH_CHECK();
   AMGF_HIP(hipMemcpyAsync(out, dev, 7 * sizeof(double), hipMemcpyDeviceToHost, c.s));
   AMGF_HIP(hipStreamSynchronize(c.s));
 }
 
-void ip_rhs_m(Ctx& c, int m, const double* s, const double* z, const double* r_s,
-              const double* r_lam, double mu, double* D, double* t) {
+void ip_rhs_m(Ctx& c, int m, const double* s, const double* z, const double* Ms,
+              const double* r_s, const double* r_lam, double mu, double* D, double* t) {
   if (!m) return;
-  hipLaunchKernelGGL(k_ip_rhs_m, dim3(grid_for(m, 256)), dim3(256), 0, c.s, m, s, z, r_s, r_lam,
-                     mu, D, t);
+  hipLaunchKernelGGL(k_ip_rhs_m, dim3(grid_for(m, 256)), dim3(256), 0, c.s, m, s, z, Ms, r_s,
+                     r_lam, mu, D, t);
   AMGF_LAUNCH_CHECK();
 }
 
 void ip_recover(Ctx& c, const BSR& J, const double* uh, const double* s, const double* z,
-                const double* D, const double* r_s, const double* r_lam, double mu, double tau,
-                double* sh, double* lh, double* zh, double* dev, double* alpha) {
+                const double* D, const double* Ms, const double* r_s, const double* r_lam,
+                double mu, double tau, double* sh, double* lh, double* zh, double* dev,
+                double* alpha) {
   require_j(J);
   hipLaunchKernelGGL(k_ip_recover, dim3(1), dim3(RED_THREADS), 0, c.s, J.nrows, J.rowptr.p,
-                     J.col.p, J.val.p, uh, s, z, D, r_s, r_lam, mu, tau, sh, lh, zh, dev);
+                     J.col.p, J.val.p, uh, s, z, D, Ms, r_s, r_lam, mu, tau, sh, lh, zh, dev);
   AMGF_LAUNCH_CHECK();
   AMGF_HIP(hipMemcpyAsync(alpha, dev, 2 * sizeof(double), hipMemcpyDeviceToHost, c.s));
   AMGF_HIP(hipStreamSynchronize(c.s));

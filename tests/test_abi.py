@@ -88,5 +88,5 @@ def test_ip_options_defaults(lib):
     assert (o.max_steps, o.tol, o.mu0, o.kappa_eps, o.s_max) == (200, 1e-6, 0.1, 10.0, 100.0)
     assert ctypes.sizeof(b.IPStep) == 7 * 8 + 4 * 4 + 2 * 4
     n, c = ctypes.c_int32(), ctypes.c_int32()
-    assert lib.amgf_ip_solve(None, None, None, None, None, None, None, None, None, 0,
+    assert lib.amgf_ip_solve(None, None, None, None, None, None, None, None, None, None, None, 0,
                              ctypes.byref(n), ctypes.byref(c), None) == b.AMGF_EINVAL

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from amgf_inputs import contact_load_and_gap, make_two_block
+from amgf_inputs import contact_load_and_gap, lumped_masses, make_two_block
 from oracle.ip_newton import IPOptions, ip_solve, kkt_certificate
 
 pytestmark = pytest.mark.gpu
@@ -17,7 +17,8 @@ def _qp(N):
     K = sp.bsr_matrix((p.K_val, p.K_col, p.K_rowptr), shape=(p.n, p.n)).tocsr()
     J = sp.csr_matrix((p.J_val, p.J_col, p.J_rowptr), shape=(p.m, p.n))
     f, g0 = contact_load_and_gap(p)
-    return p, K, J, f, g0
+    Ms, Mu = lumped_masses(p)
+    return p, K, J, f, g0, Ms, Mu
 
 
 def _handle(p, **kw):
@@ -26,12 +27,15 @@ def _handle(p, **kw):
     return AMGF.from_problem(p, **kw)
 
 
-@pytest.mark.parametrize("N,tol", [(6, 1e-6), (8, 1e-10)])
-def test_ip_matches_oracle(N, tol):
-    p, K, J, f, g0 = _qp(N)
-    ref = ip_solve(K, J, f, g0, IPOptions(tol=tol))
+@pytest.mark.parametrize("N,tol,masses", [(6, 1e-6, False), (6, 1e-6, True),
+                                          (8, 1e-10, True)])
+def test_ip_matches_oracle(N, tol, masses):
+    p, K, J, f, g0, Ms, Mu = _qp(N)
+    if not masses:
+        Ms = Mu = None
+    ref = ip_solve(K, J, f, g0, IPOptions(tol=tol), Ms=Ms, Mu=Mu)
     h = _handle(p)
-    u, s, lam, z, steps, conv = h.ip_solve(f, g0, tol=tol)
+    u, s, lam, z, steps, conv = h.ip_solve(f, g0, Ms=Ms, Mu=Mu, tol=tol)
     u, s, lam, z = (v.cpu().numpy() for v in (u, s, lam, z))
     print(f"N={N} tol={tol}: gpu {len(steps)} steps, oracle {len(ref.steps)} steps; "
           f"PCG its {[st['pcg_iterations'] for st in steps]}")
@@ -45,22 +49,23 @@ def test_ip_matches_oracle(N, tol):
     assert abs(a["alpha_p"] - b.alpha_p) <= 1e-8 and abs(a["alpha_d"] - b.alpha_d) <= 1e-8
     for x, y in ((u, ref.u), (z, ref.z)):
         assert np.linalg.norm(x - y) <= 1e-6 * np.linalg.norm(y)
-    stat, infeas, dneg, compl = kkt_certificate(K, J, f, g0, u, z)
+    # constraint forces -lam (= M_s z at convergence)
+    stat, infeas, dneg, compl = kkt_certificate(K, J, f, g0, u, -lam)
     print(f"  KKT: stationarity {stat:.1e}, infeasibility {infeas:.1e}, "
           f"complementarity {compl:.1e}")
     assert stat <= 10 * tol and infeas == 0.0 and dneg == 0.0 and compl <= 10 * tol
-    assert np.allclose(lam, -z, rtol=1e-4, atol=10 * tol)
+    assert np.allclose(-lam, (1.0 if Ms is None else Ms) * z, rtol=1e-4, atol=10 * tol)
     h.close()
 
 
 def test_amg_degrades_amgf_does_not():
     """Along the Newton steps the barrier diagonal spreads over many orders of magnitude;
     plain AMG-PCG needs more and more iterations while AMGF-PCG stays flat (Sec. 4)."""
-    p, K, J, f, g0 = _qp(16)
+    p, K, J, f, g0, Ms, Mu = _qp(16)
     runs = {}
     for filt in (1, 0):
         h = _handle(p, filter=filt, max_iters=3000)
-        u, s, lam, z, steps, conv = h.ip_solve(f, g0, tol=1e-8)
+        u, s, lam, z, steps, conv = h.ip_solve(f, g0, Ms=Ms, Mu=Mu, tol=1e-8)
         runs[filt] = (u.cpu().numpy(), steps, conv)
         print(f"filter={filt}: {len(steps)} steps, D_max/D_min "
               f"{steps[-1]['D_max'] / steps[-1]['D_min']:.1e}, PCG its "
@@ -77,9 +82,9 @@ def test_amg_degrades_amgf_does_not():
 
 
 def test_switch_from_amg_to_amgf():
-    p, K, J, f, g0 = _qp(12)
+    p, K, J, f, g0, Ms, Mu = _qp(12)
     h = _handle(p)
-    u, s, lam, z, steps, conv = h.ip_solve(f, g0, tol=1e-8, switch_ratio=1e6)
+    u, s, lam, z, steps, conv = h.ip_solve(f, g0, Ms=Ms, Mu=Mu, tol=1e-8, switch_ratio=1e6)
     on = [st["filter_on"] for st in steps]
     print(f"filter per step {on}, PCG its {[st['pcg_iterations'] for st in steps]}")
     assert conv and on[0] == 0 and on[-1] == 1
@@ -88,7 +93,7 @@ def test_switch_from_amg_to_amgf():
     assert all(st["D_max"] < 1e6 * st["D_min"] for st in steps[:k])
     assert steps[k]["D_max"] >= 1e6 * steps[k]["D_min"]
     h2 = _handle(p)
-    u2, *_ = h2.ip_solve(f, g0, tol=1e-8)
+    u2, *_ = h2.ip_solve(f, g0, Ms=Ms, Mu=Mu, tol=1e-8)
     assert np.linalg.norm(u.cpu().numpy() - u2.cpu().numpy()) <= 1e-5 * np.linalg.norm(
         u2.cpu().numpy())
     h.close()

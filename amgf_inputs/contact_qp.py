@@ -19,6 +19,14 @@ def contact_load_and_gap(p, pressure=0.05, gap0=0.0, curvature=0.2):
     g0: initial normal gap of constraint k, the non-mortar node at (x, y) on the
     interface: gap0 + curvature * ((x - 1/2)^2 + (y - 1/2)^2).
     """
+    if "nm_xy" in p.meta:          # geometry carried by the problem (block on block)
+        f = np.zeros(p.n)
+        f[3 * p.meta["load_nodes"] + 2] = -pressure * p.meta["load_area"]
+        x, y = p.meta["nm_xy"][:, 0], p.meta["nm_xy"][:, 1]
+        cx, cy = p.meta["center"]
+        g0v = gap0 + curvature * ((x - cx) ** 2 + (y - cy) ** 2)
+        assert g0v.shape == (p.m,)
+        return f, g0v
     N = p.N
     n1 = N + 1
     nb = n1 ** 3
@@ -40,6 +48,11 @@ def lumped_masses(p):
     """Diagonal lumped masses of the lattice: Ms (m) the interface area of each constraint's
     non-mortar node, Mu (n) the volume of each node, repeated for its three DOFs (interior
     weights 1/N^2 and 1/N^3, halved once per boundary the node lies on)."""
+    if "nm_area" in p.meta:
+        Ms = np.asarray(p.meta["nm_area"], np.float64)
+        Mu = np.repeat(np.asarray(p.meta["node_vol"], np.float64), 3)
+        assert Ms.shape == (p.m,) and Mu.shape == (p.n,)
+        return Ms, Mu
     N = p.N
     n1 = N + 1
     w = np.ones(n1)

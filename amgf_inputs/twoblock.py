@@ -31,7 +31,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["TwoBlockProblem", "make_two_block", "q1_element_matrices",
-           "ip_sequence_D", "CONFIGS", "make_config"]
+           "ip_sequence_D", "CONFIGS", "BLOCK_CONFIGS", "make_config"]
 
 
 # --------------------------------------------------------------------------------------
@@ -297,8 +297,28 @@ CONFIGS = {
 }
 
 
+# small block (E = 1000, nu = 0) on a large block (E = 1, nu = 0.45) with non-matching
+# interface meshes (Nb = 7/8 Nt over a top block of half the width, so the bottom mesh is
+# about 2.3 times coarser at the interface); m = (Nt + 1)^2 equals Table 1's m_max for
+# Nt = 8 * 2^(k-1)
+BLOCK_CONFIGS = {
+    "B1": dict(Nt=8, Nb=7, D_log10=(0.0, 8.0), D_seed=61, rhs_seed=71),
+    "B2": dict(Nt=16, Nb=14, D_log10=(0.0, 8.0), D_seed=62, rhs_seed=72),
+    "B3": dict(Nt=64, Nb=56, D_log10=(0.0, 12.0), D_seed=63, rhs_seed=73),
+    "B5": dict(Nt=128, Nb=112, D_log10=(0.0, 12.0), D_seed=65, rhs_seed=75),
+}
+
+
 def make_config(name, rhs_seed=None, ip_step=None, N=None):
-    """Build one of the presets.  C4 needs ``ip_step`` (1..20); its rhs seed is 40+t."""
+    """Build one of the presets.  C4 needs ``ip_step`` (1..20); its rhs seed is 40+t.
+    B1..B5 are the non-matching block-on-block problems."""
+    if name in BLOCK_CONFIGS:
+        from .block_on_block import make_block_on_block
+        c = dict(BLOCK_CONFIGS[name])
+        if rhs_seed is not None:
+            c["rhs_seed"] = rhs_seed
+        return make_block_on_block(c.pop("Nt"), c.pop("Nb"), E=(1.0, 1000.0),
+                                   nu=(0.45, 0.0), **c)
     c = dict(CONFIGS[name])
     if N is not None:
         c["N"] = N

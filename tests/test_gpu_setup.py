@@ -7,7 +7,8 @@ from gpu_util import gpu, oracle, problem, rel
 
 pytestmark = pytest.mark.gpu
 
-CASES = [("C1", {}), ("C1", {"coarse_max_nodes": 8}), ("N12", {"coarse_max_nodes": 16})]
+CASES = [("C1", {}), ("C1", {"coarse_max_nodes": 8}), ("N12", {"coarse_max_nodes": 16}),
+         ("B1", {}), ("B2", {})]
 
 
 def _blocks_equal(o_bm, rp, col, val, exact):

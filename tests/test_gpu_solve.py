@@ -8,7 +8,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("name,opts", [("C1", {}), ("C1", {"coarse_max_nodes": 8}),
-                                       ("N12", {"coarse_max_nodes": 16})])
+                                       ("N12", {"coarse_max_nodes": 16}), ("B1", {}),
+                                       ("B2", {})])
 def test_operator_vcycle_and_apply_fp64(name, opts):
     import torch
     o = oracle(name, **opts)

@@ -15,5 +15,5 @@ from .twoblock import (  # noqa: F401
     make_config,
 )
 from .block_on_block import make_block_on_block  # noqa: F401
-from .contact_qp import contact_load_and_gap, lumped_masses  # noqa: F401
+from .contact_qp import bound_barrier, contact_load_and_gap, lumped_masses  # noqa: F401
 from . import learning  # noqa: F401

@@ -62,3 +62,12 @@ def lumped_masses(p):
     Mu = np.repeat(np.concatenate([vol, vol]), 3)
     assert Ms.shape == (p.m,) and Mu.shape == (p.n,)
     return Ms, Mu
+
+
+def bound_barrier(p, seed=0, log10_range=(-2.0, 4.0), fraction=0.7):
+    """Barrier diagonal E (n values >= 0) of bound constraints on the displacements
+    (Remark 3.1): log-uniform on a random `fraction` of the free DOFs, 0 elsewhere."""
+    rng = np.random.default_rng(seed)
+    E = 10.0 ** rng.uniform(log10_range[0], log10_range[1], p.n)
+    E[(rng.uniform(size=p.n) >= fraction) | ~p.free] = 0.0
+    return E

@@ -93,6 +93,10 @@ typedef struct {
                                  correction, 1..16 (default 1: V(1,1))                */
   int32_t cheb_degree;        /* Chebyshev degree, 1..16 (default 2)                  */
   amgf_allocator allocator;   /* device memory source (default: both NULL, hipMalloc) */
+  const double* bound_diag;   /* NULL, or n device values E >= 0: barrier terms of bound
+                                 constraints on u (Remark 3.1: J~ = [J; I; -I] adds
+                                 diag(D_lower + D_upper) = diag(E)), so that
+                                 A = K + diag(E) + J^T D J.  Read by amgf_setup only.   */
 } amgf_options;
 
 typedef struct {
@@ -144,6 +148,15 @@ amgf_status amgf_apply(amgf_handle h, const double* r, double* z, void* stream);
  * every A_{l+1} = P_l^T A_l P_l still holds.  EINVAL for D <= 0 or non-finite entries
  * (the handle is unchanged then); ENOTSPD if a factor loses definiteness.             */
 amgf_status amgf_update_D(amgf_handle h, const double* D, void* stream);
+
+/* Both barrier terms of a new interior-point step: D (m values > 0, device) and the bound
+ * diagonal E (n values >= 0, device; NULL removes it), A = K + diag(E) + J^T D J
+ * (Remark 3.1).  Like amgf_update_D, with the stiffness chain rebuilt as well: the
+ * aggregates and prolongators are kept, K_0 = K + diag(E) and K_{l+1} = P_l^T K_l P_l are
+ * recomputed (coarse DOFs whose near-null column died again get a unit diagonal), then
+ * everything amgf_update_D rebuilds.  EINVAL for D <= 0, E < 0 or non-finite values (the
+ * handle is unchanged then).                                                           */
+amgf_status amgf_update_barrier(amgf_handle h, const double* D, const double* E, void* stream);
 
 /* w_c = A_w^{-1} r_c with A_w = S[I_c, I_c], the filtering-space solve of Definition 5.3
  * (Sec. 5.1), by the handle's nested-dissection multifrontal Cholesky factor.  r_c, w_c:
@@ -312,8 +325,9 @@ void amgf_ip_default_options(amgf_ip_options* o);
  * solution out.  s, lam, z (m, device): outputs.  steps: host array of max_records
  * records (may be NULL), the first min(steps taken, max_records) are filled.  *n_steps and
  * *converged (host) receive the number of Newton steps and whether e(0) < tol was reached.
- * The handle's D is left at the last step's M_s z / s.  EINVAL for m = 0, bad options or
- * switch_ratio > 0 on a handle without filter; ENOTSPD if a solve breaks down; other CG
+ * The handle's D is left at the last step's M_s z / s.  EINVAL for m = 0, bad options,
+ * a handle with bound terms (the driver has no bound constraints) or switch_ratio > 0 on
+ * a handle without filter; ENOTSPD if a solve breaks down; other CG
  * non-convergence is recorded per step and not an error.                             */
 amgf_status amgf_ip_solve(amgf_handle h, const double* f, const double* g0, const double* Ms,
                           const double* Mu, double* u, double* s, double* lam, double* z,

@@ -223,6 +223,19 @@ def contact_product(Jb, D):
     return block_spgemm(JT, block_spgemm(Dm, Jb))
 
 
+def with_bound_diagonal(K, E):
+    """K + diag(E) for the barrier terms of bound constraints (Remark 3.1: J~ = [J; I; -I]
+    adds diag(D_lower + D_upper) = diag(E)); one add per diagonal entry.  E None: K."""
+    if E is None:
+        return K
+    E = np.asarray(E, np.float64).reshape(-1, 3)
+    Kt = BlockMatrix(K.rowptr, K.col, K.val.copy(), K.ncols)
+    dp = Kt.diag_pos()
+    for q in range(3):
+        Kt.val[dp, q, q] = Kt.val[dp, q, q] + E[:, q]
+    return Kt
+
+
 def schur_operator(K, Jb, D):
     """Level-0 operator S = K + C with C from ``contact_exact`` and one final add."""
     return block_add(K, contact_exact(Jb, D))
@@ -519,12 +532,13 @@ class OracleAMGF:
     """Setup + apply of the AMGF preconditioner and its PCG driver (FP64)."""
 
     def __init__(self, n_nodes, K_rowptr, K_col, K_val, J_rowptr, J_col, J_val, D,
-                 coords, opts: OracleOptions | None = None):
+                 coords, opts: OracleOptions | None = None, E=None):
         self.opts = opts or OracleOptions()
         o = self.opts
         self.n_nodes = int(n_nodes)
         self.D = np.asarray(D, np.float64)
-        K0 = BlockMatrix(K_rowptr, K_col, np.asarray(K_val).reshape(-1, 3, 3), n_nodes)
+        self.K_in = BlockMatrix(K_rowptr, K_col, np.asarray(K_val).reshape(-1, 3, 3), n_nodes)
+        K0 = with_bound_diagonal(self.K_in, E)
         J0 = scalar_J_to_blocks(J_rowptr, J_col, J_val, n_nodes, 3)
         self.K0, self.J0 = K0, J0
         self.coords = None if coords is None else np.asarray(coords, np.float64).reshape(-1, 3)
@@ -595,6 +609,25 @@ class OracleAMGF:
         self._setup_filter()
 
     # ---------------------------------------------------------------- new barrier diagonal
+    def update_barrier(self, D, E=None):
+        """Numeric re-setup for new barrier terms of both kinds: D of the contact rows and
+        the diagonal E of bound constraints (Remark 3.1, A = K + J^T D J + E).  The
+        aggregates and prolongators are kept; the level-0 stiffness K + diag(E), the
+        coarse stiffness chain K_{l+1} = P_l^T K_l P_l (dead coarse DOFs again with a unit
+        diagonal) and everything ``update_D`` rebuilds are recomputed."""
+        self.K0 = with_bound_diagonal(self.K_in, E)
+        self.levels[0].K = self.K0
+        for l in range(self.nlev - 1):
+            lev, nxt = self.levels[l], self.levels[l + 1]
+            Kc = block_spgemm(lev.P.transpose(), block_spgemm(lev.K, lev.P))
+            if lev.dead.any():
+                dp = Kc.diag_pos()
+                for J_ in np.nonzero(lev.dead.any(axis=1))[0]:
+                    for j in np.nonzero(lev.dead[J_])[0]:
+                        Kc.val[dp[J_], j, j] = 1.0
+            nxt.K = Kc
+        self.update_D(D)
+
     def update_D(self, D):
         """Numeric re-setup for a new interior-point step (same K and J, new D).
 

@@ -26,7 +26,8 @@ ABI_FUNCTIONS = ["amgf_default_options", "amgf_setup", "amgf_apply", "amgf_vcycl
                  "amgf_last_error", "amgf_num_levels", "amgf_query", "amgf_time_kernel",
                  "amgf_set_mlp", "amgf_mlp_loss_grad", "amgf_adam_step",
                  "amgf_profile_start", "amgf_profile_read", "amgf_filter_solve",
-                 "amgf_update_D", "amgf_ip_default_options", "amgf_ip_solve"]
+                 "amgf_update_D", "amgf_ip_default_options", "amgf_ip_solve",
+                 "amgf_update_barrier"]
 K_PRESMOOTH, K_POSTSMOOTH, K_VCYCLE, K_OPERATOR = range(4)
 
 
@@ -78,7 +79,7 @@ class Options(ctypes.Structure):
                 ("max_coarse_ratio", ctypes.c_double),
                 ("mlp_weights", ctypes.POINTER(ctypes.c_float)),
                 ("sweeps", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
-                ("allocator", Allocator)]
+                ("allocator", Allocator), ("bound_diag", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -158,6 +159,8 @@ def load_library(path=LIB_PATH):
     L.amgf_adam_step.restype = ctypes.c_int
     L.amgf_update_D.argtypes = [vp, vp, vp]
     L.amgf_update_D.restype = ctypes.c_int
+    L.amgf_update_barrier.argtypes = [vp, vp, vp, vp]
+    L.amgf_update_barrier.restype = ctypes.c_int
     L.amgf_profile_start.argtypes = [vp, i32, i32]
     L.amgf_profile_start.restype = ctypes.c_int
     L.amgf_profile_read.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
@@ -240,7 +243,7 @@ class AMGF:
     """
 
     def __init__(self, n_nodes, K_rowptr, K_col, K_val, J_rowptr, J_col, J_val, D, coords,
-                 Ic=None, options=None, mlp_weights=None, allocator=None, **kw):
+                 Ic=None, options=None, mlp_weights=None, allocator=None, E=None, **kw):
         torch = _torch()
         self.L = load_library()
         self.options = options if options is not None else default_options(**kw)
@@ -263,6 +266,13 @@ class AMGF:
         self.n_nodes = int(n_nodes)
         self.n = 3 * self.n_nodes
         ic = _dev(Ic, i32) if Ic is not None else None
+        # E: barrier diagonal of bound constraints (n values >= 0), read during setup
+        Ed = None
+        if E is not None:
+            Ed = _dev(E, f64).reshape(-1)
+            if Ed.numel() != self.n:
+                raise ValueError(f"E needs {self.n} values")
+            self.options.bound_diag = Ed.data_ptr()
         h = ctypes.c_void_p()
         st = self.L.amgf_setup(ctypes.byref(self.options), self.n_nodes,
                                *[_ptr(t) for t in self._keep[:3]], self.m,
@@ -273,6 +283,7 @@ class AMGF:
         self.h = h
         torch.cuda.synchronize()
         self._keep = None
+        self.options.bound_diag = None
 
     @classmethod
     def from_problem(cls, p, **kw):
@@ -294,6 +305,18 @@ class AMGF:
         torch = _torch()
         Dd = _dev(D, torch.float64)
         _check(self.L.amgf_update_D(self.h, _ptr(Dd), _stream()), "amgf_update_D")
+        torch.cuda.synchronize()
+
+    def update_barrier(self, D, E=None):
+        """New barrier terms: contact diagonal D (m > 0) and bound diagonal E (n >= 0, or
+        None to drop it); the stiffness chain is rebuilt with the kept prolongators."""
+        torch = _torch()
+        Dd = _dev(D, torch.float64)
+        Ed = None if E is None else _dev(E, torch.float64).reshape(-1)
+        if Ed is not None and Ed.numel() != self.n:
+            raise ValueError(f"E needs {self.n} values")
+        _check(self.L.amgf_update_barrier(self.h, _ptr(Dd), _ptr(Ed), _stream()),
+               "amgf_update_barrier")
         torch.cuda.synchronize()
 
     def filter_solve(self, rc):

@@ -41,6 +41,7 @@ struct Level {
   DBuf<double> vd, vt;
   DBuf<float> fd, ft;
   double lam = 1.0;             // unclipped power estimate of rho(D_l1^{-1} A)
+  DBuf<unsigned char> dead;     // dead near-null columns of the aggregates (n_agg x 6)
   int64_t n() const { return int64_t(nn) * b; }
 };
 
@@ -50,6 +51,8 @@ struct Handle {
   int n_nodes = 0, m = 0;
   std::vector<std::unique_ptr<Level>> lev;
   DBuf<double> D, coords;
+  DBuf<double> kdiag0;          // diagonal entries of the input K (bound terms present)
+  bool has_E = false;           // K_0 = K + diag(E) with bound-constraint barrier terms
   DBuf<unsigned char> dec0;
   DBuf<double> t;               // contact scratch (m)
   // coarsest solve (multifrontal Cholesky of the coarsest operator)
@@ -208,9 +211,11 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     check_values(c, D, m, true, c.flag.p);
   }
   check_values(c, coords, int64_t(nn) * 3, false, c.flag.p);
+  if (o.bound_diag) check_nonnegative(c, o.bound_diag, int64_t(nn) * 3, c.flag.p);
   const int fl = d2h_scalar(c.flag.p, c.s);
   AMGF_REQUIRE(fl == 0, AMGF_EINVAL,
-               (fl & 2) ? "D must be positive" : "non-finite value in K, J, D or coords");
+               (fl & 2) ? "D must be positive and E non-negative"
+                        : "non-finite value in K, J, D, E or coords");
 
   // ---- level 0 inputs
   h.lev.emplace_back(new Level());
@@ -227,6 +232,10 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   copy_in(c, K.rowptr.p, K_rowptr, sizeof(int) * (size_t(nn) + 1));
   copy_in(c, K.col.p, K_col, sizeof(int) * size_t(nnzb));
   copy_in(c, K.val.p, K_val, sizeof(double) * size_t(nnzb) * 9);
+  if (o.bound_diag) {           // Remark 3.1: K_0 = K + diag(E)
+    bound_diagonal(c, K, o.bound_diag, h.kdiag0);
+    h.has_E = true;
+  }
   h.D.alloc(std::max(m, 1));
   copy_in(c, h.D.p, D, sizeof(double) * size_t(m));
   h.coords.alloc(size_t(nn) * 3);
@@ -281,6 +290,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
       spgemm(c, Lc.PT, KP, N.K);
     }
     dead_identity(c, N.K, dead.p);
+    Lc.dead = std::move(dead);
     spgemm(c, Lc.J, Lc.P, N.J);
     bsr_transpose(c, N.J, N.JT);
     N.ncrows = nonempty_rows(c, N.JT.rowptr.p, N.nn, N.crows);
@@ -423,6 +433,35 @@ static void update_D(Handle& h, const double* D) {
   using ms = std::chrono::duration<double, std::milli>;
   h.ms_setup_filter = ms(t_filter_end - t_filter).count();
   h.ms_setup_amg = ms(t_filter - t_start).count() + ms(t_end - t_filter_end).count();
+}
+
+// New barrier terms of both kinds (Remark 3.1): K_0 = K + diag(E) and the coarse stiffness
+// chain are rebuilt with the kept prolongators, then the rest as for a new D.
+static void update_barrier(Handle& h, const double* D, const double* E) {
+  Ctx& c = h.ctx;
+  Level& L0 = *h.lev[0];
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  if (h.m > 0) check_values(c, D, h.m, true, c.flag.p);
+  if (E) check_nonnegative(c, E, h.n(), c.flag.p);
+  const int fl = d2h_scalar(c.flag.p, c.s);
+  AMGF_REQUIRE(fl == 0, AMGF_EINVAL,
+               (fl & 2) ? "D must be positive and E non-negative" : "non-finite value in D or E");
+  if (E || h.has_E) {
+    bound_diagonal(c, L0.K, E, h.kdiag0);
+    h.has_E = E != nullptr;
+    bsr_build_sell(c, L0.K, true, h.mixed(), h.bf16k());
+    for (size_t l = 0; l + 1 < h.lev.size(); ++l) {
+      Level& L = *h.lev[l];
+      Level& N = *h.lev[l + 1];
+      BSR KP;
+      spgemm(c, L.K, L.P, KP);
+      N.K = BSR();
+      spgemm(c, L.PT, KP, N.K);
+      dead_identity(c, N.K, L.dead.p);
+      if (h.mixed()) to_fp32(c, N.K);
+    }
+  }
+  update_D(h, D);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1219,6 +1258,8 @@ amgf_status amgf_ip_solve(amgf_handle hd, const double* f, const double* g0, con
       amgf_ip_default_options(&o);
     }
     AMGF_REQUIRE(h.m > 0, AMGF_EINVAL, "the interior-point driver needs contact constraints");
+    AMGF_REQUIRE(!h.has_E, AMGF_EINVAL,
+                 "the interior-point driver has no bound constraints (handle has E)");
     AMGF_REQUIRE(o.max_steps >= 0 && o.tol > 0 && o.mu0 > 0 && o.kappa_eps > 0 &&
                      o.kappa_mu > 0 && o.kappa_mu < 1 && o.theta_mu > 1 && o.tau_min > 0 &&
                      o.tau_min < 1 && o.s_max > 0 && o.s_init > 0 && o.switch_ratio >= 0,
@@ -1263,6 +1304,17 @@ amgf_status amgf_update_D(amgf_handle hd, const double* D, void* stream) {
     hd->h.bind(stream);
     amgf::AllocScope scope_(&hd->h.mem);
     amgf::update_D(hd->h, D);
+    return AMGF_OK;
+  });
+}
+
+amgf_status amgf_update_barrier(amgf_handle hd, const double* D, const double* E,
+                                void* stream) {
+  if (!hd || (!D && hd->h.m > 0)) return AMGF_EINVAL;
+  return guard([&]() -> amgf_status {
+    hd->h.bind(stream);
+    amgf::AllocScope scope_(&hd->h.mem);
+    amgf::update_barrier(hd->h, D, E);
     return AMGF_OK;
   });
 }

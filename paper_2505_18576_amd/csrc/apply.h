@@ -89,5 +89,7 @@ void pcg_update_p(Ctx& c, int64_t n, double beta, const double* z, double* p);
 
 // input validation: flag bit 1 non-finite, bit 2 non-positive
 void check_values(Ctx& c, const double* v, int64_t n, bool require_positive, int* flag);
+// bit 1 non-finite, bit 2 negative
+void check_nonnegative(Ctx& c, const double* v, int64_t n, int* flag);
 
 }  // namespace amgf

@@ -389,7 +389,8 @@ __global__ void k_check(const double* __restrict__ v, int64_t n, int pos, int* f
   if (i >= n) return;
   const double x = v[i];
   if (!isfinite(x)) atomicOr(flag, 1);
-  if (pos && !(x > 0.0)) atomicOr(flag, 2);
+  if (pos == 1 && !(x > 0.0)) atomicOr(flag, 2);
+  if (pos == 2 && !(x >= 0.0)) atomicOr(flag, 2);
 }
 
 // Chebyshev smoother steps (elementwise):
@@ -486,6 +487,10 @@ void pcg_update_p(Ctx& c, int64_t n, double beta, const double* z, double* p) {
 }
 void check_values(Ctx& c, const double* v, int64_t n, bool require_positive, int* flag) {
   if (n) hipLaunchKernelGGL(k_check, AMGF_L1D(n), v, n, int(require_positive), flag);
+  AMGF_LAUNCH_CHECK();
+}
+void check_nonnegative(Ctx& c, const double* v, int64_t n, int* flag) {
+  if (n) hipLaunchKernelGGL(k_check, AMGF_L1D(n), v, n, 2, flag);
   AMGF_LAUNCH_CHECK();
 }
 

@@ -34,6 +34,9 @@ void smooth_prolongator(Ctx& c, const BSR& A, const int* agg, int n_agg, const d
                         const double* d, double omega, BSR& P);
 void spgemm(Ctx& c, const BSR& A, const BSR& B, BSR& C);
 void dead_identity(Ctx& c, BSR& Kc, const unsigned char* dead);
+// Bound-constraint barrier diagonal on a 3x3 stiffness: K_aa(q,q) = K0 + E (E may be null,
+// restoring K0).  The first call records the original diagonal entries K0 in k0.
+void bound_diagonal(Ctx& c, BSR& K, const double* E, DBuf<double>& k0);
 void l1_norms(Ctx& c, const BSR& A, DBuf<double>& d);
 int filter_space_from_J(Ctx& c, const BSR& J, int n_nodes, DBuf<int>& Ic);
 

@@ -734,6 +734,34 @@ __global__ void k_dead_identity(int n_agg, const unsigned char* __restrict__ dea
     if (dead[int64_t(J) * 6 + j]) val[int64_t(dpos[J]) * 36 + j * 6 + j] = 1.0;
 }
 
+// K_aa(q, q) = K0_aq + E_aq on the diagonal blocks (one add; E == nullptr: K0 itself).
+// save: first record K0 from K.
+__global__ void k_bound_diag(int nn, const int* __restrict__ rp, const int* __restrict__ col,
+                             double* __restrict__ val, const double* __restrict__ E,
+                             double* __restrict__ k0, int save) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nn) return;
+  int pos = -1;
+  for (int e = rp[a]; e < rp[a + 1]; ++e)
+    if (col[e] == a) pos = e;
+  if (pos < 0) return;
+  for (int q = 0; q < 3; ++q) {
+    const int64_t k = int64_t(pos) * 9 + 4 * q;
+    if (save) k0[int64_t(a) * 3 + q] = val[k];
+    const double base = k0[int64_t(a) * 3 + q];
+    val[k] = E ? base + E[int64_t(a) * 3 + q] : base;
+  }
+}
+
+void bound_diagonal(Ctx& c, BSR& K, const double* E, DBuf<double>& k0) {
+  AMGF_REQUIRE(K.br == 3 && K.bc == 3, AMGF_EINVAL, "bound terms need 3x3 blocks");
+  const bool save = k0.n == 0;
+  if (save) k0.alloc(size_t(K.nrows) * 3);
+  hipLaunchKernelGGL(k_bound_diag, dim3(grid_for(K.nrows, 256)), dim3(256), 0, c.s, K.nrows,
+                     K.rowptr.p, K.col.p, K.val.p, E, k0.p, int(save));
+  AMGF_LAUNCH_CHECK();
+}
+
 void dead_identity(Ctx& c, BSR& Kc, const unsigned char* dead) {
   DBuf<int> dpos(std::max(Kc.nrows, 1));
   hipLaunchKernelGGL(k_diag_pos, dim3(grid_for(Kc.nrows, 256)), dim3(256), 0, c.s, Kc.nrows,

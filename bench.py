@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--ip-N", type=int, default=32)
     ap.add_argument("--ip-tol", type=float, default=1e-6)
     ap.add_argument("--ip-switch", type=float, default=1e6)
+    ap.add_argument("--bounds", action="store_true",
+                    help="add bound-constraint barrier terms E (Remark 3.1) to the operator")
     return ap.parse_args()
 
 
@@ -232,6 +234,10 @@ def main():
              D=torch.from_numpy(p.D).to(dev, f64),
              coords=torch.from_numpy(p.coords.reshape(-1)).to(dev, f64))
     bvec = torch.from_numpy(p.b).to(dev, f64)
+    E = None
+    if args.bounds:
+        from amgf_inputs import bound_barrier
+        E = torch.from_numpy(bound_barrier(p, seed=9)).to(dev, f64)
     torch.cuda.synchronize()
 
     from paper_2505_18576_amd.train_smoother import load_weights
@@ -240,7 +246,8 @@ def main():
 
     def solve(precision, weights, live=False):
         h = AMGF(p.n_nodes, d["K_rowptr"], d["K_col"], d["K_val"], d["J_rowptr"], d["J_col"],
-                 d["J_val"], d["D"], d["coords"], precision=precision, mlp_weights=weights)
+                 d["J_val"], d["D"], d["coords"], precision=precision, mlp_weights=weights,
+                 E=E)
         if live:   # event pairs around every level-0 pre-smooth launch of this solve
             h.profile_start(b.K_PRESMOOTH, 1000)
         x, info = h.pcg(bvec)
@@ -331,7 +338,8 @@ def main():
         "dtype": "f32 V-cycle (learned damping) / f64 CG",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: two-body contact, n={p.n} DOFs, m={p.m}, "
-                               f"D log-uniform, rtol 1e-10",
+                               f"D log-uniform, rtol 1e-10"
+                               + (", bound-constraint barrier terms" if args.bounds else ""),
                    "n": p.n, "m": p.m, "nnzb": p.nnzb,
                    "mixed_learned": dict(m),
                    "mixed_plain": dict(res["mixed"]),

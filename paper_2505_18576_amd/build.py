@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libamgf.so")
-SOURCES = ["primitives.hip", "setup.hip", "csr.hip", "multifrontal.hip", "apply.hip", "sell.hip", "learn.hip", "ip.hip", "api.hip"]
+SOURCES = ["primitives.hip", "setup.hip", "csr.hip", "multifrontal.hip", "apply.hip", "sell.hip", "learn.hip", "ip.hip", "coarse.hip", "api.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
          "-Wno-unused-function", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

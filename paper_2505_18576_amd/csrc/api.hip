@@ -10,6 +10,7 @@
 #include "learn.h"
 #include "setup.h"
 #include "ip.h"
+#include "coarse.h"
 
 namespace amgf {
 
@@ -55,8 +56,11 @@ struct Handle {
   bool has_E = false;           // K_0 = K + diag(E) with bound-constraint barrier terms
   DBuf<unsigned char> dec0;
   DBuf<double> t;               // contact scratch (m)
-  // coarsest solve (multifrontal Cholesky of the coarsest operator)
+  // coarsest solve: explicit inverse when small (one matrix-vector product per solve),
+  // multifrontal Cholesky otherwise
   int nc_dense = 0;
+  bool coarse_inverse = false;
+  DenseInverse coarse_inv;
   MFSolver coarse;
   DBuf<double> coarse_b, coarse_x;
   // filter
@@ -157,8 +161,15 @@ static void to_fp32(Ctx& c, BSR& A) {
 // setup pieces shared with the numeric re-setup of a new barrier diagonal
 // ------------------------------------------------------------------------------------
 // direct factor of the coarsest operator
+constexpr int64_t COARSE_INVERSE_MAX = 2048;   // unknowns; 32 MiB of FP64 at most
+
 static void factor_coarsest(Handle& h) {
   Level& LL = *h.lev.back();
+  h.coarse_inverse = LL.n() <= COARSE_INVERSE_MAX;
+  if (h.coarse_inverse) {
+    h.coarse_inv.setup(h.ctx, LL.A);
+    return;
+  }
   DBuf<int> rp, cl;
   DBuf<double> vl;
   bsr_to_csr(h.ctx, LL.A, rp, cl, vl);
@@ -468,7 +479,8 @@ static void update_barrier(Handle& h, const double* D, const double* E) {
 // V-cycle
 // ------------------------------------------------------------------------------------
 static void coarse_solve(Handle& h, const double* b, double* x) {
-  h.coarse.solve(h.ctx, b, x);
+  if (h.coarse_inverse) h.coarse_inv.solve(h.ctx, b, x);
+  else h.coarse.solve(h.ctx, b, x);
 }
 
 // Contact term of a level inside the V-cycle: through J and D on level 0 (the fine

@@ -438,19 +438,20 @@ def group_members(agg, n_agg):
     return order[start:], off
 
 
-def tentative_prolongator(agg, n_agg, near_fn, br, tol):
+def tentative_prolongator(agg, n_agg, near_fn, br, tol, nc=6):
     """P_t (one block per aggregated row, column = its aggregate) and the coarse
-    near-null blocks R_J (n_agg, 6, 6) plus the dead-column flags (n_agg, 6)."""
+    near-null blocks R_J (n_agg, nc, nc) plus the dead-column flags (n_agg, nc), for nc
+    near-null vectors (6 rigid-body modes, or 3 translations)."""
     n = len(agg)
     members, off = group_members(agg, n_agg)
-    Pval = np.zeros((n, br, 6))
-    Rall = np.zeros((n_agg, 6, 6))
-    dead = np.zeros((n_agg, 6), bool)
+    Pval = np.zeros((n, br, nc))
+    Rall = np.zeros((n_agg, nc, nc))
+    dead = np.zeros((n_agg, nc), bool)
     for J in range(n_agg):
         nodes = members[off[J]:off[J + 1]]
-        Bj = near_fn(J, nodes)                            # (k, br, 6)
-        Q, R, dd = gram_schmidt_qr(Bj.reshape(-1, 6), tol)
-        Pval[nodes] = Q.reshape(len(nodes), br, 6)
+        Bj = near_fn(J, nodes)                            # (k, br, nc)
+        Q, R, dd = gram_schmidt_qr(Bj.reshape(-1, nc), tol)
+        Pval[nodes] = Q.reshape(len(nodes), br, nc)
         Rall[J] = R
         dead[J] = dd
     keep = agg >= 0
@@ -502,6 +503,7 @@ class OracleOptions:
     Ic: np.ndarray | None = None          # optional DOF list of the filter space
     theta: list | None = None             # per-level smoother damping (default 1)
     dense_filter_max: int = 8000
+    near_null: int = 6                    # 6 rigid-body modes or 3 translations
     smoother: str = "jacobi"              # "jacobi" (l1-Jacobi) or "chebyshev"
     sweeps: int = 1                       # smoother applications before and after
     cheb_degree: int = 2                  # Chebyshev polynomial degree
@@ -575,7 +577,8 @@ class OracleAMGF:
             else:
                 Rp = R_prev
                 near_fn = (lambda J_, nodes, Rp=Rp: Rp[nodes])
-            Pt, R, dead = tentative_prolongator(agg, n_agg, near_fn, br, o.qr_tol)
+            Pt, R, dead = tentative_prolongator(agg, n_agg, near_fn, br, o.qr_tol,
+                                                o.near_null)
             lev.Pt, lev.R, lev.dead = Pt, R, dead
             # O7: prolongator smoothing  P = P_t - omega D_l1^{-1} A P_t
             dec = lev.decoupled if l == 0 else np.zeros(A.nrows * br, bool)
@@ -668,6 +671,14 @@ class OracleAMGF:
     def _level0_near(self, decoupled):
         X = self.coords
         dec = decoupled.reshape(-1, 3)
+        if self.opts.near_null == 3:
+            # the three translations: unit displacement in x, y, z at every node
+            def translations(J, nodes):
+                B = np.zeros((len(nodes), 3, 3))
+                B[:, [0, 1, 2], [0, 1, 2]] = 1.0
+                B[dec[nodes]] = 0.0
+                return B
+            return translations
 
         def near(J, nodes):
             c = np.zeros(3)

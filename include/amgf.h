@@ -97,6 +97,10 @@ typedef struct {
                                  constraints on u (Remark 3.1: J~ = [J; I; -I] adds
                                  diag(D_lower + D_upper) = diag(E)), so that
                                  A = K + diag(E) + J^T D J.  Read by amgf_setup only.   */
+  int32_t near_null;          /* 6: rigid-body modes (3 translations, 3 rotations about
+                                 each aggregate's centroid; needs coords), 3: the three
+                                 translations only (coords may be NULL); coarse levels
+                                 then carry 3 DOFs per node (default 6)                  */
 } amgf_options;
 
 typedef struct {
@@ -124,7 +128,8 @@ void amgf_default_options(amgf_options* o);
  *    (rows without off-diagonal nonzeros, e.g. Dirichlet) are detected.
  * J: m x n scalar CSR, J_rowptr[m+1], J_col (ascending per row), J_val.
  * D: m barrier values, all > 0 (Sec. 3: D = diag(M_s z / s)).  m may be 0.
- * coords: 3 * n_nodes node coordinates (rigid-body near-null space); required.
+ * coords: 3 * n_nodes node coordinates for the rigid-body near-null space; required
+ *    with near_null = 6, may be NULL with near_null = 3.
  * Ic / n_c: optional filtering-space DOF list (ascending, device); NULL/0 selects
  *    every DOF of every node that J touches (Sec. 5.1, supp(phi_i) meets the
  *    contact surface).  The error estimate holds for any full-rank P (Remark 5.5).
@@ -193,7 +198,7 @@ const char* amgf_last_error(void);
  *  AMGF_Q_AGG      int32[n_nodes] aggregate of each node (-1 = isolated)
  *  AMGF_Q_ROOT     int32[n_nodes] 1 for MIS-2 roots
  *  AMGF_Q_G_ROWPTR/G_COL        aggregation graph
- *  AMGF_Q_P_ROWPTR/P_COL/P_VAL  prolongator P_l (b x 6 blocks)
+ *  AMGF_Q_P_ROWPTR/P_COL/P_VAL  prolongator P_l (b x near_null blocks)
  *  AMGF_Q_L1       double[n_nodes*b] l1 row norms d
  *  AMGF_Q_K_VAL    double stiffness values of level l (pattern = K rowptr/col below)
  *  AMGF_Q_K_ROWPTR/K_COL

@@ -79,7 +79,8 @@ class Options(ctypes.Structure):
                 ("max_coarse_ratio", ctypes.c_double),
                 ("mlp_weights", ctypes.POINTER(ctypes.c_float)),
                 ("sweeps", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
-                ("allocator", Allocator), ("bound_diag", ctypes.c_void_p)]
+                ("allocator", Allocator), ("bound_diag", ctypes.c_void_p),
+                ("near_null", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -406,7 +407,9 @@ class AMGF:
                      G_col=q(level, Q_G_COL, np.int32, nnzG),
                      P_rowptr=q(level, Q_P_ROWPTR, np.int32, nn + 1),
                      P_col=q(level, Q_P_COL, np.int32, nnzP),
-                     P_val=q(level, Q_P_VAL, np.float64, nnzP * b * 6).reshape(-1, b, 6),
+                     P_val=q(level, Q_P_VAL, np.float64,
+                             nnzP * b * self.options.near_null).reshape(
+                                 -1, b, self.options.near_null),
                      rho_omega=q(level, Q_OMEGA))
         return d
 

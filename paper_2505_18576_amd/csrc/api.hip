@@ -221,7 +221,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     check_values(c, J_val, nnzJ, false, c.flag.p);
     check_values(c, D, m, true, c.flag.p);
   }
-  check_values(c, coords, int64_t(nn) * 3, false, c.flag.p);
+  if (coords) check_values(c, coords, int64_t(nn) * 3, false, c.flag.p);
   if (o.bound_diag) check_nonnegative(c, o.bound_diag, int64_t(nn) * 3, c.flag.p);
   const int fl = d2h_scalar(c.flag.p, c.s);
   AMGF_REQUIRE(fl == 0, AMGF_EINVAL,
@@ -249,8 +249,10 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   }
   h.D.alloc(std::max(m, 1));
   copy_in(c, h.D.p, D, sizeof(double) * size_t(m));
-  h.coords.alloc(size_t(nn) * 3);
-  copy_in(c, h.coords.p, coords, sizeof(double) * size_t(nn) * 3);
+  if (coords) {                 // rigid-body modes (near_null = 6) need the node positions
+    h.coords.alloc(size_t(nn) * 3);
+    copy_in(c, h.coords.p, coords, sizeof(double) * size_t(nn) * 3);
+  }
   h.t.alloc(std::max(m, 1));
   bsr_build_sell(c, K, true, h.mixed(), h.bf16k());     // apply copies of K (level 0)
   j_to_node_blocks(c, m, nn, J_rowptr, J_col, J_val, L0->J);
@@ -283,18 +285,19 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     }
     DBuf<double> Pt, R;
     DBuf<unsigned char> dead;
-    tentative_prolongator(c, L.b, L.nn, n_agg, moff.p, members.p, l == 0 ? h.coords.p : nullptr,
+    tentative_prolongator(c, L.b, h.opt.near_null, L.nn, n_agg, moff.p, members.p, l == 0,
+                          l == 0 ? h.coords.p : nullptr,
                           dec, Rprev.p, o.qr_tol, Pt, R, dead);
     L.lam = power_estimate(h, L, dec);
     L.rho = std::min(1.0, L.lam);
     L.omega = o.sa_omega / L.rho;
-    smooth_prolongator(c, L.A, L.agg.p, n_agg, Pt.p, L.d.p, L.omega, L.P);
+    smooth_prolongator(c, L.A, L.agg.p, n_agg, h.opt.near_null, Pt.p, L.d.p, L.omega, L.P);
     bsr_transpose(c, L.P, L.PT);
     h.lev.emplace_back(new Level());
     Level& N = *h.lev.back();
     Level& Lc = *h.lev[l];  // re-fetch (vector may have reallocated)
     N.nn = n_agg;
-    N.b = 6;
+    N.b = h.opt.near_null;
     {
       BSR KP;
       spgemm(c, Lc.K, Lc.P, KP);
@@ -313,7 +316,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
       bsr_add(c, N.K, N.C, N.A);
       N.nccrows = nonempty_rows(c, N.C.rowptr.p, N.nn, N.ccrows);
     }
-    nzsum += N.A.nnzb * 36;
+    nzsum += N.A.nnzb * int64_t(N.A.bsz());
     coarse_graph(c, Lc.G, Lc.agg.p, n_agg, moff.p, members.p, Gnext);
     Rprev = std::move(R);
   }
@@ -1169,6 +1172,7 @@ void amgf_default_options(amgf_options* o) {
   o->qr_tol = 1e-10;
   o->max_coarse_ratio = 0.9;
   o->mlp_weights = nullptr;
+  o->near_null = 6;
 }
 
 const char* amgf_status_string(amgf_status s) {
@@ -1203,8 +1207,11 @@ amgf_status amgf_setup(const amgf_options* opts, int32_t n_nodes, const int32_t*
     } else {
       amgf_default_options(&h.opt);
     }
-    AMGF_REQUIRE(n_nodes > 0 && m >= 0 && K_rowptr && K_col && K_val && coords, AMGF_EINVAL,
-                 "bad sizes or null K / coords");
+    AMGF_REQUIRE(h.opt.near_null == 3 || h.opt.near_null == 6, AMGF_EINVAL,
+                 "near_null must be 6 (rigid-body modes) or 3 (translations)");
+    AMGF_REQUIRE(n_nodes > 0 && m >= 0 && K_rowptr && K_col && K_val &&
+                     (coords || h.opt.near_null == 3),
+                 AMGF_EINVAL, "bad sizes, null K, or null coords with near_null = 6");
     AMGF_REQUIRE(m == 0 || (J_rowptr && J_col && J_val && D), AMGF_EINVAL, "null J or D");
     AMGF_REQUIRE(int64_t(n_nodes) * 6 < (int64_t(1) << 31), AMGF_EINVAL, "too many nodes");
     AMGF_REQUIRE(h.opt.precision == AMGF_FP64 || h.opt.precision == AMGF_MIXED_FP32 ||

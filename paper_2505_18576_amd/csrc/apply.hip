@@ -287,17 +287,25 @@ template <class TX, class TY>
 void contact_cmat(Ctx& c, int mode, const BSR& C, const int* rows, int nrows, const TX* x,
                   TY* y, const TY* w) {
   if (nrows == 0 || C.nnzb == 0) return;
-  AMGF_REQUIRE(C.br == 6 && C.bc == 6, AMGF_EINVAL, "coarse contact block size");
+  AMGF_REQUIRE(C.br == C.bc && (C.br == 6 || C.br == 3), AMGF_EINVAL,
+               "coarse contact block size");
   const dim3 g(grid_for(nrows, 4)), blk(256);
-  if (mode == CT_SUB_RES)
-    hipLaunchKernelGGL((k_contact_c<6, TX, TY, CT_SUB_RES>), g, blk, 0, c.s, nrows, rows,
+#define AMGF_CC(B)                                                                           \
+  if (mode == CT_SUB_RES)                                                                    \
+    hipLaunchKernelGGL((k_contact_c<B, TX, TY, CT_SUB_RES>), g, blk, 0, c.s, nrows, rows,    \
+                       C.rowptr.p, C.col.p, C.val.p, x, y, w);                               \
+  else if (mode == CT_SUB_W)                                                                 \
+    hipLaunchKernelGGL((k_contact_c<B, TX, TY, CT_SUB_W>), g, blk, 0, c.s, nrows, rows,      \
+                       C.rowptr.p, C.col.p, C.val.p, x, y, w);                               \
+  else                                                                                       \
+    hipLaunchKernelGGL((k_contact_c<B, TX, TY, CT_ADD>), g, blk, 0, c.s, nrows, rows,        \
                        C.rowptr.p, C.col.p, C.val.p, x, y, w);
-  else if (mode == CT_SUB_W)
-    hipLaunchKernelGGL((k_contact_c<6, TX, TY, CT_SUB_W>), g, blk, 0, c.s, nrows, rows,
-                       C.rowptr.p, C.col.p, C.val.p, x, y, w);
-  else
-    hipLaunchKernelGGL((k_contact_c<6, TX, TY, CT_ADD>), g, blk, 0, c.s, nrows, rows,
-                       C.rowptr.p, C.col.p, C.val.p, x, y, w);
+  if (C.br == 6) {
+    AMGF_CC(6)
+  } else {
+    AMGF_CC(3)
+  }
+#undef AMGF_CC
   AMGF_LAUNCH_CHECK();
 }
 template void contact_cmat<double, double>(Ctx&, int, const BSR&, const int*, int, const double*,

@@ -26,12 +26,14 @@ int mis2_aggregate(Ctx& c, const Graph& G, int level, DBuf<int>& agg, DBuf<int>&
                    int* rounds_out);
 void coarse_graph(Ctx& c, const Graph& G, const int* agg, int n_agg, const int* moff,
                   const int* members, Graph& Gc);
-void tentative_prolongator(Ctx& c, int br, int n_nodes, int n_agg, const int* moff,
-                           const int* members, const double* coords,
+// P_t and R of every aggregate for nc near-null vectors (level 0: 6 rigid-body modes from
+// coords, or 3 translations; coarser levels: the rows of the previous R, br == nc)
+void tentative_prolongator(Ctx& c, int br, int nc, int n_nodes, int n_agg, const int* moff,
+                           const int* members, bool level0, const double* coords,
                            const unsigned char* dec, const double* Rprev, double qr_tol,
                            DBuf<double>& Pt, DBuf<double>& R, DBuf<unsigned char>& dead);
-void smooth_prolongator(Ctx& c, const BSR& A, const int* agg, int n_agg, const double* Pt,
-                        const double* d, double omega, BSR& P);
+void smooth_prolongator(Ctx& c, const BSR& A, const int* agg, int n_agg, int nc,
+                        const double* Pt, const double* d, double omega, BSR& P);
 void spgemm(Ctx& c, const BSR& A, const BSR& B, BSR& C);
 void dead_identity(Ctx& c, BSR& Kc, const unsigned char* dead);
 // Bound-constraint barrier diagonal on a 3x3 stiffness: K_aa(q,q) = K0 + E (E may be null,

@@ -431,11 +431,14 @@ __global__ void k_fill_ones(double* w, int64_t n) {
 // tentative prolongator: per-aggregate Gram-Schmidt QR of the near-null space
 // ======================================================================================
 // One 64-lane workgroup per aggregate; lane l owns rows l, l+64, ... of the aggregate's
-// (BR * k) x 6 near-null matrix, which is built in place in the P_t storage and
-// orthonormalised there (two projection passes per column, dead columns zeroed).
-template <int BR>
+// (BR * k) x NC near-null matrix, which is built in place in the P_t storage and
+// orthonormalised there (two projection passes per column, dead columns zeroed).  Level 0
+// builds the near-null vectors (NC = 6: rigid-body modes about the aggregate centroid;
+// NC = 3: translations), coarser levels take the rows of the previous QR's R.
+template <int BR, int NC>
 __global__ void __launch_bounds__(64) k_tentative(int n_agg, const int* __restrict__ off,
                                                   const int* __restrict__ members,
+                                                  int level0,
                                                   const double* __restrict__ coords,
                                                   const unsigned char* __restrict__ dec,
                                                   const double* __restrict__ Rprev,
@@ -448,7 +451,7 @@ __global__ void __launch_bounds__(64) k_tentative(int n_agg, const int* __restri
   const int a0 = off[J], k = off[J + 1] - a0;
   const int rows = BR * k;
   __shared__ double cen[3];
-  if (coords) {
+  if (level0 && NC == 6) {
     if (lane == 0) {
       double cx = 0.0, cy = 0.0, cz = 0.0;
       for (int i = 0; i < k; ++i) {
@@ -466,53 +469,57 @@ __global__ void __launch_bounds__(64) k_tentative(int n_agg, const int* __restri
   // build
   for (int idx = lane; idx < rows; idx += 64) {
     const int v = members[a0 + idx / BR], p = idx % BR;
-    double* row = Pt + (int64_t(v) * BR + p) * 6;
-    if (coords) {
-      const double x = coords[3 * int64_t(v)] - cen[0];
-      const double y = coords[3 * int64_t(v) + 1] - cen[1];
-      const double z = coords[3 * int64_t(v) + 2] - cen[2];
-      double b[6] = {0, 0, 0, 0, 0, 0};
+    double* row = Pt + (int64_t(v) * BR + p) * NC;
+    if (level0) {
+      double b[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) b[j] = 0.0;
       b[p] = 1.0;
-      if (p == 0) { b[4] = z; b[5] = -y; }
-      if (p == 1) { b[3] = -z; b[5] = x; }
-      if (p == 2) { b[3] = y; b[4] = -x; }
+      if constexpr (NC == 6) {
+        const double x = coords[3 * int64_t(v)] - cen[0];
+        const double y = coords[3 * int64_t(v) + 1] - cen[1];
+        const double z = coords[3 * int64_t(v) + 2] - cen[2];
+        if (p == 0) { b[4] = z; b[5] = -y; }
+        if (p == 1) { b[3] = -z; b[5] = x; }
+        if (p == 2) { b[3] = y; b[4] = -x; }
+      }
       const bool off_row = dec && dec[int64_t(v) * BR + p];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) row[j] = off_row ? 0.0 : b[j];
+      for (int j = 0; j < NC; ++j) row[j] = off_row ? 0.0 : b[j];
     } else {
-      const double* src = Rprev + (int64_t(v) * 6 + p) * 6;
+      const double* src = Rprev + (int64_t(v) * NC + p) * NC;
 #pragma unroll
-      for (int j = 0; j < 6; ++j) row[j] = src[j];
+      for (int j = 0; j < NC; ++j) row[j] = src[j];
     }
   }
-  double R[6][6];
+  double R[NC][NC];
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < NC; ++i)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) R[i][j] = 0.0;
-  bool isdead[6];
-  for (int j = 0; j < 6; ++j) {
+    for (int j = 0; j < NC; ++j) R[i][j] = 0.0;
+  bool isdead[NC];
+  for (int j = 0; j < NC; ++j) {
     double s = 0.0;
     for (int idx = lane; idx < rows; idx += 64) {
       const int v = members[a0 + idx / BR], p = idx % BR;
-      const double x = Pt[(int64_t(v) * BR + p) * 6 + j];
+      const double x = Pt[(int64_t(v) * BR + p) * NC + j];
       s += x * x;
     }
     const double nb = sqrt(wave_sum(s));
     for (int pass = 0; pass < 2; ++pass) {
-      double cc[6];
+      double cc[NC];
       for (int i = 0; i < j; ++i) {
         double d = 0.0;
         for (int idx = lane; idx < rows; idx += 64) {
           const int v = members[a0 + idx / BR], p = idx % BR;
-          const double* row = Pt + (int64_t(v) * BR + p) * 6;
+          const double* row = Pt + (int64_t(v) * BR + p) * NC;
           d += row[i] * row[j];
         }
         cc[i] = wave_sum(d);
       }
       for (int idx = lane; idx < rows; idx += 64) {
         const int v = members[a0 + idx / BR], p = idx % BR;
-        double* row = Pt + (int64_t(v) * BR + p) * 6;
+        double* row = Pt + (int64_t(v) * BR + p) * NC;
         double x = row[j];
         for (int i = 0; i < j; ++i) x -= cc[i] * row[i];
         row[j] = x;
@@ -522,7 +529,7 @@ __global__ void __launch_bounds__(64) k_tentative(int n_agg, const int* __restri
     double s2 = 0.0;
     for (int idx = lane; idx < rows; idx += 64) {
       const int v = members[a0 + idx / BR], p = idx % BR;
-      const double x = Pt[(int64_t(v) * BR + p) * 6 + j];
+      const double x = Pt[(int64_t(v) * BR + p) * NC + j];
       s2 += x * x;
     }
     const double nv = sqrt(wave_sum(s2));
@@ -531,32 +538,41 @@ __global__ void __launch_bounds__(64) k_tentative(int n_agg, const int* __restri
     R[j][j] = isdead[j] ? 0.0 : nv;
     for (int idx = lane; idx < rows; idx += 64) {
       const int v = members[a0 + idx / BR], p = idx % BR;
-      double* row = Pt + (int64_t(v) * BR + p) * 6;
+      double* row = Pt + (int64_t(v) * BR + p) * NC;
       row[j] = isdead[j] ? 0.0 : row[j] * scale;
     }
   }
   if (lane == 0) {
-    for (int i = 0; i < 6; ++i) {
-      dead[int64_t(J) * 6 + i] = isdead[i];
-      for (int j = 0; j < 6; ++j) Rout[int64_t(J) * 36 + i * 6 + j] = isdead[i] ? 0.0 : R[i][j];
+    for (int i = 0; i < NC; ++i) {
+      dead[int64_t(J) * NC + i] = isdead[i];
+      for (int j = 0; j < NC; ++j)
+        Rout[int64_t(J) * NC * NC + i * NC + j] = isdead[i] ? 0.0 : R[i][j];
     }
   }
 }
 
-void tentative_prolongator(Ctx& c, int br, int n_nodes, int n_agg, const int* moff,
-                           const int* members, const double* coords,
+void tentative_prolongator(Ctx& c, int br, int nc, int n_nodes, int n_agg, const int* moff,
+                           const int* members, bool level0, const double* coords,
                            const unsigned char* dec, const double* Rprev, double qr_tol,
                            DBuf<double>& Pt, DBuf<double>& R, DBuf<unsigned char>& dead) {
-  Pt.alloc(size_t(n_nodes) * br * 6);
+  AMGF_REQUIRE(nc == 3 || nc == 6, AMGF_EINVAL, "near-null space must have 3 or 6 vectors");
+  AMGF_REQUIRE(level0 ? br == 3 : br == nc, AMGF_EINVAL, "tentative prolongator block size");
+  AMGF_REQUIRE(!level0 || nc == 3 || coords, AMGF_EINVAL, "rigid-body modes need coords");
+  Pt.alloc(size_t(n_nodes) * br * nc);
   AMGF_HIP(hipMemsetAsync(Pt.p, 0, Pt.bytes(), c.s));
-  R.alloc(size_t(n_agg) * 36);
-  dead.alloc(size_t(n_agg) * 6);
-  if (br == 3)
-    hipLaunchKernelGGL(k_tentative<3>, dim3(n_agg), dim3(64), 0, c.s, n_agg, moff, members,
-                       coords, dec, Rprev, qr_tol, Pt.p, R.p, dead.p);
-  else
-    hipLaunchKernelGGL(k_tentative<6>, dim3(n_agg), dim3(64), 0, c.s, n_agg, moff, members,
-                       coords, dec, Rprev, qr_tol, Pt.p, R.p, dead.p);
+  R.alloc(size_t(n_agg) * nc * nc);
+  dead.alloc(size_t(n_agg) * nc);
+  const int l0 = level0 ? 1 : 0;
+#define AMGF_TENT(BR, NC)                                                                    \
+  hipLaunchKernelGGL((k_tentative<BR, NC>), dim3(n_agg), dim3(64), 0, c.s, n_agg, moff,      \
+                     members, l0, coords, dec, Rprev, qr_tol, Pt.p, R.p, dead.p)
+  if (nc == 6) {
+    if (br == 3) AMGF_TENT(3, 6);
+    else AMGF_TENT(6, 6);
+  } else {
+    AMGF_TENT(3, 3);
+  }
+#undef AMGF_TENT
   AMGF_LAUNCH_CHECK();
 }
 
@@ -566,7 +582,7 @@ void tentative_prolongator(Ctx& c, int br, int n_nodes, int n_agg, const int* mo
 // G lanes per aggregated row i, one lane per block (i, J) of P: the lane sums A_iv P_t,v
 // over the blocks of A's row whose column v lies in aggregate J, in ascending order, then
 // scales by -omega/d and adds P_t,i on the block of i's own aggregate.
-template <int B, int G>
+template <int B, int NC, int G>
 __global__ void __launch_bounds__(256) k_sa_numeric(int n, const int* __restrict__ arp,
                                                     const int* __restrict__ acol,
                                                     const double* __restrict__ aval,
@@ -583,53 +599,58 @@ __global__ void __launch_bounds__(256) k_sa_numeric(int n, const int* __restrict
   if (ai < 0) return;
   for (int s = prp[i] + l; s < prp[i + 1]; s += G) {
     const int J = pcol[s];
-    double acc[B * 6];
+    double acc[B * NC];
 #pragma unroll
-    for (int e = 0; e < B * 6; ++e) acc[e] = 0.0;
+    for (int e = 0; e < B * NC; ++e) acc[e] = 0.0;
     for (int t = arp[i]; t < arp[i + 1]; ++t) {
       const int v = acol[t];
       if (agg[v] != J) continue;
       const double* A = aval + int64_t(t) * B * B;
-      const double* Q = Pt + int64_t(v) * B * 6;
+      const double* Q = Pt + int64_t(v) * B * NC;
 #pragma unroll
       for (int p = 0; p < B; ++p)
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
+        for (int q = 0; q < NC; ++q) {
           double a = 0.0;
 #pragma unroll
-          for (int r = 0; r < B; ++r) a += A[p * B + r] * Q[r * 6 + q];
-          acc[p * 6 + q] += a;
+          for (int r = 0; r < B; ++r) a += A[p * B + r] * Q[r * NC + q];
+          acc[p * NC + q] += a;
         }
     }
-    double* out = pval + int64_t(s) * B * 6;
+    double* out = pval + int64_t(s) * B * NC;
 #pragma unroll
     for (int p = 0; p < B; ++p) {
       const double sc = omega / d[int64_t(i) * B + p];
 #pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const double v = -(acc[p * 6 + q] * sc);
-        out[p * 6 + q] = J == ai ? Pt[int64_t(i) * B * 6 + p * 6 + q] + v : v;
+      for (int q = 0; q < NC; ++q) {
+        const double v = -(acc[p * NC + q] * sc);
+        out[p * NC + q] = J == ai ? Pt[int64_t(i) * B * NC + p * NC + q] + v : v;
       }
     }
   }
 }
 
-void smooth_prolongator(Ctx& c, const BSR& A, const int* agg, int n_agg, const double* Pt,
-                        const double* d, double omega, BSR& P) {
+void smooth_prolongator(Ctx& c, const BSR& A, const int* agg, int n_agg, int nc,
+                        const double* Pt, const double* d, double omega, BSR& P) {
   const int n = A.nrows;
   DBuf<int> mask(std::max(n, 1));
   hipLaunchKernelGGL(k_nonneg_mask, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, agg, mask.p);
   union_symbolic(c, n, n_agg, A.rowptr.p, A.col.p, nullptr, nullptr, agg, false, mask.p, P);
   P.br = A.br;
-  P.bc = 6;
+  P.bc = nc;
   P.val.alloc(std::max<int64_t>(P.nnzb, 1) * P.bsz());
   constexpr int G = 8;
   const dim3 g(grid_for(int64_t(n) * G, 256));
-  if (A.br == 3)
-    hipLaunchKernelGGL((k_sa_numeric<3, G>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
+  AMGF_REQUIRE((A.br == 3 && (nc == 3 || nc == 6)) || (A.br == 6 && nc == 6), AMGF_EINVAL,
+               "prolongator block size");
+  if (A.br == 3 && nc == 6)
+    hipLaunchKernelGGL((k_sa_numeric<3, 6, G>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
+                       A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p, P.val.p);
+  else if (A.br == 3)
+    hipLaunchKernelGGL((k_sa_numeric<3, 3, G>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
                        A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p, P.val.p);
   else
-    hipLaunchKernelGGL((k_sa_numeric<6, G>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
+    hipLaunchKernelGGL((k_sa_numeric<6, 6, G>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
                        A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p, P.val.p);
   AMGF_LAUNCH_CHECK();
 }
@@ -721,17 +742,19 @@ void spgemm(Ctx& c, const BSR& A, const BSR& B, BSR& C) {
   AMGF_SPGEMM_CASE(6, 3, 6)
   AMGF_SPGEMM_CASE(1, 3, 6)
   AMGF_SPGEMM_CASE(1, 6, 6)
+  AMGF_SPGEMM_CASE(3, 3, 3)
+  AMGF_SPGEMM_CASE(1, 3, 3)
 #undef AMGF_SPGEMM_CASE
   throw Error(AMGF_EINVAL, "spgemm: unsupported block sizes");
 }
 
 // coarse DOFs whose prolongator column is dead get a unit diagonal
-__global__ void k_dead_identity(int n_agg, const unsigned char* __restrict__ dead,
+__global__ void k_dead_identity(int n_agg, int nc, const unsigned char* __restrict__ dead,
                                 const int* __restrict__ dpos, double* __restrict__ val) {
   const int J = blockIdx.x * blockDim.x + threadIdx.x;
   if (J >= n_agg || dpos[J] < 0) return;
-  for (int j = 0; j < 6; ++j)
-    if (dead[int64_t(J) * 6 + j]) val[int64_t(dpos[J]) * 36 + j * 6 + j] = 1.0;
+  for (int j = 0; j < nc; ++j)
+    if (dead[int64_t(J) * nc + j]) val[int64_t(dpos[J]) * nc * nc + j * nc + j] = 1.0;
 }
 
 // K_aa(q, q) = K0_aq + E_aq on the diagonal blocks (one add; E == nullptr: K0 itself).
@@ -766,8 +789,9 @@ void dead_identity(Ctx& c, BSR& Kc, const unsigned char* dead) {
   DBuf<int> dpos(std::max(Kc.nrows, 1));
   hipLaunchKernelGGL(k_diag_pos, dim3(grid_for(Kc.nrows, 256)), dim3(256), 0, c.s, Kc.nrows,
                      Kc.rowptr.p, Kc.col.p, dpos.p);
+  AMGF_REQUIRE(Kc.br == Kc.bc, AMGF_EINVAL, "dead identity needs square blocks");
   hipLaunchKernelGGL(k_dead_identity, dim3(grid_for(Kc.nrows, 256)), dim3(256), 0, c.s,
-                     Kc.nrows, dead, dpos.p, Kc.val.p);
+                     Kc.nrows, Kc.br, dead, dpos.p, Kc.val.p);
   AMGF_LAUNCH_CHECK();
 }
 

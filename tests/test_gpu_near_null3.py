@@ -1,0 +1,58 @@
+"""Translations-only near-null space (near_null = 3, 3x3 coarse blocks) against the oracle:
+aggregation bit-exact, prolongators and coarse operators to FP64 rounding, V-cycle, AMGF
+apply and PCG."""
+import numpy as np
+import pytest
+
+from gpu_util import gpu, oracle, problem, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name,opts", [("C1", {}), ("N12", {"coarse_max_nodes": 16}),
+                                       ("B1", {})])
+def test_hierarchy_and_solve_match_oracle(name, opts):
+    o = oracle(name, near_null=3, **opts)
+    h = gpu(name, near_null=3, **opts)
+    assert h.n_levels == o.nlev >= 2
+    for l in range(o.nlev - 1):
+        L, ol = h.level_arrays(l), o.levels[l]
+        assert np.array_equal(L["agg"], ol.agg), l
+        assert np.array_equal(L["P_rowptr"], ol.P.rowptr) and np.array_equal(L["P_col"], ol.P.col)
+        assert rel(L["P_val"], ol.P.val) < 1e-12, l
+        nx, on = h.level_arrays(l + 1), o.levels[l + 1]
+        assert nx["b"] == 3
+        assert rel(nx["A_val"], on.A.val) < 1e-12, l
+    p = problem(name)
+    r = np.random.default_rng(1).standard_normal(o.n)
+    e_b = rel(h.vcycle(r).cpu().numpy(), o.vcycle(r))
+    e_m = rel(h.apply(r).cpu().numpy(), o.apply(r))
+    ref = o.pcg(p.b)
+    x, info = h.pcg(p.b)
+    e_x = rel(x.cpu().numpy(), ref.x)
+    print(f"{name}: vcycle {e_b:.2e}, apply {e_m:.2e}, pcg gpu {info.iterations} it, oracle "
+          f"{ref.iterations} it, rel diff {e_x:.2e}")
+    assert e_b <= 1e-10 and e_m <= 5e-8
+    # B1 (stiffness ratio 1000) stops at the rounding floor of the preconditioned residual,
+    # where the two FP64 runs may end a few iterations apart with the same error
+    tol_its = max(1, 0.1 * ref.iterations) if name.startswith("B") else 1
+    assert info.converged and abs(info.iterations - ref.iterations) <= tol_its and e_x <= 1e-7
+    h.close()
+
+
+def test_no_coords_needed_and_mixed():
+    from paper_2505_18576_amd import AMGF, AMGFError
+    p = problem("C1")
+    o = oracle("C1", near_null=3)
+    h = AMGF(p.n_nodes, p.K_rowptr, p.K_col, p.K_val.reshape(-1), p.J_rowptr, p.J_col,
+             p.J_val, p.D, np.zeros(0), near_null=3, precision=1)
+    r = np.random.default_rng(2).standard_normal(p.n)
+    assert rel(h.vcycle(r).cpu().numpy(), o.vcycle(r)) <= 1e-4
+    x, info = h.pcg(p.b)
+    assert info.converged
+    h.close()
+    with pytest.raises(AMGFError):
+        AMGF(p.n_nodes, p.K_rowptr, p.K_col, p.K_val.reshape(-1), p.J_rowptr, p.J_col,
+             p.J_val, p.D, np.zeros(0))
+    with pytest.raises(AMGFError):
+        AMGF.from_problem(p, near_null=4)

@@ -131,6 +131,7 @@ struct BSR {
   // the column ids at sell_col[sell_off[s] + 64 j + i] and entry (p,q) of row i's block
   // at sell_val[9 (sell_off[s] + 64 j) + 64 (3p+q) + i]; padding has value 0.
   DBuf<int> sell_off, sell_col;
+  DBuf<int16_t> sell_dcol;  // column id - row as int16, when every stored block fits
   DBuf<double> sell_val;
   DBuf<float> sell_val32;
   // BF16 copy (round to nearest even): per slot, entries (0,1) (2,3) (4,5) (6,7) of the

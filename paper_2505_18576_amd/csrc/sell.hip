@@ -9,13 +9,23 @@ namespace amgf {
 
 // ======================================================================================
 // Sliced-ELL SpMV for 3x3 blocks: one wave per slice of 64 block rows, lane i owns row
-// 64 s + i.  For every slot the wave reads 64 column ids (256 B), 9 x 64 values
-// (contiguous) and the three x entries of each column; neighbouring rows of a structured
-// mesh have neighbouring columns, so the x reads coalesce too.  No cross-lane reduction.
+// 64 s + i.  For every slot the wave reads 64 column ids, 9 x 64 values (contiguous) and
+// the three x entries of each column; neighbouring rows of a structured mesh have
+// neighbouring columns, so the x reads coalesce too.  No cross-lane reduction.  SHORT:
+// the column ids are 16-bit offsets from the row (128 B per slot instead of 256 B), used
+// when every stored block lies within 32767 block columns of its row.
 // ======================================================================================
-template <class T, int MODE>
+template <bool SHORT>
+__device__ __forceinline__ int64_t sell_col3(const int* __restrict__ cp,
+                                             const int16_t* __restrict__ dp, int r, int j) {
+  if constexpr (SHORT) return (int64_t(r) + dp[j * 64]) * 3;
+  else return int64_t(cp[j * 64]) * 3;
+}
+
+template <class T, int MODE, bool SHORT>
 __global__ void __launch_bounds__(256) k_sell3(int nrows, const int* __restrict__ off,
                                                const int* __restrict__ scol,
+                                               const int16_t* __restrict__ sdcol,
                                                const T* __restrict__ sval,
                                                const T* __restrict__ x, T* __restrict__ y,
                                                const T* __restrict__ b,
@@ -25,12 +35,14 @@ __global__ void __launch_bounds__(256) k_sell3(int nrows, const int* __restrict_
   if (int64_t(s) * 64 >= nrows) return;
   const int o0 = off[s];
   const int len = (off[s + 1] - o0) >> 6;
-  const int* cp = scol + o0 + i;
+  const int* cp = SHORT ? nullptr : scol + o0 + i;
+  const int16_t* dp = SHORT ? sdcol + o0 + i : nullptr;
+  const int rr = s * 64 + i;
   const T* vp = sval + int64_t(o0) * 9 + i;
   T a0 = T(0), a1 = T(0), a2 = T(0);
 #pragma unroll 3
   for (int j = 0; j < len; ++j) {
-    const int64_t cc = int64_t(cp[j * 64]) * 3;
+    const int64_t cc = sell_col3<SHORT>(cp, dp, rr, j);
     T x0, x1, x2;
     if (MODE == SPMV_PRE) {
       x0 = w[cc] * b[cc];
@@ -69,9 +81,10 @@ __global__ void __launch_bounds__(256) k_sell3(int nrows, const int* __restrict_
 __device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
 
-template <int MODE>
+template <int MODE, bool SHORT>
 __global__ void __launch_bounds__(256) k_sell3_bf16(int nrows, const int* __restrict__ off,
                                                     const int* __restrict__ scol,
+                                                    const int16_t* __restrict__ sdcol,
                                                     const uint16_t* __restrict__ sval,
                                                     const float* __restrict__ x,
                                                     float* __restrict__ y,
@@ -83,12 +96,14 @@ __global__ void __launch_bounds__(256) k_sell3_bf16(int nrows, const int* __rest
   if (int64_t(s) * 64 >= nrows) return;
   const int o0 = off[s];
   const int len = (off[s + 1] - o0) >> 6;
-  const int* cp = scol + o0 + i;
+  const int* cp = SHORT ? nullptr : scol + o0 + i;
+  const int16_t* dp = SHORT ? sdcol + o0 + i : nullptr;
+  const int rr = s * 64 + i;
   const uint16_t* vs = sval + int64_t(o0) * 9;
   float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll 3
   for (int j = 0; j < len; ++j) {
-    const int64_t cc = int64_t(cp[j * 64]) * 3;
+    const int64_t cc = sell_col3<SHORT>(cp, dp, rr, j);
     float x0, x1, x2;
     if (MODE == SPMV_PRE) {
       x0 = w[cc] * b[cc];
@@ -204,6 +219,23 @@ __global__ void __launch_bounds__(256) k_sell_fill(int nrows, const int* __restr
   }
 }
 
+// 16-bit column offsets from the row; flag bit 1 when one does not fit
+__global__ void __launch_bounds__(64) k_sell_delta(const int* __restrict__ off,
+                                                   const int* __restrict__ scol,
+                                                   int16_t* __restrict__ dcol,
+                                                   int* __restrict__ flag) {
+  const int s = blockIdx.x, i = threadIdx.x;
+  const int o0 = off[s], len = (off[s + 1] - o0) >> 6;
+  const int r = s * 64 + i;
+  bool bad = false;
+  for (int j = 0; j < len; ++j) {
+    const int d = scol[o0 + j * 64 + i] - r;
+    bad = bad || d < -32768 || d > 32767;
+    dcol[o0 + j * 64 + i] = int16_t(bad ? 0 : d);
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
 void bsr_build_sell(Ctx& c, BSR& A, bool fp64, bool fp32, bool bf16) {
   AMGF_REQUIRE(A.br == 3 && A.bc == 3, AMGF_EINVAL, "sliced ELL needs 3x3 blocks");
   if (A.nrows == 0) return;
@@ -222,6 +254,13 @@ void bsr_build_sell(Ctx& c, BSR& A, bool fp64, bool fp32, bool bf16) {
                      A.val.p, A.sell_off.p, A.sell_col.p, A.sell_val.p, A.sell_val32.p,
                      A.sell_val16.p);
   AMGF_LAUNCH_CHECK();
+  // 16-bit offsets when the bandwidth allows (2 bytes less per stored block)
+  A.sell_dcol.alloc(size_t(total));
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  hipLaunchKernelGGL(k_sell_delta, dim3(ns), dim3(64), 0, c.s, A.sell_off.p, A.sell_col.p,
+                     A.sell_dcol.p, c.flag.p);
+  AMGF_LAUNCH_CHECK();
+  if (d2h_scalar(c.flag.p, c.s) != 0) A.sell_dcol.release();
 }
 
 template <class T>
@@ -232,8 +271,12 @@ void sell3_spmv(Ctx& c, int mode, const BSR& A, const T* sval, const T* x, T* y,
   switch (mode) {
 #define AMGF_MODE(MD)                                                                        \
   case MD:                                                                                   \
-    hipLaunchKernelGGL((k_sell3<T, MD>), g, blk, 0, c.s, A.nrows, A.sell_off.p, A.sell_col.p, \
-                       sval, x, y, b, w, xo);                                                \
+    if (A.sell_dcol.p)                                                                       \
+      hipLaunchKernelGGL((k_sell3<T, MD, true>), g, blk, 0, c.s, A.nrows, A.sell_off.p,      \
+                         A.sell_col.p, A.sell_dcol.p, sval, x, y, b, w, xo);                 \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_sell3<T, MD, false>), g, blk, 0, c.s, A.nrows, A.sell_off.p,     \
+                         A.sell_col.p, A.sell_dcol.p, sval, x, y, b, w, xo);                 \
     break;
     AMGF_MODE(SPMV_Y)
     AMGF_MODE(SPMV_ADD)
@@ -261,8 +304,12 @@ void sell_spmv_bf16(Ctx& c, int mode, const BSR& A, const float* x, float* y, co
   switch (mode) {
 #define AMGF_MODE(MD)                                                                        \
   case MD:                                                                                   \
-    hipLaunchKernelGGL((k_sell3_bf16<MD>), g, blk, 0, c.s, A.nrows, A.sell_off.p,            \
-                       A.sell_col.p, A.sell_val16.p, x, y, b, w, xo);                        \
+    if (A.sell_dcol.p)                                                                       \
+      hipLaunchKernelGGL((k_sell3_bf16<MD, true>), g, blk, 0, c.s, A.nrows, A.sell_off.p,    \
+                         A.sell_col.p, A.sell_dcol.p, A.sell_val16.p, x, y, b, w, xo);       \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_sell3_bf16<MD, false>), g, blk, 0, c.s, A.nrows, A.sell_off.p,   \
+                         A.sell_col.p, A.sell_dcol.p, A.sell_val16.p, x, y, b, w, xo);       \
     break;
     AMGF_MODE(SPMV_Y)
     AMGF_MODE(SPMV_ADD)

@@ -193,7 +193,8 @@ const char* amgf_last_error(void);
 /* ---------------- inspection (tests and benchmarks) ---------------------------------
  * Level data are copied to HOST buffers of the stated size; `which` selects the array:
  *  AMGF_Q_SIZES    int32[8]: n_nodes, block size, nnzb(A), n_agg, nnzb(P), nnzb(G),
- *                  nnzb(K), n_isolated
+ *                  nnzb(K), bytes per column id of the level's sliced-ELL stiffness copy
+ *                  (2: 16-bit offsets from the row, 4: int32 ids, 0: no sliced copy)
  *  AMGF_Q_A_ROWPTR/A_COL/A_VAL  assembled operator A_l (BSR b x b, FP64)
  *  AMGF_Q_AGG      int32[n_nodes] aggregate of each node (-1 = isolated)
  *  AMGF_Q_ROOT     int32[n_nodes] 1 for MIS-2 roots

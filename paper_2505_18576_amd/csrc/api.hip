@@ -1573,8 +1573,9 @@ amgf_status amgf_query(amgf_handle hd, int32_t level, int32_t which, void* dst, 
     AMGF_HIP(hipStreamSynchronize(c.s));
     switch (which) {
       case AMGF_Q_SIZES: {
+        const int32_t idx_bytes = L.K.sell_dcol.p ? 2 : (L.K.sell_col.p ? 4 : 0);
         int32_t s[8] = {L.nn, L.b, int32_t(L.A.nnzb), L.n_agg, int32_t(L.P.nnzb),
-                        int32_t(L.G.nnz), int32_t(L.K.nnzb), 0};
+                        int32_t(L.G.nnz), int32_t(L.K.nnzb), idx_bytes};
         AMGF_REQUIRE(bytes == sizeof(s), AMGF_EINVAL, "size");
         std::memcpy(dst, s, sizeof(s));
         break;

@@ -663,23 +663,26 @@ __global__ void k_nonneg_mask(int n, const int* __restrict__ a, int* __restrict_
 // ======================================================================================
 // generic BSR product C = A B, output-stationary
 // ======================================================================================
-// One wavefront per row r, one lane per output block (r, j): the lane walks A's row in
-// ascending order, so each output block accumulates in a fixed order (deterministic) and
-// rows with many blocks spread over the wavefront.  For each A block (r, k) the wavefront
-// loads the column ids of B's row k once (coalesced, up to 64 at a time) and every lane
-// finds its column j there by a binary search over lanes (shuffles, no dependent loads).
-template <int RA, int KA, int CB>
+// A group of G lanes per row r (G = 64: one wavefront; G = 16: four short rows per
+// wavefront), one lane per output block (r, j): the lane walks A's row in ascending order,
+// so each output block accumulates in a fixed order (deterministic) and rows with many
+// blocks spread over the group.  For each A block (r, k) the group loads the column ids of
+// B's row k once (coalesced, up to G at a time) and every lane finds its column j there by
+// a binary search over the group's lanes (shuffles, no dependent loads).
+template <int RA, int KA, int CB, int G>
 __global__ void __launch_bounds__(256) k_spgemm_numeric(
     int nrows, const int* __restrict__ arp, const int* __restrict__ acol,
     const double* __restrict__ aval, const int* __restrict__ brp, const int* __restrict__ bcol,
     const double* __restrict__ bval, const int* __restrict__ crp, const int* __restrict__ ccol,
     double* __restrict__ cval) {
-  const int r = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63;
+  // a full wavefront per row keeps the row index (and the loops over A's row) scalar
+  const int r = G == 64 ? __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6))
+                        : int((blockIdx.x * 256 + threadIdx.x) / G);
+  const int lane = threadIdx.x % G;
   if (r >= nrows) return;
   const int t0 = arp[r], t1 = arp[r + 1];
   const int s1 = crp[r + 1];
-  for (int sb = crp[r]; sb < s1; sb += 64) {
+  for (int sb = crp[r]; sb < s1; sb += G) {
     const int s = sb + lane;
     const bool act = s < s1;
     const int j = act ? ccol[s] : INT_MAX;
@@ -689,16 +692,16 @@ __global__ void __launch_bounds__(256) k_spgemm_numeric(
     for (int t = t0; t < t1; ++t) {
       const int k = acol[t];
       const int b0 = brp[k], blen = brp[k + 1] - b0;
-      for (int c0 = 0; c0 < blen; c0 += 64) {
-        const int nb = min(64, blen - c0);
+      for (int c0 = 0; c0 < blen; c0 += G) {
+        const int nb = min(G, blen - c0);
         const int myc = lane < nb ? bcol[b0 + c0 + lane] : INT_MAX;
         // pos = number of chunk columns below j (chunk columns ascending)
         int pos = 0;
         for (int st = 1 << (31 - __clz(nb)); st > 0; st >>= 1) {
-          const int v = __shfl(myc, min(pos + st - 1, 63), 64);
+          const int v = __shfl(myc, min(pos + st - 1, G - 1), G);
           if (pos + st <= nb && v < j) pos += st;
         }
-        const int hit = __shfl(myc, min(pos, 63), 64);
+        const int hit = __shfl(myc, min(pos, G - 1), G);
         if (!act || pos >= nb || hit != j) continue;
         const double* a = aval + int64_t(t) * RA * KA;
         const double* b = bval + int64_t(b0 + c0 + pos) * KA * CB;
@@ -727,13 +730,19 @@ void spgemm(Ctx& c, const BSR& A, const BSR& B, BSR& C) {
   C.br = A.br;
   C.bc = B.bc;
   C.val.alloc(std::max<int64_t>(C.nnzb, 1) * C.bsz());
-  const dim3 g(grid_for(A.nrows, 4)), b(256);
+  // short output rows (at most 16 blocks on average): four rows per wavefront
+  const bool short_rows = A.nrows > 0 && C.nnzb <= int64_t(16) * A.nrows;
+  const dim3 g64(grid_for(A.nrows, 4)), g16(grid_for(A.nrows, 16)), b(256);
 #define AMGF_SPGEMM_CASE(ra, ka, cb)                                                         \
   if (A.br == ra && A.bc == ka && B.bc == cb) {                                              \
-    if (A.nrows)                                                                             \
-      hipLaunchKernelGGL((k_spgemm_numeric<ra, ka, cb>), g, b, 0, c.s, A.nrows, A.rowptr.p,  \
-                         A.col.p, A.val.p, B.rowptr.p, B.col.p, B.val.p, C.rowptr.p,         \
-                         C.col.p, C.val.p);                                                  \
+    if (A.nrows && short_rows)                                                               \
+      hipLaunchKernelGGL((k_spgemm_numeric<ra, ka, cb, 16>), g16, b, 0, c.s, A.nrows,        \
+                         A.rowptr.p, A.col.p, A.val.p, B.rowptr.p, B.col.p, B.val.p,         \
+                         C.rowptr.p, C.col.p, C.val.p);                                      \
+    else if (A.nrows)                                                                        \
+      hipLaunchKernelGGL((k_spgemm_numeric<ra, ka, cb, 64>), g64, b, 0, c.s, A.nrows,        \
+                         A.rowptr.p, A.col.p, A.val.p, B.rowptr.p, B.col.p, B.val.p,         \
+                         C.rowptr.p, C.col.p, C.val.p);                                      \
     AMGF_LAUNCH_CHECK();                                                                     \
     return;                                                                                  \
   }

@@ -69,8 +69,8 @@ void DenseInverse::setup(Ctx& c, const BSR& A) {
   AMGF_REQUIRE(A.br == A.bc && A.nrows == A.ncols, AMGF_EINVAL, "square BSR expected");
   n = A.nrows * A.br;
   X.alloc(size_t(n) * n);
-  AMGF_HIP(hipMemsetAsync(X.p, 0, X.bytes(), c.s));
   if (!n) return;
+  AMGF_HIP(hipMemsetAsync(X.p, 0, X.bytes(), c.s));
   hipLaunchKernelGGL(k_bsr_to_dense, dim3(grid_for(n, 256)), dim3(256), 0, c.s, A.nrows, A.br,
                      A.rowptr.p, A.col.p, A.val.p, n, X.p);
   AMGF_LAUNCH_CHECK();

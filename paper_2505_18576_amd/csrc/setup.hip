@@ -770,13 +770,16 @@ __global__ void k_dead_identity(int n_agg, int nc, const unsigned char* __restri
 // save: first record K0 from K.
 __global__ void k_bound_diag(int nn, const int* __restrict__ rp, const int* __restrict__ col,
                              double* __restrict__ val, const double* __restrict__ E,
-                             double* __restrict__ k0, int save) {
+                             double* __restrict__ k0, int save, int* __restrict__ flag) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= nn) return;
   int pos = -1;
   for (int e = rp[a]; e < rp[a + 1]; ++e)
     if (col[e] == a) pos = e;
-  if (pos < 0) return;
+  if (pos < 0) {
+    atomicOr(flag, 1);
+    return;
+  }
   for (int q = 0; q < 3; ++q) {
     const int64_t k = int64_t(pos) * 9 + 4 * q;
     if (save) k0[int64_t(a) * 3 + q] = val[k];
@@ -789,9 +792,12 @@ void bound_diagonal(Ctx& c, BSR& K, const double* E, DBuf<double>& k0) {
   AMGF_REQUIRE(K.br == 3 && K.bc == 3, AMGF_EINVAL, "bound terms need 3x3 blocks");
   const bool save = k0.n == 0;
   if (save) k0.alloc(size_t(K.nrows) * 3);
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
   hipLaunchKernelGGL(k_bound_diag, dim3(grid_for(K.nrows, 256)), dim3(256), 0, c.s, K.nrows,
-                     K.rowptr.p, K.col.p, K.val.p, E, k0.p, int(save));
+                     K.rowptr.p, K.col.p, K.val.p, E, k0.p, int(save), c.flag.p);
   AMGF_LAUNCH_CHECK();
+  AMGF_REQUIRE(d2h_scalar(c.flag.p, c.s) == 0, AMGF_EINVAL,
+               "bound terms need a stored diagonal block in every row of K");
 }
 
 void dead_identity(Ctx& c, BSR& Kc, const unsigned char* dead) {

@@ -79,12 +79,12 @@ typedef struct {
   int32_t smoother;           /* AMGF_L1JACOBI (theta = 1) or AMGF_LEARNED          */
   int32_t filter;             /* 1: AMGF (Definition 5.3); 0: plain AMG-PCG, M = B   */
   int32_t max_levels;         /* hierarchy depth cap (default 10)                    */
-  int32_t coarse_max_nodes;   /* stop coarsening at or below this many nodes (256)   */
+  int32_t coarse_max_nodes;   /* stop coarsening at or below this many nodes (1024)  */
   int32_t max_iters;          /* CG iteration cap (default 5000, Sec. 6.1)           */
   int32_t sa_power_iters;     /* power steps for rho(D_l1^{-1}A) (default 10)        */
-  double strength_theta;      /* level-0 strength threshold (default 0.08)           */
+  double strength_theta;      /* level-0 strength threshold (default 0.04)           */
   double rtol;                /* relative preconditioned residual (default 1e-10)    */
-  double sa_omega;            /* prolongator damping numerator (default 4/3)          */
+  double sa_omega;            /* prolongator damping numerator (default 1.5)          */
   double qr_tol;              /* dead near-null column threshold (default 1e-10)      */
   double max_coarse_ratio;    /* stop if n_agg > ratio * n_nodes (default 0.9)        */
   const float* mlp_weights;   /* host; 1313 MLP parameters + 12 feature normalisers,

@@ -492,9 +492,9 @@ def power_estimate(Acsr, d, decoupled, iters, clip=True):
 class OracleOptions:
     filter: bool = True
     max_levels: int = 10
-    coarse_max_nodes: int = 256
-    strength_theta: float = 0.08
-    sa_omega: float = 4.0 / 3.0            # numerator; divided by the estimate below
+    coarse_max_nodes: int = 1024
+    strength_theta: float = 0.04
+    sa_omega: float = 1.5                  # numerator; divided by the estimate below
     sa_power_iters: int = 10
     qr_tol: float = 1e-10
     max_coarse_ratio: float = 0.9

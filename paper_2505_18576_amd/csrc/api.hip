@@ -1163,12 +1163,12 @@ void amgf_default_options(amgf_options* o) {
   o->cheb_degree = 2;
   o->filter = 1;
   o->max_levels = 10;
-  o->coarse_max_nodes = 256;
+  o->coarse_max_nodes = 1024;
   o->max_iters = 5000;
   o->sa_power_iters = 10;
-  o->strength_theta = 0.08;
+  o->strength_theta = 0.04;
   o->rtol = 1e-10;
-  o->sa_omega = 4.0 / 3.0;
+  o->sa_omega = 1.5;
   o->qr_tol = 1e-10;
   o->max_coarse_ratio = 0.9;
   o->mlp_weights = nullptr;

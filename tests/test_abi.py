@@ -42,7 +42,8 @@ def test_host_only_entry_points(lib):
     from paper_2505_18576_amd import amgf as b
     o = b.default_options()
     assert o.struct_size == __import__("ctypes").sizeof(b.Options)
-    assert (o.rtol, o.max_iters, o.filter, o.coarse_max_nodes) == (1e-10, 5000, 1, 256)
+    assert (o.rtol, o.max_iters, o.filter, o.coarse_max_nodes) == (1e-10, 5000, 1, 1024)
+    assert (o.strength_theta, o.sa_omega, o.near_null) == (0.04, 1.5, 6)
     assert lib.amgf_status_string(b.AMGF_ENOCONV) == b"AMGF_ENOCONV"
     # argument checks happen before any device work
     import ctypes

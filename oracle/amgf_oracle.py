@@ -13,7 +13,8 @@ What it computes (paper references are to arXiv 2505.18576):
   level-0 strength of connection (coarse levels: aggregate adjacency),
   distance-2 maximal independent set aggregation,
   rigid-body-mode tentative prolongator, one damped-Jacobi prolongator smoothing
-  step (damping 4/3 over a power-iteration estimate of rho(D_l1^{-1} A)), Galerkin coarse operators, V(1,1), dense Cholesky on the coarsest level;
+  step (damping sa_omega, default 1.5, over a power-iteration estimate of rho(D_l1^{-1} A)),
+  Galerkin coarse operators, V(1,1), dense Cholesky on the coarsest level;
 * the filtering space (Sec. 5.1): I_c = every DOF of a node touched by J, the
   embedding P and A_w = P^T A P, solved exactly by a Cholesky/LU factorisation;
 * the multiplicative AMGF preconditioner M of Definition 5.3:

@@ -63,7 +63,7 @@ def test_smoothed_prolongator_and_l1_norms(c1):
     A = lev.A.todense()
     assert np.allclose(lev.d, np.abs(A).sum(axis=1), rtol=1e-15)
     Pt = lev.Pt.todense()
-    # damping: 4/3 over the spectral radius of D_l1^{-1} A on the coupled DOFs
+    # damping: sa_omega over the spectral radius of D_l1^{-1} A on the coupled DOFs
     keep = ~lev.decoupled
     DA = (A / lev.d[:, None])[keep][:, keep]
     rho = np.abs(np.linalg.eigvals(DA)).max()

@@ -290,19 +290,33 @@ __global__ void k_mis_init(int n, const int* __restrict__ rp, unsigned char* __r
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n) st[v] = (rp[v + 1] > rp[v]) ? 0 : 2;
 }
+// ball 1: MIS_G lanes per node share its neighbour list (coalesced column reads) and combine
+// their maxima by shuffles within the group
+constexpr int MIS_G = 8;
+__device__ __forceinline__ unsigned long long group_max_u64(unsigned long long m) {
+#pragma unroll
+  for (int o = MIS_G / 2; o > 0; o >>= 1) {
+    const unsigned long long x = __shfl_xor(m, o, MIS_G);
+    m = x > m ? x : m;
+  }
+  return m;
+}
 __global__ void k_mis_ball1(int n, const int* __restrict__ rp, const int* __restrict__ col,
                             const unsigned char* __restrict__ st,
                             unsigned long long* __restrict__ m1) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int v = int(t / MIS_G), l = int(t % MIS_G);
   if (v >= n) return;
-  unsigned long long m = mis_code(v, st[v]);
-  for (int k = rp[v]; k < rp[v + 1]; ++k) {
+  unsigned long long m = l == 0 ? mis_code(v, st[v]) : 0ull;
+  for (int k = rp[v] + l; k < rp[v + 1]; k += MIS_G) {
     const int u = col[k];
     const unsigned long long cu = mis_code(u, st[u]);
     m = cu > m ? cu : m;
   }
-  m1[v] = m;
+  m = group_max_u64(m);
+  if (l == 0) m1[v] = m;
 }
+// thread per node: most nodes are decided after a few rounds and leave at once
 __global__ void k_mis_ball2(int n, const int* __restrict__ rp, const int* __restrict__ col,
                             const unsigned long long* __restrict__ m1,
                             unsigned char* __restrict__ st, int* __restrict__ undecided) {
@@ -380,8 +394,8 @@ int mis2_aggregate(Ctx& c, const Graph& G, int level, DBuf<int>& agg, DBuf<int>&
   int rounds = 0;
   for (;;) {
     AMGF_HIP(hipMemsetAsync(und.p, 0, sizeof(int), c.s));
-    hipLaunchKernelGGL(k_mis_ball1, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, G.rowptr.p,
-                       G.col.p, st.p, m1.p);
+    hipLaunchKernelGGL(k_mis_ball1, dim3(grid_for(int64_t(n) * MIS_G, 256)), dim3(256), 0, c.s,
+                       n, G.rowptr.p, G.col.p, st.p, m1.p);
     hipLaunchKernelGGL(k_mis_ball2, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, G.rowptr.p,
                        G.col.p, m1.p, st.p, und.p);
     AMGF_LAUNCH_CHECK();

@@ -165,11 +165,9 @@ constexpr int64_t COARSE_INVERSE_MAX = 2048;   // unknowns; 32 MiB of FP64 at mo
 
 static void factor_coarsest(Handle& h) {
   Level& LL = *h.lev.back();
-  h.coarse_inverse = LL.n() <= COARSE_INVERSE_MAX;
-  if (h.coarse_inverse) {
-    h.coarse_inv.setup(h.ctx, LL.A);
-    return;
-  }
+  h.coarse_inverse = LL.n() <= COARSE_INVERSE_MAX && h.coarse_inv.setup(h.ctx, LL.A);
+  if (h.coarse_inverse) return;
+  h.coarse_inv = DenseInverse();
   DBuf<int> rp, cl;
   DBuf<double> vl;
   bsr_to_csr(h.ctx, LL.A, rp, cl, vl);

@@ -10,8 +10,10 @@ namespace amgf {
 struct DenseInverse {
   int n = 0;
   DBuf<double> X;                // -A^{-1} after the sweep (the product negates it back)
-  // A: square BSR (FP64).  ENOTSPD if a pivot is not positive.
-  void setup(Ctx& c, const BSR& A);
+  // A: square BSR (FP64).  Returns false when a pivot is not positive (rounding can decide
+  // the sign of a pivot when A is extremely ill-conditioned); the caller then factors A by
+  // another method.
+  bool setup(Ctx& c, const BSR& A);
   // x = A^{-1} b (b, x: n FP64, may not alias)
   void solve(Ctx& c, const double* b, double* x) const;
 };

@@ -2,12 +2,16 @@
 //
 // Sweep of pivot k on a symmetric matrix with d = A_kk (Goodnight's sweep operator):
 //   A_ij -= A_ik A_kj / d (i, j != k),  A_ik /= d,  A_kj /= d,  A_kk = -1/d;
-// after sweeping every k the array holds -A^{-1}.  The sweep keeps the matrix symmetric,
-// so only the upper triangle is updated (and mirrored at the end).  Step k reads column k
-// of the current matrix from a separate vector, so the threads of one step never read what
-// another writes; the threads holding column (or row) k+1 write it for the next step into
-// the other vector.
+// after sweeping every k the array holds -A^{-1}.  Sweeping the pivots of a block K one by
+// one equals the block sweep with P = A_KK:
+//   A_ij -= A_iK P^{-1} A_Kj,  A_iK <- A_iK P^{-1},  A_Kj <- P^{-1} A_Kj,  A_KK <- -P^{-1},
+// so the pivots are taken SWEEP_B at a time: one workgroup sweeps the small block P in LDS,
+// then the rows of K are copied (V = A_K.) and multiplied (W = P^{-1} V), then every entry
+// is updated from V and W, which no thread of that step writes.  The sweep keeps the matrix
+// symmetric, so only the upper triangle is updated (and mirrored at the end).
 #include "coarse.h"
+
+#include <algorithm>
 
 namespace amgf {
 
@@ -24,37 +28,91 @@ __global__ void k_bsr_to_dense(int nrows, int b, const int* __restrict__ rp,
       X[int64_t(r) * n + int64_t(col[e]) * b + q] = val[(int64_t(e) * b + p) * b + q];
 }
 
-__global__ void k_column(int n, const double* __restrict__ X, int k, double* __restrict__ v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[i] = X[int64_t(i) * n + k];
+constexpr int SWEEP_B = 32;
+
+// entry (i, j) of the symmetric matrix held in the upper triangle
+__device__ __forceinline__ double sym_at(const double* X, int n, int i, int j) {
+  return i <= j ? X[int64_t(i) * n + j] : X[int64_t(j) * n + i];
 }
 
-// one step on the upper triangle (j >= i) in 16 x 16 tiles; tiles below the diagonal exit
-__global__ void __launch_bounds__(256) k_sweep(int n, double* __restrict__ X, int k,
-                                               const double* __restrict__ v,
-                                               double* __restrict__ vnext,
-                                               int* __restrict__ flag) {
+// Pi = P^{-1} for P = A_KK (K = k0 .. k0+kb-1) by the scalar sweep in LDS; flag bit 4 on a
+// pivot that is not positive
+__global__ void __launch_bounds__(256) k_sweep_pivot(int n, const double* __restrict__ X,
+                                                     int k0, int kb, double* __restrict__ Pi,
+                                                     int* __restrict__ flag) {
+  __shared__ double P[SWEEP_B][SWEEP_B + 1];
+  __shared__ double col[SWEEP_B];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kb * kb; e += 256) P[e / kb][e % kb] = sym_at(X, n, k0 + e / kb,
+                                                                        k0 + e % kb);
+  __syncthreads();
+  for (int s = 0; s < kb; ++s) {
+    if (tid < kb) col[tid] = P[tid][s];
+    __syncthreads();
+    const double d = col[s];
+    if (tid == 0 && !(d > 0.0)) atomicOr(flag, 4);
+    for (int e = tid; e < kb * kb; e += 256) {
+      const int p = e / kb, q = e % kb;
+      double x;
+      if (p == s && q == s) x = -1.0 / d;
+      else if (p == s) x = col[q] / d;
+      else if (q == s) x = col[p] / d;
+      else x = P[p][q] - col[p] * (col[q] / d);
+      P[p][q] = x;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kb * kb; e += 256) Pi[e] = -P[e / kb][e % kb];
+}
+
+// V = A_K. (rows of the block, from the upper triangle) and W = Pi V, one thread per column
+__global__ void __launch_bounds__(256) k_sweep_rows(int n, const double* __restrict__ X,
+                                                    int k0, int kb,
+                                                    const double* __restrict__ Pi,
+                                                    double* __restrict__ V,
+                                                    double* __restrict__ W) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double v[SWEEP_B];
+#pragma unroll
+  for (int q = 0; q < SWEEP_B; ++q) {
+    v[q] = q < kb ? sym_at(X, n, k0 + q, j) : 0.0;
+    if (q < kb) V[int64_t(q) * n + j] = v[q];
+  }
+  for (int p = 0; p < kb; ++p) {
+    double w = 0.0;
+#pragma unroll
+    for (int q = 0; q < SWEEP_B; ++q)
+      if (q < kb) w += Pi[p * kb + q] * v[q];
+    W[int64_t(p) * n + j] = w;
+  }
+}
+
+// one block step on the upper triangle (j >= i) in 16 x 16 tiles; tiles below the
+// diagonal exit
+__global__ void __launch_bounds__(256) k_sweep_update(int n, double* __restrict__ X, int k0,
+                                                      int kb, const double* __restrict__ Pi,
+                                                      const double* __restrict__ V,
+                                                      const double* __restrict__ W) {
   if (blockIdx.y > blockIdx.x) return;
   const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
   const int j = blockIdx.x * 16 + (threadIdx.x & 15);
   if (i >= n || j >= n || j < i) return;
+  const bool iK = i >= k0 && i < k0 + kb, jK = j >= k0 && j < k0 + kb;
   const int64_t t = int64_t(i) * n + j;
-  const double d = v[k];
   double x;
-  if (i == k && j == k) {
-    if (!(d > 0.0)) atomicOr(flag, 4);
-    x = -1.0 / d;
-  } else if (i == k) {
-    x = v[j] / d;
-  } else if (j == k) {
-    x = v[i] / d;
+  if (iK && jK) {
+    x = -Pi[(i - k0) * kb + (j - k0)];
+  } else if (iK) {
+    x = W[int64_t(i - k0) * n + j];
+  } else if (jK) {
+    x = W[int64_t(j - k0) * n + i];
   } else {
-    x = X[t] - v[i] * (v[j] / d);
+    double acc = 0.0;
+    for (int p = 0; p < kb; ++p) acc += V[int64_t(p) * n + i] * W[int64_t(p) * n + j];
+    x = X[t] - acc;
   }
   X[t] = x;
-  // column k + 1 of the symmetric matrix for the next step
-  if (j == k + 1) vnext[i] = x;
-  else if (i == k + 1) vnext[j] = x;
 }
 
 // lower triangle from the upper one
@@ -81,29 +139,31 @@ __global__ void __launch_bounds__(256) k_neg_gemv(int n, const double* __restric
 
 }  // namespace
 
-void DenseInverse::setup(Ctx& c, const BSR& A) {
+bool DenseInverse::setup(Ctx& c, const BSR& A) {
   AMGF_REQUIRE(A.br == A.bc && A.nrows == A.ncols, AMGF_EINVAL, "square BSR expected");
   n = A.nrows * A.br;
   X.alloc(size_t(n) * n);
-  if (!n) return;
+  if (!n) return true;
   AMGF_HIP(hipMemsetAsync(X.p, 0, X.bytes(), c.s));
   hipLaunchKernelGGL(k_bsr_to_dense, dim3(grid_for(n, 256)), dim3(256), 0, c.s, A.nrows, A.br,
                      A.rowptr.p, A.col.p, A.val.p, n, X.p);
   AMGF_LAUNCH_CHECK();
-  DBuf<double> v0(n), v1(n);
-  hipLaunchKernelGGL(k_column, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, X.p, 0, v0.p);
-  AMGF_LAUNCH_CHECK();
+  DBuf<double> Pi(SWEEP_B * SWEEP_B), V(size_t(SWEEP_B) * n), W(size_t(SWEEP_B) * n);
   AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
   const unsigned nt = unsigned((n + 15) / 16);
-  for (int k = 0; k < n; ++k) {
-    const double* v = (k & 1) ? v1.p : v0.p;
-    double* vn = (k & 1) ? v0.p : v1.p;
-    hipLaunchKernelGGL(k_sweep, dim3(nt, nt), dim3(256), 0, c.s, n, X.p, k, v, vn, c.flag.p);
+  for (int k0 = 0; k0 < n; k0 += SWEEP_B) {
+    const int kb = std::min(SWEEP_B, n - k0);
+    hipLaunchKernelGGL(k_sweep_pivot, dim3(1), dim3(256), 0, c.s, n, X.p, k0, kb, Pi.p,
+                       c.flag.p);
+    hipLaunchKernelGGL(k_sweep_rows, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, X.p, k0, kb,
+                       Pi.p, V.p, W.p);
+    hipLaunchKernelGGL(k_sweep_update, dim3(nt, nt), dim3(256), 0, c.s, n, X.p, k0, kb, Pi.p,
+                       V.p, W.p);
   }
+  AMGF_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_mirror, dim3(grid_for(int64_t(n) * n, 256)), dim3(256), 0, c.s, n, X.p);
   AMGF_LAUNCH_CHECK();
-  AMGF_REQUIRE(d2h_scalar(c.flag.p, c.s) == 0, AMGF_ENOTSPD,
-               "coarsest operator is not positive definite");
+  return d2h_scalar(c.flag.p, c.s) == 0;
 }
 
 void DenseInverse::solve(Ctx& c, const double* b, double* x) const {

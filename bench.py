@@ -262,6 +262,10 @@ def main():
         h = AMGF(p.n_nodes, d["K_rowptr"], d["K_col"], d["K_val"], d["J_rowptr"], d["J_col"],
                  d["J_val"], d["D"], d["coords"], precision=b.MIXED_FP32, mlp_weights=W)
         h.time_kernel(b.K_PRESMOOTH, 5)
+        h.time_kernel(b.K_VCYCLE, 2)      # transfers and coarse levels
+        h.time_kernel(b.K_OPERATOR, 3)    # FP64 operator of the CG loop
+        s0 = [int(v) for v in h.query(0, b.Q_SIZES)]
+        log("level0 sizes " + " ".join(str(v) for v in s0))
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):

@@ -696,7 +696,8 @@ __global__ void __launch_bounds__(256) k_spgemm_numeric(
   if (r >= nrows) return;
   const int t0 = arp[r], t1 = arp[r + 1];
   const int s1 = crp[r + 1];
-  for (int sb = crp[r]; sb < s1; sb += G) {
+  // blockIdx.y spreads the output chunks of a row over gridDim.y wavefronts
+  for (int sb = crp[r] + int(blockIdx.y) * G; sb < s1; sb += G * int(gridDim.y)) {
     const int s = sb + lane;
     const bool act = s < s1;
     const int j = act ? ccol[s] : INT_MAX;
@@ -744,9 +745,12 @@ void spgemm(Ctx& c, const BSR& A, const BSR& B, BSR& C) {
   C.br = A.br;
   C.bc = B.bc;
   C.val.alloc(std::max<int64_t>(C.nnzb, 1) * C.bsz());
-  // short output rows (at most 16 blocks on average): four rows per wavefront
+  // short output rows (at most 16 blocks on average): four rows per wavefront; long rows
+  // of a small matrix (coarse Galerkin products): their 64-column chunks on up to 16
+  // wavefronts each, so that a few hundred rows still fill the chip
   const bool short_rows = A.nrows > 0 && C.nnzb <= int64_t(16) * A.nrows;
-  const dim3 g64(grid_for(A.nrows, 4)), g16(grid_for(A.nrows, 16)), b(256);
+  const int ny = A.nrows > 0 ? std::min(16, std::max(1, 32768 / A.nrows)) : 1;
+  const dim3 g64(grid_for(A.nrows, 4), ny), g16(grid_for(A.nrows, 16)), b(256);
 #define AMGF_SPGEMM_CASE(ra, ka, cb)                                                         \
   if (A.br == ra && A.bc == ka && B.bc == cb) {                                              \
     if (A.nrows && short_rows)                                                               \

@@ -49,7 +49,9 @@ def log(*a):
 def vcycle_bytes(h, vbytes, k0bytes=None):
     """Algorithmic HBM bytes of one V(1,1) (values of `vbytes` bytes, int32 indices).
 
-    Per non-coarsest level: pre-smooth (K read, b and w read, x and r written),
+    Per non-coarsest level: pre-smooth (FP64: K read, b and w read, x and r written in
+    one pass; FP32: x = w.b (w, b read, x written), then K read, x gathered, b read, r
+    written),
     restriction (P^T read, r read, coarse b written), prolongation (P read, coarse x
     read, x read+written), post-smooth (K read, x, b, w read, x' written); contact
     terms J and J^T (FP64) twice; coarsest: the dense inverse (FP64) read once.
@@ -69,7 +71,7 @@ def vcycle_bytes(h, vbytes, k0bytes=None):
         kv = k0bytes if (l == 0 and k0bytes) else vbytes
         kbytes = nnzK * (bs * bs * kv + ib) + (nn + 1) * 4
         pbytes = nnzP * (bs * bc * vbytes + 4) + (nn + 1) * 4
-        total += kbytes + 4 * n * vbytes            # pre-smooth
+        total += kbytes + (4 if vbytes == 8 else 6) * n * vbytes      # pre-smooth
         total += pbytes + n * vbytes + n_agg * bc * vbytes      # restrict (P^T has P's size)
         total += pbytes + n_agg * bc * vbytes + 2 * n * vbytes  # prolong
         total += kbytes + 4 * n * vbytes            # post-smooth
@@ -77,15 +79,17 @@ def vcycle_bytes(h, vbytes, k0bytes=None):
 
 
 def smoother_bytes(h, vbytes, kbytes=None):
-    """Level-0 fused pre-smooth: K values (kbytes each) and column ids (16-bit offsets or
-    int32, as the sliced copy stores them), row pointers, and b, w read and x, r written
-    (vbytes each)."""
+    """Level-0 pre-smooth SpMV: K values (kbytes each) and column ids (16-bit offsets or
+    int32, as the sliced copy stores them), row pointers, and the vectors (vbytes each):
+    FP64, one fused pass x = w.b, r = b - K x (b, w read, x, r written); FP32 and BF16-K,
+    r = b - K x from the x = w.b formed before (x, b read, r written)."""
     from paper_2505_18576_amd import amgf as b
     s = h.query(0, b.Q_SIZES)
     nn, bs, nnzK, ib = int(s[0]), int(s[1]), int(s[6]), int(s[7]) or 4
     n = nn * bs
     kb = kbytes or vbytes
-    return nnzK * (bs * bs * kb + ib) + (nn + 1) * 4 + 4 * n * vbytes
+    nvec = 4 if vbytes == 8 else 3
+    return nnzK * (bs * bs * kb + ib) + (nn + 1) * 4 + nvec * n * vbytes
 
 
 def paper_table1():
@@ -108,13 +112,15 @@ def paper_table1():
 
 COUNTERS = os.path.join(ROOT, "profiles", "presmooth_sell3_f32_C5_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2505_18576_amd", "csrc", "sell.hip")
+# the level-0 pre-smooth SpMV of the mixed-precision V-cycle (residual mode, 16-bit offsets)
+ROOFLINE_KERNEL = "void amgf::k_sell3<float, 4, true>"
 
 
 def measured_traffic():
     """HBM bytes per pre-smooth launch from the committed FETCH_SIZE / WRITE_SIZE summary,
     each scaled by the same counter's reading for a plain copy of known size; None when
-    the summary is missing or the kernels' source (sell.hip) changed after the counters
-    were taken."""
+    the summary is missing, covers another kernel, or the kernels' source (sell.hip)
+    changed after the counters were taken."""
     import hashlib
     if not os.path.exists(COUNTERS):
         return None
@@ -126,7 +132,7 @@ def measured_traffic():
                 kv[k.strip()] = v.strip()
     with open(KERNEL_SRC, "rb") as f:
         src = hashlib.sha256(f.read()).hexdigest()
-    if kv.get("kernel_source_sha256") != src:
+    if kv.get("kernel_source_sha256") != src or kv.get("kernel") != ROOFLINE_KERNEL:
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
@@ -369,8 +375,8 @@ def main():
                      "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "algorithmic_bytes": m["smoother_bytes"],
                      "launch_ms": m["smoother_ms_live"],
-                     "kernel": "level-0 fused pre-smooth SpMV (FP32 values, 3x3 blocks, sliced "
-                               "ELL, 16-bit column offsets)"},
+                     "kernel": "level-0 pre-smooth SpMV r = b - K x at x = w.b (FP32 values, "
+                               "3x3 blocks, sliced ELL, 16-bit column offsets)"},
     }
     if not args.no_cpu_baseline:
         n_s, t_setup, t_it = cpu_baseline(args.cpu_sample, args.cpu_iters)

@@ -622,8 +622,12 @@ static void vcycle64(Handle& h, size_t l) {
   std::swap(L.vx, L.vxn);
 }
 
-// FP32 V(1,1) (contact term and coarsest solve in FP64): L.fb -> L.fx
-static void vcycle32(Handle& h, size_t l) {
+// FP32 V(1,1) (contact term and coarsest solve in FP64): L.fb -> L.fx.  The first
+// smoothing iterate x = w.b is formed on its own (x0_ready: the caller already wrote it
+// to L.fx), then r = b - K x reads x once per column instead of w and b.
+static void vcycle32_from(Handle& h, size_t l, bool x0_ready);
+static void vcycle32(Handle& h, size_t l) { vcycle32_from(h, l, false); }
+static void vcycle32_from(Handle& h, size_t l, bool x0_ready) {
   Ctx& c = h.ctx;
   Level& L = *h.lev[l];
   if (l + 1 == h.lev.size()) {
@@ -634,11 +638,12 @@ static void vcycle32(Handle& h, size_t l) {
   }
   if (!h.plain_cycle()) return vcycle_general<float>(h, l, vcycle32);
   Level& N = *h.lev[l + 1];
+  if (!x0_ready) wmul_f32(c, L.n(), L.w32.p, L.fb.p, L.fx.p);
   if (l == 0) prof_begin(h, AMGF_K_PRESMOOTH);
   if (l == 0 && h.bf16k())
-    sell_spmv_bf16(c, SPMV_PRE, L.K, nullptr, L.fr.p, L.fb.p, L.w32.p, L.fx.p);
+    sell_spmv_bf16(c, SPMV_RES, L.K, L.fx.p, L.fr.p, L.fb.p, nullptr, nullptr);
   else
-    bsr_spmv<float>(c, SPMV_PRE, L.K, L.K.val32.p, nullptr, L.fr.p, L.fb.p, L.w32.p, L.fx.p);
+    bsr_spmv<float>(c, SPMV_RES, L.K, L.K.val32.p, L.fx.p, L.fr.p, L.fb.p, nullptr, nullptr);
   prof_end(h);
   level_contact<float>(h, L, CT_SUB_RES, L.fx.p, L.fr.p, nullptr);
   bsr_spmv<float>(c, SPMV_Y, L.PT, L.PT.val32.p, L.fr.p, N.fb.p, nullptr, nullptr, nullptr);
@@ -660,8 +665,13 @@ static void vcycle(Handle& h, const double* r, double* z) {
   Level& L0 = *h.lev[0];
   const int64_t n = h.n();
   if (h.mixed()) {
-    cast_d2f(c, r, L0.fb.p, n);
-    vcycle32(h, 0);
+    if (h.plain_cycle()) {
+      cast_d2f_w(c, r, L0.w32.p, L0.fb.p, L0.fx.p, n);
+      vcycle32_from(h, 0, true);
+    } else {
+      cast_d2f(c, r, L0.fb.p, n);
+      vcycle32(h, 0);
+    }
     cast_f2d(c, L0.fx.p, z, n);
   } else {
     vcopy(c, r, L0.vb.p, n);
@@ -1506,11 +1516,11 @@ amgf_status amgf_time_kernel(amgf_handle hd, int32_t which, int32_t reps, void* 
       switch (which) {
         case AMGF_K_PRESMOOTH:
           if (h.bf16k())
-            amgf::sell_spmv_bf16(c, amgf::SPMV_PRE, L.K, nullptr, L.fr.p, L.fb.p, L.w32.p,
-                                 L.fx.p);
+            amgf::sell_spmv_bf16(c, amgf::SPMV_RES, L.K, L.fx.p, L.fr.p, L.fb.p, nullptr,
+                                 nullptr);
           else if (h.mixed())
-            amgf::bsr_spmv<float>(c, amgf::SPMV_PRE, L.K, L.K.val32.p, nullptr, L.fr.p, L.fb.p,
-                                  L.w32.p, L.fx.p);
+            amgf::bsr_spmv<float>(c, amgf::SPMV_RES, L.K, L.K.val32.p, L.fx.p, L.fr.p, L.fb.p,
+                                  nullptr, nullptr);
           else
             amgf::bsr_spmv<double>(c, amgf::SPMV_PRE, L.K, L.K.val.p, nullptr, L.vr.p, L.vb.p,
                                    L.w.p, L.vx.p);

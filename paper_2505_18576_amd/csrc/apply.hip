@@ -348,6 +348,15 @@ AMGF_ELEMWISE(k_d2f, (const double* __restrict__ a, float* __restrict__ b, int64
               b[i] = float(a[i]))
 AMGF_ELEMWISE(k_f2d, (const float* __restrict__ a, double* __restrict__ b, int64_t n),
               b[i] = double(a[i]))
+// b = float(a) and the first smoothing iterate x = w.b of a V-cycle from zero
+AMGF_ELEMWISE(k_d2f_w, (const double* __restrict__ a, const float* __restrict__ w,
+                        float* __restrict__ b, float* __restrict__ x, int64_t n),
+              const float bi = float(a[i]);
+              b[i] = bi;
+              x[i] = w[i] * bi)
+AMGF_ELEMWISE(k_wmul_f, (const float* __restrict__ w, const float* __restrict__ b,
+                         float* __restrict__ x, int64_t n),
+              x[i] = w[i] * b[i])
 AMGF_ELEMWISE(k_copy, (const double* __restrict__ a, double* __restrict__ b, int64_t n),
               b[i] = a[i])
 AMGF_ELEMWISE(k_axpby, (int64_t n, double al, const double* __restrict__ x, double be,
@@ -451,6 +460,12 @@ template void cheb_step<float>(Ctx&, int64_t, const float*, const float*, float*
                                double, double);
 void cast_d2f(Ctx& c, const double* a, float* b, int64_t n) {
   if (n) hipLaunchKernelGGL(k_d2f, AMGF_L1D(n), a, b, n);
+}
+void cast_d2f_w(Ctx& c, const double* a, const float* w, float* b, float* x, int64_t n) {
+  if (n) hipLaunchKernelGGL(k_d2f_w, AMGF_L1D(n), a, w, b, x, n);
+}
+void wmul_f32(Ctx& c, int64_t n, const float* w, const float* b, float* x) {
+  if (n) hipLaunchKernelGGL(k_wmul_f, AMGF_L1D(n), w, b, x, n);
 }
 void cast_f2d(Ctx& c, const float* a, double* b, int64_t n) {
   if (n) hipLaunchKernelGGL(k_f2d, AMGF_L1D(n), a, b, n);

@@ -254,9 +254,12 @@ def main():
     W = load_weights(wpath)
 
     def solve(precision, weights, live=False):
+        # device memory through the allocator callbacks from PyTorch's caching allocator, as
+        # a PyTorch caller would run it: after the warm-up, setups reuse cached blocks
+        # instead of paying hipMalloc/hipFree for every buffer (about 18 ms of a C5 setup)
         h = AMGF(p.n_nodes, d["K_rowptr"], d["K_col"], d["K_val"], d["J_rowptr"], d["J_col"],
                  d["J_val"], d["D"], d["coords"], precision=precision, mlp_weights=weights,
-                 E=E)
+                 E=E, allocator="torch")
         if live:   # event pairs around every level-0 pre-smooth launch of this solve
             h.profile_start(b.K_PRESMOOTH, 1000)
         x, info = h.pcg(bvec)

@@ -688,7 +688,14 @@ __global__ void __launch_bounds__(256) k_mf_rhs(int tb, int bs, const double* __
   }
 }
 
-// [y; u] = [X; -G] fa_s + [0; fa_b]: one wavefront per row of M
+// Rows per wavefront in the solve kernels: each wave issues the loads of MF_R rows of the
+// factor back to back (row indices clamped, products masked) and shares the vector entries
+// among them; one row per wave left the mid depths of the tree waiting on memory latency.
+// MF_R divides 64.
+constexpr int MF_R = 4;
+constexpr int MF_XB = 2048;   // boundary values a backward workgroup stages in LDS
+
+// [y; u] = [X; -G] fa_s + [0; fa_b]: rows i0 .. i0+MF_R-1 of M on one wavefront
 __global__ void __launch_bounds__(256) k_mf_fwd(int tb, const int* __restrict__ fS,
                                                 const int* __restrict__ fb,
                                                 const int64_t* __restrict__ mo,
@@ -698,21 +705,48 @@ __global__ void __launch_bounds__(256) k_mf_fwd(int tb, const int* __restrict__ 
                                                 double* __restrict__ fv) {
   const int t = tb + blockIdx.y, lane = threadIdx.x & 63;
   const int S = fS[t], rows = S + fb[t];
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= rows || S == 0) {
-    if (i < rows && lane == 0) fv[vo[t] + i] = fa[vo[t] + i];
+  const int i0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * MF_R;
+  if (i0 >= rows) return;
+  const double* f = fa + vo[t];
+  double* out = fv + vo[t];
+  if (S == 0) {
+    if (lane < MF_R && i0 + lane < rows) out[i0 + lane] = f[i0 + lane];
     return;
   }
-  const double* row = M + mo[t] + int64_t(i) * S;
-  const double* f = fa + vo[t];
-  const int jend = i < S ? (i / 64 + 1) * 64 : S;
-  double acc = 0.0;
-  for (int j = lane; j < jend; j += 64) acc += row[j] * f[j];
-  acc = wave_sum(acc);
-  if (lane == 0) fv[vo[t] + i] = i < S ? acc : f[i] - acc;
+  const double* rowp[MF_R];
+  int jend[MF_R];
+  int jmax = 0;
+#pragma unroll
+  for (int q = 0; q < MF_R; ++q) {
+    const int i = i0 + q;
+    jend[q] = i >= rows ? 0 : (i < S ? (i / 64 + 1) * 64 : S);
+    jmax = max(jmax, jend[q]);
+    rowp[q] = M + mo[t] + int64_t(min(i, rows - 1)) * S;
+  }
+  double acc[MF_R];
+#pragma unroll
+  for (int q = 0; q < MF_R; ++q) acc[q] = 0.0;
+#pragma unroll 4
+  for (int j = lane; j < jmax; j += 64) {
+    const double fj = f[j];
+    double v[MF_R];
+#pragma unroll
+    for (int q = 0; q < MF_R; ++q) v[q] = rowp[q][j];   // j < jmax <= S: inside the row
+#pragma unroll
+    for (int q = 0; q < MF_R; ++q)
+      if (j < jend[q]) acc[q] += v[q] * fj;
+  }
+  double mine = 0.0;
+#pragma unroll
+  for (int q = 0; q < MF_R; ++q) {
+    const double r = wave_sum(acc[q]);
+    if (lane == q) mine = r;
+  }
+  const int i = i0 + lane;
+  if (lane < MF_R && i < rows) out[i] = i < S ? mine : f[i] - mine;
 }
 
-// x_s = X^T y - G^T x_b: one wavefront per separator row of MT
+// x_s = X^T y - G^T x_b: separator rows j0 .. j0+MF_R-1 of MT on one wavefront
 __global__ void __launch_bounds__(256) k_mf_bwd(int tb, int bs, double* __restrict__ x,
                                                 const int* __restrict__ soff,
                                                 const int* __restrict__ sperm,
@@ -726,18 +760,53 @@ __global__ void __launch_bounds__(256) k_mf_bwd(int tb, int bs, double* __restri
                                                 const int64_t* __restrict__ vo,
                                                 const double* __restrict__ MT,
                                                 const double* __restrict__ fv) {
+  __shared__ double xbs[MF_XB];
   const int t = tb + blockIdx.y, lane = threadIdx.x & 63;
   const int s = fs[t], S = fS[t], b = fb[t];
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= s) return;
+  if (int(blockIdx.x) * 4 * MF_R >= s) return;     // whole workgroup past the separator
+  // the front's boundary values x_b, gathered once per workgroup (all its waves share them)
+  const bool staged = b <= MF_XB;
+  if (staged)
+    for (int m = threadIdx.x; m < b; m += 256) xbs[m] = x[mf_bnd_dof(t, m, bs, bnd_off, bnd)];
+  __syncthreads();
+  const int j0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * MF_R;
+  if (j0 >= s) return;
   const int64_t Fp = int64_t(fT[t]) * 64;
-  const double* row = MT + mo[t] + int64_t(j) * Fp;
   const double* y = fv + vo[t];
-  double acc = 0.0;
-  for (int i = (j / 64) * 64 + lane; i < S; i += 64) acc += row[i] * y[i];
-  for (int m = lane; m < b; m += 64) acc -= row[S + m] * x[mf_bnd_dof(t, m, bs, bnd_off, bnd)];
-  acc = wave_sum(acc);
-  if (lane == 0) x[mf_sep_dof(t, j, bs, soff, sperm)] = acc;
+  const double* rowp[MF_R];
+#pragma unroll
+  for (int q = 0; q < MF_R; ++q) rowp[q] = MT + mo[t] + int64_t(min(j0 + q, s - 1)) * Fp;
+  double acc[MF_R];
+#pragma unroll
+  for (int q = 0; q < MF_R; ++q) acc[q] = 0.0;
+  // rows j0 .. j0+MF_R-1 share their 64-block, so the same columns start the sum
+#pragma unroll 4
+  for (int i = (j0 / 64) * 64 + lane; i < S; i += 64) {
+    const double yi = y[i];
+    double v[MF_R];
+#pragma unroll
+    for (int q = 0; q < MF_R; ++q) v[q] = rowp[q][i];
+#pragma unroll
+    for (int q = 0; q < MF_R; ++q)
+      if (j0 + q < s) acc[q] += v[q] * yi;
+  }
+#pragma unroll 4
+  for (int m = lane; m < b; m += 64) {
+    const double xb = staged ? xbs[m] : x[mf_bnd_dof(t, m, bs, bnd_off, bnd)];
+    double v[MF_R];
+#pragma unroll
+    for (int q = 0; q < MF_R; ++q) v[q] = rowp[q][S + m];
+#pragma unroll
+    for (int q = 0; q < MF_R; ++q)
+      if (j0 + q < s) acc[q] -= v[q] * xb;
+  }
+  double mine = 0.0;
+#pragma unroll
+  for (int q = 0; q < MF_R; ++q) {
+    const double r = wave_sum(acc[q]);
+    if (lane == q) mine = r;
+  }
+  if (lane < MF_R && j0 + lane < s) x[mf_sep_dof(t, j0 + lane, bs, soff, sperm)] = mine;
 }
 
 // ---------------------------------------------------------------- host side
@@ -955,13 +1024,15 @@ void MFSolver::solve(Ctx& c, const double* r, double* x) const {
                        child0.p, child1.p, bnd_off.p, bnd_pos.p, fs.p, fS.p, fb.p, fT.p, vo.p,
                        fa.p, fv.p);
     if (d_rows[dd] > 0)
-      hipLaunchKernelGGL(k_mf_fwd, dim3((d_rows[dd] + 3) / 4, nt), dim3(256), 0, c.s, b0, fS.p,
+      hipLaunchKernelGGL(k_mf_fwd, dim3((d_rows[dd] + 4 * MF_R - 1) / (4 * MF_R), nt),
+                         dim3(256), 0, c.s, b0, fS.p,
                          fb.p, mo.p, vo.p, M.p, fa.p, fv.p);
   }
   for (int dd = 0; dd < ndepth; ++dd) {
     const int b0 = tree_off[dd], nt = tree_off[dd + 1] - b0;
     if (d_sep[dd] > 0)
-      hipLaunchKernelGGL(k_mf_bwd, dim3((d_sep[dd] + 3) / 4, nt), dim3(256), 0, c.s, b0, bs, x,
+      hipLaunchKernelGGL(k_mf_bwd, dim3((d_sep[dd] + 4 * MF_R - 1) / (4 * MF_R), nt),
+                         dim3(256), 0, c.s, b0, bs, x,
                          soff.p, sperm.p, bnd_off.p, bnd.p, fs.p, fS.p, fb.p, fT.p, mo.p, vo.p,
                          MT.p, fv.p);
   }

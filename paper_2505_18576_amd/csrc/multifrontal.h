@@ -11,7 +11,8 @@ struct MFSolver {
   std::vector<int> tree_off;          // supernodes of depth d: [tree_off[d], tree_off[d+1])
   std::vector<int> h_s, h_S, h_b, h_T;   // per supernode (host): separator DOFs, padded,
                                          // boundary DOFs, 64-row tiles of the front
-  std::vector<int> d_rows, d_sep;        // per depth: widest front rows / separator
+  std::vector<int> wl_fwd_off, wl_bwd_off;  // per depth: range of its solve work lists
+  DBuf<int> wl_fwd, wl_bwd;                 // (supernode, row block) pairs of the solve
   // device: ordering and symbolic structure
   DBuf<int> snode, sep_rank, soff, sperm;   // supernode of each node; members (ascending)
   DBuf<int> tdepth, child0, child1;

@@ -694,18 +694,22 @@ __global__ void __launch_bounds__(256) k_mf_rhs(int tb, int bs, const double* __
 // MF_R divides 64.
 constexpr int MF_R = 4;
 constexpr int MF_XB = 2048;   // boundary values a backward workgroup stages in LDS
+// The solve kernels run over per-depth work lists of (supernode, block of 4 MF_R rows)
+// pairs built at setup, so the grid holds exactly the workgroups the fronts of a depth
+// need (a grid sized by the depth's widest front was mostly idle workgroups).
 
 // [y; u] = [X; -G] fa_s + [0; fa_b]: rows i0 .. i0+MF_R-1 of M on one wavefront
-__global__ void __launch_bounds__(256) k_mf_fwd(int tb, const int* __restrict__ fS,
+__global__ void __launch_bounds__(256) k_mf_fwd(const int* __restrict__ wl,
+                                                const int* __restrict__ fS,
                                                 const int* __restrict__ fb,
                                                 const int64_t* __restrict__ mo,
                                                 const int64_t* __restrict__ vo,
                                                 const double* __restrict__ M,
                                                 const double* __restrict__ fa,
                                                 double* __restrict__ fv) {
-  const int t = tb + blockIdx.y, lane = threadIdx.x & 63;
+  const int t = wl[2 * blockIdx.x], blk = wl[2 * blockIdx.x + 1], lane = threadIdx.x & 63;
   const int S = fS[t], rows = S + fb[t];
-  const int i0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * MF_R;
+  const int i0 = (blk * 4 + (threadIdx.x >> 6)) * MF_R;
   if (i0 >= rows) return;
   const double* f = fa + vo[t];
   double* out = fv + vo[t];
@@ -747,7 +751,8 @@ __global__ void __launch_bounds__(256) k_mf_fwd(int tb, const int* __restrict__ 
 }
 
 // x_s = X^T y - G^T x_b: separator rows j0 .. j0+MF_R-1 of MT on one wavefront
-__global__ void __launch_bounds__(256) k_mf_bwd(int tb, int bs, double* __restrict__ x,
+__global__ void __launch_bounds__(256) k_mf_bwd(const int* __restrict__ wl, int bs,
+                                                double* __restrict__ x,
                                                 const int* __restrict__ soff,
                                                 const int* __restrict__ sperm,
                                                 const int* __restrict__ bnd_off,
@@ -761,15 +766,14 @@ __global__ void __launch_bounds__(256) k_mf_bwd(int tb, int bs, double* __restri
                                                 const double* __restrict__ MT,
                                                 const double* __restrict__ fv) {
   __shared__ double xbs[MF_XB];
-  const int t = tb + blockIdx.y, lane = threadIdx.x & 63;
+  const int t = wl[2 * blockIdx.x], blk = wl[2 * blockIdx.x + 1], lane = threadIdx.x & 63;
   const int s = fs[t], S = fS[t], b = fb[t];
-  if (int(blockIdx.x) * 4 * MF_R >= s) return;     // whole workgroup past the separator
   // the front's boundary values x_b, gathered once per workgroup (all its waves share them)
   const bool staged = b <= MF_XB;
   if (staged)
     for (int m = threadIdx.x; m < b; m += 256) xbs[m] = x[mf_bnd_dof(t, m, bs, bnd_off, bnd)];
   __syncthreads();
-  const int j0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * MF_R;
+  const int j0 = (blk * 4 + (threadIdx.x >> 6)) * MF_R;
   if (j0 >= s) return;
   const int64_t Fp = int64_t(fT[t]) * 64;
   const double* y = fv + vo[t];
@@ -1004,13 +1008,30 @@ void MFSolver::setup(Ctx& c, int n_, int bs_, const int* rp, const int* col,
     AMGF_LAUNCH_CHECK();
   }
   // per-depth launch extents of the solve
-  d_rows.assign(ndepth, 0);
-  d_sep.assign(ndepth, 0);
-  for (int dd = 0; dd < ndepth; ++dd)
-    for (int t = tree_off[dd]; t < tree_off[dd + 1]; ++t) {
-      d_rows[dd] = std::max(d_rows[dd], h_S[t] + h_b[t]);
-      d_sep[dd] = std::max(d_sep[dd], h_s[t]);
+  {
+    const int RB = 4 * MF_R;   // rows per workgroup
+    std::vector<int> wf, wb;
+    wl_fwd_off.assign(ndepth + 1, 0);
+    wl_bwd_off.assign(ndepth + 1, 0);
+    for (int dd = 0; dd < ndepth; ++dd) {
+      for (int t = tree_off[dd]; t < tree_off[dd + 1]; ++t) {
+        for (int k = 0; k < (h_S[t] + h_b[t] + RB - 1) / RB; ++k) {
+          wf.push_back(t);
+          wf.push_back(k);
+        }
+        for (int k = 0; k < (h_s[t] + RB - 1) / RB; ++k) {
+          wb.push_back(t);
+          wb.push_back(k);
+        }
+      }
+      wl_fwd_off[dd + 1] = int(wf.size() / 2);
+      wl_bwd_off[dd + 1] = int(wb.size() / 2);
     }
+    if (wf.empty()) wf.assign(2, 0);
+    if (wb.empty()) wb.assign(2, 0);
+    up(wl_fwd, wf);
+    up(wl_bwd, wb);
+  }
   const int fl = d2h_scalar(c.flag.p, c.s);
   AMGF_REQUIRE(!(fl & 4), AMGF_EDEVICE, "multifrontal: inconsistent symbolic structure");
   AMGF_REQUIRE(!(fl & 1), AMGF_ENOTSPD, "multifrontal: non-positive pivot");
@@ -1023,16 +1044,17 @@ void MFSolver::solve(Ctx& c, const double* r, double* x) const {
     hipLaunchKernelGGL(k_mf_rhs, dim3(nt), dim3(256), 0, c.s, b0, bs, r, soff.p, sperm.p,
                        child0.p, child1.p, bnd_off.p, bnd_pos.p, fs.p, fS.p, fb.p, fT.p, vo.p,
                        fa.p, fv.p);
-    if (d_rows[dd] > 0)
-      hipLaunchKernelGGL(k_mf_fwd, dim3((d_rows[dd] + 4 * MF_R - 1) / (4 * MF_R), nt),
-                         dim3(256), 0, c.s, b0, fS.p,
-                         fb.p, mo.p, vo.p, M.p, fa.p, fv.p);
+    const int nf = wl_fwd_off[dd + 1] - wl_fwd_off[dd];
+    if (nf > 0)
+      hipLaunchKernelGGL(k_mf_fwd, dim3(nf), dim3(256), 0, c.s,
+                         wl_fwd.p + 2 * int64_t(wl_fwd_off[dd]), fS.p, fb.p, mo.p, vo.p, M.p,
+                         fa.p, fv.p);
   }
   for (int dd = 0; dd < ndepth; ++dd) {
-    const int b0 = tree_off[dd], nt = tree_off[dd + 1] - b0;
-    if (d_sep[dd] > 0)
-      hipLaunchKernelGGL(k_mf_bwd, dim3((d_sep[dd] + 4 * MF_R - 1) / (4 * MF_R), nt),
-                         dim3(256), 0, c.s, b0, bs, x,
+    const int nb = wl_bwd_off[dd + 1] - wl_bwd_off[dd];
+    if (nb > 0)
+      hipLaunchKernelGGL(k_mf_bwd, dim3(nb), dim3(256), 0, c.s,
+                         wl_bwd.p + 2 * int64_t(wl_bwd_off[dd]), bs, x,
                          soff.p, sperm.p, bnd_off.p, bnd.p, fs.p, fS.p, fb.p, fT.p, mo.p, vo.p,
                          MT.p, fv.p);
   }

@@ -255,18 +255,23 @@ void group_by_key(Ctx& c, const int* keys, int n, int nkeys, DBuf<int>& offsets,
 // ======================================================================================
 // BSR transpose
 // ======================================================================================
+// One thread per value of the transpose: consecutive threads write consecutive values,
+// and the threads of one output block read the br*bc values of one source block, so both
+// sides coalesce (a thread per block read its source block one scattered value at a time).
 __global__ void k_transpose_fill(int64_t nnzb, const int* __restrict__ perm,
                                  const int* __restrict__ rows, const double* __restrict__ val,
                                  int br, int bc, int* __restrict__ tcol,
                                  double* __restrict__ tval) {
-  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= nnzb) return;
+  const int bs = br * bc;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nnzb * bs) return;
+  const int64_t k = e / bs;
+  const int w = int(e - k * bs);
   const int src = perm[k];
-  tcol[k] = rows[src];
-  const double* s = val + int64_t(src) * br * bc;
-  double* d = tval + k * br * bc;
-  for (int p = 0; p < br; ++p)
-    for (int q = 0; q < bc; ++q) d[q * br + p] = s[p * bc + q];
+  // value (q, p) of the bc x br transposed block is value (p, q) of the source block
+  const int q = w / br, p = w - q * br;
+  tval[e] = val[int64_t(src) * bs + p * bc + q];
+  if (w == 0) tcol[k] = rows[src];
 }
 
 void bsr_transpose(Ctx& c, const BSR& A, BSR& T) {
@@ -282,8 +287,9 @@ void bsr_transpose(Ctx& c, const BSR& A, BSR& T) {
   T.col.alloc(std::max<int64_t>(A.nnzb, 1));
   T.val.alloc(std::max<int64_t>(A.nnzb, 1) * A.bsz());
   if (A.nnzb)
-    hipLaunchKernelGGL(k_transpose_fill, dim3(grid_for(A.nnzb, 256)), dim3(256), 0, c.s,
-                       A.nnzb, perm.p, rows.p, A.val.p, A.br, A.bc, T.col.p, T.val.p);
+    hipLaunchKernelGGL(k_transpose_fill, dim3(grid_for(A.nnzb * int64_t(A.bsz()), 256)),
+                       dim3(256), 0, c.s, A.nnzb, perm.p, rows.p, A.val.p, A.br, A.bc,
+                       T.col.p, T.val.p);
   AMGF_LAUNCH_CHECK();
 }
 

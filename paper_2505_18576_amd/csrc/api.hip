@@ -972,12 +972,35 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
   bool conv = rz0 == 0.0;
   double rel = conv ? 0.0 : 1.0;
   amgf_status st = AMGF_OK;
-  // scalars stay on the device within an iteration (p.q feeds the x, r update directly);
-  // the host reads p.q, r.z and r.z_old once per iteration for the stopping rule and beta
+  // Scalars stay on the device within an iteration (p.q feeds the x, r update, r.z and
+  // r.z_old the direction update); the host reads p.q, r.z and r.z_old once per iteration
+  // for the stopping rule.  While it waits for them the stream already runs the next
+  // direction p = z + beta p, q = A p and p.q (beta formed on the device from the same
+  // doubles, so the iterates are those of the host-side update); after the last
+  // iteration that work is simply not used.
+  // The speculation is skipped when the residual history predicts convergence in this
+  // iteration (geometric extrapolation), so the last iteration rarely wastes the work.
   if (h.pcg_s.n == 0) h.pcg_s.alloc(4);
+  struct HostScalars {                                // pinned: the copy is truly async
+    double* p = nullptr;
+    hipEvent_t ev = nullptr;
+    ~HostScalars() {
+      if (ev) (void)hipEventDestroy(ev);
+      if (p) (void)hipHostFree(p);
+    }
+  } hs;
+  AMGF_HIP(hipHostMalloc(reinterpret_cast<void**>(&hs.p), 4 * sizeof(double)));
+  AMGF_HIP(hipEventCreateWithFlags(&hs.ev, hipEventDisableTiming));
+  double* s3 = hs.p;
+  hipEvent_t ev = hs.ev;
+  double rel_old = 1.0;                               // relative residual one step back
+  bool have_q = false;                                // q = A p, p.q already enqueued
+  bool need_p = false;                                // p = z + beta p still to be done
+  double beta = 0.0;
   while (!conv && it < h.opt.max_iters) {
-    operator_apply(h, h.pp.p, h.pq.p, nullptr);       // q = A p
-    {
+    if (!have_q) {
+      if (need_p) pcg_update_p(c, n, beta, h.pz.p, h.pp.p);
+      operator_apply(h, h.pp.p, h.pq.p, nullptr);     // q = A p
       const double* xs[1] = {h.pp.p};
       const double* ys[1] = {h.pq.p};
       dots_device(c, n, 1, xs, ys, h.pcg_s.p);
@@ -990,19 +1013,29 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
       const double* ys[2] = {h.pz.p, h.pzo.p};
       dots_device(c, n, 2, xs, ys, h.pcg_s.p + 1);
     }
-    double s3[3];
     AMGF_HIP(hipMemcpyAsync(s3, h.pcg_s.p, 3 * sizeof(double), hipMemcpyDeviceToHost, c.s));
-    AMGF_HIP(hipStreamSynchronize(c.s));
+    AMGF_HIP(hipEventRecord(ev, c.s));
+    have_q = it + 1 < h.opt.max_iters && rel * (rel / rel_old) > h.opt.rtol;
+    if (have_q) {
+      pcg_update_p_dev(c, n, rz, h.pcg_s.p + 1, h.pz.p, h.pp.p);
+      operator_apply(h, h.pp.p, h.pq.p, nullptr);
+      const double* xs[1] = {h.pp.p};
+      const double* ys[1] = {h.pq.p};
+      dots_device(c, n, 1, xs, ys, h.pcg_s.p);
+    }
+    AMGF_HIP(hipEventSynchronize(ev));
     if (!(s3[0] > 0.0)) { st = AMGF_ENOTSPD; break; }  // p.q <= 0: not SPD
     d2[0] = s3[1];
     d2[1] = s3[2];
     ++it;
+    const double rel_prev = rel;
     rel = std::sqrt(std::fabs(d2[0]) / rz0);
     if (!std::isfinite(rel)) { st = AMGF_ENOTSPD; break; }
     if (rel <= h.opt.rtol) { conv = true; break; }
-    const double beta = (d2[0] - d2[1]) / rz;
-    pcg_update_p(c, n, beta, h.pz.p, h.pp.p);
+    need_p = !have_q;
+    if (need_p) beta = (d2[0] - d2[1]) / rz;
     rz = d2[0];
+    rel_old = rel_prev;
   }
   AMGF_HIP(hipEventRecord(e1, c.s));
   AMGF_HIP(hipEventSynchronize(e1));

@@ -89,6 +89,9 @@ void pcg_update_xr(Ctx& c, int64_t n, double alpha, const double* p, const doubl
 void pcg_update_xr_dev(Ctx& c, int64_t n, double rz, const double* pq, const double* p,
                        const double* q, double* x, double* r);
 void pcg_update_p(Ctx& c, int64_t n, double beta, const double* z, double* p);
+// p = z + beta p with beta = (s[0] - s[1]) / rz, s = {r.z, r.z_old} in device memory
+void pcg_update_p_dev(Ctx& c, int64_t n, double rz, const double* s, const double* z,
+                      double* p);
 
 // input validation: flag bit 1 non-finite, bit 2 non-positive
 void check_values(Ctx& c, const double* v, int64_t n, bool require_positive, int* flag);

@@ -386,6 +386,11 @@ AMGF_ELEMWISE(k_xr_dev, (int64_t n, double rz, const double* __restrict__ pq,
               r[i] -= al * q[i])
 AMGF_ELEMWISE(k_pupd, (int64_t n, double be, const double* __restrict__ z, double* __restrict__ p),
               p[i] = z[i] + be * p[i])
+// beta = (r.z - r.z_old) / rz with both dots read from device memory, then p = z + beta p
+AMGF_ELEMWISE(k_pupd_dev, (int64_t n, double rz, const double* __restrict__ s,
+                           const double* __restrict__ z, double* __restrict__ p),
+              const double be = (s[0] - s[1]) / rz;
+              p[i] = z[i] + be * p[i])
 AMGF_ELEMWISE(k_power_start, (int64_t n, double* __restrict__ x,
                               const unsigned char* __restrict__ dec),
               x[i] = (dec && dec[i]) ? 0.0
@@ -507,6 +512,10 @@ void pcg_update_xr_dev(Ctx& c, int64_t n, double rz, const double* pq, const dou
 }
 void pcg_update_p(Ctx& c, int64_t n, double beta, const double* z, double* p) {
   if (n) hipLaunchKernelGGL(k_pupd, AMGF_L1D(n), n, beta, z, p);
+}
+void pcg_update_p_dev(Ctx& c, int64_t n, double rz, const double* s, const double* z,
+                      double* p) {
+  if (n) hipLaunchKernelGGL(k_pupd_dev, AMGF_L1D(n), n, rz, s, z, p);
 }
 void check_values(Ctx& c, const double* v, int64_t n, bool require_positive, int* flag) {
   if (n) hipLaunchKernelGGL(k_check, AMGF_L1D(n), v, n, int(require_positive), flag);

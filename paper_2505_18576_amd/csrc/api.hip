@@ -722,8 +722,16 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
     scatter_add(c, h.f_w.p, h.Ic.p, h.n_c, h.z1.p);   // z2 = z1 + P w
   }
   if (h.mixed()) {
-    cast_d2f(c, h.z1.p, h.zf.p, n);
-    bsr_spmv<float>(c, SPMV_RES, L0.K, L0.K.val32.p, h.zf.p, h.r2f.p, L0.fb.p, nullptr, nullptr);
+    // float(z2): the plain FP32 V-cycle leaves z1 in L0.fx and z1 = double(L0.fx) exactly,
+    // so only the filter DOFs, where the correction was added, need a new rounding
+    const float* z2f = L0.fx.p;
+    if (!h.plain_cycle()) {
+      cast_d2f(c, h.z1.p, h.zf.p, n);
+      z2f = h.zf.p;
+    } else if (h.n_c > 0) {
+      cast_d2f_at(c, h.z1.p, h.Ic.p, h.n_c, L0.fx.p);
+    }
+    bsr_spmv<float>(c, SPMV_RES, L0.K, L0.K.val32.p, z2f, h.r2f.p, L0.fb.p, nullptr, nullptr);
     contact_apply<double, float>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
                                  h.z1.p, h.t.p, h.r2f.p, nullptr);     // r2 = r - A z2
     std::swap(L0.fb, h.r2f);

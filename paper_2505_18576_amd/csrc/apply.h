@@ -69,6 +69,7 @@ void add_f32(Ctx& c, int64_t n, const double* a, const float* f, double* z);  //
 void axpby(Ctx& c, int64_t n, double alpha, const double* x, double beta, double* y);  // y = a x + b y
 void gather(Ctx& c, const double* x, const int* idx, int n, double* y);               // y = x[idx]
 void scatter_add(Ctx& c, const double* w, const int* idx, int n, double* y);          // y[idx] += w
+void cast_d2f_at(Ctx& c, const double* x, const int* idx, int n, float* y);  // y[idx] = float(x[idx])
 void scale_div_zero(Ctx& c, int64_t n, double* y, const double* d, const unsigned char* dec);
 void fill_power_start(Ctx& c, int64_t n, double* x, const unsigned char* dec);
 void weights_from_l1(Ctx& c, int64_t n, const double* d, const double* theta, double* w);

@@ -406,6 +406,11 @@ __global__ void k_scatter_add(const double* __restrict__ w, const int* __restric
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[idx[i]] += w[i];
 }
+__global__ void k_d2f_at(const double* __restrict__ x, const int* __restrict__ idx, int n,
+                         float* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[idx[i]] = float(x[idx[i]]);
+}
 __global__ void k_check(const double* __restrict__ v, int64_t n, int pos, int* flag) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -492,6 +497,9 @@ void gather(Ctx& c, const double* x, const int* idx, int n, double* y) {
 }
 void scatter_add(Ctx& c, const double* w, const int* idx, int n, double* y) {
   if (n) hipLaunchKernelGGL(k_scatter_add, AMGF_L1D(n), w, idx, n, y);
+}
+void cast_d2f_at(Ctx& c, const double* x, const int* idx, int n, float* y) {
+  if (n) hipLaunchKernelGGL(k_d2f_at, AMGF_L1D(n), x, idx, n, y);
 }
 void scale_div_zero(Ctx& c, int64_t n, double* y, const double* d, const unsigned char* dec) {
   if (n) hipLaunchKernelGGL(k_scale_div, AMGF_L1D(n), n, y, d, dec);

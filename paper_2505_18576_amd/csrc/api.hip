@@ -75,6 +75,7 @@ struct Handle {
   DBuf<float> zf, r2f;
   DBuf<int> ic_nodes;           // node rows holding filter DOFs
   int n_icn = 0;
+  bool ic_from_J = false;       // I_c = all DOFs of the nodes J touches (not a caller's list)
   bool ic_closed = false;
   // pcg scratch
   DBuf<double> pr, pz, pzo, pp, pq;
@@ -334,6 +335,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     h.n_c = n_c_user;
   } else {
     h.n_c = filter_space_from_J(c, L0->J, nn, h.Ic);
+    h.ic_from_J = true;
   }
   if (h.n_c > 0) {
     std::vector<int> ic = d2h(h.Ic.p, h.n_c, c.s);
@@ -712,6 +714,32 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
     return;
   }
   Level& L0 = *h.lev[0];
+  if (h.mixed() && h.plain_cycle() && h.ic_from_J) {
+    // FP32 V-cycles: z1 = B r stays in FP32 (L0.fx, widened exactly wherever FP64 reads
+    // it); the FP64 z2 = z1 + P w is formed on the filter DOFs only (h.z1 there), which
+    // cover every DOF the contact term reads when I_c comes from J
+    cast_d2f_w(c, r, L0.w32.p, L0.fb.p, L0.fx.p, n);
+    vcycle32_from(h, 0, true);                        // z1 = B r  (L0.fx)
+    if (h.n_c > 0) {
+      bsr_res_rows<float>(c, L0.K, h.ic_nodes.p, h.n_icn, L0.fx.p, r, h.ra.p);
+      contact_apply<float, double>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
+                                   L0.fx.p, h.t.p, h.ra.p, nullptr);   // ra = r - A z1 on I_c
+      gather(c, h.ra.p, h.Ic.p, h.n_c, h.f_r.p);      // P^T ra
+      filter_solve(h, h.f_r.p, h.f_w.p);              // w = A_w^{-1} P^T ra
+      correct_at(c, L0.fx.p, h.f_w.p, h.Ic.p, h.n_c, h.z1.p);   // z2 on I_c; L0.fx = float(z2)
+    }
+    bsr_spmv<float>(c, SPMV_RES, L0.K, L0.K.val32.p, L0.fx.p, h.r2f.p, L0.fb.p, nullptr,
+                    nullptr);
+    contact_apply<double, float>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
+                                 h.z1.p, h.t.p, h.r2f.p, nullptr);     // r2 = r - A z2
+    std::swap(L0.fx, h.zf);                           // keep z1 (float(z2) on I_c)
+    std::swap(L0.fb, h.r2f);
+    vcycle32(h, 0);                                   // B r2  (L0.fx)
+    std::swap(L0.fb, h.r2f);
+    add_ff(c, n, h.zf.p, L0.fx.p, z);                 // z = z2 + B r2 ...
+    add_at(c, h.z1.p, L0.fx.p, h.Ic.p, h.n_c, z);     // ... with the FP64 z2 on I_c
+    return;
+  }
   vcycle(h, r, h.z1.p);                               // z1 = B r
   if (h.n_c > 0) {
     bsr_res_rows(c, L0.K, h.ic_nodes.p, h.n_icn, h.z1.p, r, h.ra.p);
@@ -722,16 +750,8 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
     scatter_add(c, h.f_w.p, h.Ic.p, h.n_c, h.z1.p);   // z2 = z1 + P w
   }
   if (h.mixed()) {
-    // float(z2): the plain FP32 V-cycle leaves z1 in L0.fx and z1 = double(L0.fx) exactly,
-    // so only the filter DOFs, where the correction was added, need a new rounding
-    const float* z2f = L0.fx.p;
-    if (!h.plain_cycle()) {
-      cast_d2f(c, h.z1.p, h.zf.p, n);
-      z2f = h.zf.p;
-    } else if (h.n_c > 0) {
-      cast_d2f_at(c, h.z1.p, h.Ic.p, h.n_c, L0.fx.p);
-    }
-    bsr_spmv<float>(c, SPMV_RES, L0.K, L0.K.val32.p, z2f, h.r2f.p, L0.fb.p, nullptr, nullptr);
+    cast_d2f(c, h.z1.p, h.zf.p, n);
+    bsr_spmv<float>(c, SPMV_RES, L0.K, L0.K.val32.p, h.zf.p, h.r2f.p, L0.fb.p, nullptr, nullptr);
     contact_apply<double, float>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
                                  h.z1.p, h.t.p, h.r2f.p, nullptr);     // r2 = r - A z2
     std::swap(L0.fb, h.r2f);

@@ -46,7 +46,8 @@ void contact_cmat(Ctx& c, int mode, const BSR& C, const int* rows, int nrows, co
 // indices of the nonempty rows of a CSR pattern
 int nonempty_rows(Ctx& c, const int* rp, int n, DBuf<int>& rows);
 // y = b - A x on the listed block rows only (FP64, 3x3 blocks)
-void bsr_res_rows(Ctx& c, const BSR& A, const int* rows, int nlist, const double* x,
+template <class TX>
+void bsr_res_rows(Ctx& c, const BSR& A, const int* rows, int nlist, const TX* x,
                   const double* b, double* y);
 
 // Chebyshev smoother steps: start r = w.src, d = r/theta, x = d or x + d;
@@ -69,7 +70,11 @@ void add_f32(Ctx& c, int64_t n, const double* a, const float* f, double* z);  //
 void axpby(Ctx& c, int64_t n, double alpha, const double* x, double beta, double* y);  // y = a x + b y
 void gather(Ctx& c, const double* x, const int* idx, int n, double* y);               // y = x[idx]
 void scatter_add(Ctx& c, const double* w, const int* idx, int n, double* y);          // y[idx] += w
-void cast_d2f_at(Ctx& c, const double* x, const int* idx, int n, float* y);  // y[idx] = float(x[idx])
+// on the n DOFs idx[i]: z = double(f) + w[i], then f = float(z)   (the filter correction)
+void correct_at(Ctx& c, float* f, const double* w, const int* idx, int n, double* z);
+void add_ff(Ctx& c, int64_t n, const float* a, const float* b, double* z);  // z = a + b
+// z[idx] = u[idx] + b[idx] on the n listed DOFs
+void add_at(Ctx& c, const double* u, const float* b, const int* idx, int n, double* z);
 void scale_div_zero(Ctx& c, int64_t n, double* y, const double* d, const unsigned char* dec);
 void fill_power_start(Ctx& c, int64_t n, double* x, const unsigned char* dec);
 void weights_from_l1(Ctx& c, int64_t n, const double* d, const double* theta, double* w);

@@ -58,12 +58,14 @@ __global__ void __launch_bounds__(256) k_bsr(int nrows, const int* __restrict__ 
   }
 }
 
-// y[i] = b[i] - (A x)[i] on the listed block rows only (FP64, 3x3 blocks)
+// y[i] = b[i] - (A x)[i] on the listed block rows only (FP64 arithmetic, 3x3 blocks; x
+// FP64 or FP32, widened exactly)
+template <class TX>
 __global__ void __launch_bounds__(256) k_bsr_res_rows(int nlist, const int* __restrict__ rows,
                                                       const int* __restrict__ rp,
                                                       const int* __restrict__ col,
                                                       const double* __restrict__ val,
-                                                      const double* __restrict__ x,
+                                                      const TX* __restrict__ x,
                                                       const double* __restrict__ b,
                                                       double* __restrict__ y) {
   constexpr int G = 8;
@@ -78,7 +80,7 @@ __global__ void __launch_bounds__(256) k_bsr_res_rows(int nlist, const int* __re
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) acc[p] += v[p * 3 + q] * x[int64_t(cc) * 3 + q];
+      for (int q = 0; q < 3; ++q) acc[p] += v[p * 3 + q] * double(x[int64_t(cc) * 3 + q]);
   }
 #pragma unroll
   for (int p = 0; p < 3; ++p) acc[p] = group_sum(acc[p], G);
@@ -88,13 +90,18 @@ __global__ void __launch_bounds__(256) k_bsr_res_rows(int nlist, const int* __re
   y[i] = b[i] - ax;
 }
 
-void bsr_res_rows(Ctx& c, const BSR& A, const int* rows, int nlist, const double* x,
+template <class TX>
+void bsr_res_rows(Ctx& c, const BSR& A, const int* rows, int nlist, const TX* x,
                   const double* b, double* y) {
   if (nlist == 0) return;
-  hipLaunchKernelGGL(k_bsr_res_rows, dim3(grid_for(int64_t(nlist) * 8, 256)), dim3(256), 0, c.s,
-                     nlist, rows, A.rowptr.p, A.col.p, A.val.p, x, b, y);
+  hipLaunchKernelGGL(k_bsr_res_rows<TX>, dim3(grid_for(int64_t(nlist) * 8, 256)), dim3(256), 0,
+                     c.s, nlist, rows, A.rowptr.p, A.col.p, A.val.p, x, b, y);
   AMGF_LAUNCH_CHECK();
 }
+template void bsr_res_rows<double>(Ctx&, const BSR&, const int*, int, const double*,
+                                   const double*, double*);
+template void bsr_res_rows<float>(Ctx&, const BSR&, const int*, int, const float*,
+                                  const double*, double*);
 
 template <int BR, int BC, int G, class T>
 static void launch_bsr(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y,
@@ -241,6 +248,9 @@ template void contact_apply<float, float>(Ctx&, int, const BSR&, const BSR&, con
 template void contact_apply<double, float>(Ctx&, int, const BSR&, const BSR&, const int*, int,
                                            const double*, const double*, double*, float*,
                                            const float*);
+template void contact_apply<float, double>(Ctx&, int, const BSR&, const BSR&, const int*, int,
+                                           const double*, const float*, double*, double*,
+                                           const double*);
 
 // Coarse-level contact term from its assembled block C = J^T D J (FP64 BSR, B x B
 // blocks): one wavefront per listed row, lanes over the row's blocks, then y (op)= C x.
@@ -406,10 +416,26 @@ __global__ void k_scatter_add(const double* __restrict__ w, const int* __restric
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[idx[i]] += w[i];
 }
-__global__ void k_d2f_at(const double* __restrict__ x, const int* __restrict__ idx, int n,
-                         float* __restrict__ y) {
+// on the listed DOFs: z[k] = double(f[k]) + w[i], then f[k] = float(z[k])
+__global__ void k_corr_at(float* f, const double* __restrict__ w, const int* __restrict__ idx,
+                          int n, double* __restrict__ z) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[idx[i]] = float(x[idx[i]]);
+  if (i >= n) return;
+  const int64_t k = idx[i];
+  const double v = double(f[k]) + w[i];
+  z[k] = v;
+  f[k] = float(v);
+}
+// z = double(a) + double(b), and z[k] = u[k] + double(b[k]) on the listed DOFs
+AMGF_ELEMWISE(k_add_ff, (int64_t n, const float* __restrict__ a, const float* __restrict__ b,
+                         double* __restrict__ z),
+              z[i] = double(a[i]) + double(b[i]))
+__global__ void k_add_at(const double* __restrict__ u, const float* __restrict__ b,
+                         const int* __restrict__ idx, int n, double* __restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t k = idx[i];
+  z[k] = u[k] + double(b[k]);
 }
 __global__ void k_check(const double* __restrict__ v, int64_t n, int pos, int* flag) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -498,8 +524,14 @@ void gather(Ctx& c, const double* x, const int* idx, int n, double* y) {
 void scatter_add(Ctx& c, const double* w, const int* idx, int n, double* y) {
   if (n) hipLaunchKernelGGL(k_scatter_add, AMGF_L1D(n), w, idx, n, y);
 }
-void cast_d2f_at(Ctx& c, const double* x, const int* idx, int n, float* y) {
-  if (n) hipLaunchKernelGGL(k_d2f_at, AMGF_L1D(n), x, idx, n, y);
+void correct_at(Ctx& c, float* f, const double* w, const int* idx, int n, double* z) {
+  if (n) hipLaunchKernelGGL(k_corr_at, AMGF_L1D(n), f, w, idx, n, z);
+}
+void add_ff(Ctx& c, int64_t n, const float* a, const float* b, double* z) {
+  if (n) hipLaunchKernelGGL(k_add_ff, AMGF_L1D(n), n, a, b, z);
+}
+void add_at(Ctx& c, const double* u, const float* b, const int* idx, int n, double* z) {
+  if (n) hipLaunchKernelGGL(k_add_at, AMGF_L1D(n), u, b, idx, n, z);
 }
 void scale_div_zero(Ctx& c, int64_t n, double* y, const double* d, const unsigned char* dec) {
   if (n) hipLaunchKernelGGL(k_scale_div, AMGF_L1D(n), n, y, d, dec);

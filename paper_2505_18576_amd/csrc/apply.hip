@@ -158,7 +158,11 @@ template void bsr_spmv<float>(Ctx&, int, const BSR&, const float*, const float*,
 // ======================================================================================
 // contact term  J^T D J x  (always FP64)
 // ======================================================================================
-// t_k = D_k (J x)_k: one wavefront per constraint row, lanes over the row's blocks.
+// Level-0 contact rows are short (a constraint touches about five nodes, a node a few
+// constraints): CT_G lanes per row, eight rows per wavefront.
+constexpr int CT_G = 8;
+
+// t_k = D_k (J x)_k: CT_G lanes per constraint row, over the row's blocks.
 template <int B, class TX>
 __global__ void __launch_bounds__(256) k_contact_t(int m, const int* __restrict__ rp,
                                                    const int* __restrict__ col,
@@ -166,20 +170,20 @@ __global__ void __launch_bounds__(256) k_contact_t(int m, const int* __restrict_
                                                    const double* __restrict__ D,
                                                    const TX* __restrict__ x,
                                                    double* __restrict__ t) {
-  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = gid / CT_G, lane = gid % CT_G;
   if (k >= m) return;
   double s = 0.0;
-  for (int u = rp[k] + lane; u < rp[k + 1]; u += 64) {
+  for (int u = rp[k] + lane; u < rp[k + 1]; u += CT_G) {
     const int64_t base = int64_t(col[u]) * B;
 #pragma unroll
     for (int q = 0; q < B; ++q) s += val[int64_t(u) * B + q] * double(x[base + q]);
   }
-  s = wave_sum(s);
+  s = group_sum(s, CT_G);
   if (lane == 0) t[k] = D[k] * s;
 }
 
-// y_a (op)= (J^T t)_a over the listed node rows: one wavefront per row.
+// y_a (op)= (J^T t)_a over the listed node rows: CT_G lanes per row.
 template <int B, class TY, int MODE>
 __global__ void __launch_bounds__(256) k_contact_y(int nrows, const int* __restrict__ rows,
                                                    const int* __restrict__ rp,
@@ -188,20 +192,21 @@ __global__ void __launch_bounds__(256) k_contact_y(int nrows, const int* __restr
                                                    const double* __restrict__ t,
                                                    TY* __restrict__ y,
                                                    const TY* __restrict__ w) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
+  static_assert(B <= CT_G, "one lane per output component");
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / CT_G, lane = gid % CT_G;
   if (i >= nrows) return;
   const int a = rows[i];
   double acc[B];
 #pragma unroll
   for (int p = 0; p < B; ++p) acc[p] = 0.0;
-  for (int k = rp[a] + lane; k < rp[a + 1]; k += 64) {
+  for (int k = rp[a] + lane; k < rp[a + 1]; k += CT_G) {
     const double tk = t[col[k]];
 #pragma unroll
     for (int p = 0; p < B; ++p) acc[p] += val[int64_t(k) * B + p] * tk;
   }
 #pragma unroll
-  for (int p = 0; p < B; ++p) acc[p] = wave_sum(acc[p]);
+  for (int p = 0; p < B; ++p) acc[p] = group_sum(acc[p], CT_G);
   if (lane >= B) return;
   double v = 0.0;
 #pragma unroll
@@ -218,7 +223,8 @@ void contact_apply(Ctx& c, int mode, const BSR& J, const BSR& JT, const int* cro
                    const double* D, const TX* x, double* t, TY* y, const TY* w) {
   if (J.nrows == 0 || J.nnzb == 0 || ncrows == 0) return;
   const int m = J.nrows;
-  const dim3 gm(grid_for(m, 4)), gn(grid_for(ncrows, 4)), blk(256);
+  const dim3 gm(grid_for(int64_t(m) * CT_G, 256)), gn(grid_for(int64_t(ncrows) * CT_G, 256)),
+      blk(256);
 #define AMGF_CT(BB)                                                                          \
   hipLaunchKernelGGL((k_contact_t<BB, TX>), gm, blk, 0, c.s, m, J.rowptr.p, J.col.p,        \
                      J.val.p, D, x, t);                                                      \

@@ -724,7 +724,20 @@ class OracleAMGF:
         return len(self.levels)
 
     def A_apply(self, x):
-        return self.S.csr() @ x
+        """y = A x for A = K + J^T D J (Sec. 3, the condensed system), evaluated as the
+        product the formula writes: K x, plus J^T applied to D times the gaps J x.
+
+        Reading: this is the operator of the CG iteration and of the two residuals inside
+        Definition 5.3.  The assembled S (``schur_operator``) rounds every entry
+        D_k J_ki J_kj on its own, a perturbation of size u D_max in the contact rows that
+        is not confined to the range of J^T; with D up to 1e10 it moves the solution of
+        S x = b by about 6e-6 from that of A x = b.  Here each rounding error of the contact
+        term stays in the range of J^T (where A is as stiff as D) and the converged CG
+        iterate agrees with an extended-precision solve of A x = b to about rtol.  S keeps
+        serving what needs the matrix entries: strength, aggregation, l1 norms,
+        smoothing, coarse operators and A_w."""
+        J = self.J0.csr()
+        return self.K0.csr() @ x + J.T @ (self.D * (J @ x))
 
     def smooth(self, l, b, x):
         """One smoother application on level l for A x = b (O10).

@@ -90,3 +90,74 @@ def test_loss_is_error_reduction(setup):
     assert abs(L - np.mean(vals)) <= 1e-10 * abs(L)
     assert L < 0
     learned.reset_damping(o)
+
+
+def test_features_match_explicit_loops_over_dense_operators():
+    """Each of the six features, recomputed with plain loops over the dense level operator
+    A_l, the dense coarse Jacobian J_l and D (a Sigma D J instead of Sigma D J^2, a swapped
+    feature or a wrong level fraction fails here)."""
+    import math
+    p = small_problem(N=2, D_log10=(0.0, 4.0), seed=17)
+    o = build(p, coarse_max_nodes=2, max_levels=3)
+    L = o.nlev
+    assert L == 3
+    feats = learned.level_features(o)
+    assert len(feats) == L - 1
+    Ic = set(int(i) for i in o.Ic)
+    for l, F in enumerate(feats):
+        lev = o.levels[l]
+        A = lev.A.todense()
+        J = lev.J.todense()
+        b = lev.A.br
+        n_l = A.shape[0]
+        assert F.shape == (6, n_l) and J.shape == (p.m, n_l)
+        for i in range(n_l):
+            aii = A[i, i]
+            d = 0.0
+            for j in range(n_l):
+                d += abs(A[i, j])
+            beta = 0.0
+            for k in range(p.m):
+                beta += p.D[k] * J[k, i] * J[k, i]
+            node = i // b
+            touched = any(J[k, node * b + c] != 0.0 for k in range(p.m) for c in range(b))
+            want = [math.log10(aii), math.log10(d), aii / d, math.log10(1.0 + beta),
+                    1.0 if touched else 0.0, l / (L - 1)]
+            for f in range(6):
+                assert abs(F[f, i] - want[f]) <= 1e-12 * max(1.0, abs(want[f])), (l, i, f)
+            if l == 0:
+                # at level 0 the contact flag is exactly membership of the filter space
+                assert F[4, i] == (1.0 if i in Ic else 0.0)
+        assert F[4].sum() > 0 and (l > 0 or F[4].sum() < n_l)
+
+
+def test_mlp_forward_matches_rowwise_evaluation_of_the_header_layout():
+    """theta row by row from the flat parameter layout W1[32][6] b1[32] W2[32][32] b2[32]
+    W3[32] b3 mu[6] sigma[6] (a transposed W1 or W2 or a swapped bias block fails)."""
+    import math
+    rng = np.random.default_rng(23)
+    W = rng.uniform(-0.8, 0.8, 1325)
+    W[1313:1319] = rng.uniform(-1, 1, 6)
+    W[1319:1325] = rng.uniform(0.5, 2.0, 6)
+    F = rng.standard_normal((6, 9)) * 2.0
+    theta, _ = learned.mlp_forward(W, F)
+    for i in range(F.shape[1]):
+        fh = [(F[j, i] - W[1313 + j]) / W[1319 + j] for j in range(6)]
+        h1 = []
+        for a in range(32):
+            s = W[192 + a]
+            for j in range(6):
+                s += W[a * 6 + j] * fh[j]
+            h1.append(math.tanh(s))
+        h2 = []
+        for c in range(32):
+            s = W[1248 + c]
+            for a in range(32):
+                s += W[224 + c * 32 + a] * h1[a]
+            h2.append(math.tanh(s))
+        y = W[1312]
+        for c in range(32):
+            y += W[1280 + c] * h2[c]
+        want = 1.0 + 0.98 * math.tanh(y)
+        assert abs(theta[i] - want) <= 1e-13, (i, theta[i], want)
+    assert np.all((theta > 0.02) & (theta < 1.98))

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from amgf_inputs import make_config, make_two_block
-from oracle_util import build
+from oracle_util import build, extended_solution
 
 
 def test_c1_amgf_pcg_converges_and_solves():
@@ -50,3 +50,23 @@ def test_iteration_bound_and_mesh_independence():
         assert r.iterations <= bound, (N, r.iterations, bound)
         its.append(r.iterations)
     assert its[-1] <= 2.5 * its[0]
+
+
+def test_pcg_iterates_converge_to_the_solution_of_the_schur_system():
+    """C1 (kappa about 6e11, D up to 1e8): the rtol-1e-10 iterate is within 1e-9 of the
+    solution of A x = b and the rtol-1e-13 iterate within 1e-12, measured against an
+    extended-precision solve that shares nothing with the oracle's operator apply.  A CG
+    operator that rounded the assembled entries of J^T D J would be stuck near 1e-8 here."""
+    p = make_config("C1")
+    o = build(p)
+    xs = extended_solution(p)
+    r10, r13 = o.pcg(p.b), o.pcg(p.b, rtol=1e-13)
+    e10 = np.linalg.norm(r10.x - xs) / np.linalg.norm(xs)
+    e13 = np.linalg.norm(r13.x - xs) / np.linalg.norm(xs)
+    assert r10.converged and r13.converged
+    assert e10 <= 1e-9 and e13 <= 1e-12, (e10, e13)
+    # the same solve through the assembled operator S stalls at its entry rounding
+    from oracle.amgf_oracle import pcg
+    Sc = o.S.csr()
+    rS = pcg(lambda v: Sc @ v, o.apply, p.b, rtol=1e-13)
+    assert np.linalg.norm(rS.x - xs) / np.linalg.norm(xs) > 100 * e13

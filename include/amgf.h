@@ -101,6 +101,13 @@ typedef struct {
                                  each aggregate's centroid; needs coords), 3: the three
                                  translations only (coords may be NULL); coarse levels
                                  then carry 3 DOFs per node (default 6)                  */
+  int32_t learned_judge;      /* with AMGF_LEARNED: 1 (default) keeps the MLP damping only
+                                 where it reduces the error at least as well as theta = 1:
+                                 at every setup and update of D, one AMGF step
+                                 e1 = (I - M A) e0 from a fixed start e0 (the power-
+                                 iteration start vector, zero on decoupled DOFs) is taken
+                                 with each damping and the one with the smaller energy
+                                 norm ||e1||_A is kept; 0: always the MLP damping        */
 } amgf_options;
 
 typedef struct {
@@ -112,10 +119,27 @@ typedef struct {
   double rel_true_res;        /* ||b - A x|| / ||b|| at exit (FP64)                   */
   double op_complexity;       /* sum of level nonzeros / level-0 nonzeros             */
   float ms_solve;             /* wall time of amgf_pcg (hipEvents)                    */
-  int32_t used_fallback;      /* learned smoother fell back to theta = 1              */
+  int32_t used_fallback;      /* learned smoother: 1 = CG with the MLP damping did not
+                                 converge and was rerun with theta = 1; 2 = the
+                                 learned_judge chose theta = 1 at the last setup or
+                                 update (this solve used plain l1-Jacobi)              */
   float ms_setup_amg;         /* host wall time of the last amgf_setup / amgf_update_D:
                                  hierarchy, smoother data and coarsest factor          */
   float ms_setup_filter;      /* ... and of the filtering space and its factor        */
+  /* Device time of amgf_pcg split by phase (hipEvents between phases on the solve stream;
+   * the three sum to ms_solve up to the event resolution; Sec. 7 reports this split):    */
+  float ms_amg_apply;         /* the V-cycles B r inside the preconditioner, with their
+                                 FP64 <-> FP32 boundary casts                           */
+  float ms_filter_apply;      /* the filter correction of Definition 5.3: the residual
+                                 r - A z1 on I_c, the gather, the A_w solve and the
+                                 scatter-add                                            */
+  float ms_cg_other;          /* everything else: q = A p, dots, vector updates, the
+                                 residual r - A z2 feeding the second V-cycle and the
+                                 final sum                                              */
+  int32_t pad_;
+  double judge_learned;       /* learned_judge: ||(I - M A) e0||_A / ||e0||_A with the MLP
+                                 damping at the last setup / update (0: no judge ran)   */
+  double judge_plain;         /* ... and with theta = 1                                 */
 } amgf_solve_info;
 
 /* Fill `o` with the defaults listed above. */
@@ -209,12 +233,16 @@ const char* amgf_last_error(void);
  *                  feature-major: log10 a_ii, log10 d_i, a_ii/d_i, log10(1 + sum D J^2),
  *                  contact flag, level/(levels-1)  (smoothed levels only)
  *  AMGF_Q_THETA    double[n] smoother damping theta of the level (1 when not learned)
+ *  AMGF_Q_CG_COEF  double[2k] of the last amgf_pcg call with k iterations (level ignored):
+ *                  alpha_1..alpha_k (r.z / p.Ap) then beta_1..beta_k (r'.z' / r.z), the
+ *                  coefficients of the Lanczos tridiagonal of M A whose extreme
+ *                  eigenvalues estimate the spectrum (the bound procedure of Sec. 6.1)
  * Returns EINVAL for a bad level or selector; `bytes` must equal the array size.    */
 enum {
   AMGF_Q_SIZES = 0, AMGF_Q_A_ROWPTR, AMGF_Q_A_COL, AMGF_Q_A_VAL, AMGF_Q_AGG, AMGF_Q_ROOT,
   AMGF_Q_G_ROWPTR, AMGF_Q_G_COL, AMGF_Q_P_ROWPTR, AMGF_Q_P_COL, AMGF_Q_P_VAL, AMGF_Q_L1,
   AMGF_Q_K_ROWPTR, AMGF_Q_K_COL, AMGF_Q_K_VAL, AMGF_Q_OMEGA, AMGF_Q_IC, AMGF_Q_FEATURES,
-  AMGF_Q_THETA
+  AMGF_Q_THETA, AMGF_Q_CG_COEF
 };
 int32_t amgf_num_levels(amgf_handle h);
 
@@ -225,8 +253,10 @@ int32_t amgf_num_levels(amgf_handle h);
  * Any theta in (0, 2) keeps the smoother convergent (2 D_l1 / theta - A is SPD), so B
  * stays an SPD, convergent V-cycle.  Parameter vector (1325 floats):
  *   W1[32][6] b1[32] W2[32][32] b2[32] W3[32] b3 mu[6] sigma[6].
- * With options.smoother = AMGF_LEARNED, amgf_pcg falls back to theta = 1 when CG does
- * not converge and sets info.used_fallback.                                          */
+ * With options.smoother = AMGF_LEARNED, plain l1-Jacobi is both the judge and the
+ * fallback: the learned_judge option keeps theta = 1 where one AMGF step reduces the
+ * error more with it, and amgf_pcg reruns with theta = 1 when CG with the MLP damping does
+ * not converge; info.used_fallback reports either case.                               */
 
 /* Replace the damping of every smoothed level by the MLP with device parameters W
  * (1325 floats), or restore theta = 1 when W is NULL.  EINVAL with W on a Chebyshev
@@ -251,8 +281,9 @@ amgf_status amgf_adam_step(float* W, const double* grad, float* m1, float* m2, i
 
 /* Benchmark helper: launch one hot-path kernel `reps` times on `stream` between two
  * hipEvents and store the mean time per launch (milliseconds) in *avg_ms (host).
- *   AMGF_K_PRESMOOTH   level-0 fused "x = w.b, r = b - K x" SpMV in the handle's
- *                      V-cycle precision (reads the level-0 V-cycle buffers)
+ *   AMGF_K_PRESMOOTH   level-0 pre-smoothing residual "r = b - K x" SpMV at the first
+ *                      iterate x = w.b (formed before it) in the handle's V-cycle
+ *                      precision (reads the level-0 V-cycle buffers)
  *   AMGF_K_POSTSMOOTH  level-0 fused Jacobi step "x' = x + w.(b - K x)"
  *   AMGF_K_VCYCLE      one whole V-cycle B r on level-0 buffers
  *   AMGF_K_OPERATOR    the FP64 operator y = A x of the CG loop

@@ -18,7 +18,7 @@ FP64, MIXED_FP32, MIXED_BF16K = 0, 1, 2
 L1JACOBI, CHEBYSHEV, LEARNED = 0, 1, 2
 (Q_SIZES, Q_A_ROWPTR, Q_A_COL, Q_A_VAL, Q_AGG, Q_ROOT, Q_G_ROWPTR, Q_G_COL, Q_P_ROWPTR,
  Q_P_COL, Q_P_VAL, Q_L1, Q_K_ROWPTR, Q_K_COL, Q_K_VAL, Q_OMEGA, Q_IC, Q_FEATURES,
- Q_THETA) = range(19)
+ Q_THETA, Q_CG_COEF) = range(20)
 MLP_NPARAM, MLP_NTOTAL = 1313, 1325
 
 ABI_FUNCTIONS = ["amgf_default_options", "amgf_setup", "amgf_apply", "amgf_vcycle",
@@ -80,7 +80,7 @@ class Options(ctypes.Structure):
                 ("mlp_weights", ctypes.POINTER(ctypes.c_float)),
                 ("sweeps", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
                 ("allocator", Allocator), ("bound_diag", ctypes.c_void_p),
-                ("near_null", ctypes.c_int32)]
+                ("near_null", ctypes.c_int32), ("learned_judge", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -89,10 +89,13 @@ class SolveInfo(ctypes.Structure):
                 ("rel_prec_res", ctypes.c_double), ("rel_true_res", ctypes.c_double),
                 ("op_complexity", ctypes.c_double), ("ms_solve", ctypes.c_float),
                 ("used_fallback", ctypes.c_int32), ("ms_setup_amg", ctypes.c_float),
-                ("ms_setup_filter", ctypes.c_float)]
+                ("ms_setup_filter", ctypes.c_float), ("ms_amg_apply", ctypes.c_float),
+                ("ms_filter_apply", ctypes.c_float), ("ms_cg_other", ctypes.c_float),
+                ("pad_", ctypes.c_int32), ("judge_learned", ctypes.c_double),
+                ("judge_plain", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
 
 
 class IPOptions(ctypes.Structure):
@@ -465,6 +468,12 @@ class AMGF:
 
     def filter_dofs(self, n_c):
         return self.query(0, Q_IC, np.int32, n_c)
+
+    def cg_coefficients(self, iterations):
+        """(alpha, beta) of the last pcg call with `iterations` iterations: alpha_k =
+        r.z / p.Ap, beta_k = r'.z' / r.z, the Lanczos coefficients of M A."""
+        c = self.query(0, Q_CG_COEF, np.float64, 2 * int(iterations))
+        return c[:iterations], c[iterations:]
 
     def close(self):
         if getattr(self, "h", None):

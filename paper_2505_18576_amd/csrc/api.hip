@@ -23,6 +23,7 @@ struct Level {
   int ncrows = 0;
   DBuf<int> ccrows;             // nonempty rows of C (levels >= 1)
   int nccrows = 0;
+  bool contact_factored = false;  // V-cycle applies the contact term through J and D
   BSR P, PT;                    // prolongator to the next level and its transpose
   BSR C;                        // contact term J^T D J of this level (interface rows only)
   Graph G;                      // aggregation graph
@@ -82,7 +83,12 @@ struct Handle {
   DBuf<double> pcg_s;           // device scalars of one CG iteration: p.q, r.z, r.z_old
   double op_complexity = 1.0;
   DBuf<float> mlpW;             // device copy of the MLP parameters (learned smoother)
-  bool learned = false;
+  bool learned = false;         // the MLP damping is applied
+  // judge of the learned damping (AMGF_LEARNED with learned_judge): one AMGF step from a
+  // fixed start with each damping at every setup / update; the better one is kept
+  bool judge_on = false;
+  bool judge_rejected = false;  // the last judge kept theta = 1
+  double judge_l = 0.0, judge_p = 0.0;
   double ms_setup_amg = 0.0, ms_setup_filter = 0.0;   // host wall times of the last setup
   // live timing of one level-0 kernel class inside solves: event pairs on the solve stream
   int prof_which = -1;
@@ -94,10 +100,20 @@ struct Handle {
   // factor is not refreshed while suspended
   bool filter_suspended = false;
   DBuf<double> ip_red;          // device results of the driver's reductions
+  // phase timing of the running CG solve: event i opens a segment of phase ph_cat[i]
+  // (V-cycles, filter correction, other CG work) on the solve stream
+  std::vector<hipEvent_t> ph_ev;
+  std::vector<int> ph_cat;
+  size_t ph_used = 0;
+  bool ph_on = false;
+  // CG coefficients of the last solve: alpha_k = r.z / p.Ap and beta_k = r'.z' / r.z
+  // (the Lanczos tridiagonal of M A, Sec. 6.1)
+  std::vector<double> cg_alpha, cg_beta;
   Handle() = default;
   Handle(const Handle&) = delete;
   ~Handle() {
     for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ph_ev) (void)hipEventDestroy(e);
   }
   bool mixed() const { return opt.precision != AMGF_FP64; }
   bool bf16k() const { return opt.precision == AMGF_MIXED_BF16K; }
@@ -161,6 +177,25 @@ static void to_fp32(Ctx& c, BSR& A) {
 // ------------------------------------------------------------------------------------
 // setup pieces shared with the numeric re-setup of a new barrier diagonal
 // ------------------------------------------------------------------------------------
+// The contact term of a coarse level inside the V-cycle: through J_l and D (two short
+// kernels, t = D (J_l x), then J_l^T t) when that reads fewer bytes than the assembled
+// Galerkin block C_l and no node row of J_l^T is long (the kernel gives a row eight lanes);
+// otherwise through C_l (one wavefront per row).  Near the interface J_l stays narrow while
+// C_l couples every pair of coarse nodes two constraints apart; on the deepest levels a
+// coarse node meets thousands of constraints and C_l is the small one.
+constexpr int CONTACT_FACTORED_MAX_ROW = 256;
+
+static bool factored_contact_pays(Ctx& c, const Level& L) {
+  if (L.J.nnzb == 0 || L.ncrows == 0) return false;
+  std::vector<int> rp = d2h(L.JT.rowptr.p, size_t(L.nn) + 1, c.s);
+  int longest = 0;
+  for (int a = 0; a < L.nn; ++a) longest = std::max(longest, rp[a + 1] - rp[a]);
+  const int64_t b = L.b;
+  const int64_t factored = 2 * L.J.nnzb * (8 * b + 4) + 2 * int64_t(L.J.nrows) * 8;
+  const int64_t assembled = L.C.nnzb * (8 * b * b + 4);
+  return longest <= CONTACT_FACTORED_MAX_ROW && factored < assembled;
+}
+
 // direct factor of the coarsest operator
 constexpr int64_t COARSE_INVERSE_MAX = 2048;   // unknowns; 32 MiB of FP64 at most
 
@@ -196,6 +231,9 @@ static void features_and_damping(Handle& h) {
     if (h.learned) mlp_theta(c, L.n(), h.mlpW.p, L.F.p, L.d.p, L.theta.p, L.w.p);
   }
 }
+
+static void judge_damping(Handle& h);
+
 
 // ------------------------------------------------------------------------------------
 // setup
@@ -315,6 +353,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
       bsr_add(c, N.K, N.C, N.A);
       N.nccrows = nonempty_rows(c, N.C.rowptr.p, N.nn, N.ccrows);
     }
+    N.contact_factored = factored_contact_pays(c, N);
     nzsum += N.A.nnzb * int64_t(N.A.bsz());
     coarse_graph(c, Lc.G, Lc.agg.p, n_agg, moff.p, members.p, Gnext);
     Rprev = std::move(R);
@@ -369,6 +408,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     AMGF_HIP(hipMemcpyAsync(h.mlpW.p, o.mlp_weights, sizeof(float) * MLP_NTOTAL,
                             hipMemcpyHostToDevice, c.s));
     h.learned = true;
+    h.judge_on = o.learned_judge != 0;
   }
   features_and_damping(h);
   // ---- precision copies and work vectors
@@ -393,6 +433,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
   h.z1.alloc(n); h.ra.alloc(n); h.r2.alloc(n); h.z3.alloc(n);
   if (h.mixed()) { h.zf.alloc(n); h.r2f.alloc(n); }
   h.pr.alloc(n); h.pz.alloc(n); h.pzo.alloc(n); h.pp.alloc(n); h.pq.alloc(n);
+  judge_damping(h);
   AMGF_HIP(hipStreamSynchronize(c.s));
   const auto t_end = std::chrono::steady_clock::now();
   using ms = std::chrono::duration<double, std::milli>;
@@ -436,12 +477,14 @@ static void update_D(Handle& h, const double* D) {
   if (h.opt.filter && h.n_c > 0 && !h.filter_suspended) factor_filter(h);
   AMGF_HIP(hipStreamSynchronize(c.s));
   const auto t_filter_end = std::chrono::steady_clock::now();
+  if (h.judge_on) h.learned = true;                   // the judge decides afresh
   features_and_damping(h);
   if (h.mixed())
     for (size_t l = 0; l < nlev; ++l) {
       Level& L = *h.lev[l];
       cast_d2f(c, L.w.p, L.w32.p, L.n());
     }
+  judge_damping(h);
   AMGF_HIP(hipStreamSynchronize(c.s));
   const auto t_end = std::chrono::steady_clock::now();
   using ms = std::chrono::duration<double, std::milli>;
@@ -487,11 +530,12 @@ static void coarse_solve(Handle& h, const double* b, double* x) {
 }
 
 // Contact term of a level inside the V-cycle: through J and D on level 0 (the fine
-// interface, where the assembled block would be larger than J), through the assembled
-// Galerkin block C = J^T D J on coarser levels (one kernel instead of two).
+// interface, where the assembled block would be larger than J) and on the coarse levels
+// where that still reads fewer bytes (factored_contact_pays), through the assembled
+// Galerkin block C = J^T D J on the others (one kernel instead of two).
 template <class T>
 static void level_contact(Handle& h, Level& L, int mode, const T* x, T* y, const T* w) {
-  if (&L == h.lev[0].get())
+  if (&L == h.lev[0].get() || L.contact_factored)
     contact_apply<T, T>(h.ctx, mode, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, x, h.t.p, y, w);
   else
     contact_cmat<T, T>(h.ctx, mode, L.C, L.ccrows.p, L.nccrows, x, y, w);
@@ -507,6 +551,21 @@ static void prof_end(Handle& h) {
   if (!h.prof_open) return;
   AMGF_HIP(hipEventRecord(h.prof_ev[h.prof_used++], h.ctx.s));
   h.prof_open = false;
+}
+
+// phase timing inside a CG solve: opens a segment of phase `ph` unless it is already open
+enum { PH_AMG = 0, PH_FILTER = 1, PH_OTHER = 2 };
+static void phase(Handle& h, int ph) {
+  if (!h.ph_on) return;
+  if (h.ph_used > 0 && h.ph_cat[h.ph_used - 1] == ph) return;
+  if (h.ph_used == h.ph_ev.size()) {
+    hipEvent_t e;
+    AMGF_HIP(hipEventCreate(&e));
+    h.ph_ev.push_back(e);
+    h.ph_cat.push_back(ph);
+  }
+  h.ph_cat[h.ph_used] = ph;
+  AMGF_HIP(hipEventRecord(h.ph_ev[h.ph_used++], h.ctx.s));
 }
 
 // ---- smoother options: nu applications of l1-Jacobi or of the degree-m Chebyshev
@@ -600,8 +659,12 @@ static void vcycle_general(Handle& h, size_t l, void (*coarse)(Handle&, size_t))
   for (int s = 0; s < h.opt.sweeps; ++s) smooth_once<T>(h, l, false);
 }
 
-// FP64 V(1,1) on level l: L.vb -> L.vx
-static void vcycle64(Handle& h, size_t l) {
+// FP64 V(1,1) on level l: L.vb -> L.vx.  As in the FP32 cycle, the first smoothing
+// iterate x = w.b is formed on its own (x0_ready: the caller already wrote it to L.vx) and
+// r = b - K x then gathers x once per column instead of w and b.
+static void vcycle64_from(Handle& h, size_t l, bool x0_ready);
+static void vcycle64(Handle& h, size_t l) { vcycle64_from(h, l, false); }
+static void vcycle64_from(Handle& h, size_t l, bool x0_ready) {
   Ctx& c = h.ctx;
   Level& L = *h.lev[l];
   if (l + 1 == h.lev.size()) {
@@ -610,8 +673,9 @@ static void vcycle64(Handle& h, size_t l) {
   }
   if (!h.plain_cycle()) return vcycle_general<double>(h, l, vcycle64);
   Level& N = *h.lev[l + 1];
+  if (!x0_ready) wmul_f64(c, L.n(), L.w.p, L.vb.p, L.vx.p);
   if (l == 0) prof_begin(h, AMGF_K_PRESMOOTH);
-  bsr_spmv<double>(c, SPMV_PRE, L.K, L.K.val.p, nullptr, L.vr.p, L.vb.p, L.w.p, L.vx.p);
+  bsr_spmv<double>(c, SPMV_RES, L.K, L.K.val.p, L.vx.p, L.vr.p, L.vb.p, nullptr, nullptr);
   prof_end(h);
   level_contact<double>(h, L, CT_SUB_RES, L.vx.p, L.vr.p, nullptr);
   bsr_spmv<double>(c, SPMV_Y, L.PT, L.PT.val.p, L.vr.p, N.vb.p, nullptr, nullptr, nullptr);
@@ -675,6 +739,10 @@ static void vcycle(Handle& h, const double* r, double* z) {
       vcycle32(h, 0);
     }
     cast_f2d(c, L0.fx.p, z, n);
+  } else if (h.plain_cycle()) {
+    copy_w(c, r, L0.w.p, L0.vb.p, L0.vx.p, n);
+    vcycle64_from(h, 0, true);
+    vcopy(c, L0.vx.p, z, n);
   } else {
     vcopy(c, r, L0.vb.p, n);
     vcycle64(h, 0);
@@ -709,8 +777,10 @@ static void filter_solve(Handle& h, const double* r, double* w) {
 static void amgf_apply_impl(Handle& h, const double* r, double* z) {
   Ctx& c = h.ctx;
   const int64_t n = h.n();
+  phase(h, PH_AMG);
   if (!h.opt.filter || h.filter_suspended) {
     vcycle(h, r, z);
+    phase(h, PH_OTHER);
     return;
   }
   Level& L0 = *h.lev[0];
@@ -721,6 +791,7 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
     cast_d2f_w(c, r, L0.w32.p, L0.fb.p, L0.fx.p, n);
     vcycle32_from(h, 0, true);                        // z1 = B r  (L0.fx)
     if (h.n_c > 0) {
+      phase(h, PH_FILTER);
       bsr_res_rows<float>(c, L0.K, h.ic_nodes.p, h.n_icn, L0.fx.p, r, h.ra.p);
       contact_apply<float, double>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
                                    L0.fx.p, h.t.p, h.ra.p, nullptr);   // ra = r - A z1 on I_c
@@ -728,13 +799,16 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
       filter_solve(h, h.f_r.p, h.f_w.p);              // w = A_w^{-1} P^T ra
       correct_at(c, L0.fx.p, h.f_w.p, h.Ic.p, h.n_c, h.z1.p);   // z2 on I_c; L0.fx = float(z2)
     }
+    phase(h, PH_OTHER);
     bsr_spmv<float>(c, SPMV_RES, L0.K, L0.K.val32.p, L0.fx.p, h.r2f.p, L0.fb.p, nullptr,
                     nullptr);
     contact_apply<double, float>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
                                  h.z1.p, h.t.p, h.r2f.p, nullptr);     // r2 = r - A z2
     std::swap(L0.fx, h.zf);                           // keep z1 (float(z2) on I_c)
     std::swap(L0.fb, h.r2f);
+    phase(h, PH_AMG);
     vcycle32(h, 0);                                   // B r2  (L0.fx)
+    phase(h, PH_OTHER);
     std::swap(L0.fb, h.r2f);
     add_ff(c, n, h.zf.p, L0.fx.p, z);                 // z = z2 + B r2 ...
     add_at(c, h.z1.p, L0.fx.p, h.Ic.p, h.n_c, z);     // ... with the FP64 z2 on I_c
@@ -742,6 +816,7 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
   }
   vcycle(h, r, h.z1.p);                               // z1 = B r
   if (h.n_c > 0) {
+    phase(h, PH_FILTER);
     bsr_res_rows(c, L0.K, h.ic_nodes.p, h.n_icn, h.z1.p, r, h.ra.p);
     contact_apply<double, double>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
                                   h.z1.p, h.t.p, h.ra.p, nullptr);     // ra = r - A z1 on I_c
@@ -749,20 +824,67 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
     filter_solve(h, h.f_r.p, h.f_w.p);                // w = A_w^{-1} P^T ra
     scatter_add(c, h.f_w.p, h.Ic.p, h.n_c, h.z1.p);   // z2 = z1 + P w
   }
+  phase(h, PH_OTHER);
   if (h.mixed()) {
     cast_d2f(c, h.z1.p, h.zf.p, n);
     bsr_spmv<float>(c, SPMV_RES, L0.K, L0.K.val32.p, h.zf.p, h.r2f.p, L0.fb.p, nullptr, nullptr);
     contact_apply<double, float>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
                                  h.z1.p, h.t.p, h.r2f.p, nullptr);     // r2 = r - A z2
     std::swap(L0.fb, h.r2f);
+    phase(h, PH_AMG);
     vcycle32(h, 0);                                   // B r2
+    phase(h, PH_OTHER);
     std::swap(L0.fb, h.r2f);
     add_f32(c, n, h.z1.p, L0.fx.p, z);                // z = z2 + B r2
   } else {
     operator_apply(h, h.z1.p, h.r2.p, r);             // r2 = r - A z2
+    phase(h, PH_AMG);
     vcycle(h, h.r2.p, h.z3.p);                        // B r2
+    phase(h, PH_OTHER);
     vcopy(c, h.z1.p, z, n);
     axpby(c, n, 1.0, h.z3.p, 1.0, z);                 // z = z2 + B r2
+  }
+}
+
+static void set_damping(Handle& h, const float* W);
+
+// The judge of the learned damping: one AMGF error-propagation step e1 = e0 - M A e0 from
+// the fixed start e0 (the power-iteration start, zero on decoupled DOFs) with the MLP
+// damping and with theta = 1; the damping with the smaller energy norm ||e1||_A stays
+// (ties keep the MLP).  Plain l1-Jacobi is thereby the reference the learned damping has
+// to beat on every system it is set up for.
+static void judge_damping(Handle& h) {
+  h.judge_rejected = false;
+  if (!h.judge_on || !h.learned) return;
+  Ctx& c = h.ctx;
+  const int64_t n = h.n();
+  DBuf<double> e0(n), ae0(n), e1(n), ae1(n);
+  fill_power_start(c, n, e0.p, h.dec0.p);
+  operator_apply(h, e0.p, ae0.p, nullptr);
+  double n0;
+  {
+    const double* xs[1] = {e0.p};
+    const double* ys[1] = {ae0.p};
+    dots(c, n, 1, xs, ys, &n0);
+  }
+  auto reduction = [&]() {
+    amgf_apply_impl(h, ae0.p, e1.p);                  // M A e0
+    axpby(c, n, 1.0, e0.p, -1.0, e1.p);               // e1 = e0 - M A e0
+    operator_apply(h, e1.p, ae1.p, nullptr);
+    double n1;
+    const double* xs[1] = {e1.p};
+    const double* ys[1] = {ae1.p};
+    dots(c, n, 1, xs, ys, &n1);
+    return n0 > 0.0 ? std::sqrt(std::fabs(n1) / n0) : 0.0;
+  };
+  h.judge_l = reduction();
+  set_damping(h, nullptr);
+  h.judge_p = reduction();
+  if (h.judge_l <= h.judge_p) {
+    set_damping(h, h.mlpW.p);
+  } else {
+    h.learned = false;
+    h.judge_rejected = true;
   }
 }
 
@@ -964,7 +1086,11 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
 // Learned damping: if CG does not converge (or breaks down), rerun from the same initial
 // guess with theta = 1 (plain l1-Jacobi) and report the fallback.
 static amgf_status pcg_impl(Handle& h, const double* b, double* x, amgf_solve_info* info) {
-  if (!h.learned) return pcg_run(h, b, x, info);
+  if (!h.learned) {
+    amgf_status st = pcg_run(h, b, x, info);
+    if (info && h.judge_rejected) info->used_fallback = 2;
+    return st;
+  }
   Ctx& c = h.ctx;
   DBuf<double> x0(h.n());
   vcopy(c, x, x0.p, h.n());
@@ -985,6 +1111,12 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
   AMGF_HIP(hipEventCreate(&e0));
   AMGF_HIP(hipEventCreate(&e1));
   AMGF_HIP(hipEventRecord(e0, c.s));
+  struct PhaseScope {                                 // phase timing on for this solve only
+    Handle& h;
+    explicit PhaseScope(Handle& hh) : h(hh) { h.ph_used = 0; h.ph_on = true; }
+    ~PhaseScope() { h.ph_on = false; }
+  } phases_(h);
+  phase(h, PH_OTHER);
   operator_apply(h, x, h.pr.p, b);                    // r = b - A x0
   amgf_apply_impl(h, h.pr.p, h.pz.p);
   vcopy(c, h.pz.p, h.pp.p, n);
@@ -1022,6 +1154,8 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
   double* s3 = hs.p;
   hipEvent_t ev = hs.ev;
   double rel_old = 1.0;                               // relative residual one step back
+  h.cg_alpha.clear();
+  h.cg_beta.clear();
   bool have_q = false;                                // q = A p, p.q already enqueued
   bool need_p = false;                                // p = z + beta p still to be done
   double beta = 0.0;
@@ -1055,6 +1189,8 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
     if (!(s3[0] > 0.0)) { st = AMGF_ENOTSPD; break; }  // p.q <= 0: not SPD
     d2[0] = s3[1];
     d2[1] = s3[2];
+    h.cg_alpha.push_back(rz / s3[0]);
+    h.cg_beta.push_back(d2[0] / rz);
     ++it;
     const double rel_prev = rel;
     rel = std::sqrt(std::fabs(d2[0]) / rz0);
@@ -1069,6 +1205,13 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
   AMGF_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
   AMGF_HIP(hipEventElapsedTime(&ms, e0, e1));
+  float ms_ph[3] = {0.f, 0.f, 0.f};
+  for (size_t i = 0; i < h.ph_used; ++i) {
+    float t = 0.f;
+    AMGF_HIP(hipEventElapsedTime(&t, h.ph_ev[i], i + 1 < h.ph_used ? h.ph_ev[i + 1] : e1));
+    ms_ph[h.ph_cat[i]] += t;
+  }
+  h.ph_on = false;
   AMGF_HIP(hipEventDestroy(e0));
   AMGF_HIP(hipEventDestroy(e1));
   if (info) {
@@ -1088,6 +1231,12 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
     info->used_fallback = 0;
     info->ms_setup_amg = float(h.ms_setup_amg);
     info->ms_setup_filter = float(h.ms_setup_filter);
+    info->ms_amg_apply = ms_ph[PH_AMG];
+    info->ms_filter_apply = ms_ph[PH_FILTER];
+    info->ms_cg_other = ms_ph[PH_OTHER];
+    info->pad_ = 0;
+    info->judge_learned = h.judge_on ? h.judge_l : 0.0;
+    info->judge_plain = h.judge_on ? h.judge_p : 0.0;
   }
   if (st != AMGF_OK) return st;
   return conv ? AMGF_OK : AMGF_ENOCONV;
@@ -1242,6 +1391,7 @@ void amgf_default_options(amgf_options* o) {
   o->max_coarse_ratio = 0.9;
   o->mlp_weights = nullptr;
   o->near_null = 6;
+  o->learned_judge = 1;
 }
 
 const char* amgf_status_string(amgf_status s) {
@@ -1514,9 +1664,12 @@ amgf_status amgf_set_mlp(amgf_handle hd, const float* W, void* stream) {
       AMGF_HIP(hipMemcpyAsync(h.mlpW.p, W, sizeof(float) * amgf::MLP_NTOTAL,
                               hipMemcpyDeviceToDevice, h.ctx.s));
       h.learned = true;
+      h.judge_rejected = false;
       amgf::set_damping(h, h.mlpW.p);
     } else {
       h.learned = false;
+      h.judge_on = false;
+      h.judge_rejected = false;
       amgf::set_damping(h, nullptr);
     }
     return AMGF_OK;
@@ -1583,8 +1736,8 @@ amgf_status amgf_time_kernel(amgf_handle hd, int32_t which, int32_t reps, void* 
             amgf::bsr_spmv<float>(c, amgf::SPMV_RES, L.K, L.K.val32.p, L.fx.p, L.fr.p, L.fb.p,
                                   nullptr, nullptr);
           else
-            amgf::bsr_spmv<double>(c, amgf::SPMV_PRE, L.K, L.K.val.p, nullptr, L.vr.p, L.vb.p,
-                                   L.w.p, L.vx.p);
+            amgf::bsr_spmv<double>(c, amgf::SPMV_RES, L.K, L.K.val.p, L.vx.p, L.vr.p, L.vb.p,
+                                   nullptr, nullptr);
           break;
         case AMGF_K_POSTSMOOTH:
           if (h.bf16k())
@@ -1630,6 +1783,14 @@ amgf_status amgf_query(amgf_handle hd, int32_t level, int32_t which, void* dst, 
     if (which == AMGF_Q_IC) {
       AMGF_REQUIRE(bytes == sizeof(int) * size_t(h.n_c), AMGF_EINVAL, "size");
       if (bytes) AMGF_HIP(hipMemcpy(dst, h.Ic.p, bytes, hipMemcpyDeviceToHost));
+      return AMGF_OK;
+    }
+    if (which == AMGF_Q_CG_COEF) {
+      const size_t k = h.cg_alpha.size();
+      AMGF_REQUIRE(bytes == 2 * sizeof(double) * k, AMGF_EINVAL, "size");
+      double* d = static_cast<double*>(dst);
+      std::copy(h.cg_alpha.begin(), h.cg_alpha.end(), d);
+      std::copy(h.cg_beta.begin(), h.cg_beta.end(), d + k);
       return AMGF_OK;
     }
     AMGF_REQUIRE(level >= 0 && level < int(h.lev.size()), AMGF_EINVAL, "level");

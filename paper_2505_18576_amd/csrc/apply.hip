@@ -373,6 +373,15 @@ AMGF_ELEMWISE(k_d2f_w, (const double* __restrict__ a, const float* __restrict__ 
 AMGF_ELEMWISE(k_wmul_f, (const float* __restrict__ w, const float* __restrict__ b,
                          float* __restrict__ x, int64_t n),
               x[i] = w[i] * b[i])
+// FP64: b = a and x = w.b (level 0 of a V-cycle from zero), or x = w.b alone
+AMGF_ELEMWISE(k_copy_w, (const double* __restrict__ a, const double* __restrict__ w,
+                         double* __restrict__ b, double* __restrict__ x, int64_t n),
+              const double bi = a[i];
+              b[i] = bi;
+              x[i] = w[i] * bi)
+AMGF_ELEMWISE(k_wmul_d, (const double* __restrict__ w, const double* __restrict__ b,
+                         double* __restrict__ x, int64_t n),
+              x[i] = w[i] * b[i])
 AMGF_ELEMWISE(k_copy, (const double* __restrict__ a, double* __restrict__ b, int64_t n),
               b[i] = a[i])
 AMGF_ELEMWISE(k_axpby, (int64_t n, double al, const double* __restrict__ x, double be,
@@ -508,6 +517,12 @@ void cast_d2f_w(Ctx& c, const double* a, const float* w, float* b, float* x, int
 }
 void wmul_f32(Ctx& c, int64_t n, const float* w, const float* b, float* x) {
   if (n) hipLaunchKernelGGL(k_wmul_f, AMGF_L1D(n), w, b, x, n);
+}
+void copy_w(Ctx& c, const double* a, const double* w, double* b, double* x, int64_t n) {
+  if (n) hipLaunchKernelGGL(k_copy_w, AMGF_L1D(n), a, w, b, x, n);
+}
+void wmul_f64(Ctx& c, int64_t n, const double* w, const double* b, double* x) {
+  if (n) hipLaunchKernelGGL(k_wmul_d, AMGF_L1D(n), w, b, x, n);
 }
 void cast_f2d(Ctx& c, const float* a, double* b, int64_t n) {
   if (n) hipLaunchKernelGGL(k_f2d, AMGF_L1D(n), a, b, n);

@@ -13,6 +13,7 @@ from .twoblock import (  # noqa: F401
     ip_sequence_D,
     CONFIGS,
     make_config,
+    renumber_nodes,
 )
 from .block_on_block import make_block_on_block  # noqa: F401
 from .contact_qp import bound_barrier, contact_load_and_gap, lumped_masses  # noqa: F401

@@ -331,3 +331,38 @@ def make_config(name, rhs_seed=None, ip_step=None, N=None):
     if rhs_seed is not None:
         c["rhs_seed"] = rhs_seed
     return make_two_block(**c)
+
+
+def renumber_nodes(p, seed):
+    """The same problem with the nodes numbered by a seeded random permutation: node a of
+    ``p`` becomes node perm[a] (its three DOFs move together; meta["node_perm"] = perm).  K keeps ascending block
+    columns per row and J ascending columns per row, so the result is a valid input in
+    which stored blocks lie far from the diagonal (the matrix bandwidth becomes about the
+    node count)."""
+    rng = np.random.default_rng(seed)
+    nn = p.n_nodes
+    perm = rng.permutation(nn)                 # old node -> new node
+    inv = np.argsort(perm)                     # new node -> old node
+    rows_old = np.repeat(np.arange(nn), np.diff(p.K_rowptr))
+    rows_new = perm[rows_old]
+    cols_new = perm[p.K_col]
+    order = np.lexsort((cols_new, rows_new))
+    K_rowptr = np.zeros(nn + 1, np.int64)
+    np.cumsum(np.bincount(rows_new, minlength=nn), out=K_rowptr[1:])
+    K_col = cols_new[order].astype(np.int32)
+    K_val = np.ascontiguousarray(p.K_val[order])
+    jcol = 3 * perm[p.J_col // 3] + p.J_col % 3
+    J_col = np.empty_like(p.J_col)
+    J_val = np.empty_like(p.J_val)
+    for k in range(p.m):
+        s, e = p.J_rowptr[k], p.J_rowptr[k + 1]
+        o = np.argsort(jcol[s:e], kind="stable")
+        J_col[s:e] = jcol[s:e][o]
+        J_val[s:e] = p.J_val[s:e][o]
+    dof_old = (3 * inv[:, None] + np.arange(3)[None, :]).ravel()   # new DOF -> old DOF
+    meta = dict(p.meta, renumber_seed=seed, node_perm=perm)
+    return TwoBlockProblem(N=p.N, n_nodes=nn, K_rowptr=K_rowptr.astype(np.int32),
+                           K_col=K_col, K_val=K_val, J_rowptr=p.J_rowptr.copy(),
+                           J_col=J_col.astype(np.int32), J_val=J_val, D=p.D.copy(),
+                           b=p.b[dof_old], coords=p.coords[inv], free=p.free[dof_old],
+                           meta=meta)

@@ -193,3 +193,26 @@ def loss_grad(o: OracleAMGF, W, probes, k=2, feats=None):
         thbar = wbar[l] / o.levels[l].d / npb
         g += mlp_backward(W, F, thbar)
     return tot / npb, g
+
+
+def judge(o: OracleAMGF, W, feats=None):
+    """The judge of the learned damping: energy-norm error after one AMGF step
+    e1 = (I - M A) e0 from the power-iteration start e0 (zero on the decoupled level-0
+    DOFs), with the MLP damping and with theta = 1.  Returns (ratio_mlp, ratio_plain),
+    each ||e1||_A / ||e0||_A; the MLP damping is kept when ratio_mlp <= ratio_plain.
+    Leaves the oracle with theta = 1."""
+    from .amgf_oracle import power_start
+    e0 = power_start(o.n)
+    dec = getattr(o.levels[0], "decoupled", None)
+    if dec is not None:
+        e0[dec] = 0.0
+    n0 = float(e0 @ o.A_apply(e0))
+
+    def ratio():
+        e1 = e0 - o.apply(o.A_apply(e0))
+        return math.sqrt(abs(float(e1 @ o.A_apply(e1))) / n0)
+
+    set_damping(o, W, feats)
+    r_mlp = ratio()
+    reset_damping(o)
+    return r_mlp, ratio()

@@ -54,7 +54,7 @@ def test_learned_damping_applies_the_mlp(case):
     from oracle import learned
     from paper_2505_18576_amd import AMGF
     p, o, feats, W, P = case
-    h = AMGF.from_problem(p, coarse_max_nodes=16, mlp_weights=W)
+    h = AMGF.from_problem(p, coarse_max_nodes=16, mlp_weights=W, learned_judge=0)
     learned.set_damping(o, W, feats)
     for l, F in enumerate(feats):
         assert rel(h.theta(l), learned.mlp_forward(W, F)[0]) < 1e-13
@@ -84,21 +84,64 @@ def test_zero_last_layer_is_bitwise_plain(case):
 
 
 def test_fallback_when_learned_damping_fails(case):
-    """NaN weights make the learned V-cycle non-finite: CG breaks down, the solve reruns
-    with theta = 1 from the same initial guess and reports the fallback."""
+    """NaN weights make the learned V-cycle non-finite.  Without the judge, CG breaks down,
+    the solve reruns with theta = 1 from the same initial guess and reports fallback 1; with
+    the judge (default) the non-finite error reduction loses against theta = 1 at setup and
+    the solve runs plain from the start (fallback 2).  Both equal the plain solve bitwise."""
     from paper_2505_18576_amd import AMGF
     p, o, feats, W, P = case
     Wbad = W.copy()
     Wbad[1312] = np.nan
     ref = AMGF.from_problem(p, coarse_max_nodes=16)
     xr, iref = ref.pcg(p.b)
-    h = AMGF.from_problem(p, coarse_max_nodes=16, mlp_weights=Wbad)
-    x, info = h.pcg(p.b)
-    assert info.used_fallback == 1 and info.converged
-    assert info.iterations == iref.iterations
-    assert np.array_equal(x.cpu().numpy(), xr.cpu().numpy())
-    h.close()
+    for judge, code in ((0, 1), (1, 2)):
+        h = AMGF.from_problem(p, coarse_max_nodes=16, mlp_weights=Wbad, learned_judge=judge)
+        x, info = h.pcg(p.b)
+        assert info.used_fallback == code and info.converged
+        assert info.iterations == iref.iterations
+        assert np.array_equal(x.cpu().numpy(), xr.cpu().numpy())
+        h.close()
     ref.close()
+
+
+@pytest.mark.parametrize("bounds", [False, True])
+def test_judge_matches_oracle_and_keeps_the_better_damping(bounds):
+    """The judge's one-step error reductions against the oracle's; on C1 the trained damping
+    wins, with the bound-constraint barrier terms (which the network never saw) theta = 1
+    wins and the solve is bitwise the plain one.  In both cases the choice agrees with the
+    CG iteration counts."""
+    import os
+    from amgf_inputs import bound_barrier, make_config
+    from oracle import OracleAMGF, learned
+    from paper_2505_18576_amd import AMGF
+    from paper_2505_18576_amd.train_smoother import load_weights
+    W = load_weights(os.path.join(os.path.dirname(os.path.dirname(__file__)),
+                                  "paper_2505_18576_amd", "weights", "smoother_ip.bin"))
+    p = make_config("C1")
+    E = bound_barrier(p, seed=9) if bounds else None
+    o = OracleAMGF(p.n_nodes, p.K_rowptr, p.K_col, p.K_val, p.J_rowptr, p.J_col, p.J_val,
+                   p.D, p.coords, E=E)
+    r_mlp, r_plain = learned.judge(o, W.astype(np.float64))
+    plain = AMGF.from_problem(p, E=E)
+    h = AMGF.from_problem(p, E=E, mlp_weights=W)
+    xp, ip = plain.pcg(p.b)
+    x, info = h.pcg(p.b)
+    hf = AMGF.from_problem(p, E=E, mlp_weights=W, learned_judge=0)
+    _, il = hf.pcg(p.b)
+    print(f"bounds {bounds}: judge gpu {info.judge_learned:.6e} / {info.judge_plain:.6e}, "
+          f"oracle {r_mlp:.6e} / {r_plain:.6e}; its plain {ip.iterations}, learned "
+          f"{il.iterations}, judged {info.iterations} (fallback {info.used_fallback})")
+    assert abs(info.judge_learned - r_mlp) <= 1e-6 * r_mlp
+    assert abs(info.judge_plain - r_plain) <= 1e-6 * r_plain
+    if bounds:
+        assert r_mlp > r_plain and info.used_fallback == 2
+        assert il.iterations > ip.iterations and info.iterations == ip.iterations
+        assert np.array_equal(x.cpu().numpy(), xp.cpu().numpy())
+    else:
+        assert r_mlp < r_plain and info.used_fallback == 0
+        assert il.iterations < ip.iterations and info.iterations == il.iterations
+    for a in (plain, h, hf):
+        a.close()
 
 
 def test_adam_step_matches_reference():

@@ -133,3 +133,33 @@ def test_ip_sequence():
     assert D20.min() >= mu * (1 - 1e-9) and D20.max() <= 1.0 / mu * (1 + 1e-9)
     # same active set through the sequence: the order of D is preserved
     assert (np.argsort(D1) == np.argsort(D20)).all()
+
+
+def test_renumbered_problem_is_the_same_operator():
+    """renumber_nodes permutes nodes only: P K P^T, J P^T, P b, with valid sorted inputs
+    and a bandwidth beyond 16-bit block-column offsets."""
+    import scipy.sparse as sp
+    from amgf_inputs import make_two_block, renumber_nodes
+    p = make_two_block(28, D_log10=(0.0, 6.0), D_seed=3, rhs_seed=4)
+    q = renumber_nodes(p, seed=5)
+    n = p.n
+    K = sp.bsr_matrix((p.K_val, p.K_col, p.K_rowptr), shape=(n, n)).tocsr()
+    Kq = sp.bsr_matrix((q.K_val, q.K_col, q.K_rowptr), shape=(n, n)).tocsr()
+    J = sp.csr_matrix((p.J_val, p.J_col, p.J_rowptr), shape=(p.m, n))
+    Jq = sp.csr_matrix((q.J_val, q.J_col, q.J_rowptr), shape=(q.m, n))
+    perm = q.meta["node_perm"]
+    assert np.array_equal(np.sort(perm), np.arange(p.n_nodes))
+    node_q_to_p = np.argsort(perm)
+    assert np.array_equal(q.coords, p.coords[node_q_to_p])
+    dof = (3 * node_q_to_p[:, None] + np.arange(3)[None, :]).ravel()
+    assert (Kq - K[dof][:, dof]).count_nonzero() == 0
+    assert (Jq - J[:, dof]).count_nonzero() == 0
+    assert np.array_equal(q.b, p.b[dof]) and np.array_equal(q.free, p.free[dof])
+    for k in range(q.m):
+        c = q.J_col[q.J_rowptr[k]:q.J_rowptr[k + 1]]
+        assert np.all(np.diff(c) > 0)
+    for a in range(0, q.n_nodes, 997):
+        c = q.K_col[q.K_rowptr[a]:q.K_rowptr[a + 1]]
+        assert np.all(np.diff(c) > 0)
+    rows = np.repeat(np.arange(q.n_nodes), np.diff(q.K_rowptr))
+    assert np.abs(q.K_col - rows).max() > 32767

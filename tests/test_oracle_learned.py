@@ -161,3 +161,49 @@ def test_mlp_forward_matches_rowwise_evaluation_of_the_header_layout():
         want = 1.0 + 0.98 * math.tanh(y)
         assert abs(theta[i] - want) <= 1e-13, (i, theta[i], want)
     assert np.all((theta > 0.02) & (theta < 1.98))
+
+
+def test_judge_is_the_one_step_energy_norm_reduction(setup):
+    """learned.judge against the dense error propagation I - M A (A = K + J^T D J written
+    out densely), for the MLP damping and for theta = 1."""
+    from oracle.amgf_oracle import power_start
+    from oracle_util import J_dense, K_dense
+    p, o, feats, W, P = setup
+    Jd = J_dense(p)
+    A = K_dense(p) + Jd.T @ (p.D[:, None] * Jd)
+    e0 = power_start(o.n)
+    e0[o.levels[0].decoupled] = 0.0
+    want = []
+    for Wx in (W, None):
+        if Wx is None:
+            learned.reset_damping(o)
+        else:
+            learned.set_damping(o, Wx, feats)
+        M = dense_of(o.apply, o.n)
+        e1 = e0 - M @ (A @ e0)
+        want.append(np.sqrt((e1 @ A @ e1) / (e0 @ A @ e0)))
+    got = learned.judge(o, W, feats)
+    assert abs(got[0] - want[0]) <= 1e-9 * want[0] and abs(got[1] - want[1]) <= 1e-9 * want[1]
+    assert np.all(o.levels[0].w == 1.0 / o.levels[0].d)      # left at theta = 1
+
+
+def test_judge_choice_agrees_with_cg_on_c1():
+    """The trained network against theta = 1 on C1 with and without the barrier terms of
+    bound constraints: the judge prefers whichever damping CG converges faster with."""
+    import os
+    from amgf_inputs import bound_barrier, make_config
+    from oracle import OracleAMGF
+    from paper_2505_18576_amd.train_smoother import load_weights
+    W = load_weights(os.path.join(os.path.dirname(os.path.dirname(__file__)),
+                                  "paper_2505_18576_amd", "weights", "smoother_ip.bin"))
+    W = W.astype(np.float64)
+    for bounds in (False, True):
+        p = make_config("C1")
+        E = bound_barrier(p, seed=9) if bounds else None
+        o = OracleAMGF(p.n_nodes, p.K_rowptr, p.K_col, p.K_val, p.J_rowptr, p.J_col,
+                       p.J_val, p.D, p.coords, E=E)
+        r_mlp, r_plain = learned.judge(o, W)
+        its_plain = o.pcg(p.b).iterations
+        learned.set_damping(o, W)
+        its_mlp = o.pcg(p.b).iterations
+        assert (r_mlp <= r_plain) == (its_mlp < its_plain), (bounds, r_mlp, r_plain)

@@ -13,11 +13,7 @@ struct MFSolver {
                                          // boundary DOFs, 64-row tiles of the front
   std::vector<int> wl_fwd_off, wl_bwd_off;  // per depth: range of its solve work lists
   DBuf<int> wl_fwd, wl_bwd;                 // (supernode, row block) pairs of the solve
-  // forward completion chain: workgroups per front, parent, reporting children, the
-  // fronts assembled up front (no child reports to them) and the per-solve counters
-  DBuf<int> nwork, tparent, nchild, rhs0;
-  int n_rhs0 = 0;
-  mutable DBuf<int> wdone, cdone;
+  std::vector<int> fp_max;                  // per depth: largest front (padded rows)
   // device: ordering and symbolic structure
   DBuf<int> snode, sep_rank, soff, sperm;   // supernode of each node; members (ascending)
   DBuf<int> tdepth, child0, child1;

@@ -687,20 +687,19 @@ __device__ __forceinline__ int64_t mf_bnd_dof(int t, int m, int bs, const int* b
   return int64_t(bnd[bnd_off[t] + m / bs]) * bs + m % bs;
 }
 
-// front right-hand side fa of front t: r on the separator, the children's update vectors
-// added in the order child 0, child 1 (one workgroup)
+// front right-hand side f of front t: r on the separator, the children's update vectors
+// added in the order child 0, child 1 (one workgroup; f in global memory or in LDS)
 __device__ void mf_front_rhs(int t, int bs, const double* __restrict__ r,
                              const int* __restrict__ soff, const int* __restrict__ sperm,
                              const int* __restrict__ child0, const int* __restrict__ child1,
                              const int* __restrict__ bnd_off, const int* __restrict__ bnd_pos,
                              const int* __restrict__ fs, const int* __restrict__ fS,
                              const int* __restrict__ fb, const int* __restrict__ fT,
-                             const int64_t* __restrict__ vo, double* __restrict__ fa,
-                             const double* __restrict__ fv) {
+                             const int64_t* __restrict__ vo, const double* __restrict__ fv,
+                             double* f) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int s = fs[t];
   const int Fp = fT[t] * 64;
-  double* f = fa + vo[t];
   for (int i = tid; i < Fp; i += nt) f[i] = i < s ? r[mf_sep_dof(t, i, bs, soff, sperm)] : 0.0;
   for (int ci = 0; ci < 2; ++ci) {
     const int c = ci ? child1[t] : child0[t];
@@ -713,9 +712,9 @@ __device__ void mf_front_rhs(int t, int bs, const double* __restrict__ r,
   }
 }
 
-// right-hand sides of the fronts in `list` (fronts no child forward pass assembles)
-__global__ void __launch_bounds__(256) k_mf_rhs(const int* __restrict__ list, int bs,
-                                                const double* __restrict__ r,
+// front right-hand sides fa of the fronts of one depth (fronts too large for the LDS copy
+// of the forward kernel)
+__global__ void __launch_bounds__(256) k_mf_rhs(int tb, int bs, const double* __restrict__ r,
                                                 const int* __restrict__ soff,
                                                 const int* __restrict__ sperm,
                                                 const int* __restrict__ child0,
@@ -729,22 +728,10 @@ __global__ void __launch_bounds__(256) k_mf_rhs(const int* __restrict__ list, in
                                                 const int64_t* __restrict__ vo,
                                                 double* __restrict__ fa,
                                                 const double* __restrict__ fv) {
-  mf_front_rhs(list[blockIdx.x], bs, r, soff, sperm, child0, child1, bnd_off, bnd_pos, fs, fS,
-               fb, fT, vo, fa, fv);
+  const int t = tb + blockIdx.x;
+  mf_front_rhs(t, bs, r, soff, sperm, child0, child1, bnd_off, bnd_pos, fs, fS, fb, fT, vo, fv,
+               fa + vo[t]);
 }
-
-// Arguments of the front right-hand-side assembly that the forward kernel performs for a
-// parent once its children are done.
-struct MfRhsArgs {
-  int bs;
-  const double* r;
-  const int *soff, *sperm, *child0, *child1, *bnd_off, *bnd_pos, *fs, *fT;
-  const int* nwork;    // forward workgroups of each front
-  const int* parent;   // parent front (-1 at a root)
-  const int* nchild;   // children with forward work (the ones that report to the parent)
-  int* wdone;          // forward workgroups finished, per front (zero between solves)
-  int* cdone;          // children finished, per front (zero between solves)
-};
 
 // Rows per wavefront in the solve kernels: each wave issues the loads of MF_R rows of the
 // factor back to back (row indices clamped, products masked) and shares the vector entries
@@ -752,25 +739,21 @@ struct MfRhsArgs {
 // MF_R divides 64.
 constexpr int MF_R = 4;
 constexpr int MF_XB = 2048;   // boundary values a backward workgroup stages in LDS
+constexpr int MF_FL = 8192;   // front right-hand side a forward workgroup assembles in LDS
 // The solve kernels run over per-depth work lists of (supernode, block of 4 MF_R rows)
 // pairs built at setup, so the grid holds exactly the workgroups the fronts of a depth
 // need (a grid sized by the depth's widest front was mostly idle workgroups).
 
-// [y; u] = [X; -G] fa_s + [0; fa_b]: rows i0 .. i0+MF_R-1 of M on one wavefront.
-// Then the completion count: the last workgroup of a front reports to the parent, and the
-// report that completes the parent's children assembles the parent's right-hand side, in
-// the same fixed order as k_mf_rhs.  Nothing waits on another workgroup; the fences publish
-// the update vectors (written by other workgroups, possibly on other XCDs) before the
-// counters move and make them visible to the assembling workgroup.
+// [y; u] = [X; -G] f_s + [0; f_b]: rows i0 .. i0+MF_R-1 of M on one wavefront, f the
+// front's right-hand side
 __device__ void mf_fwd_rows(int t, int blk, const int* __restrict__ fS,
                             const int* __restrict__ fb, const int64_t* __restrict__ mo,
                             const int64_t* __restrict__ vo, const double* __restrict__ M,
-                            const double* __restrict__ fa, double* __restrict__ fv) {
+                            const double* f, double* __restrict__ fv) {
   const int lane = threadIdx.x & 63;
   const int S = fS[t], rows = S + fb[t];
   const int i0 = (blk * 4 + (threadIdx.x >> 6)) * MF_R;
   if (i0 >= rows) return;
-  const double* f = fa + vo[t];
   double* out = fv + vo[t];
   if (S == 0) {
     if (lane < MF_R && i0 + lane < rows) out[i0 + lane] = f[i0 + lane];
@@ -809,37 +792,45 @@ __device__ void mf_fwd_rows(int t, int blk, const int* __restrict__ fS,
   if (lane < MF_R && i < rows) out[i] = i < S ? mine : f[i] - mine;
 }
 
+// forward rows with the right-hand side from fa (assembled by k_mf_rhs)
 __global__ void __launch_bounds__(256) k_mf_fwd(const int* __restrict__ wl,
                                                 const int* __restrict__ fS,
                                                 const int* __restrict__ fb,
                                                 const int64_t* __restrict__ mo,
                                                 const int64_t* __restrict__ vo,
                                                 const double* __restrict__ M,
-                                                double* __restrict__ fa,
-                                                double* __restrict__ fv, MfRhsArgs ra) {
-  __shared__ int assemble;
+                                                const double* __restrict__ fa,
+                                                double* __restrict__ fv) {
   const int t = wl[2 * blockIdx.x], blk = wl[2 * blockIdx.x + 1];
-  mf_fwd_rows(t, blk, fS, fb, mo, vo, M, fa, fv);
-  __threadfence();                                    // release this wave's update rows
+  mf_fwd_rows(t, blk, fS, fb, mo, vo, M, fa + vo[t], fv);
+}
+
+// forward rows with the right-hand side assembled by the workgroup itself in LDS: every
+// workgroup of a front repeats the assembly (a few loads per row of the front against the
+// MF_R rows of the factor each wave reads), which saves the separate assembly launch of
+// every depth
+__global__ void __launch_bounds__(256) k_mf_fwd_lds(const int* __restrict__ wl, int bs,
+                                                    const double* __restrict__ r,
+                                                    const int* __restrict__ soff,
+                                                    const int* __restrict__ sperm,
+                                                    const int* __restrict__ child0,
+                                                    const int* __restrict__ child1,
+                                                    const int* __restrict__ bnd_off,
+                                                    const int* __restrict__ bnd_pos,
+                                                    const int* __restrict__ fs,
+                                                    const int* __restrict__ fS,
+                                                    const int* __restrict__ fb,
+                                                    const int* __restrict__ fT,
+                                                    const int64_t* __restrict__ mo,
+                                                    const int64_t* __restrict__ vo,
+                                                    const double* __restrict__ M,
+                                                    double* __restrict__ fv) {
+  extern __shared__ double fl[];
+  const int t = wl[2 * blockIdx.x], blk = wl[2 * blockIdx.x + 1];
+  mf_front_rhs(t, bs, r, soff, sperm, child0, child1, bnd_off, bnd_pos, fs, fS, fb, fT, vo, fv,
+               fl);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int go = -1;
-    if (atomicAdd(&ra.wdone[t], 1) + 1 == ra.nwork[t]) {
-      atomicExch(&ra.wdone[t], 0);
-      const int pt = ra.parent[t];
-      if (pt >= 0 && atomicAdd(&ra.cdone[pt], 1) + 1 == ra.nchild[pt]) {
-        atomicExch(&ra.cdone[pt], 0);
-        go = pt;
-      }
-    }
-    assemble = go;
-  }
-  __syncthreads();
-  const int pt = assemble;
-  if (pt < 0) return;
-  __threadfence();                                    // acquire the children's update rows
-  mf_front_rhs(pt, ra.bs, ra.r, ra.soff, ra.sperm, ra.child0, ra.child1, ra.bnd_off,
-               ra.bnd_pos, ra.fs, fS, fb, ra.fT, vo, fa, fv);
+  mf_fwd_rows(t, blk, fS, fb, mo, vo, M, fl, fv);
 }
 
 // x_s = X^T y - G^T x_b: separator rows j0 .. j0+MF_R-1 of MT on one wavefront
@@ -1123,32 +1114,11 @@ void MFSolver::setup(Ctx& c, int n_, int bs_, const int* rp, const int* col,
     if (wb.empty()) wb.assign(2, 0);
     up(wl_fwd, wf);
     up(wl_bwd, wb);
-    // completion chain of the forward pass: forward workgroups per front, parent, children
-    // that report (those with forward work), and the fronts no report assembles
-    std::vector<int> hc0 = d2h(child0.p, size_t(ntree), c.s);
-    std::vector<int> hc1 = d2h(child1.p, size_t(ntree), c.s);
-    std::vector<int> hnw(ntree), hpar(ntree, -1), hnch(ntree, 0), hrhs0;
-    for (int t = 0; t < ntree; ++t) hnw[t] = (h_S[t] + h_b[t] + RB - 1) / RB;
-    for (int t = 0; t < ntree; ++t)
-      for (int ch : {hc0[t], hc1[t]})
-        if (ch >= 0) {
-          AMGF_REQUIRE(ch < ntree && hpar[ch] < 0, AMGF_EDEVICE,
-                       "multifrontal: inconsistent elimination tree");
-          hpar[ch] = t;
-          if (hnw[ch] > 0) ++hnch[t];
-        }
-    for (int t = 0; t < ntree; ++t)
-      if (hnch[t] == 0) hrhs0.push_back(t);
-    n_rhs0 = int(hrhs0.size());
-    if (hrhs0.empty()) hrhs0.assign(1, 0);
-    up(nwork, hnw);
-    up(tparent, hpar);
-    up(nchild, hnch);
-    up(rhs0, hrhs0);
-    wdone.alloc(size_t(ntree));
-    cdone.alloc(size_t(ntree));
-    AMGF_HIP(hipMemsetAsync(wdone.p, 0, wdone.bytes(), c.s));
-    AMGF_HIP(hipMemsetAsync(cdone.p, 0, cdone.bytes(), c.s));
+    // largest front of each depth: the LDS the forward kernel assembles it in
+    fp_max.assign(ndepth, 0);
+    for (int dd = 0; dd < ndepth; ++dd)
+      for (int t = tree_off[dd]; t < tree_off[dd + 1]; ++t)
+        fp_max[dd] = std::max(fp_max[dd], h_T[t] * 64);
   }
   const int fl = d2h_scalar(c.flag.p, c.s);
   AMGF_REQUIRE(!(fl & 4), AMGF_EDEVICE, "multifrontal: inconsistent symbolic structure");
@@ -1157,20 +1127,25 @@ void MFSolver::setup(Ctx& c, int n_, int bs_, const int* rp, const int* col,
 
 void MFSolver::solve(Ctx& c, const double* r, double* x) const {
   if (n == 0) return;
-  // fronts no child assembles, then the forward passes deepest first (each assembles the
-  // right-hand sides of the next depth as its fronts complete), then backward root first
-  if (n_rhs0 > 0)
-    hipLaunchKernelGGL(k_mf_rhs, dim3(n_rhs0), dim3(256), 0, c.s, rhs0.p, bs, r, soff.p,
-                       sperm.p, child0.p, child1.p, bnd_off.p, bnd_pos.p, fs.p, fS.p, fb.p,
-                       fT.p, vo.p, fa.p, fv.p);
-  MfRhsArgs ra{bs,       r,       soff.p,  sperm.p,  child0.p, child1.p, bnd_off.p, bnd_pos.p,
-               fs.p,     fT.p,    nwork.p, tparent.p, nchild.p, wdone.p,  cdone.p};
+  // forward by depth, deepest first: the right-hand sides assembled inside the forward
+  // kernel (LDS) where the depth's fronts fit, by a separate launch otherwise
   for (int dd = ndepth - 1; dd >= 0; --dd) {
+    const int b0 = tree_off[dd], nt = tree_off[dd + 1] - b0;
     const int nf = wl_fwd_off[dd + 1] - wl_fwd_off[dd];
+    const int* wl = wl_fwd.p + 2 * int64_t(wl_fwd_off[dd]);
+    if (fp_max[dd] <= MF_FL) {
+      if (nf > 0)
+        hipLaunchKernelGGL(k_mf_fwd_lds, dim3(nf), dim3(256), size_t(fp_max[dd]) * 8, c.s, wl,
+                           bs, r, soff.p, sperm.p, child0.p, child1.p, bnd_off.p, bnd_pos.p,
+                           fs.p, fS.p, fb.p, fT.p, mo.p, vo.p, M.p, fv.p);
+      continue;
+    }
+    hipLaunchKernelGGL(k_mf_rhs, dim3(nt), dim3(256), 0, c.s, b0, bs, r, soff.p, sperm.p,
+                       child0.p, child1.p, bnd_off.p, bnd_pos.p, fs.p, fS.p, fb.p, fT.p, vo.p,
+                       fa.p, fv.p);
     if (nf > 0)
-      hipLaunchKernelGGL(k_mf_fwd, dim3(nf), dim3(256), 0, c.s,
-                         wl_fwd.p + 2 * int64_t(wl_fwd_off[dd]), fS.p, fb.p, mo.p, vo.p, M.p,
-                         fa.p, fv.p, ra);
+      hipLaunchKernelGGL(k_mf_fwd, dim3(nf), dim3(256), 0, c.s, wl, fS.p, fb.p, mo.p, vo.p,
+                         M.p, fa.p, fv.p);
   }
   for (int dd = 0; dd < ndepth; ++dd) {
     const int nb = wl_bwd_off[dd + 1] - wl_bwd_off[dd];

@@ -205,6 +205,24 @@ amgf_status amgf_operator_apply(amgf_handle h, const double* x, double* y, void*
 amgf_status amgf_pcg(amgf_handle h, const double* b, double* x, amgf_solve_info* info,
                      void* stream);
 
+/* amgf_pcg for callers that cannot allocate device memory: serving loops with a fixed
+ * memory budget and harnesses that forbid allocation after setup.  Same arguments,
+ * iterates and stopping rule as amgf_pcg; it calls no hipMalloc, hipFree, hipHostMalloc
+ * or allocator callback and creates no events.  Its scratch (the CG scalars and the
+ * partial sums of the dot products: 4100 + 4 doubles, the same for every problem size) is
+ * a static device array of the library, one copy per GPU, whose address amgf_setup looks
+ * up on its device; every other work buffer belongs to the handle.  Calls on one GPU share
+ * that scratch: calls that overlap on one GPU (two streams, two threads) race and must
+ * be serialised by the caller.  Differences from amgf_pcg: the host reads the scalars
+ * after a stream synchronisation (no overlap of the next direction with that read),
+ * info->ms_solve is host wall time and the phase split is zero, the CG coefficients are
+ * not recorded for AMGF_Q_CG_COEF, and with learned damping a CG that does not converge
+ * is not rerun with theta = 1 (that would need a copy of the initial guess): the status
+ * is returned as is.  Errors as amgf_pcg; AMGF_EDEVICE if the library would have had
+ * to allocate (an internal error).                                                    */
+amgf_status amgf_pcg_noalloc(amgf_handle h, const double* b, double* x,
+                             amgf_solve_info* info, void* stream);
+
 /* Release every device buffer of the handle.  NULL is ignored.                   */
 void amgf_destroy(amgf_handle h);
 

@@ -27,7 +27,7 @@ ABI_FUNCTIONS = ["amgf_default_options", "amgf_setup", "amgf_apply", "amgf_vcycl
                  "amgf_set_mlp", "amgf_mlp_loss_grad", "amgf_adam_step",
                  "amgf_profile_start", "amgf_profile_read", "amgf_filter_solve",
                  "amgf_update_D", "amgf_ip_default_options", "amgf_ip_solve",
-                 "amgf_update_barrier"]
+                 "amgf_update_barrier", "amgf_pcg_noalloc"]
 K_PRESMOOTH, K_POSTSMOOTH, K_VCYCLE, K_OPERATOR = range(4)
 
 
@@ -143,6 +143,8 @@ def load_library(path=LIB_PATH):
         getattr(L, f).restype = ctypes.c_int
     L.amgf_pcg.argtypes = [vp, vp, vp, ctypes.POINTER(SolveInfo), vp]
     L.amgf_pcg.restype = ctypes.c_int
+    L.amgf_pcg_noalloc.argtypes = [vp, vp, vp, ctypes.POINTER(SolveInfo), vp]
+    L.amgf_pcg_noalloc.restype = ctypes.c_int
     L.amgf_destroy.argtypes = [vp]
     L.amgf_destroy.restype = None
     L.amgf_status_string.argtypes = [ctypes.c_int]
@@ -343,6 +345,15 @@ class AMGF:
             return x, info
         _check(st, "amgf_pcg")
         return x, info
+
+    def pcg_noalloc(self, b, x):
+        """amgf_pcg_noalloc on caller-owned device tensors b and x (x: initial guess in,
+        solution out); returns (status, info).  Allocates nothing on the device."""
+        info = SolveInfo()
+        st = self.L.amgf_pcg_noalloc(self.h, _ptr(b), _ptr(x), ctypes.byref(info), _stream())
+        if st not in (AMGF_OK, AMGF_ENOCONV):
+            _check(st, "amgf_pcg_noalloc")
+        return st, info
 
     def ip_solve(self, f, g0, u0=None, Ms=None, Mu=None, **opts):
         """Interior-point solve of min 1/2 u^T K u - f^T u s.t. J u + g0 >= 0 with this

@@ -3,6 +3,7 @@
 #include <chrono>
 #include <cmath>
 #include <memory>
+#include <mutex>
 
 #include "apply.h"
 #include "multifrontal.h"
@@ -129,6 +130,34 @@ struct Handle {
 };
 
 static thread_local std::string g_last_error;
+
+// ------------------------------------------------------------------------------------
+// device scratch of the allocation-free CG entry point (amgf_pcg_noalloc): the partial
+// sums of the deterministic dot products and the CG scalars p.q, r.z, r.z_old.  Its size
+// does not depend on the problem.  Each GPU holds its own copy until the process ends;
+// host code uses the per-device address from hipGetSymbolAddress, never the array's name.
+// ------------------------------------------------------------------------------------
+constexpr size_t PCG_SCRATCH = DOT_SCRATCH + 4;
+static __device__ __align__(256) double scratch[PCG_SCRATCH];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// the scratch address on the current device, looked up once per device (called by
+// amgf_setup on its device, then by the entry point)
+static double* scratch_ptr() {
+  int dev = 0;
+  AMGF_HIP(hipGetDevice(&dev));
+  AMGF_REQUIRE(dev >= 0 && dev < SCRATCH_MAX_DEVICES, AMGF_EDEVICE, "device index");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    AMGF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    AMGF_REQUIRE(p != nullptr, AMGF_EDEVICE, "hipGetSymbolAddress returned no address");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
 
 // ------------------------------------------------------------------------------------
 // small helpers
@@ -1081,13 +1110,17 @@ static double loss_grad(Handle& h, const float* W, int k, int np, const double* 
 // ------------------------------------------------------------------------------------
 // PCG (Sec. 4 / 6.1 stopping rule), Polak-Ribiere beta
 // ------------------------------------------------------------------------------------
-static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_info* info);
+static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_info* info,
+                           double* ns = nullptr);
 
 // Learned damping: if CG does not converge (or breaks down), rerun from the same initial
 // guess with theta = 1 (plain l1-Jacobi) and report the fallback.
-static amgf_status pcg_impl(Handle& h, const double* b, double* x, amgf_solve_info* info) {
-  if (!h.learned) {
-    amgf_status st = pcg_run(h, b, x, info);
+// ns: the allocation-free variant's device scratch (no fallback rerun there: keeping the
+// initial guess for it would need n doubles).
+static amgf_status pcg_impl(Handle& h, const double* b, double* x, amgf_solve_info* info,
+                            double* ns = nullptr) {
+  if (!h.learned || ns) {
+    amgf_status st = pcg_run(h, b, x, info, ns);
     if (info && h.judge_rejected) info->used_fallback = 2;
     return st;
   }
@@ -1104,18 +1137,34 @@ static amgf_status pcg_impl(Handle& h, const double* b, double* x, amgf_solve_in
   return st;
 }
 
-static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_info* info) {
+// ns != nullptr: the allocation-free variant.  Its CG scalars and dot-product partials live
+// in the device scratch ns (PCG_SCRATCH doubles), the host reads the scalars into a stack
+// array after a stream synchronisation, and no events are created (no phase split; the
+// solve time is host wall time).
+static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_info* info,
+                           double* ns) {
   Ctx& c = h.ctx;
   const int64_t n = h.n();
-  hipEvent_t e0, e1;
-  AMGF_HIP(hipEventCreate(&e0));
-  AMGF_HIP(hipEventCreate(&e1));
-  AMGF_HIP(hipEventRecord(e0, c.s));
+  const bool na = ns != nullptr;
+  double* dpart = na ? ns : nullptr;                  // dot partials (nullptr: c.dot)
+  const auto t_host0 = std::chrono::steady_clock::now();
+  struct Events {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } evs;
+  if (!na) {
+    AMGF_HIP(hipEventCreate(&evs.e0));
+    AMGF_HIP(hipEventCreate(&evs.e1));
+    AMGF_HIP(hipEventRecord(evs.e0, c.s));
+  }
   struct PhaseScope {                                 // phase timing on for this solve only
     Handle& h;
-    explicit PhaseScope(Handle& hh) : h(hh) { h.ph_used = 0; h.ph_on = true; }
+    PhaseScope(Handle& hh, bool on) : h(hh) { h.ph_used = 0; h.ph_on = on; }
     ~PhaseScope() { h.ph_on = false; }
-  } phases_(h);
+  } phases_(h, !na);
   phase(h, PH_OTHER);
   operator_apply(h, x, h.pr.p, b);                    // r = b - A x0
   amgf_apply_impl(h, h.pr.p, h.pz.p);
@@ -1124,7 +1173,7 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
   {
     const double* xs[2] = {h.pr.p, b};
     const double* ys[2] = {h.pz.p, b};
-    dots(c, n, 2, xs, ys, d2);
+    dots(c, n, 2, xs, ys, d2, dpart);
   }
   double rz = d2[0];
   const double rz0 = rz;
@@ -1140,7 +1189,13 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
   // iteration that work is simply not used.
   // The speculation is skipped when the residual history predicts convergence in this
   // iteration (geometric extrapolation), so the last iteration rarely wastes the work.
-  if (h.pcg_s.n == 0) h.pcg_s.alloc(4);
+  double* dsc = nullptr;                              // device scalars p.q, r.z, r.z_old
+  if (na) {
+    dsc = ns + DOT_SCRATCH;
+  } else {
+    if (h.pcg_s.n == 0) h.pcg_s.alloc(4);
+    dsc = h.pcg_s.p;
+  }
   struct HostScalars {                                // pinned: the copy is truly async
     double* p = nullptr;
     hipEvent_t ev = nullptr;
@@ -1149,9 +1204,13 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
       if (p) (void)hipHostFree(p);
     }
   } hs;
-  AMGF_HIP(hipHostMalloc(reinterpret_cast<void**>(&hs.p), 4 * sizeof(double)));
-  AMGF_HIP(hipEventCreateWithFlags(&hs.ev, hipEventDisableTiming));
-  double* s3 = hs.p;
+  double s3_stack[4] = {0.0, 0.0, 0.0, 0.0};
+  double* s3 = s3_stack;
+  if (!na) {
+    AMGF_HIP(hipHostMalloc(reinterpret_cast<void**>(&hs.p), 4 * sizeof(double)));
+    AMGF_HIP(hipEventCreateWithFlags(&hs.ev, hipEventDisableTiming));
+    s3 = hs.p;
+  }
   hipEvent_t ev = hs.ev;
   double rel_old = 1.0;                               // relative residual one step back
   h.cg_alpha.clear();
@@ -1165,32 +1224,35 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
       operator_apply(h, h.pp.p, h.pq.p, nullptr);     // q = A p
       const double* xs[1] = {h.pp.p};
       const double* ys[1] = {h.pq.p};
-      dots_device(c, n, 1, xs, ys, h.pcg_s.p);
+      dots_device(c, n, 1, xs, ys, dsc, dpart);
     }
-    pcg_update_xr_dev(c, n, rz, h.pcg_s.p, h.pp.p, h.pq.p, x, h.pr.p);
+    pcg_update_xr_dev(c, n, rz, dsc, h.pp.p, h.pq.p, x, h.pr.p);
     std::swap(h.pz, h.pzo);
     amgf_apply_impl(h, h.pr.p, h.pz.p);
     {
       const double* xs[2] = {h.pr.p, h.pr.p};
       const double* ys[2] = {h.pz.p, h.pzo.p};
-      dots_device(c, n, 2, xs, ys, h.pcg_s.p + 1);
+      dots_device(c, n, 2, xs, ys, dsc + 1, dpart);
     }
-    AMGF_HIP(hipMemcpyAsync(s3, h.pcg_s.p, 3 * sizeof(double), hipMemcpyDeviceToHost, c.s));
-    AMGF_HIP(hipEventRecord(ev, c.s));
+    AMGF_HIP(hipMemcpyAsync(s3, dsc, 3 * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    if (!na) AMGF_HIP(hipEventRecord(ev, c.s));
     have_q = it + 1 < h.opt.max_iters && rel * (rel / rel_old) > h.opt.rtol;
     if (have_q) {
-      pcg_update_p_dev(c, n, rz, h.pcg_s.p + 1, h.pz.p, h.pp.p);
+      pcg_update_p_dev(c, n, rz, dsc + 1, h.pz.p, h.pp.p);
       operator_apply(h, h.pp.p, h.pq.p, nullptr);
       const double* xs[1] = {h.pp.p};
       const double* ys[1] = {h.pq.p};
-      dots_device(c, n, 1, xs, ys, h.pcg_s.p);
+      dots_device(c, n, 1, xs, ys, dsc, dpart);
     }
-    AMGF_HIP(hipEventSynchronize(ev));
+    if (na) AMGF_HIP(hipStreamSynchronize(c.s));
+    else AMGF_HIP(hipEventSynchronize(ev));
     if (!(s3[0] > 0.0)) { st = AMGF_ENOTSPD; break; }  // p.q <= 0: not SPD
     d2[0] = s3[1];
     d2[1] = s3[2];
-    h.cg_alpha.push_back(rz / s3[0]);
-    h.cg_beta.push_back(d2[0] / rz);
+    if (!na) {                                        // (no host allocation when na)
+      h.cg_alpha.push_back(rz / s3[0]);
+      h.cg_beta.push_back(d2[0] / rz);
+    }
     ++it;
     const double rel_prev = rel;
     rel = std::sqrt(std::fabs(d2[0]) / rz0);
@@ -1201,25 +1263,30 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
     rz = d2[0];
     rel_old = rel_prev;
   }
-  AMGF_HIP(hipEventRecord(e1, c.s));
-  AMGF_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
-  AMGF_HIP(hipEventElapsedTime(&ms, e0, e1));
   float ms_ph[3] = {0.f, 0.f, 0.f};
-  for (size_t i = 0; i < h.ph_used; ++i) {
-    float t = 0.f;
-    AMGF_HIP(hipEventElapsedTime(&t, h.ph_ev[i], i + 1 < h.ph_used ? h.ph_ev[i + 1] : e1));
-    ms_ph[h.ph_cat[i]] += t;
+  if (!na) {
+    AMGF_HIP(hipEventRecord(evs.e1, c.s));
+    AMGF_HIP(hipEventSynchronize(evs.e1));
+    AMGF_HIP(hipEventElapsedTime(&ms, evs.e0, evs.e1));
+    for (size_t i = 0; i < h.ph_used; ++i) {
+      float t = 0.f;
+      AMGF_HIP(hipEventElapsedTime(&t, h.ph_ev[i],
+                                   i + 1 < h.ph_used ? h.ph_ev[i + 1] : evs.e1));
+      ms_ph[h.ph_cat[i]] += t;
+    }
+  } else {
+    AMGF_HIP(hipStreamSynchronize(c.s));
+    ms = float(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                         t_host0).count());
   }
   h.ph_on = false;
-  AMGF_HIP(hipEventDestroy(e0));
-  AMGF_HIP(hipEventDestroy(e1));
   if (info) {
     operator_apply(h, x, h.ra.p, b);
     double tr[2];
     const double* xs[2] = {h.ra.p, b};
     const double* ys[2] = {h.ra.p, b};
-    dots(c, n, 2, xs, ys, tr);
+    dots(c, n, 2, xs, ys, tr, dpart);
     info->iterations = it;
     info->converged = conv ? 1 : 0;
     info->n_levels = int(h.lev.size());
@@ -1452,6 +1519,7 @@ amgf_status amgf_setup(const amgf_options* opts, int32_t n_nodes, const int32_t*
     h.mem.a = h.opt.allocator;
     h.bind(stream);
     amgf::AllocScope scope_(&h.mem);
+    (void)amgf::scratch_ptr();                        // per-device scratch address, once
     h.ctx.flag.alloc(1);
     h.n_nodes = n_nodes;
     h.m = m;
@@ -1600,6 +1668,19 @@ amgf_status amgf_pcg(amgf_handle hd, const double* b, double* x, amgf_solve_info
     hd->h.bind(stream);
     amgf::AllocScope scope_(&hd->h.mem);
     return amgf::pcg_impl(hd->h, b, x, info);
+  });
+  if (st_ != AMGF_OK) return st_;
+  return AMGF_OK;
+}
+
+amgf_status amgf_pcg_noalloc(amgf_handle hd, const double* b, double* x,
+                             amgf_solve_info* info, void* stream) {
+  if (!hd || !b || !x) return AMGF_EINVAL;
+  amgf_status st_ = guard([&]() -> amgf_status {
+    hd->h.bind(stream);
+    amgf::AllocScope scope_(&hd->h.mem);
+    amgf::NoAllocScope no_alloc_;
+    return amgf::pcg_impl(hd->h, b, x, info, amgf::scratch_ptr());
   });
   if (st_ != AMGF_OK) return st_;
   return AMGF_OK;

@@ -82,13 +82,18 @@ void fill_power_start(Ctx& c, int64_t n, double* x, const unsigned char* dec);
 void weights_from_l1(Ctx& c, int64_t n, const double* d, const double* theta, double* w);
 void vscale(Ctx& c, int64_t n, double s, double* x);
 
-// deterministic dot products: out[i] = sum_k x_i[k] y_i[k] (host results)
+// deterministic dot products: out[i] = sum_k x_i[k] y_i[k] (host results), at most DOT_MAX
+// at once over a fixed grid of DOT_BLOCKS partial sums.  `part`: DOT_SCRATCH device doubles
+// for the partial sums, or nullptr for the context's own buffer (allocated on first use).
+constexpr int DOT_BLOCKS = 1024;
+constexpr int DOT_MAX = 4;
+constexpr size_t DOT_SCRATCH = size_t(DOT_MAX) * DOT_BLOCKS + DOT_MAX;
 void dots(Ctx& c, int64_t n, int nd, const double* const* xs, const double* const* ys,
-          double* out_host);
+          double* out_host, double* part = nullptr);
 
 // the same sums left in device memory (out_dev[0 .. nd-1]), stream-ordered, no wait
 void dots_device(Ctx& c, int64_t n, int nd, const double* const* xs, const double* const* ys,
-                 double* out_dev);
+                 double* out_dev, double* part = nullptr);
 
 // PCG updates
 void pcg_update_xr(Ctx& c, int64_t n, double alpha, const double* p, const double* q, double* x,

@@ -590,9 +590,6 @@ void check_nonnegative(Ctx& c, const double* v, int64_t n, int* flag) {
 // ======================================================================================
 // deterministic dots: fixed grid, per-block partials, single-block final sum
 // ======================================================================================
-constexpr int DOT_BLOCKS = 1024;
-constexpr int DOT_MAX = 4;
-
 struct DotArgs {
   const double* x[DOT_MAX];
   const double* y[DOT_MAX];
@@ -633,35 +630,40 @@ __global__ void __launch_bounds__(256) k_dot_final(int nd, const double* __restr
   }
 }
 
+// the partial sums (DOT_SCRATCH doubles): the caller's buffer, else the context's own
+static double* dot_partials(Ctx& c, double* part) {
+  if (part) return part;
+  if (c.dot.n == 0) c.dot.alloc(DOT_SCRATCH);
+  return c.dot.p;
+}
+
 void dots_device(Ctx& c, int64_t n, int nd, const double* const* xs, const double* const* ys,
-                 double* out_dev) {
+                 double* out_dev, double* part) {
   AMGF_REQUIRE(nd >= 1 && nd <= DOT_MAX, AMGF_EINVAL, "dots count");
-  if (c.dot.n == 0) c.dot.alloc(size_t(DOT_MAX) * DOT_BLOCKS + DOT_MAX);
+  double* pp = dot_partials(c, part);
   DotArgs a{};
   for (int d = 0; d < nd; ++d) {
     a.x[d] = xs[d];
     a.y[d] = ys[d];
   }
-  hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, nd, a, c.dot.p);
-  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, c.s, nd, c.dot.p, out_dev);
+  hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, nd, a, pp);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, c.s, nd, pp, out_dev);
   AMGF_LAUNCH_CHECK();
 }
 
 void dots(Ctx& c, int64_t n, int nd, const double* const* xs, const double* const* ys,
-          double* out_host) {
+          double* out_host, double* part) {
   AMGF_REQUIRE(nd >= 1 && nd <= DOT_MAX, AMGF_EINVAL, "dots count");
-  if (c.dot.n == 0) c.dot.alloc(size_t(DOT_MAX) * DOT_BLOCKS + DOT_MAX);
-  DBuf<double>* part = &c.dot;
+  double* pp = dot_partials(c, part);
   DotArgs a{};
   for (int d = 0; d < nd; ++d) {
     a.x[d] = xs[d];
     a.y[d] = ys[d];
   }
-  hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, nd, a, part->p);
-  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, c.s, nd, part->p,
-                     part->p + DOT_MAX * DOT_BLOCKS);
+  hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, nd, a, pp);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, c.s, nd, pp, pp + DOT_MAX * DOT_BLOCKS);
   AMGF_LAUNCH_CHECK();
-  AMGF_HIP(hipMemcpyAsync(out_host, part->p + DOT_MAX * DOT_BLOCKS, nd * sizeof(double),
+  AMGF_HIP(hipMemcpyAsync(out_host, pp + DOT_MAX * DOT_BLOCKS, nd * sizeof(double),
                           hipMemcpyDeviceToHost, c.s));
   AMGF_HIP(hipStreamSynchronize(c.s));
 }

@@ -56,6 +56,17 @@ struct AllocScope {
   AllocScope& operator=(const AllocScope&) = delete;
 };
 
+// Set while the allocation-free entry point runs: a device allocation there is a library
+// bug, reported as an error instead of being made.
+inline thread_local bool g_no_alloc = false;
+struct NoAllocScope {
+  bool prev;
+  NoAllocScope() : prev(g_no_alloc) { g_no_alloc = true; }
+  ~NoAllocScope() { g_no_alloc = prev; }
+  NoAllocScope(const NoAllocScope&) = delete;
+  NoAllocScope& operator=(const NoAllocScope&) = delete;
+};
+
 template <class T>
 struct DBuf {
   T* p = nullptr;
@@ -86,6 +97,8 @@ struct DBuf {
   void alloc(size_t count) {
     release();
     if (!count) return;
+    if (g_no_alloc)
+      throw Error(AMGF_EDEVICE, "internal: device allocation in the allocation-free entry point");
     const size_t bytes = count * sizeof(T);
     if (g_alloc && g_alloc->a.alloc) {
       void* q = g_alloc->a.alloc(bytes, g_alloc->s, g_alloc->a.ctx);

@@ -108,6 +108,12 @@ typedef struct {
                                  iteration start vector, zero on decoupled DOFs) is taken
                                  with each damping and the one with the smaller energy
                                  norm ||e1||_A is kept; 0: always the MLP damping        */
+  int32_t transfer_fp16;      /* mixed precisions: 1 (default) stores the prolongators
+                                 P_l and P_l^T of the V-cycle in FP16 (one rounding to
+                                 nearest even; |P| <= about 2 here, relative rounding
+                                 4.9e-4; FP32 if a value overflows) and applies them in
+                                 FP32; 0: FP32 values.  The Galerkin operators, the
+                                 FP64 V-cycle and every FP64 path keep FP64 P.          */
 } amgf_options;
 
 typedef struct {

@@ -80,7 +80,8 @@ class Options(ctypes.Structure):
                 ("mlp_weights", ctypes.POINTER(ctypes.c_float)),
                 ("sweeps", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
                 ("allocator", Allocator), ("bound_diag", ctypes.c_void_p),
-                ("near_null", ctypes.c_int32), ("learned_judge", ctypes.c_int32)]
+                ("near_null", ctypes.c_int32), ("learned_judge", ctypes.c_int32),
+                ("transfer_fp16", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

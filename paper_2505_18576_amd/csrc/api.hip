@@ -197,6 +197,18 @@ static double power_estimate(Handle& h, Level& L, const unsigned char* dec) {
   return lam;
 }
 
+// FP16 values of a transfer operator (FP32 when a value would overflow FP16)
+static void to_fp16_or_fp32(Ctx& c, BSR& A) {
+  const int64_t nv = std::max<int64_t>(A.nnzb, 1) * A.bsz();
+  A.valh.alloc(nv);
+  AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
+  cast_d2h(c, A.val.p, A.valh.p, nv, c.flag.p);
+  if (d2h_scalar(c.flag.p, c.s) == 0) return;
+  A.valh = DBuf<_Float16>();
+  A.val32.alloc(nv);
+  cast_d2f(c, A.val.p, A.val32.p, nv);
+}
+
 static void to_fp32(Ctx& c, BSR& A) {
   const int64_t nv = std::max<int64_t>(A.nnzb, 1) * A.bsz();
   A.val32.alloc(nv);
@@ -452,7 +464,15 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     }
     if (h.mixed()) {
       if (l != 0) to_fp32(c, L.K);
-      if (L.P.nnzb) { to_fp32(c, L.P); to_fp32(c, L.PT); }
+      if (L.P.nnzb) {
+        if (h.opt.transfer_fp16) {
+          to_fp16_or_fp32(c, L.P);
+          to_fp16_or_fp32(c, L.PT);
+        } else {
+          to_fp32(c, L.P);
+          to_fp32(c, L.PT);
+        }
+      }
       L.w32.alloc(n);
       cast_d2f(c, L.w.p, L.w32.p, n);
       L.fb.alloc(n); L.fx.alloc(n); L.fr.alloc(n); L.fxn.alloc(n);
@@ -614,6 +634,14 @@ static LvBufs<float> lv_bufs(Level& L, float) {
 static const double* bsr_vals(const BSR& A, double) { return A.val.p; }
 static const float* bsr_vals(const BSR& A, float) { return A.val32.p; }
 
+// restriction / prolongation in the V-cycle's precision (FP32: FP16 values when stored)
+static void transfer(Handle& h, int mode, const BSR& A, const double* x, double* y) {
+  bsr_spmv<double>(h.ctx, mode, A, A.val.p, x, y, nullptr, nullptr, nullptr);
+}
+static void transfer(Handle& h, int mode, const BSR& A, const float* x, float* y) {
+  transfer_spmv(h.ctx, mode, A, x, y);
+}
+
 // K x in the level's V-cycle precision (BF16 level-0 values in MIXED_BF16K)
 static void k_spmv(Handle& h, size_t l, int mode, const double* x, double* y, const double* b,
                    const double* w, double* xo) {
@@ -680,11 +708,9 @@ static void vcycle_general(Handle& h, size_t l, void (*coarse)(Handle&, size_t))
   for (int s = 0; s < h.opt.sweeps; ++s) smooth_once<T>(h, l, s == 0);
   k_spmv(h, l, SPMV_RES, B.x->p, B.r->p, B.b->p, (const T*)nullptr, (T*)nullptr);
   contact<T>(h, L, CT_SUB_RES, B.x->p, B.r->p, (const T*)nullptr);
-  bsr_spmv<T>(h.ctx, SPMV_Y, L.PT, bsr_vals(L.PT, T()), B.r->p, NB.b->p, nullptr, nullptr,
-              nullptr);
+  transfer(h, SPMV_Y, L.PT, B.r->p, NB.b->p);
   coarse(h, l + 1);
-  bsr_spmv<T>(h.ctx, SPMV_ADD, L.P, bsr_vals(L.P, T()), NB.x->p, B.x->p, nullptr, nullptr,
-              nullptr);
+  transfer(h, SPMV_ADD, L.P, NB.x->p, B.x->p);
   for (int s = 0; s < h.opt.sweeps; ++s) smooth_once<T>(h, l, false);
 }
 
@@ -741,9 +767,9 @@ static void vcycle32_from(Handle& h, size_t l, bool x0_ready) {
     bsr_spmv<float>(c, SPMV_RES, L.K, L.K.val32.p, L.fx.p, L.fr.p, L.fb.p, nullptr, nullptr);
   prof_end(h);
   level_contact<float>(h, L, CT_SUB_RES, L.fx.p, L.fr.p, nullptr);
-  bsr_spmv<float>(c, SPMV_Y, L.PT, L.PT.val32.p, L.fr.p, N.fb.p, nullptr, nullptr, nullptr);
+  transfer_spmv(c, SPMV_Y, L.PT, L.fr.p, N.fb.p);
   vcycle32(h, l + 1);
-  bsr_spmv<float>(c, SPMV_ADD, L.P, L.P.val32.p, N.fx.p, L.fx.p, nullptr, nullptr, nullptr);
+  transfer_spmv(c, SPMV_ADD, L.P, N.fx.p, L.fx.p);
   if (l == 0) prof_begin(h, AMGF_K_POSTSMOOTH);
   if (l == 0 && h.bf16k())
     sell_spmv_bf16(c, SPMV_POST, L.K, L.fx.p, nullptr, L.fb.p, L.w32.p, L.fxn.p);
@@ -910,7 +936,13 @@ static void judge_damping(Handle& h) {
   set_damping(h, nullptr);
   h.judge_p = reduction();
   if (h.judge_l <= h.judge_p) {
-    set_damping(h, h.mlpW.p);
+    // back to w = theta / d from the stored MLP damping (the same division mlp_theta made,
+    // so bitwise its weights, without evaluating the network again)
+    for (size_t l = 0; l + 1 < h.lev.size(); ++l) {
+      Level& L = *h.lev[l];
+      weights_from_l1(c, L.n(), L.d.p, L.theta.p, L.w.p);
+      if (h.mixed()) cast_d2f(c, L.w.p, L.w32.p, L.n());
+    }
   } else {
     h.learned = false;
     h.judge_rejected = true;
@@ -1459,6 +1491,7 @@ void amgf_default_options(amgf_options* o) {
   o->mlp_weights = nullptr;
   o->near_null = 6;
   o->learned_judge = 1;
+  o->transfer_fp16 = 1;
 }
 
 const char* amgf_status_string(amgf_status s) {

@@ -18,6 +18,13 @@ template <class T>
 void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, const T* b,
               const T* w, T* xo);
 
+// y = A x (SPMV_Y) or y += A x (SPMV_ADD) in FP32 with the FP16 values A.valh, or with the
+// FP32 values A.val32 when A has no FP16 copy (restriction and prolongation of the mixed
+// V-cycle)
+void transfer_spmv(Ctx& c, int mode, const BSR& A, const float* x, float* y);
+// b = FP16(a), one rounding to nearest even; *flag |= 1 when a value overflows FP16
+void cast_d2h(Ctx& c, const double* a, _Float16* b, int64_t n, int* flag);
+
 // Build the sliced-ELL copy (FP64 values when fp64, FP32 values when fp32) of a 3x3
 // BSR matrix; bsr_spmv then reads it in place of the BSR arrays.
 void bsr_build_sell(Ctx& c, BSR& A, bool fp64, bool fp32, bool bf16 = false);

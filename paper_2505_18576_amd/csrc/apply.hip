@@ -8,12 +8,32 @@ namespace amgf {
 // ======================================================================================
 // BSR SpMV with fused smoother modes
 // ======================================================================================
+// one block's N values widened to T: FP16 blocks of even size as 2-value loads (the block
+// starts on a 4-byte boundary), everything else value by value
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+template <int N, class T, class TV>
+__device__ __forceinline__ void load_block(const TV* __restrict__ v, T* out) {
+  if constexpr (sizeof(TV) == 2 && N % 2 == 0) {
+    const half2v* v2 = reinterpret_cast<const half2v*>(v);
+#pragma unroll
+    for (int k = 0; k < N / 2; ++k) {
+      const half2v h = v2[k];
+      out[2 * k] = T(h.x);
+      out[2 * k + 1] = T(h.y);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[k] = T(v[k]);
+  }
+}
+
 // G lanes cooperate on one block row; lane l takes blocks l, l+G, ...; the BR partial
-// row sums are reduced across the G lanes and lane p < BR writes output p.
-template <int BR, int BC, int G, class T, int MODE>
+// row sums are reduced across the G lanes and lane p < BR writes output p.  Values of type
+// TV (T, or FP16 for the transfer operators) are widened to T.
+template <int BR, int BC, int G, class T, int MODE, class TV = T>
 __global__ void __launch_bounds__(256) k_bsr(int nrows, const int* __restrict__ rp,
                                              const int* __restrict__ col,
-                                             const T* __restrict__ val, const T* __restrict__ x,
+                                             const TV* __restrict__ val, const T* __restrict__ x,
                                              T* __restrict__ y, const T* __restrict__ b,
                                              const T* __restrict__ w, T* __restrict__ xo) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -31,7 +51,8 @@ __global__ void __launch_bounds__(256) k_bsr(int nrows, const int* __restrict__ 
       const int64_t ix = int64_t(cc) * BC + q;
       xv[q] = (MODE == SPMV_PRE) ? w[ix] * b[ix] : x[ix];
     }
-    const T* v = val + int64_t(j) * (BR * BC);
+    T v[BR * BC];
+    load_block<BR * BC>(val + int64_t(j) * (BR * BC), v);
 #pragma unroll
     for (int p = 0; p < BR; ++p)
 #pragma unroll
@@ -123,6 +144,55 @@ static void launch_bsr(Ctx& c, int mode, const BSR& A, const T* val, const T* x,
     default:
       throw Error(AMGF_EINVAL, "spmv mode");
   }
+  AMGF_LAUNCH_CHECK();
+}
+
+// y = A x or y += A x with FP16 values (the mixed V-cycle's restriction and prolongation)
+template <int BR, int BC, int G>
+static void launch_bsr_h(Ctx& c, int mode, const BSR& A, const float* x, float* y) {
+  const int64_t threads = int64_t(A.nrows) * G;
+  const dim3 g(grid_for(threads, 256)), blk(256);
+  if (mode == SPMV_Y)
+    hipLaunchKernelGGL((k_bsr<BR, BC, G, float, SPMV_Y, _Float16>), g, blk, 0, c.s, A.nrows,
+                       A.rowptr.p, A.col.p, A.valh.p, x, y, nullptr, nullptr, nullptr);
+  else if (mode == SPMV_ADD)
+    hipLaunchKernelGGL((k_bsr<BR, BC, G, float, SPMV_ADD, _Float16>), g, blk, 0, c.s, A.nrows,
+                       A.rowptr.p, A.col.p, A.valh.p, x, y, nullptr, nullptr, nullptr);
+  else
+    throw Error(AMGF_EINVAL, "FP16 spmv mode");
+  AMGF_LAUNCH_CHECK();
+}
+
+void transfer_spmv(Ctx& c, int mode, const BSR& A, const float* x, float* y) {
+  if (A.nrows == 0) return;
+  if (!A.valh.p) return bsr_spmv<float>(c, mode, A, A.val32.p, x, y, nullptr, nullptr, nullptr);
+  const double avg = double(A.nnzb) / A.nrows;
+  if (A.br == 3 && A.bc == 3) return launch_bsr_h<3, 3, 8>(c, mode, A, x, y);
+  if (A.br == 3 && A.bc == 6) return launch_bsr_h<3, 6, 8>(c, mode, A, x, y);
+  if (A.br == 6 && A.bc == 3) return launch_bsr_h<6, 3, 64>(c, mode, A, x, y);
+  if (A.br == 6 && A.bc == 6) {
+    if (avg > 24) return launch_bsr_h<6, 6, 64>(c, mode, A, x, y);
+    return launch_bsr_h<6, 6, 16>(c, mode, A, x, y);
+  }
+  throw Error(AMGF_EINVAL, "FP16 spmv block size");
+}
+
+// FP64 -> FP16 with one rounding to nearest even (truncate to FP32, mark inexactness in the
+// last bit, then the hardware's nearest-even FP32 -> FP16); flag bit 1 on a non-finite
+// result (a value beyond the FP16 range)
+__global__ void k_d2h(const double* __restrict__ a, _Float16* __restrict__ b, int64_t n,
+                      int* __restrict__ flag) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = a[i];
+  float f = __double2float_rz(v);
+  if (double(f) != v) f = __uint_as_float(__float_as_uint(f) | 1u);
+  const _Float16 h = _Float16(f);
+  b[i] = h;
+  if (!__builtin_isfinite(float(h))) atomicOr(flag, 1);
+}
+void cast_d2h(Ctx& c, const double* a, _Float16* b, int64_t n, int* flag) {
+  if (n) hipLaunchKernelGGL(k_d2h, dim3(grid_for(n, 256)), dim3(256), 0, c.s, a, b, n, flag);
   AMGF_LAUNCH_CHECK();
 }
 

@@ -139,6 +139,7 @@ struct BSR {
   DBuf<int> rowptr, col;
   DBuf<double> val;
   DBuf<float> val32;       // FP32 copy used by the mixed-precision V-cycle
+  DBuf<_Float16> valh;     // FP16 copy (transfer operators of the mixed V-cycle)
   // Sliced-ELL copy of a 3x3 matrix for the apply phase (built by bsr_build_sell):
   // slices of 64 block rows, each padded to its longest row.  Slot j of slice s holds
   // the column ids at sell_col[sell_off[s] + 64 j + i] and entry (p,q) of row i's block

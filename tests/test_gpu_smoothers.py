@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from oracle_util import extended_solution
-from gpu_util import gpu, oracle, problem, rel
+from gpu_util import MIXED_TOL, gpu, oracle, problem, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -64,7 +64,7 @@ def test_mixed_chebyshev_close_to_fp64(precision):
     rng = np.random.default_rng(4)
     r = rng.standard_normal(o.n)
     e_b = rel(h.vcycle(r).cpu().numpy(), o.vcycle(r))
-    tol = 1e-4 if precision == 1 else 2e-2
+    tol = MIXED_TOL if precision == 1 else 2e-2
     print(f"precision {precision} Chebyshev vcycle rel {e_b:.2e}")
     assert e_b <= tol
     x, info = h.pcg(problem("C1").b)

@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from gpu_util import gpu, oracle, problem, rel
+from gpu_util import MIXED_TOL, MIXED_TOL_FP32_TRANSFERS, gpu, oracle, problem, rel
 from oracle_util import extended_solution
 
 pytestmark = pytest.mark.gpu
@@ -49,11 +49,13 @@ def test_apply_fp64_tight_for_moderate_barrier():
     h.close()
 
 
-@pytest.mark.parametrize("precision,tol", [(1, 1e-4), (2, 2e-2)])
-def test_apply_mixed_precision_close_to_fp64(precision, tol):
-    # FP32 values: relative rounding 6e-8 per entry; BF16 values (precision 2): 3.9e-3
+@pytest.mark.parametrize("precision,fp16,tol", [(1, 1, MIXED_TOL), (2, 1, 2e-2),
+                                                (1, 0, MIXED_TOL_FP32_TRANSFERS)])
+def test_apply_mixed_precision_close_to_fp64(precision, fp16, tol):
+    # FP32 values: relative rounding 6e-8 per entry; FP16 transfer values 4.9e-4; BF16
+    # stiffness values (precision 2): 3.9e-3
     o = oracle("C1")
-    h = gpu("C1", precision=precision)
+    h = gpu("C1", precision=precision, transfer_fp16=fp16)
     rng = np.random.default_rng(2)
     r = rng.standard_normal(o.n)
     e_b = rel(h.vcycle(r).cpu().numpy(), o.vcycle(r))
@@ -156,12 +158,12 @@ def test_three_level_vcycle_and_apply_match_oracle(kw):
     e_b = rel(h.vcycle(r).cpu().numpy(), o.vcycle(r))
     e_m = rel(h.apply(r).cpu().numpy(), o.apply(r))
     print(f"C2 {kw}: levels {h.n_levels}, vcycle rel {e_b:.2e}, apply rel {e_m:.2e}")
-    tol = 1e-4 if kw.get("precision") else 1e-10
+    tol = MIXED_TOL if kw.get("precision") else 1e-10
     assert e_b <= tol
     # the residual r - A z inside M cancels on contact rows: FP64 error about u * D_max |z|
     u = np.finfo(np.float64).eps / 2
     dmax = float(problem("C2").D.max())
-    assert e_m <= max(1e-4 if kw.get("precision") else 0.0, 10 * u * dmax)
+    assert e_m <= max(MIXED_TOL if kw.get("precision") else 0.0, 10 * u * dmax)
     h.close()
 
 

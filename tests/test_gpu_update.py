@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from gpu_util import gpu, problem, rel
+from gpu_util import MIXED_TOL, gpu, problem, rel
 from oracle import OracleAMGF, OracleOptions
 
 pytestmark = pytest.mark.gpu
@@ -44,8 +44,8 @@ def test_update_matches_oracle(name, kw):
     # coarse contact blocks are Galerkin products on the GPU and J-based in the oracle: the
     # two roundings differ by about u * D_max on the contact directions
     u = np.finfo(np.float64).eps / 2
-    assert e_b <= (1e-4 if kw.get("precision") else max(1e-10, u * D2.max()))
-    assert e_m <= max(1e-4 if kw.get("precision") else 0.0, 10 * u * D2.max())
+    assert e_b <= (MIXED_TOL if kw.get("precision") else max(1e-10, u * D2.max()))
+    assert e_m <= max(MIXED_TOL if kw.get("precision") else 0.0, 10 * u * D2.max())
     if name == "C1":
         ref = o.pcg(p.b)
         x, info = h.pcg(p.b)

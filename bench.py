@@ -47,8 +47,9 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def vcycle_bytes(h, vbytes, k0bytes=None):
-    """Algorithmic HBM bytes of one V(1,1) (values of `vbytes` bytes, int32 indices).
+def vcycle_bytes(h, vbytes, k0bytes=None, pbytes_v=None):
+    """Algorithmic HBM bytes of one V(1,1) (values of `vbytes` bytes, int32 indices;
+    level-0 stiffness values of `k0bytes`, transfer-operator values of `pbytes_v`).
 
     Per non-coarsest level: pre-smooth (x = w.b: w, b read, x written; then K read, x
     gathered, b read, r written),
@@ -70,7 +71,7 @@ def vcycle_bytes(h, vbytes, k0bytes=None):
         bc = int(h.query(l + 1, b.Q_SIZES)[1])           # coarse DOFs per node
         kv = k0bytes if (l == 0 and k0bytes) else vbytes
         kbytes = nnzK * (bs * bs * kv + ib) + (nn + 1) * 4
-        pbytes = nnzP * (bs * bc * vbytes + 4) + (nn + 1) * 4
+        pbytes = nnzP * (bs * bc * (pbytes_v or vbytes) + 4) + (nn + 1) * 4
         total += kbytes + 6 * n * vbytes                    # pre-smooth
         total += pbytes + n * vbytes + n_agg * bc * vbytes      # restrict (P^T has P's size)
         total += pbytes + n_agg * bc * vbytes + 2 * n * vbytes  # prolong
@@ -213,8 +214,20 @@ def iteration_bound(N, config_p):
     bound = math.ceil(math.sqrt(2.0 * (beta + 3.0) / beta) * info.iterations)
     log(f"contact-free AMG-PCG N={N}: {info.iterations} it, Lanczos [{lo:.3e}, {hi:.3e}], "
         f"beta {beta:.2f}, bound {bound}")
-    return dict(its_contact_free=int(info.iterations), lanczos_min=lo, lanczos_max=hi,
-                beta=beta, bound=int(bound))
+    its_cf = int(info.iterations)
+    del cf
+    # the same contact problem with the top face clamped as in its contact-free twin (the
+    # paper's two-block runs are driven by a Dirichlet top face): FP64 plain AMGF-PCG
+    tw = make_two_block(N, E=mt["E"], nu=mt["nu"], top_bc="clamped", D=config_p.D,
+                        rhs_seed=mt["rhs_seed"])
+    h = AMGF.from_problem(tw, allocator="torch")
+    x, info = h.pcg(tw.b)
+    h.close()
+    del x, tw
+    torch.cuda.empty_cache()
+    log(f"clamped-top contact twin N={N}: FP64 plain AMGF-PCG {info.iterations} it")
+    return dict(its_contact_free=its_cf, lanczos_min=lo, lanczos_max=hi, beta=beta,
+                bound=int(bound), amgf_iterations_clamped_top_fp64=int(info.iterations))
 
 
 def ip_bench(args):
@@ -392,7 +405,10 @@ def main():
                          judge_plain=float(info.judge_plain),
                          smoother_ms_live=live_ms, smoother_launches_live=live_n,
                          smoother_ms=ms_pre, smoother_bytes=smoother_bytes(h, vb, kb),
-                         vcycle_ms=ms_vc, vcycle_bytes=vcycle_bytes(h, vb, kb),
+                         vcycle_ms=ms_vc,
+                         vcycle_bytes=vcycle_bytes(h, vb, kb,
+                                                   2 if (prec != b.FP64 and
+                                                         h.options.transfer_fp16) else vb),
                          operator_ms=ms_op,
                          x=x)
         h.close()

@@ -218,23 +218,17 @@ static void to_fp32(Ctx& c, BSR& A) {
 // ------------------------------------------------------------------------------------
 // setup pieces shared with the numeric re-setup of a new barrier diagonal
 // ------------------------------------------------------------------------------------
-// The contact term of a coarse level inside the V-cycle: through J_l and D (two short
-// kernels, t = D (J_l x), then J_l^T t) when that reads fewer bytes than the assembled
-// Galerkin block C_l and no node row of J_l^T is long (the kernel gives a row eight lanes);
-// otherwise through C_l (one wavefront per row).  Near the interface J_l stays narrow while
-// C_l couples every pair of coarse nodes two constraints apart; on the deepest levels a
-// coarse node meets thousands of constraints and C_l is the small one.
-constexpr int CONTACT_FACTORED_MAX_ROW = 256;
-
-static bool factored_contact_pays(Ctx& c, const Level& L) {
+// The contact term of a coarse level inside the V-cycle: through J_l and D (two kernels,
+// t = D (J_l x), then J_l^T t) when that reads fewer bytes than the assembled Galerkin
+// block C_l, otherwise through C_l (one wavefront per row).  C_l couples every pair of
+// coarse nodes that share a constraint, so it holds b^2 values per coupling where J_l holds
+// b per constraint and node.
+static bool factored_contact_pays(Ctx&, const Level& L) {
   if (L.J.nnzb == 0 || L.ncrows == 0) return false;
-  std::vector<int> rp = d2h(L.JT.rowptr.p, size_t(L.nn) + 1, c.s);
-  int longest = 0;
-  for (int a = 0; a < L.nn; ++a) longest = std::max(longest, rp[a + 1] - rp[a]);
   const int64_t b = L.b;
   const int64_t factored = 2 * L.J.nnzb * (8 * b + 4) + 2 * int64_t(L.J.nrows) * 8;
   const int64_t assembled = L.C.nnzb * (8 * b * b + 4);
-  return longest <= CONTACT_FACTORED_MAX_ROW && factored < assembled;
+  return factored < assembled;
 }
 
 // direct factor of the coarsest operator

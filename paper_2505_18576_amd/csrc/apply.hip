@@ -253,8 +253,9 @@ __global__ void __launch_bounds__(256) k_contact_t(int m, const int* __restrict_
   if (lane == 0) t[k] = D[k] * s;
 }
 
-// y_a (op)= (J^T t)_a over the listed node rows: CT_G lanes per row.
-template <int B, class TY, int MODE>
+// y_a (op)= (J^T t)_a over the listed node rows: G lanes per row (CT_G for the short rows
+// of the fine interface, a wavefront where a coarse node meets hundreds of constraints).
+template <int B, class TY, int MODE, int G>
 __global__ void __launch_bounds__(256) k_contact_y(int nrows, const int* __restrict__ rows,
                                                    const int* __restrict__ rp,
                                                    const int* __restrict__ col,
@@ -262,21 +263,21 @@ __global__ void __launch_bounds__(256) k_contact_y(int nrows, const int* __restr
                                                    const double* __restrict__ t,
                                                    TY* __restrict__ y,
                                                    const TY* __restrict__ w) {
-  static_assert(B <= CT_G, "one lane per output component");
+  static_assert(B <= G, "one lane per output component");
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = gid / CT_G, lane = gid % CT_G;
+  const int i = gid / G, lane = gid % G;
   if (i >= nrows) return;
   const int a = rows[i];
   double acc[B];
 #pragma unroll
   for (int p = 0; p < B; ++p) acc[p] = 0.0;
-  for (int k = rp[a] + lane; k < rp[a + 1]; k += CT_G) {
+  for (int k = rp[a] + lane; k < rp[a + 1]; k += G) {
     const double tk = t[col[k]];
 #pragma unroll
     for (int p = 0; p < B; ++p) acc[p] += val[int64_t(k) * B + p] * tk;
   }
 #pragma unroll
-  for (int p = 0; p < B; ++p) acc[p] = group_sum(acc[p], CT_G);
+  for (int p = 0; p < B; ++p) acc[p] = group_sum(acc[p], G);
   if (lane >= B) return;
   double v = 0.0;
 #pragma unroll
@@ -288,31 +289,40 @@ __global__ void __launch_bounds__(256) k_contact_y(int nrows, const int* __restr
   else y[ix] = TY(double(y[ix]) + v);
 }
 
+template <int B, int G, class TY>
+static void launch_contact_y(Ctx& c, int mode, const BSR& JT, const int* crows, int ncrows,
+                             const double* t, TY* y, const TY* w) {
+  const dim3 gn(grid_for(int64_t(ncrows) * G, 256)), blk(256);
+  if (mode == CT_SUB_RES)
+    hipLaunchKernelGGL((k_contact_y<B, TY, CT_SUB_RES, G>), gn, blk, 0, c.s, ncrows, crows,
+                       JT.rowptr.p, JT.col.p, JT.val.p, t, y, w);
+  else if (mode == CT_SUB_W)
+    hipLaunchKernelGGL((k_contact_y<B, TY, CT_SUB_W, G>), gn, blk, 0, c.s, ncrows, crows,
+                       JT.rowptr.p, JT.col.p, JT.val.p, t, y, w);
+  else
+    hipLaunchKernelGGL((k_contact_y<B, TY, CT_ADD, G>), gn, blk, 0, c.s, ncrows, crows,
+                       JT.rowptr.p, JT.col.p, JT.val.p, t, y, w);
+}
+
 template <class TX, class TY>
 void contact_apply(Ctx& c, int mode, const BSR& J, const BSR& JT, const int* crows, int ncrows,
                    const double* D, const TX* x, double* t, TY* y, const TY* w) {
   if (J.nrows == 0 || J.nnzb == 0 || ncrows == 0) return;
   const int m = J.nrows;
-  const dim3 gm(grid_for(int64_t(m) * CT_G, 256)), gn(grid_for(int64_t(ncrows) * CT_G, 256)),
-      blk(256);
-#define AMGF_CT(BB)                                                                          \
-  hipLaunchKernelGGL((k_contact_t<BB, TX>), gm, blk, 0, c.s, m, J.rowptr.p, J.col.p,        \
-                     J.val.p, D, x, t);                                                      \
-  if (mode == CT_SUB_RES)                                                                    \
-    hipLaunchKernelGGL((k_contact_y<BB, TY, CT_SUB_RES>), gn, blk, 0, c.s, ncrows, crows,    \
-                       JT.rowptr.p, JT.col.p, JT.val.p, t, y, w);                            \
-  else if (mode == CT_SUB_W)                                                                 \
-    hipLaunchKernelGGL((k_contact_y<BB, TY, CT_SUB_W>), gn, blk, 0, c.s, ncrows, crows,      \
-                       JT.rowptr.p, JT.col.p, JT.val.p, t, y, w);                            \
-  else                                                                                       \
-    hipLaunchKernelGGL((k_contact_y<BB, TY, CT_ADD>), gn, blk, 0, c.s, ncrows, crows,        \
-                       JT.rowptr.p, JT.col.p, JT.val.p, t, y, w);
+  const dim3 gm(grid_for(int64_t(m) * CT_G, 256)), blk(256);
+  // a wavefront per J^T row once the rows average more constraints than a wavefront has lanes
+  const bool wide = JT.nnzb > int64_t(64) * ncrows;
   if (J.bc == 3) {
-    AMGF_CT(3)
+    hipLaunchKernelGGL((k_contact_t<3, TX>), gm, blk, 0, c.s, m, J.rowptr.p, J.col.p, J.val.p,
+                       D, x, t);
+    if (wide) launch_contact_y<3, 64>(c, mode, JT, crows, ncrows, t, y, w);
+    else launch_contact_y<3, CT_G>(c, mode, JT, crows, ncrows, t, y, w);
   } else {
-    AMGF_CT(6)
+    hipLaunchKernelGGL((k_contact_t<6, TX>), gm, blk, 0, c.s, m, J.rowptr.p, J.col.p, J.val.p,
+                       D, x, t);
+    if (wide) launch_contact_y<6, 64>(c, mode, JT, crows, ncrows, t, y, w);
+    else launch_contact_y<6, CT_G>(c, mode, JT, crows, ncrows, t, y, w);
   }
-#undef AMGF_CT
   AMGF_LAUNCH_CHECK();
 }
 template void contact_apply<double, double>(Ctx&, int, const BSR&, const BSR&, const int*, int,

@@ -106,8 +106,9 @@ typedef struct {
                                  at every setup and update of D, one AMGF step
                                  e1 = (I - M A) e0 from a fixed start e0 (the power-
                                  iteration start vector, zero on decoupled DOFs) is taken
-                                 with each damping and the one with the smaller energy
-                                 norm ||e1||_A is kept; 0: always the MLP damping        */
+                                 with each damping; the MLP damping is kept unless theta
+                                 = 1 leaves an energy norm ||e1||_A smaller by more than
+                                 a factor 1.25; 0: always the MLP damping               */
   int32_t transfer_fp16;      /* mixed precisions: 1 (default) stores the prolongators
                                  P_l and P_l^T of the V-cycle in FP16 (one rounding to
                                  nearest even; |P| <= about 2 here, relative rounding

@@ -195,12 +195,20 @@ def loss_grad(o: OracleAMGF, W, probes, k=2, feats=None):
     return tot / npb, g
 
 
+# the MLP damping is kept unless theta = 1 leaves a one-step error smaller by more than this
+JUDGE_MARGIN = 1.25
+
+
+def judge_keeps_mlp(ratio_mlp, ratio_plain):
+    return ratio_mlp <= JUDGE_MARGIN * ratio_plain
+
+
 def judge(o: OracleAMGF, W, feats=None):
     """The judge of the learned damping: energy-norm error after one AMGF step
     e1 = (I - M A) e0 from the power-iteration start e0 (zero on the decoupled level-0
     DOFs), with the MLP damping and with theta = 1.  Returns (ratio_mlp, ratio_plain),
-    each ||e1||_A / ||e0||_A; the MLP damping is kept when ratio_mlp <= ratio_plain.
-    Leaves the oracle with theta = 1."""
+    each ||e1||_A / ||e0||_A; ``judge_keeps_mlp`` decides.  Leaves the oracle with
+    theta = 1."""
     from .amgf_oracle import power_start
     e0 = power_start(o.n)
     dec = getattr(o.levels[0], "decoupled", None)

@@ -899,9 +899,14 @@ static void set_damping(Handle& h, const float* W);
 
 // The judge of the learned damping: one AMGF error-propagation step e1 = e0 - M A e0 from
 // the fixed start e0 (the power-iteration start, zero on decoupled DOFs) with the MLP
-// damping and with theta = 1; the damping with the smaller energy norm ||e1||_A stays
-// (ties keep the MLP).  Plain l1-Jacobi is thereby the reference the learned damping has
-// to beat on every system it is set up for.
+// damping and with theta = 1.  Plain l1-Jacobi is the reference the learned damping has to
+// beat on every system it is set up for: the MLP damping stays unless theta = 1 leaves an
+// energy-norm error smaller by more than JUDGE_MARGIN.  One step from one start vector
+// ranks clear differences (3x in favour of the MLP on the trained workloads, 18x against
+// it with bound-constraint terms it never saw) but not near-ties, where the CG counts can
+// go either way (C3: 9.81e-5 against 9.73e-5, 233 iterations with the MLP, 248 without).
+constexpr double JUDGE_MARGIN = 1.25;
+
 static void judge_damping(Handle& h) {
   h.judge_rejected = false;
   if (!h.judge_on || !h.learned) return;
@@ -929,7 +934,7 @@ static void judge_damping(Handle& h) {
   h.judge_l = reduction();
   set_damping(h, nullptr);
   h.judge_p = reduction();
-  if (h.judge_l <= h.judge_p) {
+  if (h.judge_l <= JUDGE_MARGIN * h.judge_p) {
     // back to w = theta / d from the stored MLP damping (the same division mlp_theta made,
     // so bitwise its weights, without evaluating the network again)
     for (size_t l = 0; l + 1 < h.lev.size(); ++l) {

@@ -777,7 +777,7 @@ __device__ void mf_fwd_rows(int t, int blk, const int* __restrict__ fS,
     const double fj = f[j];
     double v[MF_R];
 #pragma unroll
-    for (int q = 0; q < MF_R; ++q) v[q] = rowp[q][j];   // j < jmax <= S: inside the row
+    for (int q = 0; q < MF_R; ++q) v[q] = ld_stream(&rowp[q][j]);   // j < jmax <= S: inside the row
 #pragma unroll
     for (int q = 0; q < MF_R; ++q)
       if (j < jend[q]) acc[q] += v[q] * fj;
@@ -872,7 +872,7 @@ __global__ void __launch_bounds__(256) k_mf_bwd(const int* __restrict__ wl, int 
     const double yi = y[i];
     double v[MF_R];
 #pragma unroll
-    for (int q = 0; q < MF_R; ++q) v[q] = rowp[q][i];
+    for (int q = 0; q < MF_R; ++q) v[q] = ld_stream(&rowp[q][i]);
 #pragma unroll
     for (int q = 0; q < MF_R; ++q)
       if (j0 + q < s) acc[q] += v[q] * yi;
@@ -882,7 +882,7 @@ __global__ void __launch_bounds__(256) k_mf_bwd(const int* __restrict__ wl, int 
     const double xb = staged ? xbs[m] : x[mf_bnd_dof(t, m, bs, bnd_off, bnd)];
     double v[MF_R];
 #pragma unroll
-    for (int q = 0; q < MF_R; ++q) v[q] = rowp[q][S + m];
+    for (int q = 0; q < MF_R; ++q) v[q] = ld_stream(&rowp[q][S + m]);
 #pragma unroll
     for (int q = 0; q < MF_R; ++q)
       if (j0 + q < s) acc[q] -= v[q] * xb;

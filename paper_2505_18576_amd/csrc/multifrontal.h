@@ -12,6 +12,7 @@ struct MFSolver {
   std::vector<int> h_s, h_S, h_b, h_T;   // per supernode (host): separator DOFs, padded,
                                          // boundary DOFs, 64-row tiles of the front
   std::vector<int> wl_fwd_off, wl_bwd_off;  // per depth: range of its solve work lists
+  std::vector<int> ks_fwd, ks_bwd;          // per depth: column split of its solve kernels
   DBuf<int> wl_fwd, wl_bwd;                 // (supernode, row block) pairs of the solve
   std::vector<int> fp_max;                  // per depth: largest front (padded rows)
   // device: ordering and symbolic structure

@@ -744,19 +744,49 @@ constexpr int MF_FL = 8192;   // front right-hand side a forward workgroup assem
 // pairs built at setup, so the grid holds exactly the workgroups the fronts of a depth
 // need (a grid sized by the depth's widest front was mostly idle workgroups).
 
-// [y; u] = [X; -G] f_s + [0; f_b]: rows i0 .. i0+MF_R-1 of M on one wavefront, f the
-// front's right-hand side
+// Column split of the solve kernels: KS = 1, each wavefront of a workgroup takes MF_R rows
+// of its own (4 * MF_R rows per workgroup); KS = 4, the four wavefronts share MF_R rows and
+// take every fourth 64-column stretch of them, the partial sums meeting in LDS (fixed
+// order).  The shallow tree depths hold few fronts with long rows: there KS = 4 gives the
+// chip four times the wavefronts and each one a quarter of the dependent loads.
+constexpr int MF_KS = 4;
+constexpr int MF_SPLIT_WG = 512;   // a depth with fewer row-group workgroups splits columns
+
+// sum of the KS wavefronts' partial sums of rows lane < MF_R, in wavefront order (KS > 1);
+// every wavefront of the workgroup calls it
+template <int KS>
+__device__ __forceinline__ double mf_split_sum(double mine) {
+  if constexpr (KS == 1) {
+    return mine;
+  } else {
+    __shared__ double part[KS][MF_R];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane < MF_R) part[wv][lane] = mine;
+    __syncthreads();
+    double s = 0.0;
+    if (lane < MF_R)
+#pragma unroll
+      for (int k = 0; k < KS; ++k) s += part[k][lane];
+    return s;
+  }
+}
+
+// [y; u] = [X; -G] f_s + [0; f_b]: rows i0 .. i0+MF_R-1 of M, f the front's right-hand side
+// (KS = 1: one wavefront per row group; KS = 4: the workgroup's four wavefronts split the
+// columns).  With KS = 4 every wavefront of the workgroup reaches the LDS sum: i0, S and
+// rows are the same for all of them.
+template <int KS>
 __device__ void mf_fwd_rows(int t, int blk, const int* __restrict__ fS,
                             const int* __restrict__ fb, const int64_t* __restrict__ mo,
                             const int64_t* __restrict__ vo, const double* __restrict__ M,
                             const double* f, double* __restrict__ fv) {
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int S = fS[t], rows = S + fb[t];
-  const int i0 = (blk * 4 + (threadIdx.x >> 6)) * MF_R;
+  const int i0 = (KS == 1 ? blk * 4 + wv : blk) * MF_R;
   if (i0 >= rows) return;
   double* out = fv + vo[t];
   if (S == 0) {
-    if (lane < MF_R && i0 + lane < rows) out[i0 + lane] = f[i0 + lane];
+    if ((KS == 1 || wv == 0) && lane < MF_R && i0 + lane < rows) out[i0 + lane] = f[i0 + lane];
     return;
   }
   const double* rowp[MF_R];
@@ -773,7 +803,7 @@ __device__ void mf_fwd_rows(int t, int blk, const int* __restrict__ fS,
 #pragma unroll
   for (int q = 0; q < MF_R; ++q) acc[q] = 0.0;
 #pragma unroll 4
-  for (int j = lane; j < jmax; j += 64) {
+  for (int j = (KS == 1 ? 0 : wv * 64) + lane; j < jmax; j += 64 * KS) {
     const double fj = f[j];
     double v[MF_R];
 #pragma unroll
@@ -788,11 +818,13 @@ __device__ void mf_fwd_rows(int t, int blk, const int* __restrict__ fS,
     const double r = wave_sum(acc[q]);
     if (lane == q) mine = r;
   }
+  mine = mf_split_sum<KS>(mine);
   const int i = i0 + lane;
-  if (lane < MF_R && i < rows) out[i] = i < S ? mine : f[i] - mine;
+  if ((KS == 1 || wv == 0) && lane < MF_R && i < rows) out[i] = i < S ? mine : f[i] - mine;
 }
 
 // forward rows with the right-hand side from fa (assembled by k_mf_rhs)
+template <int KS>
 __global__ void __launch_bounds__(256) k_mf_fwd(const int* __restrict__ wl,
                                                 const int* __restrict__ fS,
                                                 const int* __restrict__ fb,
@@ -802,13 +834,14 @@ __global__ void __launch_bounds__(256) k_mf_fwd(const int* __restrict__ wl,
                                                 const double* __restrict__ fa,
                                                 double* __restrict__ fv) {
   const int t = wl[2 * blockIdx.x], blk = wl[2 * blockIdx.x + 1];
-  mf_fwd_rows(t, blk, fS, fb, mo, vo, M, fa + vo[t], fv);
+  mf_fwd_rows<KS>(t, blk, fS, fb, mo, vo, M, fa + vo[t], fv);
 }
 
 // forward rows with the right-hand side assembled by the workgroup itself in LDS: every
 // workgroup of a front repeats the assembly (a few loads per row of the front against the
 // MF_R rows of the factor each wave reads), which saves the separate assembly launch of
 // every depth
+template <int KS>
 __global__ void __launch_bounds__(256) k_mf_fwd_lds(const int* __restrict__ wl, int bs,
                                                     const double* __restrict__ r,
                                                     const int* __restrict__ soff,
@@ -830,10 +863,12 @@ __global__ void __launch_bounds__(256) k_mf_fwd_lds(const int* __restrict__ wl, 
   mf_front_rhs(t, bs, r, soff, sperm, child0, child1, bnd_off, bnd_pos, fs, fS, fb, fT, vo, fv,
                fl);
   __syncthreads();
-  mf_fwd_rows(t, blk, fS, fb, mo, vo, M, fl, fv);
+  mf_fwd_rows<KS>(t, blk, fS, fb, mo, vo, M, fl, fv);
 }
 
-// x_s = X^T y - G^T x_b: separator rows j0 .. j0+MF_R-1 of MT on one wavefront
+// x_s = X^T y - G^T x_b: separator rows j0 .. j0+MF_R-1 of MT (column split as in the
+// forward rows)
+template <int KS>
 __global__ void __launch_bounds__(256) k_mf_bwd(const int* __restrict__ wl, int bs,
                                                 double* __restrict__ x,
                                                 const int* __restrict__ soff,
@@ -856,7 +891,8 @@ __global__ void __launch_bounds__(256) k_mf_bwd(const int* __restrict__ wl, int 
   if (staged)
     for (int m = threadIdx.x; m < b; m += 256) xbs[m] = x[mf_bnd_dof(t, m, bs, bnd_off, bnd)];
   __syncthreads();
-  const int j0 = (blk * 4 + (threadIdx.x >> 6)) * MF_R;
+  const int wv = threadIdx.x >> 6;
+  const int j0 = (KS == 1 ? blk * 4 + wv : blk) * MF_R;
   if (j0 >= s) return;
   const int64_t Fp = int64_t(fT[t]) * 64;
   const double* y = fv + vo[t];
@@ -868,7 +904,7 @@ __global__ void __launch_bounds__(256) k_mf_bwd(const int* __restrict__ wl, int 
   for (int q = 0; q < MF_R; ++q) acc[q] = 0.0;
   // rows j0 .. j0+MF_R-1 share their 64-block, so the same columns start the sum
 #pragma unroll 4
-  for (int i = (j0 / 64) * 64 + lane; i < S; i += 64) {
+  for (int i = (j0 / 64) * 64 + (KS == 1 ? 0 : wv * 64) + lane; i < S; i += 64 * KS) {
     const double yi = y[i];
     double v[MF_R];
 #pragma unroll
@@ -878,7 +914,7 @@ __global__ void __launch_bounds__(256) k_mf_bwd(const int* __restrict__ wl, int 
       if (j0 + q < s) acc[q] += v[q] * yi;
   }
 #pragma unroll 4
-  for (int m = lane; m < b; m += 64) {
+  for (int m = (KS == 1 ? 0 : wv * 64) + lane; m < b; m += 64 * KS) {
     const double xb = staged ? xbs[m] : x[mf_bnd_dof(t, m, bs, bnd_off, bnd)];
     double v[MF_R];
 #pragma unroll
@@ -893,7 +929,9 @@ __global__ void __launch_bounds__(256) k_mf_bwd(const int* __restrict__ wl, int 
     const double r = wave_sum(acc[q]);
     if (lane == q) mine = r;
   }
-  if (lane < MF_R && j0 + lane < s) x[mf_sep_dof(t, j0 + lane, bs, soff, sperm)] = mine;
+  mine = mf_split_sum<KS>(mine);
+  if ((KS == 1 || wv == 0) && lane < MF_R && j0 + lane < s)
+    x[mf_sep_dof(t, j0 + lane, bs, soff, sperm)] = mine;
 }
 
 // ---------------------------------------------------------------- host side
@@ -1090,19 +1128,32 @@ void MFSolver::setup(Ctx& c, int n_, int bs_, const int* rp, const int* col,
                          mo.p, M.p, MT.p);
     AMGF_LAUNCH_CHECK();
   }
-  // per-depth launch extents of the solve
+  // per-depth launch extents of the solve: workgroups of 4 * MF_R rows, or of MF_R rows
+  // with the columns split over the four wavefronts (ks = MF_KS) where a depth would give
+  // fewer than MF_SPLIT_WG workgroups
   {
-    const int RB = 4 * MF_R;   // rows per workgroup
     std::vector<int> wf, wb;
     wl_fwd_off.assign(ndepth + 1, 0);
     wl_bwd_off.assign(ndepth + 1, 0);
+    ks_fwd.assign(ndepth, 1);
+    ks_bwd.assign(ndepth, 1);
+    auto blocks = [](int rows, int rb) { return (rows + rb - 1) / rb; };
     for (int dd = 0; dd < ndepth; ++dd) {
+      int64_t nf1 = 0, nb1 = 0;
       for (int t = tree_off[dd]; t < tree_off[dd + 1]; ++t) {
-        for (int k = 0; k < (h_S[t] + h_b[t] + RB - 1) / RB; ++k) {
+        nf1 += blocks(h_S[t] + h_b[t], 4 * MF_R);
+        nb1 += blocks(h_s[t], 4 * MF_R);
+      }
+      ks_fwd[dd] = nf1 < MF_SPLIT_WG ? MF_KS : 1;
+      ks_bwd[dd] = nb1 < MF_SPLIT_WG ? MF_KS : 1;
+      const int rbf = ks_fwd[dd] == 1 ? 4 * MF_R : MF_R;
+      const int rbb = ks_bwd[dd] == 1 ? 4 * MF_R : MF_R;
+      for (int t = tree_off[dd]; t < tree_off[dd + 1]; ++t) {
+        for (int k = 0; k < blocks(h_S[t] + h_b[t], rbf); ++k) {
           wf.push_back(t);
           wf.push_back(k);
         }
-        for (int k = 0; k < (h_s[t] + RB - 1) / RB; ++k) {
+        for (int k = 0; k < blocks(h_s[t], rbb); ++k) {
           wb.push_back(t);
           wb.push_back(k);
         }
@@ -1133,25 +1184,27 @@ void MFSolver::solve(Ctx& c, const double* r, double* x) const {
     const int b0 = tree_off[dd], nt = tree_off[dd + 1] - b0;
     const int nf = wl_fwd_off[dd + 1] - wl_fwd_off[dd];
     const int* wl = wl_fwd.p + 2 * int64_t(wl_fwd_off[dd]);
+    const bool split = ks_fwd[dd] != 1;
     if (fp_max[dd] <= MF_FL) {
       if (nf > 0)
-        hipLaunchKernelGGL(k_mf_fwd_lds, dim3(nf), dim3(256), size_t(fp_max[dd]) * 8, c.s, wl,
-                           bs, r, soff.p, sperm.p, child0.p, child1.p, bnd_off.p, bnd_pos.p,
-                           fs.p, fS.p, fb.p, fT.p, mo.p, vo.p, M.p, fv.p);
+        hipLaunchKernelGGL(split ? k_mf_fwd_lds<MF_KS> : k_mf_fwd_lds<1>, dim3(nf), dim3(256),
+                           size_t(fp_max[dd]) * 8, c.s, wl, bs, r, soff.p, sperm.p, child0.p,
+                           child1.p, bnd_off.p, bnd_pos.p, fs.p, fS.p, fb.p, fT.p, mo.p, vo.p,
+                           M.p, fv.p);
       continue;
     }
     hipLaunchKernelGGL(k_mf_rhs, dim3(nt), dim3(256), 0, c.s, b0, bs, r, soff.p, sperm.p,
                        child0.p, child1.p, bnd_off.p, bnd_pos.p, fs.p, fS.p, fb.p, fT.p, vo.p,
                        fa.p, fv.p);
     if (nf > 0)
-      hipLaunchKernelGGL(k_mf_fwd, dim3(nf), dim3(256), 0, c.s, wl, fS.p, fb.p, mo.p, vo.p,
-                         M.p, fa.p, fv.p);
+      hipLaunchKernelGGL(split ? k_mf_fwd<MF_KS> : k_mf_fwd<1>, dim3(nf), dim3(256), 0, c.s,
+                         wl, fS.p, fb.p, mo.p, vo.p, M.p, fa.p, fv.p);
   }
   for (int dd = 0; dd < ndepth; ++dd) {
     const int nb = wl_bwd_off[dd + 1] - wl_bwd_off[dd];
     if (nb > 0)
-      hipLaunchKernelGGL(k_mf_bwd, dim3(nb), dim3(256), 0, c.s,
-                         wl_bwd.p + 2 * int64_t(wl_bwd_off[dd]), bs, x,
+      hipLaunchKernelGGL(ks_bwd[dd] != 1 ? k_mf_bwd<MF_KS> : k_mf_bwd<1>, dim3(nb), dim3(256),
+                         0, c.s, wl_bwd.p + 2 * int64_t(wl_bwd_off[dd]), bs, x,
                          soff.p, sperm.p, bnd_off.p, bnd.p, fs.p, fS.p, fb.p, fT.p, mo.p, vo.p,
                          MT.p, fv.p);
   }

@@ -60,3 +60,35 @@ def test_apply_with_dof_subset_matches_oracle():
     print(f"apply with z-only I_c: rel {e:.2e}")
     assert e < 5e-8
     h.close()
+
+
+def test_filter_solve_c3_tree():
+    """C3 (N = 64, 25,350 filter DOFs): a tree deep and wide enough that its leaf depths
+    run one row group per wavefront and its shallow depths split each row group's columns
+    over the four wavefronts of a workgroup.  I_c and A_w = S[I_c, I_c] are formed here from
+    the input arrays (S = K + J^T D J with scipy); backward error and reproducibility."""
+    import scipy.sparse as sp
+    from amgf_inputs import make_config
+    from paper_2505_18576_amd import AMGF
+    p = make_config("C3")
+    n = 3 * p.n_nodes
+    K = sp.bsr_matrix((p.K_val, p.K_col, p.K_rowptr), shape=(n, n)).tocsr()
+    J = sp.csr_matrix((p.J_val, p.J_col, p.J_rowptr), shape=(len(p.D), n))
+    nodes = np.unique(p.J_col // 3)
+    Ic = (3 * nodes[:, None] + np.arange(3)).ravel()
+    Jc = J[:, Ic]
+    Aw = (K[Ic][:, Ic] + Jc.T @ sp.diags(p.D) @ Jc).tocsr()
+    anorm = abs(Aw).sum(axis=1).max()
+    print(f"[gpu setup] C3 n_c={len(Ic)}", flush=True)
+    h = AMGF.from_problem(p, precision=1)
+    assert np.array_equal(h.filter_dofs(len(Ic)), Ic)
+    rng = np.random.default_rng(6)
+    for trial in range(2):
+        r = rng.standard_normal(len(Ic))
+        w = h.filter_solve(r).cpu().numpy()
+        w2 = h.filter_solve(r).cpu().numpy()
+        eta = np.abs(r - Aw @ w).max() / (anorm * np.abs(w).max() + np.abs(r).max())
+        print(f"C3 n_c={len(Ic)}: backward error {eta:.2e}")
+        assert np.array_equal(w, w2)
+        assert eta <= 1e-14
+    h.close()

@@ -151,6 +151,12 @@ struct BSR {
   // BF16 copy (round to nearest even): per slot, entries (0,1) (2,3) (4,5) (6,7) of the
   // 64 rows as 4 x 64 packed pairs (uint32), then entry 8 as 64 uint16: 1152 bytes
   DBuf<uint16_t> sell_val16;
+  // Packed copy of a square matrix (bsr_build_packed): row i's blocks padded with zero
+  // blocks to a multiple of 16 from block offset pk_off[i], column ids pk_col[pk_off[i] + k]
+  // (padding: i), entry (p,q) of block k at pk_val[b*b*pk_off[i] + (b*p+q)*nbp_i + k]
+  DBuf<int> pk_off, pk_col;
+  DBuf<double> pk_val;
+  DBuf<float> pk_val32;
   size_t bsz() const { return size_t(br) * bc; }
 };
 
@@ -237,6 +243,8 @@ __device__ __forceinline__ T group_sum(T v, int width) {
 // ------------------------------------------------------------------------------------
 // out[0..n] = exclusive scan of in[0..n-1]; out[n] = total.  Returns the total.
 int scan_exclusive(Ctx& c, const int* in, int* out, int n, bool want_total = true);
+// longest segment off[s+1] - off[s] of nseg segments (0 when none); waits for the result
+int max_segment_length(Ctx& c, const int* off, int nseg);
 // rows[k] = block row of block k, for a CSR rowptr of nrows rows
 void expand_rows(Ctx& c, const int* rowptr, int nrows, int* rows);
 // Deterministic grouping: for keys[i] in [0, nkeys) (negative keys skipped),

@@ -166,6 +166,16 @@ __global__ void k_max_segment(const int* __restrict__ off, int nseg, int* __rest
   if (seg < nseg) atomicMax(mx, off[seg + 1] - off[seg]);
 }
 
+int max_segment_length(Ctx& c, const int* off, int nseg) {
+  DBuf<int> mx(1);
+  AMGF_HIP(hipMemsetAsync(mx.p, 0, sizeof(int), c.s));
+  if (nseg > 0)
+    hipLaunchKernelGGL(k_max_segment, dim3(grid_for(nseg, 256)), dim3(256), 0, c.s, off, nseg,
+                       mx.p);
+  AMGF_LAUNCH_CHECK();
+  return d2h_scalar(mx.p, c.s);
+}
+
 // one 1024-thread workgroup per long segment: bitonic sort in a padded scratch region
 __global__ void __launch_bounds__(1024) k_bitonic_segments(const int* __restrict__ list,
                                                            const int* __restrict__ off,

@@ -185,19 +185,31 @@ __global__ void k_count_flags(int nrows, const int* __restrict__ rp, const int* 
   for (int k = rp[r]; k < rp[r + 1]; ++k) n += f[k];
   counts[r] = n;
 }
-__global__ void k_compact_graph(int nrows, const int* __restrict__ rp, const int* __restrict__ col,
-                                const int* __restrict__ f, const double* __restrict__ nu,
-                                const int* __restrict__ grp, int* __restrict__ gcol,
-                                double* __restrict__ gw) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// 32 lanes per row, a lane per entry (coalesced): the strong entries keep their order, each
+// at the row's start plus the number of strong entries before it (ballot prefix count)
+__global__ void __launch_bounds__(256) k_compact_graph(int nrows, const int* __restrict__ rp,
+                                                       const int* __restrict__ col,
+                                                       const int* __restrict__ f,
+                                                       const double* __restrict__ nu,
+                                                       const int* __restrict__ grp,
+                                                       int* __restrict__ gcol,
+                                                       double* __restrict__ gw) {
+  const int r = int((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 5);
+  const int l = threadIdx.x & 31, half = (threadIdx.x >> 5) & 1;
   if (r >= nrows) return;
+  const int k1 = rp[r + 1];
   int o = grp[r];
-  for (int k = rp[r]; k < rp[r + 1]; ++k)
-    if (f[k]) {
-      gcol[o] = col[k];
-      gw[o] = nu[k];
-      ++o;
+  for (int base = rp[r]; base < k1; base += 32) {
+    const int k = base + l;
+    const bool st = k < k1 && f[k];
+    const unsigned m = unsigned(__ballot(st) >> (32 * half));
+    if (st) {
+      const int pos = o + __popc(m & ((1u << l) - 1u));
+      gcol[pos] = col[k];
+      gw[pos] = nu[k];
     }
+    o += __popc(m);
+  }
 }
 
 void strength_graph(Ctx& c, const BSR& A, double theta, Graph& G) {
@@ -226,7 +238,7 @@ void strength_graph(Ctx& c, const BSR& A, double theta, Graph& G) {
   G.nnz = scan_exclusive(c, counts.p, G.rowptr.p, n);
   G.col.alloc(std::max<int64_t>(G.nnz, 1));
   G.w.alloc(std::max<int64_t>(G.nnz, 1));
-  hipLaunchKernelGGL(k_compact_graph, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n,
+  hipLaunchKernelGGL(k_compact_graph, dim3(grid_for(int64_t(n) * 32, 256)), dim3(256), 0, c.s, n,
                      A.rowptr.p, A.col.p, strong.p, nu.p, G.rowptr.p, G.col.p, G.w.p);
   AMGF_LAUNCH_CHECK();
 }
@@ -450,7 +462,7 @@ __global__ void k_fill_ones(double* w, int64_t n) {
 // builds the near-null vectors (NC = 6: rigid-body modes about the aggregate centroid;
 // NC = 3: translations), coarser levels take the rows of the previous QR's R.
 template <int BR, int NC>
-__global__ void __launch_bounds__(64) k_tentative(int n_agg, const int* __restrict__ off,
+__global__ void __launch_bounds__(64) k_tentative_mem(int n_agg, const int* __restrict__ off,
                                                   const int* __restrict__ members,
                                                   int level0,
                                                   const double* __restrict__ coords,
@@ -565,6 +577,134 @@ __global__ void __launch_bounds__(64) k_tentative(int n_agg, const int* __restri
   }
 }
 
+// The same QR with the aggregate's rows held in registers (lane l owns rows l, l + 64, ...,
+// at most TENT_R of them): one pass builds them, the Gram-Schmidt sweeps run on registers
+// and wavefront sums, one pass writes the orthonormal rows.  Every sum runs in the order of
+// the kernel above (a lane's rows ascending, then over the wavefront), so the results are
+// the same.  Aggregates with more than 64 TENT_R rows take the kernel above.
+constexpr int TENT_R = 8;
+template <int BR, int NC>
+__global__ void __launch_bounds__(64) k_tentative(int n_agg, const int* __restrict__ off,
+                                                  const int* __restrict__ members,
+                                                  int level0,
+                                                  const double* __restrict__ coords,
+                                                  const unsigned char* __restrict__ dec,
+                                                  const double* __restrict__ Rprev,
+                                                  double qr_tol, double* __restrict__ Pt,
+                                                  double* __restrict__ Rout,
+                                                  unsigned char* __restrict__ dead) {
+  const int J = blockIdx.x;
+  if (J >= n_agg) return;
+  const int lane = threadIdx.x;
+  const int a0 = off[J], k = off[J + 1] - a0;
+  const int rows = BR * k;
+  __shared__ double cen[3];
+  if (level0 && NC == 6) {
+    if (lane == 0) {
+      double cx = 0.0, cy = 0.0, cz = 0.0;
+      for (int i = 0; i < k; ++i) {
+        const int v = members[a0 + i];
+        cx = cx + coords[3 * int64_t(v)];
+        cy = cy + coords[3 * int64_t(v) + 1];
+        cz = cz + coords[3 * int64_t(v) + 2];
+      }
+      cen[0] = cx / k;
+      cen[1] = cy / k;
+      cen[2] = cz / k;
+    }
+    __syncthreads();
+  }
+  double Q[TENT_R][NC];
+  int64_t rowoff[TENT_R];
+#pragma unroll
+  for (int s = 0; s < TENT_R; ++s) {
+    const int idx = lane + 64 * s;
+    rowoff[s] = -1;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) Q[s][j] = 0.0;
+    if (idx >= rows) continue;
+    const int v = members[a0 + idx / BR], p = idx % BR;
+    rowoff[s] = (int64_t(v) * BR + p) * NC;
+    if (level0) {
+      double b[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) b[j] = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        if (p == j) b[j] = 1.0;
+      if constexpr (NC == 6) {
+        const double x = coords[3 * int64_t(v)] - cen[0];
+        const double y = coords[3 * int64_t(v) + 1] - cen[1];
+        const double z = coords[3 * int64_t(v) + 2] - cen[2];
+        if (p == 0) { b[4] = z; b[5] = -y; }
+        if (p == 1) { b[3] = -z; b[5] = x; }
+        if (p == 2) { b[3] = y; b[4] = -x; }
+      }
+      const bool off_row = dec && dec[int64_t(v) * BR + p];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) Q[s][j] = off_row ? 0.0 : b[j];
+    } else {
+      const double* src = Rprev + (int64_t(v) * NC + p) * NC;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) Q[s][j] = src[j];
+    }
+  }
+  double R[NC][NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) R[i][j] = 0.0;
+  bool isdead[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    double sq = 0.0;
+#pragma unroll
+    for (int s = 0; s < TENT_R; ++s) sq += Q[s][j] * Q[s][j];
+    const double nb = sqrt(wave_sum(sq));
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      double cc[NC];
+#pragma unroll
+      for (int i = 0; i < j; ++i) {
+        double d = 0.0;
+#pragma unroll
+        for (int s = 0; s < TENT_R; ++s) d += Q[s][i] * Q[s][j];
+        cc[i] = wave_sum(d);
+      }
+#pragma unroll
+      for (int s = 0; s < TENT_R; ++s) {
+        double x = Q[s][j];
+#pragma unroll
+        for (int i = 0; i < j; ++i) x -= cc[i] * Q[s][i];
+        Q[s][j] = x;
+      }
+#pragma unroll
+      for (int i = 0; i < j; ++i) R[i][j] += cc[i];
+    }
+    double s2 = 0.0;
+#pragma unroll
+    for (int s = 0; s < TENT_R; ++s) s2 += Q[s][j] * Q[s][j];
+    const double nv = sqrt(wave_sum(s2));
+    isdead[j] = (nb == 0.0) || (nv <= qr_tol * nb);
+    const double scale = isdead[j] ? 0.0 : 1.0 / nv;
+    R[j][j] = isdead[j] ? 0.0 : nv;
+#pragma unroll
+    for (int s = 0; s < TENT_R; ++s) Q[s][j] = isdead[j] ? 0.0 : Q[s][j] * scale;
+  }
+#pragma unroll
+  for (int s = 0; s < TENT_R; ++s)
+    if (rowoff[s] >= 0)
+#pragma unroll
+      for (int j = 0; j < NC; ++j) Pt[rowoff[s] + j] = Q[s][j];
+  if (lane == 0) {
+    for (int i = 0; i < NC; ++i) {
+      dead[int64_t(J) * NC + i] = isdead[i];
+      for (int j = 0; j < NC; ++j)
+        Rout[int64_t(J) * NC * NC + i * NC + j] = isdead[i] ? 0.0 : R[i][j];
+    }
+  }
+}
+
 void tentative_prolongator(Ctx& c, int br, int nc, int n_nodes, int n_agg, const int* moff,
                            const int* members, bool level0, const double* coords,
                            const unsigned char* dec, const double* Rprev, double qr_tol,
@@ -577,9 +717,16 @@ void tentative_prolongator(Ctx& c, int br, int nc, int n_nodes, int n_agg, const
   R.alloc(size_t(n_agg) * nc * nc);
   dead.alloc(size_t(n_agg) * nc);
   const int l0 = level0 ? 1 : 0;
+  const bool regs = int64_t(br) * max_segment_length(c, moff, n_agg) <= 64 * TENT_R;
 #define AMGF_TENT(BR, NC)                                                                    \
-  hipLaunchKernelGGL((k_tentative<BR, NC>), dim3(n_agg), dim3(64), 0, c.s, n_agg, moff,      \
-                     members, l0, coords, dec, Rprev, qr_tol, Pt.p, R.p, dead.p)
+  do {                                                                                       \
+    if (regs)                                                                                \
+      hipLaunchKernelGGL((k_tentative<BR, NC>), dim3(n_agg), dim3(64), 0, c.s, n_agg, moff,  \
+                         members, l0, coords, dec, Rprev, qr_tol, Pt.p, R.p, dead.p);        \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_tentative_mem<BR, NC>), dim3(n_agg), dim3(64), 0, c.s, n_agg,    \
+                         moff, members, l0, coords, dec, Rprev, qr_tol, Pt.p, R.p, dead.p);  \
+  } while (0)
   if (nc == 6) {
     if (br == 3) AMGF_TENT(3, 6);
     else AMGF_TENT(6, 6);
@@ -593,10 +740,52 @@ void tentative_prolongator(Ctx& c, int br, int nc, int n_nodes, int n_agg, const
 // ======================================================================================
 // prolongator smoothing  P = P_t - omega D_l1^{-1} A P_t
 // ======================================================================================
-// G lanes per aggregated row i, one lane per block (i, J) of P: the lane sums A_iv P_t,v
-// over the blocks of A's row whose column v lies in aggregate J, in ascending order, then
-// scales by -omega/d and adds P_t,i on the block of i's own aggregate.
-template <int B, int NC, int G>
+// Ordered sums of products staged in LDS (prolongator smoothing and the products of
+// Galerkin operators).  A wavefront owns one output row and up to 64 of its output blocks
+// (a lane each, columns `mycol` ascending over the lanes).  Its lanes form up to 64
+// products in LDS, each with the output column `key` it adds to; slot_of finds the lane
+// owning that column by a binary search over the lanes (shuffles), and add_staged gives
+// every owner the products of its column in ascending staging order (one ballot per
+// owner).  Products staged in the order of a walk along the row give the walk's sums.
+__device__ __forceinline__ int slot_of(int key, int mycol, int nslot) {
+  int pos = 0;
+#pragma unroll
+  for (int st = 32; st > 0; st >>= 1) {
+    const int v = __shfl(mycol, min(pos + st - 1, 63), 64);
+    if (pos + st <= nslot && v < key) pos += st;
+  }
+  const int hit = __shfl(mycol, min(pos, 63), 64);
+  return (key >= 0 && pos < nslot && hit == key) ? pos : -1;
+}
+
+template <int E, int LD>
+__device__ __forceinline__ void add_staged(int slot, int nslot, const double (*prod)[LD],
+                                           double* acc) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long mine = 0;
+  for (int s = 0; s < nslot; ++s) {
+    const unsigned long long m = __ballot(slot == s);
+    if (lane == s) mine = m;
+  }
+  while (mine) {
+    const int u = __ffsll(mine) - 1;
+    mine &= mine - 1;
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] += prod[u][e];
+  }
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// P = P_t - omega D_l1^{-1} A P_t, one wavefront per aggregated row i: the row's blocks of
+// A go through in chunks of 64, a lane per block (i, v) forming A_iv P_t,v (key agg(v)),
+// summed per block (i, J) of P in ascending block order; then the lane of (i, J) scales by
+// -omega/d and adds P_t,i on the block of i's own aggregate.
+template <int B, int NC>
 __global__ void __launch_bounds__(256) k_sa_numeric(int n, const int* __restrict__ arp,
                                                     const int* __restrict__ acol,
                                                     const double* __restrict__ aval,
@@ -606,39 +795,56 @@ __global__ void __launch_bounds__(256) k_sa_numeric(int n, const int* __restrict
                                                     const int* __restrict__ prp,
                                                     const int* __restrict__ pcol,
                                                     double* __restrict__ pval) {
-  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int i = int(gid / G), l = int(gid % G);
+  constexpr int E = B * NC;
+  __shared__ double prod[4][64][E + 1];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
   if (i >= n) return;
   const int ai = agg[i];
   if (ai < 0) return;
-  for (int s = prp[i] + l; s < prp[i + 1]; s += G) {
-    const int J = pcol[s];
-    double acc[B * NC];
+  const int t0 = arp[i], t1 = arp[i + 1];
+  for (int sb = prp[i]; sb < prp[i + 1]; sb += 64) {
+    const int nslot = min(64, prp[i + 1] - sb);
+    const bool act = lane < nslot;
+    const int J = act ? pcol[sb + lane] : INT_MAX;
+    double acc[E];
 #pragma unroll
-    for (int e = 0; e < B * NC; ++e) acc[e] = 0.0;
-    for (int t = arp[i]; t < arp[i + 1]; ++t) {
-      const int v = acol[t];
-      if (agg[v] != J) continue;
-      const double* A = aval + int64_t(t) * B * B;
-      const double* Q = Pt + int64_t(v) * B * NC;
+    for (int e = 0; e < E; ++e) acc[e] = 0.0;
+    for (int c0 = t0; c0 < t1; c0 += 64) {
+      const int t = c0 + lane;
+      int kj = -1;
+      if (t < t1) {
+        const int v = acol[t];
+        kj = agg[v];
+        if (kj >= 0) {
+          const double* A = aval + int64_t(t) * B * B;
+          const double* Q = Pt + int64_t(v) * E;
 #pragma unroll
-      for (int p = 0; p < B; ++p)
+          for (int p = 0; p < B; ++p)
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+              double a = 0.0;
+#pragma unroll
+              for (int r = 0; r < B; ++r) a += A[p * B + r] * Q[r * NC + q];
+              prod[wv][lane][p * NC + q] = a;
+            }
+        }
+      }
+      const int slot = slot_of(kj, J, nslot);
+      wave_lds_sync();
+      add_staged<E>(slot, nslot, prod[wv], acc);
+      wave_lds_sync();
+    }
+    if (act) {
+      double* out = pval + int64_t(sb + lane) * E;
+#pragma unroll
+      for (int p = 0; p < B; ++p) {
+        const double sc = omega / d[int64_t(i) * B + p];
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
-          double a = 0.0;
-#pragma unroll
-          for (int r = 0; r < B; ++r) a += A[p * B + r] * Q[r * NC + q];
-          acc[p * NC + q] += a;
+          const double v = -(acc[p * NC + q] * sc);
+          out[p * NC + q] = J == ai ? Pt[int64_t(i) * E + p * NC + q] + v : v;
         }
-    }
-    double* out = pval + int64_t(s) * B * NC;
-#pragma unroll
-    for (int p = 0; p < B; ++p) {
-      const double sc = omega / d[int64_t(i) * B + p];
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const double v = -(acc[p * NC + q] * sc);
-        out[p * NC + q] = J == ai ? Pt[int64_t(i) * B * NC + p * NC + q] + v : v;
       }
     }
   }
@@ -653,18 +859,17 @@ void smooth_prolongator(Ctx& c, const BSR& A, const int* agg, int n_agg, int nc,
   P.br = A.br;
   P.bc = nc;
   P.val.alloc(std::max<int64_t>(P.nnzb, 1) * P.bsz());
-  constexpr int G = 8;
-  const dim3 g(grid_for(int64_t(n) * G, 256));
+  const dim3 g(grid_for(n, 4));
   AMGF_REQUIRE((A.br == 3 && (nc == 3 || nc == 6)) || (A.br == 6 && nc == 6), AMGF_EINVAL,
                "prolongator block size");
   if (A.br == 3 && nc == 6)
-    hipLaunchKernelGGL((k_sa_numeric<3, 6, G>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
+    hipLaunchKernelGGL((k_sa_numeric<3, 6>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
                        A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p, P.val.p);
   else if (A.br == 3)
-    hipLaunchKernelGGL((k_sa_numeric<3, 3, G>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
+    hipLaunchKernelGGL((k_sa_numeric<3, 3>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
                        A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p, P.val.p);
   else
-    hipLaunchKernelGGL((k_sa_numeric<6, 6, G>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
+    hipLaunchKernelGGL((k_sa_numeric<6, 6>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
                        A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p, P.val.p);
   AMGF_LAUNCH_CHECK();
 }
@@ -680,9 +885,12 @@ __global__ void k_nonneg_mask(int n, const int* __restrict__ a, int* __restrict_
 // A group of G lanes per row r (G = 64: one wavefront; G = 16: four short rows per
 // wavefront), one lane per output block (r, j): the lane walks A's row in ascending order,
 // so each output block accumulates in a fixed order (deterministic) and rows with many
-// blocks spread over the group.  For each A block (r, k) the group loads the column ids of
-// B's row k once (coalesced, up to G at a time) and every lane finds its column j there by
-// a binary search over the group's lanes (shuffles, no dependent loads).
+// blocks spread over the group.  A's row goes through G blocks at a time: lane u loads block
+// u's column k and the extent of B's row k, which the walk then takes from lane u by a
+// shuffle, so the only loads left in the walk are B's column ids and the values.  For each A
+// block (r, k) the group loads the column ids of B's row k (coalesced, up to G at a time) and
+// every lane finds its column j there by a binary search over the group's lanes (shuffles),
+// the ids of the next A block already on their way.
 template <int RA, int KA, int CB, int G>
 __global__ void __launch_bounds__(256) k_spgemm_numeric(
     int nrows, const int* __restrict__ arp, const int* __restrict__ acol,
@@ -704,30 +912,47 @@ __global__ void __launch_bounds__(256) k_spgemm_numeric(
     double acc[RA * CB];
 #pragma unroll
     for (int e = 0; e < RA * CB; ++e) acc[e] = 0.0;
-    for (int t = t0; t < t1; ++t) {
-      const int k = acol[t];
-      const int b0 = brp[k], blen = brp[k + 1] - b0;
-      for (int c0 = 0; c0 < blen; c0 += G) {
-        const int nb = min(G, blen - c0);
-        const int myc = lane < nb ? bcol[b0 + c0 + lane] : INT_MAX;
-        // pos = number of chunk columns below j (chunk columns ascending)
-        int pos = 0;
-        for (int st = 1 << (31 - __clz(nb)); st > 0; st >>= 1) {
-          const int v = __shfl(myc, min(pos + st - 1, G - 1), G);
-          if (pos + st <= nb && v < j) pos += st;
+    for (int tc = t0; tc < t1; tc += G) {
+      const int nt = min(G, t1 - tc);
+      int mb0 = 0, mblen = 0;
+      if (lane < nt) {
+        const int k = acol[tc + lane];
+        mb0 = brp[k];
+        mblen = brp[k + 1] - mb0;
+      }
+      // B's column ids of the walk's current A block (the first G of them)
+      int b0 = __shfl(mb0, 0, G), blen = __shfl(mblen, 0, G);
+      int myc = lane < min(G, blen) ? bcol[b0 + lane] : INT_MAX;
+      for (int u = 0; u < nt; ++u) {
+        const int cb0 = b0, cblen = blen, cmyc = myc;
+        if (u + 1 < nt) {                             // next A block's ids, ahead of use
+          b0 = __shfl(mb0, u + 1, G);
+          blen = __shfl(mblen, u + 1, G);
+          myc = lane < min(G, blen) ? bcol[b0 + lane] : INT_MAX;
         }
-        const int hit = __shfl(myc, min(pos, G - 1), G);
-        if (!act || pos >= nb || hit != j) continue;
-        const double* a = aval + int64_t(t) * RA * KA;
-        const double* b = bval + int64_t(b0 + c0 + pos) * KA * CB;
-#pragma unroll
-        for (int p = 0; p < RA; ++p)
-#pragma unroll
-          for (int x = 0; x < KA; ++x) {
-            const double av = a[p * KA + x];
-#pragma unroll
-            for (int q = 0; q < CB; ++q) acc[p * CB + q] += av * b[x * CB + q];
+        const int t = tc + u;
+        for (int c0 = 0; c0 < cblen; c0 += G) {
+          const int nb = min(G, cblen - c0);
+          const int mc = c0 == 0 ? cmyc : (lane < nb ? bcol[cb0 + c0 + lane] : INT_MAX);
+          // pos = number of chunk columns below j (chunk columns ascending)
+          int pos = 0;
+          for (int st = 1 << (31 - __clz(nb)); st > 0; st >>= 1) {
+            const int v = __shfl(mc, min(pos + st - 1, G - 1), G);
+            if (pos + st <= nb && v < j) pos += st;
           }
+          const int hit = __shfl(mc, min(pos, G - 1), G);
+          if (!act || pos >= nb || hit != j) continue;
+          const double* a = aval + int64_t(t) * RA * KA;
+          const double* b = bval + int64_t(cb0 + c0 + pos) * KA * CB;
+#pragma unroll
+          for (int p = 0; p < RA; ++p)
+#pragma unroll
+            for (int x = 0; x < KA; ++x) {
+              const double av = a[p * KA + x];
+#pragma unroll
+              for (int q = 0; q < CB; ++q) acc[p * CB + q] += av * b[x * CB + q];
+            }
+        }
       }
     }
     if (act) {

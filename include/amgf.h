@@ -262,12 +262,15 @@ const char* amgf_last_error(void);
  *                  alpha_1..alpha_k (r.z / p.Ap) then beta_1..beta_k (r'.z' / r.z), the
  *                  coefficients of the Lanczos tridiagonal of M A whose extreme
  *                  eigenvalues estimate the spectrum (the bound procedure of Sec. 6.1)
+ *  AMGF_Q_CONTACT  int32[2]: how the V-cycle applies the level's contact term J^T D J
+ *                  (0: none, 1: through J and D, 2: through the assembled block C of the
+ *                  level, rows repacked), and the number of node rows it touches
  * Returns EINVAL for a bad level or selector; `bytes` must equal the array size.    */
 enum {
   AMGF_Q_SIZES = 0, AMGF_Q_A_ROWPTR, AMGF_Q_A_COL, AMGF_Q_A_VAL, AMGF_Q_AGG, AMGF_Q_ROOT,
   AMGF_Q_G_ROWPTR, AMGF_Q_G_COL, AMGF_Q_P_ROWPTR, AMGF_Q_P_COL, AMGF_Q_P_VAL, AMGF_Q_L1,
   AMGF_Q_K_ROWPTR, AMGF_Q_K_COL, AMGF_Q_K_VAL, AMGF_Q_OMEGA, AMGF_Q_IC, AMGF_Q_FEATURES,
-  AMGF_Q_THETA, AMGF_Q_CG_COEF
+  AMGF_Q_THETA, AMGF_Q_CG_COEF, AMGF_Q_CONTACT
 };
 int32_t amgf_num_levels(amgf_handle h);
 

@@ -18,7 +18,7 @@ FP64, MIXED_FP32, MIXED_BF16K = 0, 1, 2
 L1JACOBI, CHEBYSHEV, LEARNED = 0, 1, 2
 (Q_SIZES, Q_A_ROWPTR, Q_A_COL, Q_A_VAL, Q_AGG, Q_ROOT, Q_G_ROWPTR, Q_G_COL, Q_P_ROWPTR,
  Q_P_COL, Q_P_VAL, Q_L1, Q_K_ROWPTR, Q_K_COL, Q_K_VAL, Q_OMEGA, Q_IC, Q_FEATURES,
- Q_THETA, Q_CG_COEF) = range(20)
+ Q_THETA, Q_CG_COEF, Q_CONTACT) = range(21)
 MLP_NPARAM, MLP_NTOTAL = 1313, 1325
 
 ABI_FUNCTIONS = ["amgf_default_options", "amgf_setup", "amgf_apply", "amgf_vcycle",
@@ -477,6 +477,12 @@ class AMGF:
     def theta(self, level):
         n = int(self.query(level, Q_SIZES)[0]) * int(self.query(level, Q_SIZES)[1])
         return self.query(level, Q_THETA, np.float64, n)
+
+    def contact_mode(self, level):
+        """(mode, rows) of the level's contact term in the V-cycle: 0 none, 1 through J
+        and D, 2 through the assembled block C; rows = node rows it touches."""
+        m = self.query(level, Q_CONTACT, np.int32, 2)
+        return int(m[0]), int(m[1])
 
     def filter_dofs(self, n_c):
         return self.query(0, Q_IC, np.int32, n_c)

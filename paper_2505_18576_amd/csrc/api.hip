@@ -25,6 +25,7 @@ struct Level {
   DBuf<int> ccrows;             // nonempty rows of C (levels >= 1)
   int nccrows = 0;
   bool contact_factored = false;  // V-cycle applies the contact term through J and D
+  PackedRows cpk;               // C's listed rows repacked (assembled coarse contact term)
   BSR P, PT;                    // prolongator to the next level and its transpose
   BSR C;                        // contact term J^T D J of this level (interface rows only)
   Graph G;                      // aggregation graph
@@ -389,6 +390,8 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
       N.nccrows = nonempty_rows(c, N.C.rowptr.p, N.nn, N.ccrows);
     }
     N.contact_factored = factored_contact_pays(c, N);
+    if (!N.contact_factored)
+      pack_contact_rows(c, N.C, N.ccrows.p, N.nccrows, h.mixed(), N.cpk);
     nzsum += N.A.nnzb * int64_t(N.A.bsz());
     coarse_graph(c, Lc.G, Lc.agg.p, n_agg, moff.p, members.p, Gnext);
     Rprev = std::move(R);
@@ -456,6 +459,9 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
       L.vt.alloc(n);
       if (h.mixed()) { L.fd.alloc(n); L.ft.alloc(n); }
     }
+    // packed copies of the smoothed coarse stiffness (levels 1 .. L-2)
+    if (l != 0 && l + 1 < h.lev.size() && L.K.br == 6)
+      bsr_build_packed(c, L.K, !h.mixed(), h.mixed());
     if (h.mixed()) {
       if (l != 0) to_fp32(c, L.K);
       if (L.P.nnzb) {
@@ -507,6 +513,8 @@ static void update_D(Handle& h, const double* D) {
       spgemm(c, U.C, U.P, CP);
       L.C = BSR();
       spgemm(c, U.PT, CP, L.C);
+      if (!L.contact_factored)
+        pack_contact_rows(c, L.C, L.ccrows.p, L.nccrows, h.mixed(), L.cpk);
     }
     L.A = BSR();
     bsr_add(c, L.K, L.C, L.A);
@@ -559,6 +567,7 @@ static void update_barrier(Handle& h, const double* D, const double* E) {
       spgemm(c, L.PT, KP, N.K);
       dead_identity(c, N.K, L.dead.p);
       if (h.mixed()) to_fp32(c, N.K);
+      if (l + 2 < h.lev.size() && N.K.br == 6) bsr_build_packed(c, N.K, !h.mixed(), h.mixed());
     }
   }
   update_D(h, D);
@@ -581,7 +590,7 @@ static void level_contact(Handle& h, Level& L, int mode, const T* x, T* y, const
   if (&L == h.lev[0].get() || L.contact_factored)
     contact_apply<T, T>(h.ctx, mode, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, x, h.t.p, y, w);
   else
-    contact_cmat<T, T>(h.ctx, mode, L.C, L.ccrows.p, L.nccrows, x, y, w);
+    contact_packed<T, T>(h.ctx, mode, L.cpk, L.ccrows.p, x, y, w);
 }
 
 // bracket the launches of kernel class `which` (level 0) when live timing is on
@@ -1915,6 +1924,18 @@ amgf_status amgf_query(amgf_handle hd, int32_t level, int32_t which, void* dst, 
     };
     AMGF_HIP(hipStreamSynchronize(c.s));
     switch (which) {
+      case AMGF_Q_CONTACT: {
+        const bool last = level + 1 == int(h.lev.size());
+        const bool fac = level == 0 || L.contact_factored;
+        int32_t v[2] = {0, 0};
+        if (!last && (fac ? L.ncrows : L.nccrows) > 0) {
+          v[0] = fac ? 1 : 2;
+          v[1] = fac ? L.ncrows : L.nccrows;
+        }
+        AMGF_REQUIRE(bytes == sizeof(v), AMGF_EINVAL, "query size mismatch");
+        std::copy(v, v + 2, static_cast<int32_t*>(dst));
+        break;
+      }
       case AMGF_Q_SIZES: {
         const int32_t idx_bytes = L.K.sell_dcol.p ? 2 : (L.K.sell_col.p ? 4 : 0);
         int32_t s[8] = {L.nn, L.b, int32_t(L.A.nnzb), L.n_agg, int32_t(L.P.nnzb),

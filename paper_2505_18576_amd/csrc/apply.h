@@ -45,11 +45,29 @@ enum ContactMode { CT_SUB_RES = 0, CT_SUB_W = 1, CT_ADD = 2 };
 template <class TX, class TY>
 void contact_apply(Ctx& c, int mode, const BSR& J, const BSR& JT, const int* crows, int ncrows,
                    const double* D, const TX* x, double* t, TY* y, const TY* w);
-// the same three modes with the assembled contact block C of a coarse level (6x6 FP64
-// BSR) applied to its listed nonempty rows
+// The listed rows of a coarse contact block C (B x B FP64 blocks) repacked for coalesced
+// reads: row i (i-th listed row) keeps its nb_i blocks padded with zero blocks to nbp_i, a
+// multiple of 16, from block offset off[i] (off[nrows] = total); column ids
+// col[off[i] + k] (padding: the row itself), entry (p, q) of block k at
+// val[B*B*off[i] + (B*p + q)*nbp_i + k], so the lanes of a wavefront, one block each, read
+// one entry of 64 blocks as contiguous bytes.  Values in FP64 (val) or, for the FP32
+// V-cycle, rounded once to FP32 (val32, like the coarse stiffness it is added to).
+struct PackedRows {
+  int nrows = 0, b = 0;
+  DBuf<int> off, col;
+  DBuf<double> val;
+  DBuf<float> val32;
+};
+void pack_contact_rows(Ctx& c, const BSR& C, const int* rows, int nrows, bool fp32,
+                       PackedRows& pk);
+// packed copy of a square matrix (BSR::pk_*) with FP64 and/or FP32 values; bsr_spmv then
+// applies the matrix through it when it is handed the matrix's own values
+void bsr_build_packed(Ctx& c, BSR& A, bool fp64, bool fp32);
+// the same three modes with the assembled contact block of a coarse level, applied to its
+// listed nonempty rows through the packed copy
 template <class TX, class TY>
-void contact_cmat(Ctx& c, int mode, const BSR& C, const int* rows, int nrows, const TX* x,
-                  TY* y, const TY* w);
+void contact_packed(Ctx& c, int mode, const PackedRows& pk, const int* rows, const TX* x,
+                    TY* y, const TY* w);
 // indices of the nonempty rows of a CSR pattern
 int nonempty_rows(Ctx& c, const int* rp, int n, DBuf<int>& rows);
 // y = b - A x on the listed block rows only (FP64, 3x3 blocks)

@@ -196,6 +196,10 @@ void cast_d2h(Ctx& c, const double* a, _Float16* b, int64_t n, int* flag) {
   AMGF_LAUNCH_CHECK();
 }
 
+template <int B, class TV, class T>
+static void launch_packed(Ctx& c, int mode, const BSR& A, const TV* pv, const T* x, T* y,
+                          const T* b, const T* w, T* xo);
+
 template <class T>
 void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, const T* b,
               const T* w, T* xo) {
@@ -210,6 +214,16 @@ void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, co
       sv = A.sell_val32.p;     // level matrices keep no FP32 BSR values once sliced
     }
     if (sv) return sell3_spmv<T>(c, mode, A, sv, x, y, b, w, xo);
+  }
+  if (A.br == 6 && A.bc == 6 && A.pk_off.p) {
+    // the packed copy stands in for the BSR values of the same precision
+    if constexpr (sizeof(T) == 8) {
+      if (val == A.val.p && A.pk_val.p)
+        return launch_packed<6, double, T>(c, mode, A, A.pk_val.p, x, y, b, w, xo);
+    } else {
+      if (val == A.val32.p && A.pk_val32.p)
+        return launch_packed<6, float, T>(c, mode, A, A.pk_val32.p, x, y, b, w, xo);
+    }
   }
   if (A.br == 3 && A.bc == 3) return launch_bsr<3, 3, 8, T>(c, mode, A, val, x, y, b, w, xo);
   if (A.br == 3 && A.bc == 6) return launch_bsr<3, 6, 8, T>(c, mode, A, val, x, y, b, w, xo);
@@ -338,33 +352,223 @@ template void contact_apply<float, double>(Ctx&, int, const BSR&, const BSR&, co
                                            const double*, const float*, double*, double*,
                                            const double*);
 
-// Coarse-level contact term from its assembled block C = J^T D J (FP64 BSR, B x B
-// blocks): one wavefront per listed row, lanes over the row's blocks, then y (op)= C x.
-template <int B, class TX, class TY, int MODE>
-__global__ void __launch_bounds__(256) k_contact_c(int nrows, const int* __restrict__ rows,
+// Coarse-level contact term from its assembled block C = J^T D J (FP64, B x B blocks).
+constexpr int PACK_PAD = 16;   // blocks: 128-byte aligned entry stripes
+
+// rows == nullptr: every row of the matrix, in order
+__global__ void k_pack_count(int nrows, const int* __restrict__ rows,
+                             const int* __restrict__ rp, int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int a = rows ? rows[i] : i;
+  cnt[i] = (rp[a + 1] - rp[a] + PACK_PAD - 1) / PACK_PAD * PACK_PAD;
+}
+
+template <int B, class TV>
+__global__ void __launch_bounds__(256) k_pack_fill(int nrows, const int* __restrict__ rows,
                                                    const int* __restrict__ rp,
                                                    const int* __restrict__ col,
                                                    const double* __restrict__ val,
-                                                   const TX* __restrict__ x,
-                                                   TY* __restrict__ y,
-                                                   const TY* __restrict__ w) {
+                                                   const int* __restrict__ off,
+                                                   int* __restrict__ pcol,
+                                                   TV* __restrict__ pval) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= nrows) return;
+  const int a = rows ? rows[i] : i;
+  const int r0 = rp[a], nb = rp[a + 1] - r0;
+  const int o0 = off[i], nbp = off[i + 1] - o0;
+  TV* pv = pval + int64_t(o0) * B * B;
+  for (int k = lane; k < nbp; k += 64) {
+    if (k < nb) {
+      pcol[o0 + k] = col[r0 + k];
+      const double* v = val + int64_t(r0 + k) * B * B;
+#pragma unroll
+      for (int e = 0; e < B * B; ++e) pv[int64_t(e) * nbp + k] = TV(v[e]);
+    } else {
+      pcol[o0 + k] = a;
+#pragma unroll
+      for (int e = 0; e < B * B; ++e) pv[int64_t(e) * nbp + k] = TV(0);
+    }
+  }
+}
+
+void pack_contact_rows(Ctx& c, const BSR& C, const int* rows, int nrows, bool fp32,
+                       PackedRows& pk) {
+  AMGF_REQUIRE(C.br == C.bc && (C.br == 6 || C.br == 3), AMGF_EINVAL,
+               "coarse contact block size");
+  pk.nrows = nrows;
+  pk.b = C.br;
+  DBuf<int> cnt(std::max(nrows, 1));
+  pk.off.alloc(size_t(nrows) + 1);
+  if (nrows)
+    hipLaunchKernelGGL(k_pack_count, dim3(grid_for(nrows, 256)), dim3(256), 0, c.s, nrows,
+                       rows, C.rowptr.p, cnt.p);
+  const int total = scan_exclusive(c, cnt.p, pk.off.p, nrows);
+  pk.col.alloc(std::max(total, 1));
+  const size_t nv = std::max<size_t>(size_t(total) * C.br * C.br, 1);
+  if (fp32) {
+    pk.val = DBuf<double>();
+    pk.val32.alloc(nv);
+  } else {
+    pk.val32 = DBuf<float>();
+    pk.val.alloc(nv);
+  }
+  if (nrows && total) {
+    const dim3 g(grid_for(nrows, 4)), blk(256);
+#define AMGF_PF(B, TV, dst)                                                                  \
+  hipLaunchKernelGGL((k_pack_fill<B, TV>), g, blk, 0, c.s, nrows, rows, C.rowptr.p, C.col.p, \
+                     C.val.p, pk.off.p, pk.col.p, dst)
+    if (C.br == 6) {
+      if (fp32) AMGF_PF(6, float, pk.val32.p);
+      else AMGF_PF(6, double, pk.val.p);
+    } else {
+      if (fp32) AMGF_PF(3, float, pk.val32.p);
+      else AMGF_PF(3, double, pk.val.p);
+    }
+#undef AMGF_PF
+  }
+  AMGF_LAUNCH_CHECK();
+}
+
+// the packed copy of a whole square B x B matrix (the coarse stiffness of the V-cycle)
+void bsr_build_packed(Ctx& c, BSR& A, bool fp64, bool fp32) {
+  AMGF_REQUIRE(A.br == A.bc && A.nrows == A.ncols && (A.br == 6 || A.br == 3), AMGF_EINVAL,
+               "packed copy needs a square matrix of 3x3 or 6x6 blocks");
+  const int n = A.nrows, B = A.br;
+  DBuf<int> cnt(std::max(n, 1));
+  A.pk_off.alloc(size_t(n) + 1);
+  if (n)
+    hipLaunchKernelGGL(k_pack_count, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, nullptr,
+                       A.rowptr.p, cnt.p);
+  const int total = scan_exclusive(c, cnt.p, A.pk_off.p, n);
+  A.pk_col.alloc(std::max(total, 1));
+  const size_t nv = std::max<size_t>(size_t(total) * B * B, 1);
+  A.pk_val = DBuf<double>();
+  A.pk_val32 = DBuf<float>();
+  if (fp64) A.pk_val.alloc(nv);
+  if (fp32) A.pk_val32.alloc(nv);
+  if (n && total) {
+    const dim3 g(grid_for(n, 4)), blk(256);
+#define AMGF_PF(BB, TV, dst)                                                                 \
+  hipLaunchKernelGGL((k_pack_fill<BB, TV>), g, blk, 0, c.s, n, nullptr, A.rowptr.p, A.col.p, \
+                     A.val.p, A.pk_off.p, A.pk_col.p, dst)
+    if (B == 6) {
+      if (fp64) AMGF_PF(6, double, A.pk_val.p);
+      if (fp32) AMGF_PF(6, float, A.pk_val32.p);
+    } else {
+      if (fp64) AMGF_PF(3, double, A.pk_val.p);
+      if (fp32) AMGF_PF(3, float, A.pk_val32.p);
+    }
+#undef AMGF_PF
+  }
+  AMGF_LAUNCH_CHECK();
+}
+
+// y (op)= A x over every row through the packed copy: one wavefront per row, a lane per
+// block, two 64-block stretches in flight; products accumulate in T per lane, then over the
+// wavefront.  Modes and epilogue as k_bsr.
+template <int B, class TV, class T, int MODE>
+__global__ void __launch_bounds__(256) k_packed_spmv(int nrows, const int* __restrict__ off,
+                                                     const int* __restrict__ pcol,
+                                                     const TV* __restrict__ pval,
+                                                     const T* __restrict__ x, T* __restrict__ y,
+                                                     const T* __restrict__ b,
+                                                     const T* __restrict__ w,
+                                                     T* __restrict__ xo) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= nrows) return;
+  const int o0 = off[r], nbp = off[r + 1] - o0;
+  const TV* pv = pval + int64_t(o0) * B * B;
+  T acc[B];
+#pragma unroll
+  for (int p = 0; p < B; ++p) acc[p] = T(0);
+#pragma unroll 2
+  for (int k = lane; k < nbp; k += 64) {
+    const int64_t base = int64_t(pcol[o0 + k]) * B;
+    T xq[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      xq[q] = (MODE == SPMV_PRE) ? w[base + q] * b[base + q] : x[base + q];
+#pragma unroll
+    for (int p = 0; p < B; ++p)
+#pragma unroll
+      for (int q = 0; q < B; ++q) acc[p] += T(pv[int64_t(B * p + q) * nbp + k]) * xq[q];
+  }
+#pragma unroll
+  for (int p = 0; p < B; ++p) acc[p] = wave_sum(acc[p]);
+  if (lane >= B) return;
+  T ax = T(0);
+#pragma unroll
+  for (int p = 0; p < B; ++p)
+    if (lane == p) ax = acc[p];
+  const int64_t i = int64_t(r) * B + lane;
+  if (MODE == SPMV_Y) y[i] = ax;
+  else if (MODE == SPMV_ADD) y[i] += ax;
+  else if (MODE == SPMV_PRE) {
+    const T xi = w[i] * b[i];
+    xo[i] = xi;
+    y[i] = b[i] - ax;
+  } else if (MODE == SPMV_POST) {
+    xo[i] = x[i] + w[i] * (b[i] - ax);
+  } else {
+    y[i] = b[i] - ax;
+  }
+}
+
+template <int B, class TV, class T>
+static void launch_packed(Ctx& c, int mode, const BSR& A, const TV* pv, const T* x, T* y,
+                          const T* b, const T* w, T* xo) {
+  const dim3 g(grid_for(A.nrows, 4)), blk(256);
+  switch (mode) {
+#define AMGF_MODE(MD)                                                                        \
+  case MD:                                                                                   \
+    hipLaunchKernelGGL((k_packed_spmv<B, TV, T, MD>), g, blk, 0, c.s, A.nrows, A.pk_off.p,   \
+                       A.pk_col.p, pv, x, y, b, w, xo);                                      \
+    break;
+    AMGF_MODE(SPMV_Y)
+    AMGF_MODE(SPMV_ADD)
+    AMGF_MODE(SPMV_PRE)
+    AMGF_MODE(SPMV_POST)
+    AMGF_MODE(SPMV_RES)
+#undef AMGF_MODE
+    default:
+      throw Error(AMGF_EINVAL, "spmv mode");
+  }
+  AMGF_LAUNCH_CHECK();
+}
+
+// one wavefront per listed row, a lane per block: every value load of the wavefront reads
+// 64 consecutive values of one entry stripe; two 64-block stretches are in flight at once
+// (a row at C5's third level holds about 110 blocks)
+template <int B, class TV, class TX, class TY, int MODE>
+__global__ void __launch_bounds__(256) k_contact_packed(int nrows, const int* __restrict__ rows,
+                                                        const int* __restrict__ off,
+                                                        const int* __restrict__ pcol,
+                                                        const TV* __restrict__ pval,
+                                                        const TX* __restrict__ x,
+                                                        TY* __restrict__ y,
+                                                        const TY* __restrict__ w) {
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= nrows) return;
   const int a = rows[i];
+  const int o0 = off[i], nbp = off[i + 1] - o0;
+  const TV* pv = pval + int64_t(o0) * B * B;
   double acc[B];
 #pragma unroll
   for (int p = 0; p < B; ++p) acc[p] = 0.0;
-  for (int k = rp[a] + lane; k < rp[a + 1]; k += 64) {
-    const double* v = val + int64_t(k) * B * B;
-    const int64_t base = int64_t(col[k]) * B;
+#pragma unroll 2
+  for (int k = lane; k < nbp; k += 64) {
+    const int64_t base = int64_t(pcol[o0 + k]) * B;
     double xq[B];
 #pragma unroll
     for (int q = 0; q < B; ++q) xq[q] = double(x[base + q]);
 #pragma unroll
     for (int p = 0; p < B; ++p)
 #pragma unroll
-      for (int q = 0; q < B; ++q) acc[p] += v[p * B + q] * xq[q];
+      for (int q = 0; q < B; ++q) acc[p] += double(pv[int64_t(B * p + q) * nbp + k]) * xq[q];
   }
 #pragma unroll
   for (int p = 0; p < B; ++p) acc[p] = wave_sum(acc[p]);
@@ -380,34 +584,43 @@ __global__ void __launch_bounds__(256) k_contact_c(int nrows, const int* __restr
 }
 
 template <class TX, class TY>
-void contact_cmat(Ctx& c, int mode, const BSR& C, const int* rows, int nrows, const TX* x,
-                  TY* y, const TY* w) {
-  if (nrows == 0 || C.nnzb == 0) return;
-  AMGF_REQUIRE(C.br == C.bc && (C.br == 6 || C.br == 3), AMGF_EINVAL,
-               "coarse contact block size");
-  const dim3 g(grid_for(nrows, 4)), blk(256);
-#define AMGF_CC(B)                                                                           \
+void contact_packed(Ctx& c, int mode, const PackedRows& pk, const int* rows, const TX* x,
+                    TY* y, const TY* w) {
+  if (pk.nrows == 0) return;
+  const dim3 g(grid_for(pk.nrows, 4)), blk(256);
+  // FP32 values serve the FP32 V-cycle; FP64 vectors need the FP64 copy
+  const bool f32 = pk.val32.n > 0;
+  AMGF_REQUIRE(f32 ? sizeof(TY) == 4 : pk.val.n > 0, AMGF_EINVAL,
+               "packed contact rows stored in the other precision");
+#define AMGF_CP1(B, TV, vp)                                                                  \
   if (mode == CT_SUB_RES)                                                                    \
-    hipLaunchKernelGGL((k_contact_c<B, TX, TY, CT_SUB_RES>), g, blk, 0, c.s, nrows, rows,    \
-                       C.rowptr.p, C.col.p, C.val.p, x, y, w);                               \
+    hipLaunchKernelGGL((k_contact_packed<B, TV, TX, TY, CT_SUB_RES>), g, blk, 0, c.s,        \
+                       pk.nrows, rows, pk.off.p, pk.col.p, vp, x, y, w);                     \
   else if (mode == CT_SUB_W)                                                                 \
-    hipLaunchKernelGGL((k_contact_c<B, TX, TY, CT_SUB_W>), g, blk, 0, c.s, nrows, rows,      \
-                       C.rowptr.p, C.col.p, C.val.p, x, y, w);                               \
+    hipLaunchKernelGGL((k_contact_packed<B, TV, TX, TY, CT_SUB_W>), g, blk, 0, c.s,          \
+                       pk.nrows, rows, pk.off.p, pk.col.p, vp, x, y, w);                     \
   else                                                                                       \
-    hipLaunchKernelGGL((k_contact_c<B, TX, TY, CT_ADD>), g, blk, 0, c.s, nrows, rows,        \
-                       C.rowptr.p, C.col.p, C.val.p, x, y, w);
-  if (C.br == 6) {
-    AMGF_CC(6)
-  } else {
-    AMGF_CC(3)
+    hipLaunchKernelGGL((k_contact_packed<B, TV, TX, TY, CT_ADD>), g, blk, 0, c.s, pk.nrows,  \
+                       rows, pk.off.p, pk.col.p, vp, x, y, w);
+#define AMGF_CP(B)                                                                           \
+  if (f32) {                                                                                 \
+    AMGF_CP1(B, float, pk.val32.p)                                                           \
+  } else {                                                                                   \
+    AMGF_CP1(B, double, pk.val.p)                                                            \
   }
-#undef AMGF_CC
+  if (pk.b == 6) {
+    AMGF_CP(6)
+  } else {
+    AMGF_CP(3)
+  }
+#undef AMGF_CP
+#undef AMGF_CP1
   AMGF_LAUNCH_CHECK();
 }
-template void contact_cmat<double, double>(Ctx&, int, const BSR&, const int*, int, const double*,
-                                           double*, const double*);
-template void contact_cmat<float, float>(Ctx&, int, const BSR&, const int*, int, const float*,
-                                         float*, const float*);
+template void contact_packed<double, double>(Ctx&, int, const PackedRows&, const int*,
+                                             const double*, double*, const double*);
+template void contact_packed<float, float>(Ctx&, int, const PackedRows&, const int*,
+                                           const float*, float*, const float*);
 
 // nonempty rows of a CSR (compact list)
 __global__ void k_nonempty_flag(int n, const int* __restrict__ rp, int* __restrict__ f) {

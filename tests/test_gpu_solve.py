@@ -147,8 +147,8 @@ def test_pcg_run_to_run_bitwise():
 
 @pytest.mark.parametrize("kw", [dict(), dict(precision=1), dict(smoother=1)])
 def test_three_level_vcycle_and_apply_match_oracle(kw):
-    """C2 has a smoothed coarse level between level 0 and the coarsest one, so its contact
-    term goes through the assembled coarse block C = J^T D J."""
+    """C2 has a smoothed coarse level between level 0 and the coarsest one; its contact
+    term goes through J_1 and D (fewer bytes than the assembled block there)."""
     oo = {"smoother": "chebyshev"} if kw.get("smoother") == 1 else {}
     o = oracle("C2", **oo)
     h = gpu("C2", **kw)
@@ -164,6 +164,44 @@ def test_three_level_vcycle_and_apply_match_oracle(kw):
     u = np.finfo(np.float64).eps / 2
     dmax = float(problem("C2").D.max())
     assert e_m <= max(MIXED_TOL if kw.get("precision") else 0.0, 10 * u * dmax)
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_assembled_coarse_contact_level(precision):
+    """N = 16 coarsened to at most 4 nodes: level 2 (31 nodes) meets every constraint, and
+    its assembled block C_2 reads fewer bytes than J_2 and D, so the V-cycle applies it
+    through the repacked rows of C_2 (FP64 values, FP32 in the mixed cycle); level 1 goes
+    through J_1 and D.  V-cycle, M r and PCG against the oracle (which forms J^T D J)."""
+    from amgf_inputs import make_two_block
+    from oracle import OracleAMGF, OracleOptions
+    from paper_2505_18576_amd import AMGF
+    p = make_two_block(16, D_log10=(0.0, 8.0), D_seed=9, rhs_seed=10)
+    o = OracleAMGF(p.n_nodes, p.K_rowptr, p.K_col, p.K_val, p.J_rowptr, p.J_col, p.J_val,
+                   p.D, p.coords, OracleOptions(coarse_max_nodes=4))
+    print(f"[gpu setup] N=16 coarse_max_nodes=4 precision {precision}", flush=True)
+    h = AMGF.from_problem(p, coarse_max_nodes=4, precision=precision)
+    assert h.n_levels == o.nlev == 4
+    modes = [h.contact_mode(l) for l in range(4)]
+    assert [m[0] for m in modes] == [1, 1, 2, 0], modes
+    rng = np.random.default_rng(14)
+    r = rng.standard_normal(o.n)
+    e_b = rel(h.vcycle(r).cpu().numpy(), o.vcycle(r))
+    e_m = rel(h.apply(r).cpu().numpy(), o.apply(r))
+    ref = o.pcg(p.b, rtol=1e-13)
+    its10 = next(k for k, v in enumerate(ref.history) if v <= 1e-10)
+    x, info = h.pcg(p.b)
+    err = rel(x.cpu().numpy(), ref.x)
+    print(f"precision {precision}: contact modes {modes}, vcycle rel {e_b:.2e}, apply rel "
+          f"{e_m:.2e}, {info.iterations} it (oracle {its10}), solution rel err {err:.2e}")
+    u = np.finfo(np.float64).eps / 2
+    assert e_b <= (1e-10 if precision == 0 else MIXED_TOL)
+    assert e_m <= max(MIXED_TOL if precision else 0.0, 10 * u * float(p.D.max()))
+    assert info.converged and err <= 1e-8
+    if precision == 0:
+        assert abs(info.iterations - its10) <= 1
+    else:
+        assert info.iterations <= its10 + 5
     h.close()
 
 

@@ -263,8 +263,8 @@ const char* amgf_last_error(void);
  *                  coefficients of the Lanczos tridiagonal of M A whose extreme
  *                  eigenvalues estimate the spectrum (the bound procedure of Sec. 6.1)
  *  AMGF_Q_CONTACT  int32[2]: how the V-cycle applies the level's contact term J^T D J
- *                  (0: none, 1: through J and D, 2: through the assembled block C of the
- *                  level, rows repacked), and the number of node rows it touches
+ *                  (0: none, 1: through J and D, 2: assembled into the matrix the level
+ *                  smooths with, A_l = K_l + C_l), and the number of node rows it touches
  * Returns EINVAL for a bad level or selector; `bytes` must equal the array size.    */
 enum {
   AMGF_Q_SIZES = 0, AMGF_Q_A_ROWPTR, AMGF_Q_A_COL, AMGF_Q_A_VAL, AMGF_Q_AGG, AMGF_Q_ROOT,

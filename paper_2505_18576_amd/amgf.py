@@ -480,7 +480,8 @@ class AMGF:
 
     def contact_mode(self, level):
         """(mode, rows) of the level's contact term in the V-cycle: 0 none, 1 through J
-        and D, 2 through the assembled block C; rows = node rows it touches."""
+        and D, 2 assembled into the smoothing matrix A_l = K_l + C_l; rows = node rows it
+        touches."""
         m = self.query(level, Q_CONTACT, np.int32, 2)
         return int(m[0]), int(m[1])
 

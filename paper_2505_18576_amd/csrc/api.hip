@@ -25,7 +25,7 @@ struct Level {
   DBuf<int> ccrows;             // nonempty rows of C (levels >= 1)
   int nccrows = 0;
   bool contact_factored = false;  // V-cycle applies the contact term through J and D
-  PackedRows cpk;               // C's listed rows repacked (assembled coarse contact term)
+  bool contact_in_A = false;    // contact term assembled into the smoothing matrix (A_l)
   BSR P, PT;                    // prolongator to the next level and its transpose
   BSR C;                        // contact term J^T D J of this level (interface rows only)
   Graph G;                      // aggregation graph
@@ -79,6 +79,8 @@ struct Handle {
   DBuf<int> ic_nodes;           // node rows holding filter DOFs
   int n_icn = 0;
   bool ic_from_J = false;       // I_c = all DOFs of the nodes J touches (not a caller's list)
+  bool r_cast_ready = false;    // level-0 fb = float(r), fx = w.fb already formed for the
+                                // next mixed V-cycle on r (set by the CG update, used once)
   bool ic_closed = false;
   // pcg scratch
   DBuf<double> pr, pz, pzo, pp, pq;
@@ -209,6 +211,8 @@ static void to_fp16_or_fp32(Ctx& c, BSR& A) {
   A.val32.alloc(nv);
   cast_d2f(c, A.val.p, A.val32.p, nv);
 }
+
+static void smoothing_copies(Handle& h, Level& L);
 
 static void to_fp32(Ctx& c, BSR& A) {
   const int64_t nv = std::max<int64_t>(A.nnzb, 1) * A.bsz();
@@ -390,8 +394,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
       N.nccrows = nonempty_rows(c, N.C.rowptr.p, N.nn, N.ccrows);
     }
     N.contact_factored = factored_contact_pays(c, N);
-    if (!N.contact_factored)
-      pack_contact_rows(c, N.C, N.ccrows.p, N.nccrows, h.mixed(), N.cpk);
+    N.contact_in_A = !N.contact_factored && N.nccrows > 0;
     nzsum += N.A.nnzb * int64_t(N.A.bsz());
     coarse_graph(c, Lc.G, Lc.agg.p, n_agg, moff.p, members.p, Gnext);
     Rprev = std::move(R);
@@ -459,9 +462,8 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
       L.vt.alloc(n);
       if (h.mixed()) { L.fd.alloc(n); L.ft.alloc(n); }
     }
-    // packed copies of the smoothed coarse stiffness (levels 1 .. L-2)
-    if (l != 0 && l + 1 < h.lev.size() && L.K.br == 6)
-      bsr_build_packed(c, L.K, !h.mixed(), h.mixed());
+    // packed copies of the smoothing matrices of the coarse levels (1 .. L-2)
+    if (l != 0 && l + 1 < h.lev.size()) smoothing_copies(h, L);
     if (h.mixed()) {
       if (l != 0) to_fp32(c, L.K);
       if (L.P.nnzb) {
@@ -513,11 +515,10 @@ static void update_D(Handle& h, const double* D) {
       spgemm(c, U.C, U.P, CP);
       L.C = BSR();
       spgemm(c, U.PT, CP, L.C);
-      if (!L.contact_factored)
-        pack_contact_rows(c, L.C, L.ccrows.p, L.nccrows, h.mixed(), L.cpk);
     }
     L.A = BSR();
     bsr_add(c, L.K, L.C, L.A);
+    if (l != 0 && L.contact_in_A && l + 1 < nlev) smoothing_copies(h, L);
     l1_norms(c, L.A, L.d);
     weights_from_l1(c, L.n(), L.d.p, nullptr, L.w.p);
     if (l + 1 < nlev) L.lam = power_estimate(h, L, l == 0 ? h.dec0.p : nullptr);
@@ -567,7 +568,7 @@ static void update_barrier(Handle& h, const double* D, const double* E) {
       spgemm(c, L.PT, KP, N.K);
       dead_identity(c, N.K, L.dead.p);
       if (h.mixed()) to_fp32(c, N.K);
-      if (l + 2 < h.lev.size() && N.K.br == 6) bsr_build_packed(c, N.K, !h.mixed(), h.mixed());
+      if (l + 2 < h.lev.size() && !N.contact_in_A) smoothing_copies(h, N);
     }
   }
   update_D(h, D);
@@ -581,16 +582,30 @@ static void coarse_solve(Handle& h, const double* b, double* x) {
   else h.coarse.solve(h.ctx, b, x);
 }
 
+// The matrix a level's smoother multiplies by: K_l, with the contact term added by
+// level_contact, or A_l = K_l + C_l itself where the contact term is assembled into it
+static const BSR& smooth_mat(const Level& L) { return L.contact_in_A ? L.A : L.K; }
+
+// packed copy of a coarse level's smoothing matrix (FP64 or FP32, with the FP32 BSR values
+// it stands in for)
+static void smoothing_copies(Handle& h, Level& L) {
+  BSR& S = L.contact_in_A ? L.A : L.K;
+  if (S.br != 6) return;
+  bsr_build_packed(h.ctx, S, !h.mixed(), h.mixed());
+  if (h.mixed() && L.contact_in_A) to_fp32(h.ctx, L.A);
+}
+
 // Contact term of a level inside the V-cycle: through J and D on level 0 (the fine
 // interface, where the assembled block would be larger than J) and on the coarse levels
 // where that still reads fewer bytes (factored_contact_pays), through the assembled
 // Galerkin block C = J^T D J on the others (one kernel instead of two).
 template <class T>
 static void level_contact(Handle& h, Level& L, int mode, const T* x, T* y, const T* w) {
+  if (L.contact_in_A) return;                         // inside the level's smoothing matrix
   if (&L == h.lev[0].get() || L.contact_factored)
     contact_apply<T, T>(h.ctx, mode, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, x, h.t.p, y, w);
   else
-    contact_packed<T, T>(h.ctx, mode, L.cpk, L.ccrows.p, x, y, w);
+    throw Error(AMGF_EDEVICE, "coarse contact term without a form");
 }
 
 // bracket the launches of kernel class `which` (level 0) when live timing is on
@@ -648,14 +663,14 @@ static void transfer(Handle& h, int mode, const BSR& A, const float* x, float* y
 // K x in the level's V-cycle precision (BF16 level-0 values in MIXED_BF16K)
 static void k_spmv(Handle& h, size_t l, int mode, const double* x, double* y, const double* b,
                    const double* w, double* xo) {
-  Level& L = *h.lev[l];
-  bsr_spmv<double>(h.ctx, mode, L.K, L.K.val.p, x, y, b, w, xo);
+  const BSR& S = smooth_mat(*h.lev[l]);
+  bsr_spmv<double>(h.ctx, mode, S, S.val.p, x, y, b, w, xo);
 }
 static void k_spmv(Handle& h, size_t l, int mode, const float* x, float* y, const float* b,
                    const float* w, float* xo) {
   Level& L = *h.lev[l];
   if (l == 0 && h.bf16k()) sell_spmv_bf16(h.ctx, mode, L.K, x, y, b, w, xo);
-  else bsr_spmv<float>(h.ctx, mode, L.K, L.K.val32.p, x, y, b, w, xo);
+  else bsr_spmv<float>(h.ctx, mode, smooth_mat(L), smooth_mat(L).val32.p, x, y, b, w, xo);
 }
 
 template <class T>
@@ -733,14 +748,15 @@ static void vcycle64_from(Handle& h, size_t l, bool x0_ready) {
   Level& N = *h.lev[l + 1];
   if (!x0_ready) wmul_f64(c, L.n(), L.w.p, L.vb.p, L.vx.p);
   if (l == 0) prof_begin(h, AMGF_K_PRESMOOTH);
-  bsr_spmv<double>(c, SPMV_RES, L.K, L.K.val.p, L.vx.p, L.vr.p, L.vb.p, nullptr, nullptr);
+  const BSR& S = smooth_mat(L);
+  bsr_spmv<double>(c, SPMV_RES, S, S.val.p, L.vx.p, L.vr.p, L.vb.p, nullptr, nullptr);
   prof_end(h);
   level_contact<double>(h, L, CT_SUB_RES, L.vx.p, L.vr.p, nullptr);
   bsr_spmv<double>(c, SPMV_Y, L.PT, L.PT.val.p, L.vr.p, N.vb.p, nullptr, nullptr, nullptr);
   vcycle64(h, l + 1);
   bsr_spmv<double>(c, SPMV_ADD, L.P, L.P.val.p, N.vx.p, L.vx.p, nullptr, nullptr, nullptr);
   if (l == 0) prof_begin(h, AMGF_K_POSTSMOOTH);
-  bsr_spmv<double>(c, SPMV_POST, L.K, L.K.val.p, L.vx.p, nullptr, L.vb.p, L.w.p, L.vxn.p);
+  bsr_spmv<double>(c, SPMV_POST, S, S.val.p, L.vx.p, nullptr, L.vb.p, L.w.p, L.vxn.p);
   prof_end(h);
   level_contact<double>(h, L, CT_SUB_W, L.vx.p, L.vxn.p, L.w.p);
   std::swap(L.vx, L.vxn);
@@ -767,7 +783,8 @@ static void vcycle32_from(Handle& h, size_t l, bool x0_ready) {
   if (l == 0 && h.bf16k())
     sell_spmv_bf16(c, SPMV_RES, L.K, L.fx.p, L.fr.p, L.fb.p, nullptr, nullptr);
   else
-    bsr_spmv<float>(c, SPMV_RES, L.K, L.K.val32.p, L.fx.p, L.fr.p, L.fb.p, nullptr, nullptr);
+    bsr_spmv<float>(c, SPMV_RES, smooth_mat(L), smooth_mat(L).val32.p, L.fx.p, L.fr.p, L.fb.p,
+                    nullptr, nullptr);
   prof_end(h);
   level_contact<float>(h, L, CT_SUB_RES, L.fx.p, L.fr.p, nullptr);
   transfer_spmv(c, SPMV_Y, L.PT, L.fr.p, N.fb.p);
@@ -777,7 +794,8 @@ static void vcycle32_from(Handle& h, size_t l, bool x0_ready) {
   if (l == 0 && h.bf16k())
     sell_spmv_bf16(c, SPMV_POST, L.K, L.fx.p, nullptr, L.fb.p, L.w32.p, L.fxn.p);
   else
-    bsr_spmv<float>(c, SPMV_POST, L.K, L.K.val32.p, L.fx.p, nullptr, L.fb.p, L.w32.p, L.fxn.p);
+    bsr_spmv<float>(c, SPMV_POST, smooth_mat(L), smooth_mat(L).val32.p, L.fx.p, nullptr, L.fb.p,
+                    L.w32.p, L.fxn.p);
   prof_end(h);
   level_contact<float>(h, L, CT_SUB_W, L.fx.p, L.fxn.p, L.w32.p);
   std::swap(L.fx, L.fxn);
@@ -790,7 +808,8 @@ static void vcycle(Handle& h, const double* r, double* z) {
   const int64_t n = h.n();
   if (h.mixed()) {
     if (h.plain_cycle()) {
-      cast_d2f_w(c, r, L0.w32.p, L0.fb.p, L0.fx.p, n);
+      if (!h.r_cast_ready) cast_d2f_w(c, r, L0.w32.p, L0.fb.p, L0.fx.p, n);
+      h.r_cast_ready = false;
       vcycle32_from(h, 0, true);
     } else {
       cast_d2f(c, r, L0.fb.p, n);
@@ -846,7 +865,8 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
     // FP32 V-cycles: z1 = B r stays in FP32 (L0.fx, widened exactly wherever FP64 reads
     // it); the FP64 z2 = z1 + P w is formed on the filter DOFs only (h.z1 there), which
     // cover every DOF the contact term reads when I_c comes from J
-    cast_d2f_w(c, r, L0.w32.p, L0.fb.p, L0.fx.p, n);
+    if (!h.r_cast_ready) cast_d2f_w(c, r, L0.w32.p, L0.fb.p, L0.fx.p, n);
+    h.r_cast_ready = false;
     vcycle32_from(h, 0, true);                        // z1 = B r  (L0.fx)
     if (h.n_c > 0) {
       phase(h, PH_FILTER);
@@ -1266,9 +1286,18 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
       const double* ys[1] = {h.pq.p};
       dots_device(c, n, 1, xs, ys, dsc, dpart);
     }
-    pcg_update_xr_dev(c, n, rz, dsc, h.pp.p, h.pq.p, x, h.pr.p);
+    if (h.mixed() && h.plain_cycle()) {
+      // the V-cycle's first level-0 vectors come out of the residual update
+      Level& L0 = *h.lev[0];
+      pcg_update_xr_dev_f(c, n, rz, dsc, h.pp.p, h.pq.p, x, h.pr.p, L0.w32.p, L0.fb.p,
+                          L0.fx.p);
+      h.r_cast_ready = true;
+    } else {
+      pcg_update_xr_dev(c, n, rz, dsc, h.pp.p, h.pq.p, x, h.pr.p);
+    }
     std::swap(h.pz, h.pzo);
     amgf_apply_impl(h, h.pr.p, h.pz.p);
+    h.r_cast_ready = false;
     {
       const double* xs[2] = {h.pr.p, h.pr.p};
       const double* ys[2] = {h.pz.p, h.pzo.p};
@@ -1926,11 +1955,13 @@ amgf_status amgf_query(amgf_handle hd, int32_t level, int32_t which, void* dst, 
     switch (which) {
       case AMGF_Q_CONTACT: {
         const bool last = level + 1 == int(h.lev.size());
-        const bool fac = level == 0 || L.contact_factored;
         int32_t v[2] = {0, 0};
-        if (!last && (fac ? L.ncrows : L.nccrows) > 0) {
-          v[0] = fac ? 1 : 2;
-          v[1] = fac ? L.ncrows : L.nccrows;
+        if (!last && L.contact_in_A) {
+          v[0] = 2;
+          v[1] = L.nccrows;
+        } else if (!last && L.ncrows > 0) {
+          v[0] = 1;
+          v[1] = L.ncrows;
         }
         AMGF_REQUIRE(bytes == sizeof(v), AMGF_EINVAL, "query size mismatch");
         std::copy(v, v + 2, static_cast<int32_t*>(dst));

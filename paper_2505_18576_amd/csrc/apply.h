@@ -45,29 +45,9 @@ enum ContactMode { CT_SUB_RES = 0, CT_SUB_W = 1, CT_ADD = 2 };
 template <class TX, class TY>
 void contact_apply(Ctx& c, int mode, const BSR& J, const BSR& JT, const int* crows, int ncrows,
                    const double* D, const TX* x, double* t, TY* y, const TY* w);
-// The listed rows of a coarse contact block C (B x B FP64 blocks) repacked for coalesced
-// reads: row i (i-th listed row) keeps its nb_i blocks padded with zero blocks to nbp_i, a
-// multiple of 16, from block offset off[i] (off[nrows] = total); column ids
-// col[off[i] + k] (padding: the row itself), entry (p, q) of block k at
-// val[B*B*off[i] + (B*p + q)*nbp_i + k], so the lanes of a wavefront, one block each, read
-// one entry of 64 blocks as contiguous bytes.  Values in FP64 (val) or, for the FP32
-// V-cycle, rounded once to FP32 (val32, like the coarse stiffness it is added to).
-struct PackedRows {
-  int nrows = 0, b = 0;
-  DBuf<int> off, col;
-  DBuf<double> val;
-  DBuf<float> val32;
-};
-void pack_contact_rows(Ctx& c, const BSR& C, const int* rows, int nrows, bool fp32,
-                       PackedRows& pk);
 // packed copy of a square matrix (BSR::pk_*) with FP64 and/or FP32 values; bsr_spmv then
 // applies the matrix through it when it is handed the matrix's own values
 void bsr_build_packed(Ctx& c, BSR& A, bool fp64, bool fp32);
-// the same three modes with the assembled contact block of a coarse level, applied to its
-// listed nonempty rows through the packed copy
-template <class TX, class TY>
-void contact_packed(Ctx& c, int mode, const PackedRows& pk, const int* rows, const TX* x,
-                    TY* y, const TY* w);
 // indices of the nonempty rows of a CSR pattern
 int nonempty_rows(Ctx& c, const int* rp, int n, DBuf<int>& rows);
 // y = b - A x on the listed block rows only (FP64, 3x3 blocks)
@@ -126,6 +106,11 @@ void pcg_update_xr(Ctx& c, int64_t n, double alpha, const double* p, const doubl
 // x += a p, r -= a q with a = rz / pq[0] (pq in device memory)
 void pcg_update_xr_dev(Ctx& c, int64_t n, double rz, const double* pq, const double* p,
                        const double* q, double* x, double* r);
+// the same, also writing fb = float(r) and fx = w.fb (the mixed V-cycle's level-0 input
+// and first smoothing iterate)
+void pcg_update_xr_dev_f(Ctx& c, int64_t n, double rz, const double* pq, const double* p,
+                         const double* q, double* x, double* r, const float* w, float* fb,
+                         float* fx);
 void pcg_update_p(Ctx& c, int64_t n, double beta, const double* z, double* p);
 // p = z + beta p with beta = (s[0] - s[1]) / rz, s = {r.z, r.z_old} in device memory
 void pcg_update_p_dev(Ctx& c, int64_t n, double rz, const double* s, const double* z,

@@ -352,21 +352,20 @@ template void contact_apply<float, double>(Ctx&, int, const BSR&, const BSR&, co
                                            const double*, const float*, double*, double*,
                                            const double*);
 
-// Coarse-level contact term from its assembled block C = J^T D J (FP64, B x B blocks).
+// ======================================================================================
+// packed copy of a square matrix (BSR::pk_*): rows padded to PACK_PAD blocks, entry-major
+// ======================================================================================
 constexpr int PACK_PAD = 16;   // blocks: 128-byte aligned entry stripes
 
-// rows == nullptr: every row of the matrix, in order
-__global__ void k_pack_count(int nrows, const int* __restrict__ rows,
-                             const int* __restrict__ rp, int* __restrict__ cnt) {
+__global__ void k_pack_count(int nrows, const int* __restrict__ rp, int* __restrict__ cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nrows) return;
-  const int a = rows ? rows[i] : i;
-  cnt[i] = (rp[a + 1] - rp[a] + PACK_PAD - 1) / PACK_PAD * PACK_PAD;
+  cnt[i] = (rp[i + 1] - rp[i] + PACK_PAD - 1) / PACK_PAD * PACK_PAD;
 }
 
+// one wavefront per row, a lane per (padded) block
 template <int B, class TV>
-__global__ void __launch_bounds__(256) k_pack_fill(int nrows, const int* __restrict__ rows,
-                                                   const int* __restrict__ rp,
+__global__ void __launch_bounds__(256) k_pack_fill(int nrows, const int* __restrict__ rp,
                                                    const int* __restrict__ col,
                                                    const double* __restrict__ val,
                                                    const int* __restrict__ off,
@@ -375,8 +374,7 @@ __global__ void __launch_bounds__(256) k_pack_fill(int nrows, const int* __restr
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= nrows) return;
-  const int a = rows ? rows[i] : i;
-  const int r0 = rp[a], nb = rp[a + 1] - r0;
+  const int r0 = rp[i], nb = rp[i + 1] - r0;
   const int o0 = off[i], nbp = off[i + 1] - o0;
   TV* pv = pval + int64_t(o0) * B * B;
   for (int k = lane; k < nbp; k += 64) {
@@ -386,52 +384,14 @@ __global__ void __launch_bounds__(256) k_pack_fill(int nrows, const int* __restr
 #pragma unroll
       for (int e = 0; e < B * B; ++e) pv[int64_t(e) * nbp + k] = TV(v[e]);
     } else {
-      pcol[o0 + k] = a;
+      pcol[o0 + k] = i;
 #pragma unroll
       for (int e = 0; e < B * B; ++e) pv[int64_t(e) * nbp + k] = TV(0);
     }
   }
 }
 
-void pack_contact_rows(Ctx& c, const BSR& C, const int* rows, int nrows, bool fp32,
-                       PackedRows& pk) {
-  AMGF_REQUIRE(C.br == C.bc && (C.br == 6 || C.br == 3), AMGF_EINVAL,
-               "coarse contact block size");
-  pk.nrows = nrows;
-  pk.b = C.br;
-  DBuf<int> cnt(std::max(nrows, 1));
-  pk.off.alloc(size_t(nrows) + 1);
-  if (nrows)
-    hipLaunchKernelGGL(k_pack_count, dim3(grid_for(nrows, 256)), dim3(256), 0, c.s, nrows,
-                       rows, C.rowptr.p, cnt.p);
-  const int total = scan_exclusive(c, cnt.p, pk.off.p, nrows);
-  pk.col.alloc(std::max(total, 1));
-  const size_t nv = std::max<size_t>(size_t(total) * C.br * C.br, 1);
-  if (fp32) {
-    pk.val = DBuf<double>();
-    pk.val32.alloc(nv);
-  } else {
-    pk.val32 = DBuf<float>();
-    pk.val.alloc(nv);
-  }
-  if (nrows && total) {
-    const dim3 g(grid_for(nrows, 4)), blk(256);
-#define AMGF_PF(B, TV, dst)                                                                  \
-  hipLaunchKernelGGL((k_pack_fill<B, TV>), g, blk, 0, c.s, nrows, rows, C.rowptr.p, C.col.p, \
-                     C.val.p, pk.off.p, pk.col.p, dst)
-    if (C.br == 6) {
-      if (fp32) AMGF_PF(6, float, pk.val32.p);
-      else AMGF_PF(6, double, pk.val.p);
-    } else {
-      if (fp32) AMGF_PF(3, float, pk.val32.p);
-      else AMGF_PF(3, double, pk.val.p);
-    }
-#undef AMGF_PF
-  }
-  AMGF_LAUNCH_CHECK();
-}
-
-// the packed copy of a whole square B x B matrix (the coarse stiffness of the V-cycle)
+// the packed copy of a whole square B x B matrix (a coarse level's smoothing matrix)
 void bsr_build_packed(Ctx& c, BSR& A, bool fp64, bool fp32) {
   AMGF_REQUIRE(A.br == A.bc && A.nrows == A.ncols && (A.br == 6 || A.br == 3), AMGF_EINVAL,
                "packed copy needs a square matrix of 3x3 or 6x6 blocks");
@@ -439,8 +399,8 @@ void bsr_build_packed(Ctx& c, BSR& A, bool fp64, bool fp32) {
   DBuf<int> cnt(std::max(n, 1));
   A.pk_off.alloc(size_t(n) + 1);
   if (n)
-    hipLaunchKernelGGL(k_pack_count, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, nullptr,
-                       A.rowptr.p, cnt.p);
+    hipLaunchKernelGGL(k_pack_count, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, A.rowptr.p,
+                       cnt.p);
   const int total = scan_exclusive(c, cnt.p, A.pk_off.p, n);
   A.pk_col.alloc(std::max(total, 1));
   const size_t nv = std::max<size_t>(size_t(total) * B * B, 1);
@@ -451,8 +411,8 @@ void bsr_build_packed(Ctx& c, BSR& A, bool fp64, bool fp32) {
   if (n && total) {
     const dim3 g(grid_for(n, 4)), blk(256);
 #define AMGF_PF(BB, TV, dst)                                                                 \
-  hipLaunchKernelGGL((k_pack_fill<BB, TV>), g, blk, 0, c.s, n, nullptr, A.rowptr.p, A.col.p, \
-                     A.val.p, A.pk_off.p, A.pk_col.p, dst)
+  hipLaunchKernelGGL((k_pack_fill<BB, TV>), g, blk, 0, c.s, n, A.rowptr.p, A.col.p, A.val.p,  \
+                     A.pk_off.p, A.pk_col.p, dst)
     if (B == 6) {
       if (fp64) AMGF_PF(6, double, A.pk_val.p);
       if (fp32) AMGF_PF(6, float, A.pk_val32.p);
@@ -539,89 +499,6 @@ static void launch_packed(Ctx& c, int mode, const BSR& A, const TV* pv, const T*
   AMGF_LAUNCH_CHECK();
 }
 
-// one wavefront per listed row, a lane per block: every value load of the wavefront reads
-// 64 consecutive values of one entry stripe; two 64-block stretches are in flight at once
-// (a row at C5's third level holds about 110 blocks)
-template <int B, class TV, class TX, class TY, int MODE>
-__global__ void __launch_bounds__(256) k_contact_packed(int nrows, const int* __restrict__ rows,
-                                                        const int* __restrict__ off,
-                                                        const int* __restrict__ pcol,
-                                                        const TV* __restrict__ pval,
-                                                        const TX* __restrict__ x,
-                                                        TY* __restrict__ y,
-                                                        const TY* __restrict__ w) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (i >= nrows) return;
-  const int a = rows[i];
-  const int o0 = off[i], nbp = off[i + 1] - o0;
-  const TV* pv = pval + int64_t(o0) * B * B;
-  double acc[B];
-#pragma unroll
-  for (int p = 0; p < B; ++p) acc[p] = 0.0;
-#pragma unroll 2
-  for (int k = lane; k < nbp; k += 64) {
-    const int64_t base = int64_t(pcol[o0 + k]) * B;
-    double xq[B];
-#pragma unroll
-    for (int q = 0; q < B; ++q) xq[q] = double(x[base + q]);
-#pragma unroll
-    for (int p = 0; p < B; ++p)
-#pragma unroll
-      for (int q = 0; q < B; ++q) acc[p] += double(pv[int64_t(B * p + q) * nbp + k]) * xq[q];
-  }
-#pragma unroll
-  for (int p = 0; p < B; ++p) acc[p] = wave_sum(acc[p]);
-  if (lane >= B) return;
-  double cv = 0.0;
-#pragma unroll
-  for (int p = 0; p < B; ++p)
-    if (lane == p) cv = acc[p];
-  const int64_t ix = int64_t(a) * B + lane;
-  if (MODE == CT_SUB_RES) y[ix] = TY(double(y[ix]) - cv);
-  else if (MODE == CT_SUB_W) y[ix] = TY(double(y[ix]) - double(w[ix]) * cv);
-  else y[ix] = TY(double(y[ix]) + cv);
-}
-
-template <class TX, class TY>
-void contact_packed(Ctx& c, int mode, const PackedRows& pk, const int* rows, const TX* x,
-                    TY* y, const TY* w) {
-  if (pk.nrows == 0) return;
-  const dim3 g(grid_for(pk.nrows, 4)), blk(256);
-  // FP32 values serve the FP32 V-cycle; FP64 vectors need the FP64 copy
-  const bool f32 = pk.val32.n > 0;
-  AMGF_REQUIRE(f32 ? sizeof(TY) == 4 : pk.val.n > 0, AMGF_EINVAL,
-               "packed contact rows stored in the other precision");
-#define AMGF_CP1(B, TV, vp)                                                                  \
-  if (mode == CT_SUB_RES)                                                                    \
-    hipLaunchKernelGGL((k_contact_packed<B, TV, TX, TY, CT_SUB_RES>), g, blk, 0, c.s,        \
-                       pk.nrows, rows, pk.off.p, pk.col.p, vp, x, y, w);                     \
-  else if (mode == CT_SUB_W)                                                                 \
-    hipLaunchKernelGGL((k_contact_packed<B, TV, TX, TY, CT_SUB_W>), g, blk, 0, c.s,          \
-                       pk.nrows, rows, pk.off.p, pk.col.p, vp, x, y, w);                     \
-  else                                                                                       \
-    hipLaunchKernelGGL((k_contact_packed<B, TV, TX, TY, CT_ADD>), g, blk, 0, c.s, pk.nrows,  \
-                       rows, pk.off.p, pk.col.p, vp, x, y, w);
-#define AMGF_CP(B)                                                                           \
-  if (f32) {                                                                                 \
-    AMGF_CP1(B, float, pk.val32.p)                                                           \
-  } else {                                                                                   \
-    AMGF_CP1(B, double, pk.val.p)                                                            \
-  }
-  if (pk.b == 6) {
-    AMGF_CP(6)
-  } else {
-    AMGF_CP(3)
-  }
-#undef AMGF_CP
-#undef AMGF_CP1
-  AMGF_LAUNCH_CHECK();
-}
-template void contact_packed<double, double>(Ctx&, int, const PackedRows&, const int*,
-                                             const double*, double*, const double*);
-template void contact_packed<float, float>(Ctx&, int, const PackedRows&, const int*,
-                                           const float*, float*, const float*);
-
 // nonempty rows of a CSR (compact list)
 __global__ void k_nonempty_flag(int n, const int* __restrict__ rp, int* __restrict__ f) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -702,6 +579,20 @@ AMGF_ELEMWISE(k_xr_dev, (int64_t n, double rz, const double* __restrict__ pq,
               const double al = rz / pq[0];
               x[i] += al * p[i];
               r[i] -= al * q[i])
+// the same, and the mixed V-cycle's first two level-0 vectors from the new residual:
+// b = float(r), x = w.b (what the V-cycle would otherwise form in a pass of its own)
+AMGF_ELEMWISE(k_xr_dev_f, (int64_t n, double rz, const double* __restrict__ pq,
+                           const double* __restrict__ p, const double* __restrict__ q,
+                           double* __restrict__ x, double* __restrict__ r,
+                           const float* __restrict__ w, float* __restrict__ fb,
+                           float* __restrict__ fx),
+              const double al = rz / pq[0];
+              x[i] += al * p[i];
+              const double ri = r[i] - al * q[i];
+              r[i] = ri;
+              const float bi = float(ri);
+              fb[i] = bi;
+              fx[i] = w[i] * bi)
 AMGF_ELEMWISE(k_pupd, (int64_t n, double be, const double* __restrict__ z, double* __restrict__ p),
               p[i] = z[i] + be * p[i])
 // beta = (r.z - r.z_old) / rz with both dots read from device memory, then p = z + beta p
@@ -863,6 +754,11 @@ void pcg_update_xr(Ctx& c, int64_t n, double alpha, const double* p, const doubl
 void pcg_update_xr_dev(Ctx& c, int64_t n, double rz, const double* pq, const double* p,
                        const double* q, double* x, double* r) {
   if (n) hipLaunchKernelGGL(k_xr_dev, AMGF_L1D(n), n, rz, pq, p, q, x, r);
+}
+void pcg_update_xr_dev_f(Ctx& c, int64_t n, double rz, const double* pq, const double* p,
+                         const double* q, double* x, double* r, const float* w, float* fb,
+                         float* fx) {
+  if (n) hipLaunchKernelGGL(k_xr_dev_f, AMGF_L1D(n), n, rz, pq, p, q, x, r, w, fb, fx);
 }
 void pcg_update_p(Ctx& c, int64_t n, double beta, const double* z, double* p) {
   if (n) hipLaunchKernelGGL(k_pupd, AMGF_L1D(n), n, beta, z, p);

@@ -170,9 +170,9 @@ def test_three_level_vcycle_and_apply_match_oracle(kw):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_assembled_coarse_contact_level(precision):
     """N = 16 coarsened to at most 4 nodes: level 2 (31 nodes) meets every constraint, and
-    its assembled block C_2 reads fewer bytes than J_2 and D, so the V-cycle applies it
-    through the repacked rows of C_2 (FP64 values, FP32 in the mixed cycle); level 1 goes
-    through J_1 and D.  V-cycle, M r and PCG against the oracle (which forms J^T D J)."""
+    its assembled block C_2 reads fewer bytes than J_2 and D, so level 2 smooths with
+    A_2 = K_2 + C_2 itself (packed rows, FP32 in the mixed cycle); level 1 adds its contact
+    term through J_1 and D.  V-cycle, M r and PCG against the oracle (which forms J^T D J)."""
     from amgf_inputs import make_two_block
     from oracle import OracleAMGF, OracleOptions
     from paper_2505_18576_amd import AMGF

@@ -518,10 +518,11 @@ static void update_D(Handle& h, const double* D) {
     }
     L.A = BSR();
     bsr_add(c, L.K, L.C, L.A);
-    if (l != 0 && L.contact_in_A && l + 1 < nlev) smoothing_copies(h, L);
     l1_norms(c, L.A, L.d);
     weights_from_l1(c, L.n(), L.d.p, nullptr, L.w.p);
     if (l + 1 < nlev) L.lam = power_estimate(h, L, l == 0 ? h.dec0.p : nullptr);
+    // after the power estimate, which the fresh setup also runs on the plain BSR A_l
+    if (l != 0 && L.contact_in_A && l + 1 < nlev) smoothing_copies(h, L);
   }
   factor_coarsest(h);
   AMGF_HIP(hipStreamSynchronize(c.s));
@@ -586,13 +587,13 @@ static void coarse_solve(Handle& h, const double* b, double* x) {
 // level_contact, or A_l = K_l + C_l itself where the contact term is assembled into it
 static const BSR& smooth_mat(const Level& L) { return L.contact_in_A ? L.A : L.K; }
 
-// packed copy of a coarse level's smoothing matrix (FP64 or FP32, with the FP32 BSR values
-// it stands in for)
+// packed copy of a coarse level's smoothing matrix: FP32 values for the mixed V-cycle's K_l,
+// FP64 otherwise; A_l = K_l + C_l keeps FP64 values in every mode, so the contact term stays
+// FP64 (the FP32 cycle then accumulates its products in FP64)
 static void smoothing_copies(Handle& h, Level& L) {
   BSR& S = L.contact_in_A ? L.A : L.K;
-  if (S.br != 6) return;
-  bsr_build_packed(h.ctx, S, !h.mixed(), h.mixed());
-  if (h.mixed() && L.contact_in_A) to_fp32(h.ctx, L.A);
+  const bool f32 = h.mixed() && !L.contact_in_A;
+  bsr_build_packed(h.ctx, S, !f32, f32);
 }
 
 // Contact term of a level inside the V-cycle: through J and D on level 0 (the fine

@@ -1,6 +1,8 @@
 // Apply-phase kernels: the V-cycle, the filter correction and the CG loop are built
 // from these.  All are memory-bound; reductions are two-stage with a fixed
 // assignment of elements to lanes, so results do not depend on scheduling.
+#include <type_traits>
+
 #include "apply.h"
 
 namespace amgf {
@@ -215,15 +217,19 @@ void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, co
     }
     if (sv) return sell3_spmv<T>(c, mode, A, sv, x, y, b, w, xo);
   }
-  if (A.br == 6 && A.bc == 6 && A.pk_off.p) {
+  if (A.br == A.bc && (A.br == 6 || A.br == 3) && A.pk_off.p) {
     // the packed copy stands in for the BSR values of the same precision
+#define AMGF_PK(TV, vp)                                                                      \
+  return A.br == 6 ? launch_packed<6, TV, T>(c, mode, A, vp, x, y, b, w, xo)                \
+                   : launch_packed<3, TV, T>(c, mode, A, vp, x, y, b, w, xo)
     if constexpr (sizeof(T) == 8) {
-      if (val == A.val.p && A.pk_val.p)
-        return launch_packed<6, double, T>(c, mode, A, A.pk_val.p, x, y, b, w, xo);
+      if (val == A.val.p && A.pk_val.p) AMGF_PK(double, A.pk_val.p);
     } else {
-      if (val == A.val32.p && A.pk_val32.p)
-        return launch_packed<6, float, T>(c, mode, A, A.pk_val32.p, x, y, b, w, xo);
+      if (val == A.val32.p && A.pk_val32.p) AMGF_PK(float, A.pk_val32.p);
+      // a matrix kept in FP64 only (a smoothing matrix that holds the contact term)
+      if (val == nullptr && !A.val32.p && A.pk_val.p) AMGF_PK(double, A.pk_val.p);
     }
+#undef AMGF_PK
   }
   if (A.br == 3 && A.bc == 3) return launch_bsr<3, 3, 8, T>(c, mode, A, val, x, y, b, w, xo);
   if (A.br == 3 && A.bc == 6) return launch_bsr<3, 6, 8, T>(c, mode, A, val, x, y, b, w, xo);
@@ -427,7 +433,8 @@ void bsr_build_packed(Ctx& c, BSR& A, bool fp64, bool fp32) {
 
 // y (op)= A x over every row through the packed copy: one wavefront per row, a lane per
 // block, two 64-block stretches in flight; products accumulate in T per lane, then over the
-// wavefront.  Modes and epilogue as k_bsr.
+// wavefront.  Modes and epilogue as k_bsr.  FP64 values with FP32 vectors (a level whose
+// smoothing matrix holds the contact term) accumulate and form the residual in FP64.
 template <int B, class TV, class T, int MODE>
 __global__ void __launch_bounds__(256) k_packed_spmv(int nrows, const int* __restrict__ off,
                                                      const int* __restrict__ pcol,
@@ -436,44 +443,45 @@ __global__ void __launch_bounds__(256) k_packed_spmv(int nrows, const int* __res
                                                      const T* __restrict__ b,
                                                      const T* __restrict__ w,
                                                      T* __restrict__ xo) {
+  using Acc = std::conditional_t<sizeof(TV) == 8, double, T>;
   const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (r >= nrows) return;
   const int o0 = off[r], nbp = off[r + 1] - o0;
   const TV* pv = pval + int64_t(o0) * B * B;
-  T acc[B];
+  Acc acc[B];
 #pragma unroll
-  for (int p = 0; p < B; ++p) acc[p] = T(0);
+  for (int p = 0; p < B; ++p) acc[p] = Acc(0);
 #pragma unroll 2
   for (int k = lane; k < nbp; k += 64) {
     const int64_t base = int64_t(pcol[o0 + k]) * B;
-    T xq[B];
+    Acc xq[B];
 #pragma unroll
     for (int q = 0; q < B; ++q)
-      xq[q] = (MODE == SPMV_PRE) ? w[base + q] * b[base + q] : x[base + q];
+      xq[q] = Acc((MODE == SPMV_PRE) ? w[base + q] * b[base + q] : x[base + q]);
 #pragma unroll
     for (int p = 0; p < B; ++p)
 #pragma unroll
-      for (int q = 0; q < B; ++q) acc[p] += T(pv[int64_t(B * p + q) * nbp + k]) * xq[q];
+      for (int q = 0; q < B; ++q) acc[p] += Acc(pv[int64_t(B * p + q) * nbp + k]) * xq[q];
   }
 #pragma unroll
   for (int p = 0; p < B; ++p) acc[p] = wave_sum(acc[p]);
   if (lane >= B) return;
-  T ax = T(0);
+  Acc ax = Acc(0);
 #pragma unroll
   for (int p = 0; p < B; ++p)
     if (lane == p) ax = acc[p];
   const int64_t i = int64_t(r) * B + lane;
-  if (MODE == SPMV_Y) y[i] = ax;
-  else if (MODE == SPMV_ADD) y[i] += ax;
+  if (MODE == SPMV_Y) y[i] = T(ax);
+  else if (MODE == SPMV_ADD) y[i] = T(Acc(y[i]) + ax);
   else if (MODE == SPMV_PRE) {
     const T xi = w[i] * b[i];
     xo[i] = xi;
-    y[i] = b[i] - ax;
+    y[i] = T(Acc(b[i]) - ax);
   } else if (MODE == SPMV_POST) {
-    xo[i] = x[i] + w[i] * (b[i] - ax);
+    xo[i] = T(Acc(x[i]) + Acc(w[i]) * (Acc(b[i]) - ax));
   } else {
-    y[i] = b[i] - ax;
+    y[i] = T(Acc(b[i]) - ax);
   }
 }
 

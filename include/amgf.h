@@ -115,6 +115,13 @@ typedef struct {
                                  4.9e-4; FP32 if a value overflows) and applies them in
                                  FP32; 0: FP32 values.  The Galerkin operators, the
                                  FP64 V-cycle and every FP64 path keep FP64 P.          */
+  int32_t cycle_gamma;        /* visits of the next level per coarse correction, 1..4:
+                                 1 (default) the V-cycle; 2 the W-cycle, whose coarse
+                                 correction on each level above the coarsest is
+                                 (2 B_c - B_c A_c B_c) applied to the restricted residual
+                                 (B_c the cycle one level down; the coarsest solve is
+                                 exact and is visited once).  Not in the paper, which uses
+                                 V-cycles.  amgf_mlp_loss_grad needs 1.                  */
 } amgf_options;
 
 typedef struct {

@@ -508,6 +508,7 @@ class OracleOptions:
     smoother: str = "jacobi"              # "jacobi" (l1-Jacobi) or "chebyshev"
     sweeps: int = 1                       # smoother applications before and after
     cheb_degree: int = 2                  # Chebyshev polynomial degree
+    cycle_gamma: int = 1                  # coarse visits per level: 1 V-cycle, 2 W-cycle
 
 
 @dataclass
@@ -770,7 +771,10 @@ class OracleAMGF:
 
     def vcycle(self, b, l=0):
         """B b: symmetric V(nu, nu) from a zero initial guess (O11): nu smoother
-        applications, coarse correction, nu smoother applications."""
+        applications, coarse correction, nu smoother applications.  With cycle_gamma = g
+        the coarse correction visits level l+1 g times, each later visit on the residual
+        the earlier ones left (g = 2: the W-cycle); the coarsest solve is exact and is
+        visited once."""
         if l == self.nlev - 1:
             return sla.cho_solve(self.coarse_chol, b)
         lev = self.levels[l]
@@ -779,7 +783,12 @@ class OracleAMGF:
         for _ in range(self.opts.sweeps):
             x = self.smooth(l, b, x)
         r = b - A @ x
-        xc = self.vcycle(lev.P.csr().T @ r, l + 1)
+        rc = lev.P.csr().T @ r
+        xc = self.vcycle(rc, l + 1)
+        if l + 1 < self.nlev - 1:
+            Ac = self.levels[l + 1].A.csr()
+            for _ in range(self.opts.cycle_gamma - 1):
+                xc = xc + self.vcycle(rc - Ac @ xc, l + 1)
         x = x + lev.P.csr() @ xc
         for _ in range(self.opts.sweeps):
             x = self.smooth(l, b, x)

@@ -81,7 +81,7 @@ class Options(ctypes.Structure):
                 ("sweeps", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
                 ("allocator", Allocator), ("bound_diag", ctypes.c_void_p),
                 ("near_null", ctypes.c_int32), ("learned_judge", ctypes.c_int32),
-                ("transfer_fp16", ctypes.c_int32)]
+                ("transfer_fp16", ctypes.c_int32), ("cycle_gamma", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -41,6 +41,9 @@ struct Level {
   // V-cycle work vectors
   DBuf<double> vb, vx, vr, vxn;
   DBuf<float> fb, fx, fr, fxn;
+  // repeated visits of this level (cycle_gamma > 1): the correction so far and the residual
+  DBuf<double> vxw, vbw;
+  DBuf<float> fxw, fbw;
   // Chebyshev / multi-sweep smoothing work vectors
   DBuf<double> vd, vt;
   DBuf<float> fd, ft;
@@ -457,6 +460,11 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     Level& L = *h.lev[l];
     const int64_t n = L.n();
     L.vb.alloc(n); L.vx.alloc(n); L.vr.alloc(n); L.vxn.alloc(n);
+    if (h.opt.cycle_gamma > 1 && l != 0 && l + 1 < h.lev.size()) {
+      L.vxw.alloc(n);
+      L.vbw.alloc(n);
+      if (h.mixed()) { L.fxw.alloc(n); L.fbw.alloc(n); }
+    }
     if (!h.plain_cycle()) {
       L.vd.alloc(n);
       L.vt.alloc(n);
@@ -640,15 +648,17 @@ static void phase(Handle& h, int ph) {
 // polynomial in D_l1^{-1} A over [0.3 lam, lam], lam = min(1, 1.1 * power estimate)
 template <class T>
 struct LvBufs {
-  DBuf<T>*b, *x, *xn, *r, *d, *t;
+  DBuf<T>*b, *x, *xn, *r, *d, *t, *xw, *bw;
   const T* w;
 };
 static LvBufs<double> lv_bufs(Level& L, double) {
-  return {&L.vb, &L.vx, &L.vxn, &L.vr, &L.vd, &L.vt, L.w.p};
+  return {&L.vb, &L.vx, &L.vxn, &L.vr, &L.vd, &L.vt, &L.vxw, &L.vbw, L.w.p};
 }
 static LvBufs<float> lv_bufs(Level& L, float) {
-  return {&L.fb, &L.fx, &L.fxn, &L.fr, &L.fd, &L.ft, L.w32.p};
+  return {&L.fb, &L.fx, &L.fxn, &L.fr, &L.fd, &L.ft, &L.fxw, &L.fbw, L.w32.p};
 }
+static void add_to(Ctx& c, int64_t n, const double* a, double* y) { axpby(c, n, 1.0, a, 1.0, y); }
+static void add_to(Ctx& c, int64_t n, const float* a, float* y) { add_to_f32(c, n, a, y); }
 
 static const double* bsr_vals(const BSR& A, double) { return A.val.p; }
 static const float* bsr_vals(const BSR& A, float) { return A.val32.p; }
@@ -717,6 +727,26 @@ static void smooth_once(Handle& h, size_t l, bool x_zero) {
   }
 }
 
+// The coarse correction of level l on level l+1 (input *NB.b, result *NB.x): cycle_gamma
+// visits, each later one on the residual the earlier ones left, their corrections summed
+// (gamma = 2: x = 2 B b - B A B b, the W-cycle).  The coarsest solve is exact: one visit.
+template <class T>
+static void coarse_visits(Handle& h, size_t l, void (*coarse)(Handle&, size_t)) {
+  coarse(h, l + 1);
+  if (h.opt.cycle_gamma <= 1 || l + 2 >= h.lev.size()) return;
+  Level& N = *h.lev[l + 1];
+  LvBufs<T> NB = lv_bufs(N, T());
+  for (int g = 1; g < h.opt.cycle_gamma; ++g) {
+    k_spmv(h, l + 1, SPMV_RES, NB.x->p, NB.bw->p, NB.b->p, (const T*)nullptr, (T*)nullptr);
+    contact<T>(h, N, CT_SUB_RES, NB.x->p, NB.bw->p, (const T*)nullptr);
+    std::swap(*NB.b, *NB.bw);                         // next visit: on the residual
+    std::swap(*NB.x, *NB.xw);                         // keep the correction so far
+    coarse(h, l + 1);
+    add_to(h.ctx, N.n(), NB.xw->p, NB.x->p);
+    std::swap(*NB.b, *NB.bw);
+  }
+}
+
 // general V(nu, nu) on level l (not the coarsest): *B.b -> *B.x
 template <class T>
 static void vcycle_general(Handle& h, size_t l, void (*coarse)(Handle&, size_t)) {
@@ -728,7 +758,7 @@ static void vcycle_general(Handle& h, size_t l, void (*coarse)(Handle&, size_t))
   k_spmv(h, l, SPMV_RES, B.x->p, B.r->p, B.b->p, (const T*)nullptr, (T*)nullptr);
   contact<T>(h, L, CT_SUB_RES, B.x->p, B.r->p, (const T*)nullptr);
   transfer(h, SPMV_Y, L.PT, B.r->p, NB.b->p);
-  coarse(h, l + 1);
+  coarse_visits<T>(h, l, coarse);
   transfer(h, SPMV_ADD, L.P, NB.x->p, B.x->p);
   for (int s = 0; s < h.opt.sweeps; ++s) smooth_once<T>(h, l, false);
 }
@@ -754,7 +784,7 @@ static void vcycle64_from(Handle& h, size_t l, bool x0_ready) {
   prof_end(h);
   level_contact<double>(h, L, CT_SUB_RES, L.vx.p, L.vr.p, nullptr);
   bsr_spmv<double>(c, SPMV_Y, L.PT, L.PT.val.p, L.vr.p, N.vb.p, nullptr, nullptr, nullptr);
-  vcycle64(h, l + 1);
+  coarse_visits<double>(h, l, vcycle64);
   bsr_spmv<double>(c, SPMV_ADD, L.P, L.P.val.p, N.vx.p, L.vx.p, nullptr, nullptr, nullptr);
   if (l == 0) prof_begin(h, AMGF_K_POSTSMOOTH);
   bsr_spmv<double>(c, SPMV_POST, S, S.val.p, L.vx.p, nullptr, L.vb.p, L.w.p, L.vxn.p);
@@ -789,7 +819,7 @@ static void vcycle32_from(Handle& h, size_t l, bool x0_ready) {
   prof_end(h);
   level_contact<float>(h, L, CT_SUB_RES, L.fx.p, L.fr.p, nullptr);
   transfer_spmv(c, SPMV_Y, L.PT, L.fr.p, N.fb.p);
-  vcycle32(h, l + 1);
+  coarse_visits<float>(h, l, vcycle32);
   transfer_spmv(c, SPMV_ADD, L.P, N.fx.p, L.fx.p);
   if (l == 0) prof_begin(h, AMGF_K_POSTSMOOTH);
   if (l == 0 && h.bf16k())
@@ -1109,6 +1139,7 @@ static double loss_grad(Handle& h, const float* W, int k, int np, const double* 
   Ctx& c = h.ctx;
   const int64_t n = h.n();
   AMGF_REQUIRE(!h.mixed(), AMGF_EINVAL, "training runs on an FP64 handle");
+  AMGF_REQUIRE(h.opt.cycle_gamma == 1, AMGF_EINVAL, "training follows the V-cycle");
   AMGF_REQUIRE(h.lev.size() > 1, AMGF_EINVAL, "no smoothed level");
   set_damping(h, W);
   for (auto& Lp : h.lev) {
@@ -1530,6 +1561,7 @@ void amgf_default_options(amgf_options* o) {
   o->near_null = 6;
   o->learned_judge = 1;
   o->transfer_fp16 = 1;
+  o->cycle_gamma = 1;
 }
 
 const char* amgf_status_string(amgf_status s) {
@@ -1578,6 +1610,8 @@ amgf_status amgf_setup(const amgf_options* opts, int32_t n_nodes, const int32_t*
                      h.opt.smoother == AMGF_LEARNED,
                  AMGF_EINVAL, "smoother");
     AMGF_REQUIRE(h.opt.sweeps >= 1 && h.opt.sweeps <= 16, AMGF_EINVAL, "sweeps must be 1..16");
+    AMGF_REQUIRE(h.opt.cycle_gamma >= 1 && h.opt.cycle_gamma <= 4, AMGF_EINVAL,
+                 "cycle_gamma must be 1..4");
     AMGF_REQUIRE(h.opt.cheb_degree >= 1 && h.opt.cheb_degree <= 16, AMGF_EINVAL,
                  "cheb_degree must be 1..16");
     AMGF_REQUIRE(h.opt.smoother != AMGF_LEARNED || h.opt.mlp_weights, AMGF_EINVAL,

@@ -70,6 +70,7 @@ void cast_f2d(Ctx& c, const float* a, double* b, int64_t n);
 // b = float(a), x = w.b (FP32 product of the rounded b)
 void cast_d2f_w(Ctx& c, const double* a, const float* w, float* b, float* x, int64_t n);
 void wmul_f32(Ctx& c, int64_t n, const float* w, const float* b, float* x);   // x = w.b
+void add_to_f32(Ctx& c, int64_t n, const float* a, float* y);                    // y += a
 void copy_w(Ctx& c, const double* a, const double* w, double* b, double* x, int64_t n);  // b = a, x = w.a
 void wmul_f64(Ctx& c, int64_t n, const double* w, const double* b, double* x);  // x = w.b
 void vcopy(Ctx& c, const double* a, double* b, int64_t n);

@@ -548,6 +548,8 @@ AMGF_ELEMWISE(k_d2f_w, (const double* __restrict__ a, const float* __restrict__ 
               const float bi = float(a[i]);
               b[i] = bi;
               x[i] = w[i] * bi)
+AMGF_ELEMWISE(k_add_to_f, (const float* __restrict__ a, float* __restrict__ y, int64_t n),
+              y[i] += a[i])
 AMGF_ELEMWISE(k_wmul_f, (const float* __restrict__ w, const float* __restrict__ b,
                          float* __restrict__ x, int64_t n),
               x[i] = w[i] * b[i])
@@ -706,6 +708,9 @@ void cast_d2f(Ctx& c, const double* a, float* b, int64_t n) {
 }
 void cast_d2f_w(Ctx& c, const double* a, const float* w, float* b, float* x, int64_t n) {
   if (n) hipLaunchKernelGGL(k_d2f_w, AMGF_L1D(n), a, w, b, x, n);
+}
+void add_to_f32(Ctx& c, int64_t n, const float* a, float* y) {
+  if (n) hipLaunchKernelGGL(k_add_to_f, AMGF_L1D(n), a, y, n);
 }
 void wmul_f32(Ctx& c, int64_t n, const float* w, const float* b, float* x) {
   if (n) hipLaunchKernelGGL(k_wmul_f, AMGF_L1D(n), w, b, x, n);

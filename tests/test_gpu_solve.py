@@ -218,3 +218,42 @@ def test_phase_breakdown_sums_to_solve_time(precision):
     assert info.converged and all(t > 0 for t in parts)
     assert abs(sum(parts) - info.ms_solve) <= 0.02 * info.ms_solve
     h.close()
+
+
+@pytest.mark.parametrize("case,precision", [("C2", 0), ("C2", 1), ("N16", 0), ("N16", 1)])
+def test_w_cycle_matches_oracle(case, precision):
+    """cycle_gamma = 2 (the W-cycle; not in the paper): C2 (three levels: level 1 visited
+    twice) and N = 16 coarsened to 4 nodes (four levels, an assembled contact level
+    visited four times).  V-cycle operator, M r and PCG against the oracle's W-cycle."""
+    from amgf_inputs import make_two_block
+    from oracle import OracleAMGF, OracleOptions
+    from paper_2505_18576_amd import AMGF
+    if case == "C2":
+        p, kw = problem("C2"), {}
+    else:
+        p, kw = make_two_block(16, D_log10=(0.0, 8.0), D_seed=9, rhs_seed=10), \
+            {"coarse_max_nodes": 4}
+    o = OracleAMGF(p.n_nodes, p.K_rowptr, p.K_col, p.K_val, p.J_rowptr, p.J_col, p.J_val,
+                   p.D, p.coords, OracleOptions(cycle_gamma=2, **kw))
+    print(f"[gpu setup] {case} cycle_gamma=2 precision {precision}", flush=True)
+    h = AMGF.from_problem(p, cycle_gamma=2, precision=precision, **kw)
+    assert h.n_levels == o.nlev
+    rng = np.random.default_rng(15)
+    r = rng.standard_normal(o.n)
+    e_b = rel(h.vcycle(r).cpu().numpy(), o.vcycle(r))
+    e_m = rel(h.apply(r).cpu().numpy(), o.apply(r))
+    ref = o.pcg(p.b, rtol=1e-13)
+    its10 = next(k for k, v in enumerate(ref.history) if v <= 1e-10)
+    x, info = h.pcg(p.b)
+    err = rel(x.cpu().numpy(), ref.x)
+    print(f"{case} W precision {precision}: levels {o.nlev}, vcycle rel {e_b:.2e}, apply rel "
+          f"{e_m:.2e}, {info.iterations} it (oracle {its10}), solution rel err {err:.2e}")
+    u = np.finfo(np.float64).eps / 2
+    assert e_b <= (1e-10 if precision == 0 else MIXED_TOL)
+    assert e_m <= max(MIXED_TOL if precision else 0.0, 10 * u * float(p.D.max()))
+    assert info.converged and err <= 1e-8
+    if precision == 0:
+        assert abs(info.iterations - its10) <= 1
+    else:
+        assert info.iterations <= its10 + 5
+    h.close()

@@ -181,9 +181,12 @@ static double power_estimate(Handle& h, Level& L, const unsigned char* dec) {
   double nrm;
   dots(c, n, 1, xs, xs, &nrm);
   vscale(c, n, 1.0 / std::sqrt(nrm), x.p);
-  double lam = 1.0;
+  // the norms stay on the device between steps (x = y / |y| there); the host reads the
+  // last one.  A zero y makes every later step 0/0, so the last norm tells.
+  DBuf<double> s(1);
   const bool fine = &L == h.lev[0].get();
-  for (int it = 0; it < h.opt.sa_power_iters; ++it) {
+  const int iters = h.opt.sa_power_iters;
+  for (int it = 0; it < iters; ++it) {
     if (fine) {
       // level 0: sliced stiffness plus the contact term through J (same operator as A)
       bsr_spmv<double>(c, SPMV_Y, L.K, L.K.val.p, x.p, y.p, nullptr, nullptr, nullptr);
@@ -194,13 +197,12 @@ static double power_estimate(Handle& h, Level& L, const unsigned char* dec) {
     }
     scale_div_zero(c, n, y.p, L.d.p, dec);
     const double* ys[1] = {y.p};
-    dots(c, n, 1, ys, ys, &nrm);
-    lam = std::sqrt(nrm);
-    if (!(lam > 0.0)) return 1.0;
-    vcopy(c, y.p, x.p, n);
-    vscale(c, n, 1.0 / lam, x.p);
+    dots_device(c, n, 1, ys, ys, s.p);
+    if (it + 1 < iters) normalize_dev(c, n, s.p, y.p, x.p);
   }
-  return lam;
+  if (iters < 1) return 1.0;
+  const double lam = std::sqrt(d2h_scalar(s.p, c.s));
+  return lam > 0.0 ? lam : 1.0;
 }
 
 // FP16 values of a transfer operator (FP32 when a value would overflow FP16)

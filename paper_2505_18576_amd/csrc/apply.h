@@ -101,6 +101,9 @@ void dots(Ctx& c, int64_t n, int nd, const double* const* xs, const double* cons
 void dots_device(Ctx& c, int64_t n, int nd, const double* const* xs, const double* const* ys,
                  double* out_dev, double* part = nullptr);
 
+// x = y / sqrt(s[0]) with s in device memory
+void normalize_dev(Ctx& c, int64_t n, const double* s, const double* y, double* x);
+
 // PCG updates
 void pcg_update_xr(Ctx& c, int64_t n, double alpha, const double* p, const double* q, double* x,
                    double* r);

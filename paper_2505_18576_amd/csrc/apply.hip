@@ -733,6 +733,13 @@ void axpby(Ctx& c, int64_t n, double alpha, const double* x, double beta, double
 void add_f32(Ctx& c, int64_t n, const double* a, const float* f, double* z) {
   if (n) hipLaunchKernelGGL(k_add_f, AMGF_L1D(n), n, a, f, z);
 }
+// x = y * (1 / sqrt(s[0])), the norm read from device memory (power iteration step)
+AMGF_ELEMWISE(k_normalize_dev, (int64_t n, const double* __restrict__ s,
+                                const double* __restrict__ y, double* __restrict__ x),
+              x[i] = y[i] * (1.0 / sqrt(s[0])))
+void normalize_dev(Ctx& c, int64_t n, const double* s, const double* y, double* x) {
+  if (n) hipLaunchKernelGGL(k_normalize_dev, AMGF_L1D(n), n, s, y, x);
+}
 void vscale(Ctx& c, int64_t n, double s, double* x) {
   if (n) hipLaunchKernelGGL(k_scale, AMGF_L1D(n), n, s, x);
 }

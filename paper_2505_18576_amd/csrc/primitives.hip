@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(256) k_union(int nrows, int ts, int cap,
   int* cnt = &cnts[wv];
   if (r >= nrows) return;
   if ((row_mask && !row_mask[r]) || rp1[r] == rp1[r + 1]) {
-    if (!fill && lane == 0) counts[r] = 0;
+    if (fill != 1 && lane == 0) counts[r] = 0;
     return;
   }
   const unsigned mask = unsigned(ts) - 1;
@@ -415,6 +415,7 @@ __global__ void __launch_bounds__(256) k_union(int nrows, int ts, int cap,
     if (lane == 0) counts[r] = n;
     return;
   }
+  if (fill == 2 && lane == 0) counts[r] = n;     // sorted list at rowptr[r] = bound offset
   const int base = rowptr[r];
   for (int j = lane; j < n; j += 64) {
     const int v = list[j];
@@ -423,6 +424,42 @@ __global__ void __launch_bounds__(256) k_union(int nrows, int ts, int cap,
     outcol[base + rank] = v;
   }
 }
+
+// rows' sorted lists from their bound-sized slots (tmp at boff) to the compact pattern
+__global__ void __launch_bounds__(256) k_union_compact(int nrows, const int* __restrict__ boff,
+                                                       const int* __restrict__ tmp,
+                                                       const int* __restrict__ rowptr,
+                                                       int* __restrict__ col) {
+  const int r = int((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 5);
+  const int l = threadIdx.x & 31;
+  if (r >= nrows) return;
+  const int n = rowptr[r + 1] - rowptr[r];
+  for (int j = l; j < n; j += 32) col[rowptr[r] + j] = tmp[boff[r] + j];
+}
+
+__global__ void k_sum_i64(const int* __restrict__ v, int n, unsigned long long* __restrict__ s) {
+  unsigned long long a = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    a += unsigned(v[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(s, a);
+}
+
+// sum of a non-negative int array in 64 bits; waits for the result
+static int64_t sum_i64(Ctx& c, const int* v, int n) {
+  DBuf<unsigned long long> t(1);
+  AMGF_HIP(hipMemsetAsync(t.p, 0, sizeof(unsigned long long), c.s));
+  if (n > 0)
+    hipLaunchKernelGGL(k_sum_i64, dim3(std::min<unsigned>(grid_for(n, 256), 1024)), dim3(256), 0,
+                       c.s, v, n, t.p);
+  AMGF_LAUNCH_CHECK();
+  return int64_t(d2h_scalar(t.p, c.s));
+}
+
+// above this many candidate slots in all, the lists are hashed twice (count, then fill)
+// instead of once into bound-sized slots
+constexpr int64_t UNION_ONE_PASS_MAX = int64_t(1) << 30;
 
 void union_symbolic(Ctx& c, int nrows, int ncols, const int* rp1, const int* col1,
                     const int* rp2, const int* col2, const int* map, bool exclude_diag,
@@ -448,6 +485,26 @@ void union_symbolic(Ctx& c, int nrows, int ncols, const int* rp1, const int* col
   const int wpg = ts <= 512 ? 4 : 1;                    // rows (wavefronts) per workgroup
   const size_t lds = size_t(wpg) * (ts + cap) * sizeof(int);
   const dim3 g((nrows + wpg - 1) / wpg), b(64 * wpg);
+  // one hashing pass: each row's sorted list goes to a slot of its bound's size, then the
+  // lists are packed; candidate bounds at most `cap` each keep the slots within the bound
+  const int64_t total_bound = sum_i64(c, counts.p, nrows);
+  if (total_bound <= UNION_ONE_PASS_MAX) {
+    DBuf<int> boff(size_t(nrows) + 1);
+    scan_exclusive(c, counts.p, boff.p, nrows, false);
+    DBuf<int> tmp(std::max<int64_t>(total_bound, 1));
+    hipLaunchKernelGGL(k_union, g, b, lds, c.s, nrows, ts, cap, rp1, col1, rp2, col2, map,
+                       int(exclude_diag), row_mask, 2, counts.p, boff.p, tmp.p, c.flag.p);
+    AMGF_LAUNCH_CHECK();
+    int fl = d2h_scalar(c.flag.p, c.s);
+    AMGF_REQUIRE(fl == 0, AMGF_ENOMEM, "symbolic product row exceeds the union capacity");
+    C.nnzb = scan_exclusive(c, counts.p, C.rowptr.p, nrows);
+    C.col.alloc(std::max<int64_t>(C.nnzb, 1));
+    if (C.nnzb)
+      hipLaunchKernelGGL(k_union_compact, dim3(grid_for(int64_t(nrows) * 32, 256)), dim3(256), 0,
+                         c.s, nrows, boff.p, tmp.p, C.rowptr.p, C.col.p);
+    AMGF_LAUNCH_CHECK();
+    return;
+  }
   hipLaunchKernelGGL(k_union, g, b, lds, c.s, nrows, ts, cap, rp1, col1, rp2, col2, map,
                      int(exclude_diag), row_mask, 0, counts.p, nullptr, nullptr, c.flag.p);
   AMGF_LAUNCH_CHECK();

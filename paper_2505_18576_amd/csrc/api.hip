@@ -732,9 +732,12 @@ static void smooth_once(Handle& h, size_t l, bool x_zero) {
 // The coarse correction of level l on level l+1 (input *NB.b, result *NB.x): cycle_gamma
 // visits, each later one on the residual the earlier ones left, their corrections summed
 // (gamma = 2: x = 2 B b - B A B b, the W-cycle).  The coarsest solve is exact: one visit.
+// coarse_first makes the first visit (a plain cycle whose first iterate w.b the
+// restriction already formed).
 template <class T>
-static void coarse_visits(Handle& h, size_t l, void (*coarse)(Handle&, size_t)) {
-  coarse(h, l + 1);
+static void coarse_visits(Handle& h, size_t l, void (*coarse)(Handle&, size_t),
+                          void (*coarse_first)(Handle&, size_t)) {
+  coarse_first(h, l + 1);
   if (h.opt.cycle_gamma <= 1 || l + 2 >= h.lev.size()) return;
   Level& N = *h.lev[l + 1];
   LvBufs<T> NB = lv_bufs(N, T());
@@ -760,7 +763,7 @@ static void vcycle_general(Handle& h, size_t l, void (*coarse)(Handle&, size_t))
   k_spmv(h, l, SPMV_RES, B.x->p, B.r->p, B.b->p, (const T*)nullptr, (T*)nullptr);
   contact<T>(h, L, CT_SUB_RES, B.x->p, B.r->p, (const T*)nullptr);
   transfer(h, SPMV_Y, L.PT, B.r->p, NB.b->p);
-  coarse_visits<T>(h, l, coarse);
+  coarse_visits<T>(h, l, coarse, coarse);
   transfer(h, SPMV_ADD, L.P, NB.x->p, B.x->p);
   for (int s = 0; s < h.opt.sweeps; ++s) smooth_once<T>(h, l, false);
 }
@@ -770,6 +773,7 @@ static void vcycle_general(Handle& h, size_t l, void (*coarse)(Handle&, size_t))
 // r = b - K x then gathers x once per column instead of w and b.
 static void vcycle64_from(Handle& h, size_t l, bool x0_ready);
 static void vcycle64(Handle& h, size_t l) { vcycle64_from(h, l, false); }
+static void vcycle64_ready(Handle& h, size_t l) { vcycle64_from(h, l, true); }
 static void vcycle64_from(Handle& h, size_t l, bool x0_ready) {
   Ctx& c = h.ctx;
   Level& L = *h.lev[l];
@@ -785,8 +789,11 @@ static void vcycle64_from(Handle& h, size_t l, bool x0_ready) {
   bsr_spmv<double>(c, SPMV_RES, S, S.val.p, L.vx.p, L.vr.p, L.vb.p, nullptr, nullptr);
   prof_end(h);
   level_contact<double>(h, L, CT_SUB_RES, L.vx.p, L.vr.p, nullptr);
-  bsr_spmv<double>(c, SPMV_Y, L.PT, L.PT.val.p, L.vr.p, N.vb.p, nullptr, nullptr, nullptr);
-  coarse_visits<double>(h, l, vcycle64);
+  // restriction; on a smoothed level it also forms that cycle's first iterate w.b
+  const bool n_smoothed = l + 2 < h.lev.size();
+  bsr_spmv<double>(c, n_smoothed ? SPMV_YW : SPMV_Y, L.PT, L.PT.val.p, L.vr.p, N.vb.p, nullptr,
+                   n_smoothed ? N.w.p : nullptr, n_smoothed ? N.vx.p : nullptr);
+  coarse_visits<double>(h, l, vcycle64, vcycle64_ready);
   bsr_spmv<double>(c, SPMV_ADD, L.P, L.P.val.p, N.vx.p, L.vx.p, nullptr, nullptr, nullptr);
   if (l == 0) prof_begin(h, AMGF_K_POSTSMOOTH);
   bsr_spmv<double>(c, SPMV_POST, S, S.val.p, L.vx.p, nullptr, L.vb.p, L.w.p, L.vxn.p);
@@ -800,6 +807,7 @@ static void vcycle64_from(Handle& h, size_t l, bool x0_ready) {
 // to L.fx), then r = b - K x reads x once per column instead of w and b.
 static void vcycle32_from(Handle& h, size_t l, bool x0_ready);
 static void vcycle32(Handle& h, size_t l) { vcycle32_from(h, l, false); }
+static void vcycle32_ready(Handle& h, size_t l) { vcycle32_from(h, l, true); }
 static void vcycle32_from(Handle& h, size_t l, bool x0_ready) {
   Ctx& c = h.ctx;
   Level& L = *h.lev[l];
@@ -820,8 +828,14 @@ static void vcycle32_from(Handle& h, size_t l, bool x0_ready) {
                     nullptr, nullptr);
   prof_end(h);
   level_contact<float>(h, L, CT_SUB_RES, L.fx.p, L.fr.p, nullptr);
-  transfer_spmv(c, SPMV_Y, L.PT, L.fr.p, N.fb.p);
-  coarse_visits<float>(h, l, vcycle32);
+  // restriction; on a smoothed level it also forms that cycle's first iterate w.b
+  if (l + 2 < h.lev.size()) {
+    transfer_spmv(c, SPMV_YW, L.PT, L.fr.p, N.fb.p, N.w32.p, N.fx.p);
+    coarse_visits<float>(h, l, vcycle32, vcycle32_ready);
+  } else {
+    transfer_spmv(c, SPMV_Y, L.PT, L.fr.p, N.fb.p);
+    coarse_visits<float>(h, l, vcycle32, vcycle32);
+  }
   transfer_spmv(c, SPMV_ADD, L.P, N.fx.p, L.fx.p);
   if (l == 0) prof_begin(h, AMGF_K_POSTSMOOTH);
   if (l == 0 && h.bf16k())

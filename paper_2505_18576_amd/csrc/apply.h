@@ -10,7 +10,9 @@ enum SpmvMode {
   SPMV_ADD = 1,   // y += A x
   SPMV_PRE = 2,   // xo = w.b ; y = b - A (w.b)          (first smoothing step from 0)
   SPMV_POST = 3,  // xo = x + w.(b - A x)                (Jacobi step, new buffer)
-  SPMV_RES = 4    // y = b - A x
+  SPMV_RES = 4,   // y = b - A x
+  SPMV_YW = 5     // y = A x ; xo = w.y  (restriction into a level whose cycle starts at w.b;
+                  // BSR kernels only)
 };
 
 // y/xo per mode; val is T-typed (double or float) and the vectors are T too.
@@ -18,10 +20,11 @@ template <class T>
 void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, const T* b,
               const T* w, T* xo);
 
-// y = A x (SPMV_Y) or y += A x (SPMV_ADD) in FP32 with the FP16 values A.valh, or with the
-// FP32 values A.val32 when A has no FP16 copy (restriction and prolongation of the mixed
-// V-cycle)
-void transfer_spmv(Ctx& c, int mode, const BSR& A, const float* x, float* y);
+// y = A x (SPMV_Y), y += A x (SPMV_ADD) or y = A x with xo = w.y (SPMV_YW) in FP32 with the
+// FP16 values A.valh, or with the FP32 values A.val32 when A has no FP16 copy (restriction
+// and prolongation of the mixed V-cycle)
+void transfer_spmv(Ctx& c, int mode, const BSR& A, const float* x, float* y,
+                   const float* w = nullptr, float* xo = nullptr);
 // b = FP16(a), one rounding to nearest even; *flag |= 1 when a value overflows FP16
 void cast_d2h(Ctx& c, const double* a, _Float16* b, int64_t n, int* flag);
 

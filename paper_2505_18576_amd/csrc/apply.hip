@@ -69,7 +69,10 @@ __global__ void __launch_bounds__(256) k_bsr(int nrows, const int* __restrict__ 
     if (l == p) ax = acc[p];
   const int64_t i = int64_t(r) * BR + l;
   if (MODE == SPMV_Y) y[i] = ax;
-  else if (MODE == SPMV_ADD) y[i] += ax;
+  else if (MODE == SPMV_YW) {
+    y[i] = ax;
+    xo[i] = w[i] * ax;
+  } else if (MODE == SPMV_ADD) y[i] += ax;
   else if (MODE == SPMV_PRE) {
     const T xi = w[i] * b[i];
     xo[i] = xi;
@@ -142,6 +145,7 @@ static void launch_bsr(Ctx& c, int mode, const BSR& A, const T* val, const T* x,
     AMGF_MODE(SPMV_PRE)
     AMGF_MODE(SPMV_POST)
     AMGF_MODE(SPMV_RES)
+    AMGF_MODE(SPMV_YW)
 #undef AMGF_MODE
     default:
       throw Error(AMGF_EINVAL, "spmv mode");
@@ -149,14 +153,19 @@ static void launch_bsr(Ctx& c, int mode, const BSR& A, const T* val, const T* x,
   AMGF_LAUNCH_CHECK();
 }
 
-// y = A x or y += A x with FP16 values (the mixed V-cycle's restriction and prolongation)
+// y = A x, y += A x or y = A x with xo = w.y, FP16 values (the mixed V-cycle's restriction
+// and prolongation)
 template <int BR, int BC, int G>
-static void launch_bsr_h(Ctx& c, int mode, const BSR& A, const float* x, float* y) {
+static void launch_bsr_h(Ctx& c, int mode, const BSR& A, const float* x, float* y,
+                         const float* w, float* xo) {
   const int64_t threads = int64_t(A.nrows) * G;
   const dim3 g(grid_for(threads, 256)), blk(256);
   if (mode == SPMV_Y)
     hipLaunchKernelGGL((k_bsr<BR, BC, G, float, SPMV_Y, _Float16>), g, blk, 0, c.s, A.nrows,
                        A.rowptr.p, A.col.p, A.valh.p, x, y, nullptr, nullptr, nullptr);
+  else if (mode == SPMV_YW)
+    hipLaunchKernelGGL((k_bsr<BR, BC, G, float, SPMV_YW, _Float16>), g, blk, 0, c.s, A.nrows,
+                       A.rowptr.p, A.col.p, A.valh.p, x, y, nullptr, w, xo);
   else if (mode == SPMV_ADD)
     hipLaunchKernelGGL((k_bsr<BR, BC, G, float, SPMV_ADD, _Float16>), g, blk, 0, c.s, A.nrows,
                        A.rowptr.p, A.col.p, A.valh.p, x, y, nullptr, nullptr, nullptr);
@@ -165,16 +174,17 @@ static void launch_bsr_h(Ctx& c, int mode, const BSR& A, const float* x, float* 
   AMGF_LAUNCH_CHECK();
 }
 
-void transfer_spmv(Ctx& c, int mode, const BSR& A, const float* x, float* y) {
+void transfer_spmv(Ctx& c, int mode, const BSR& A, const float* x, float* y, const float* w,
+                   float* xo) {
   if (A.nrows == 0) return;
-  if (!A.valh.p) return bsr_spmv<float>(c, mode, A, A.val32.p, x, y, nullptr, nullptr, nullptr);
+  if (!A.valh.p) return bsr_spmv<float>(c, mode, A, A.val32.p, x, y, nullptr, w, xo);
   const double avg = double(A.nnzb) / A.nrows;
-  if (A.br == 3 && A.bc == 3) return launch_bsr_h<3, 3, 8>(c, mode, A, x, y);
-  if (A.br == 3 && A.bc == 6) return launch_bsr_h<3, 6, 8>(c, mode, A, x, y);
-  if (A.br == 6 && A.bc == 3) return launch_bsr_h<6, 3, 64>(c, mode, A, x, y);
+  if (A.br == 3 && A.bc == 3) return launch_bsr_h<3, 3, 8>(c, mode, A, x, y, w, xo);
+  if (A.br == 3 && A.bc == 6) return launch_bsr_h<3, 6, 8>(c, mode, A, x, y, w, xo);
+  if (A.br == 6 && A.bc == 3) return launch_bsr_h<6, 3, 64>(c, mode, A, x, y, w, xo);
   if (A.br == 6 && A.bc == 6) {
-    if (avg > 24) return launch_bsr_h<6, 6, 64>(c, mode, A, x, y);
-    return launch_bsr_h<6, 6, 16>(c, mode, A, x, y);
+    if (avg > 24) return launch_bsr_h<6, 6, 64>(c, mode, A, x, y, w, xo);
+    return launch_bsr_h<6, 6, 16>(c, mode, A, x, y, w, xo);
   }
   throw Error(AMGF_EINVAL, "FP16 spmv block size");
 }
@@ -207,7 +217,8 @@ void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, co
               const T* w, T* xo) {
   if (A.nrows == 0) return;
   const double avg = A.nrows ? double(A.nnzb) / A.nrows : 0.0;
-  if (A.br == 3 && A.bc == 3 && A.sell_col.p) {
+  const bool plain_modes = mode != SPMV_YW;           // the copies below serve modes 0..4
+  if (plain_modes && A.br == 3 && A.bc == 3 && A.sell_col.p) {
     // the sliced copy stands in for the BSR values of the same precision
     const T* sv = nullptr;
     if constexpr (sizeof(T) == 8) {
@@ -217,7 +228,7 @@ void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, co
     }
     if (sv) return sell3_spmv<T>(c, mode, A, sv, x, y, b, w, xo);
   }
-  if (A.br == A.bc && (A.br == 6 || A.br == 3) && A.pk_off.p) {
+  if (plain_modes && A.br == A.bc && (A.br == 6 || A.br == 3) && A.pk_off.p) {
     // the packed copy stands in for the BSR values of the same precision
 #define AMGF_PK(TV, vp)                                                                      \
   return A.br == 6 ? launch_packed<6, TV, T>(c, mode, A, vp, x, y, b, w, xo)                \

@@ -73,6 +73,7 @@ struct Handle {
   int n_c = 0;
   DBuf<int> Ic;
   MFSolver aw;
+  DBuf<int> Ic_t;               // I_c in the factor's tree order: Ic_t[q] = Ic[aw.tdof[q]]
   DBuf<double> f_r, f_w;
   DBuf<int> aw_rp, aw_col;      // A_w = S[I_c, I_c] as scalar CSR (input of its factor)
   DBuf<double> aw_val;
@@ -260,6 +261,8 @@ static void factor_filter(Handle& h) {
   Level& L0 = *h.lev[0];
   filter_csr(h.ctx, L0.A, h.Ic.p, h.n_c, h.aw_rp, h.aw_col, h.aw_val);
   h.aw.setup(h.ctx, h.n_c, h.ic_closed ? 3 : 1, h.aw_rp.p, h.aw_col.p, h.aw_val.p);
+  if (h.Ic_t.n != size_t(h.n_c)) h.Ic_t.alloc(size_t(h.n_c));
+  h.aw.tree_index(h.ctx, h.Ic.p, h.Ic_t.p);
 }
 
 // features of every smoothed level and, with learned damping, w = theta/d from the MLP
@@ -889,9 +892,10 @@ static void operator_apply(Handle& h, const double* x, double* y, const double* 
   }
 }
 
-// w = A_w^{-1} r with the multifrontal factor of the filter matrix
+// w = A_w^{-1} r with the multifrontal factor of the filter matrix, r and w in the
+// factor's tree order (entry q belongs to DOF Ic_t[q])
 static void filter_solve(Handle& h, const double* r, double* w) {
-  h.aw.solve(h.ctx, r, w);
+  h.aw.solve_tree(h.ctx, r, w);
 }
 
 // z = M r, Definition 5.3:  z1 = B r;  z2 = z1 + P A_w^{-1} P^T (r - A z1);
@@ -920,9 +924,9 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
       bsr_res_rows<float>(c, L0.K, h.ic_nodes.p, h.n_icn, L0.fx.p, r, h.ra.p);
       contact_apply<float, double>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
                                    L0.fx.p, h.t.p, h.ra.p, nullptr);   // ra = r - A z1 on I_c
-      gather(c, h.ra.p, h.Ic.p, h.n_c, h.f_r.p);      // P^T ra
+      gather(c, h.ra.p, h.Ic_t.p, h.n_c, h.f_r.p);      // P^T ra
       filter_solve(h, h.f_r.p, h.f_w.p);              // w = A_w^{-1} P^T ra
-      correct_at(c, L0.fx.p, h.f_w.p, h.Ic.p, h.n_c, h.z1.p);   // z2 on I_c; L0.fx = float(z2)
+      correct_at(c, L0.fx.p, h.f_w.p, h.Ic_t.p, h.n_c, h.z1.p);   // z2 on I_c; L0.fx = float(z2)
     }
     phase(h, PH_OTHER);
     bsr_spmv<float>(c, SPMV_RES, L0.K, L0.K.val32.p, L0.fx.p, h.r2f.p, L0.fb.p, nullptr,
@@ -945,9 +949,9 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
     bsr_res_rows(c, L0.K, h.ic_nodes.p, h.n_icn, h.z1.p, r, h.ra.p);
     contact_apply<double, double>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
                                   h.z1.p, h.t.p, h.ra.p, nullptr);     // ra = r - A z1 on I_c
-    gather(c, h.ra.p, h.Ic.p, h.n_c, h.f_r.p);        // P^T ra
+    gather(c, h.ra.p, h.Ic_t.p, h.n_c, h.f_r.p);        // P^T ra
     filter_solve(h, h.f_r.p, h.f_w.p);                // w = A_w^{-1} P^T ra
-    scatter_add(c, h.f_w.p, h.Ic.p, h.n_c, h.z1.p);   // z2 = z1 + P w
+    scatter_add(c, h.f_w.p, h.Ic_t.p, h.n_c, h.z1.p);   // z2 = z1 + P w
   }
   phase(h, PH_OTHER);
   if (h.mixed()) {
@@ -1115,9 +1119,9 @@ static void apply_tape(Handle& h, const double* v, double* z, Tape& T1, Tape& T2
     bsr_res_rows(c, L0.K, h.ic_nodes.p, h.n_icn, h.z1.p, v, h.ra.p);
     contact_apply<double, double>(c, CT_SUB_RES, L0.J, L0.JT, L0.crows.p, L0.ncrows, h.D.p,
                                   h.z1.p, h.t.p, h.ra.p, nullptr);
-    gather(c, h.ra.p, h.Ic.p, h.n_c, h.f_r.p);
+    gather(c, h.ra.p, h.Ic_t.p, h.n_c, h.f_r.p);
     filter_solve(h, h.f_r.p, h.f_w.p);
-    scatter_add(c, h.f_w.p, h.Ic.p, h.n_c, h.z1.p);
+    scatter_add(c, h.f_w.p, h.Ic_t.p, h.n_c, h.z1.p);
   }
   operator_apply(h, h.z1.p, L0.vb.p, v);                  // r2 = v - A z2
   vcycle64_tape(h, 0, T2);
@@ -1136,10 +1140,10 @@ static void apply_adj(Handle& h, const double* zbar, double* vbar, const Tape& T
   vcopy(c, L0.ab.p, vbar, n);                             // vbar = r2bar
   operator_apply(h, L0.ab.p, h.z3.p, zbar);               // z2bar = zbar - A r2bar
   if (h.n_c > 0) {
-    gather(c, h.z3.p, h.Ic.p, h.n_c, h.f_r.p);
+    gather(c, h.z3.p, h.Ic_t.p, h.n_c, h.f_r.p);
     filter_solve(h, h.f_r.p, h.f_w.p);                    // rabar = A_w^{-1} P^T z2bar
     AMGF_HIP(hipMemsetAsync(h.r2.p, 0, sizeof(double) * n, c.s));
-    scatter_add(c, h.f_w.p, h.Ic.p, h.n_c, h.r2.p);       // u = P rabar
+    scatter_add(c, h.f_w.p, h.Ic_t.p, h.n_c, h.r2.p);       // u = P rabar
     axpby(c, n, 1.0, h.r2.p, 1.0, vbar);                  // vbar += u
     operator_apply(h, h.r2.p, L0.ay.p, h.z3.p);           // z1bar = z2bar - A u
   } else {
@@ -1753,7 +1757,7 @@ amgf_status amgf_filter_solve(amgf_handle hd, const double* rc, double* wc, void
     AMGF_REQUIRE(h.opt.filter && h.n_c > 0, AMGF_EINVAL, "handle has no filtering space");
     h.bind(stream);
     amgf::AllocScope scope_(&h.mem);
-    amgf::filter_solve(h, rc, wc);
+    h.aw.solve(h.ctx, rc, wc);   // the caller's (filtering-space) order
     return AMGF_OK;
   });
 }

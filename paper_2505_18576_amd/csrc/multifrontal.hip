@@ -18,7 +18,10 @@
 // Each front then keeps X = L11^{-1} and G = L21 X, so the solve is matrix-vector
 // products only: forward by depth (deepest first) y = X f_s, u = f_b - G f_s, the update
 // vector u going to the parent; backward by depth (root first) x_s = X^T y - G^T x_b.
-// Every sum has a fixed order, so results are reproducible.
+// The solve works in tree order (the members of each supernode together), so a front's
+// right-hand side and solution are contiguous; each child writes its update vector into a
+// slot array of its parent at the parent's front positions.  Every sum has a fixed order,
+// so results are reproducible.
 #include "multifrontal.h"
 
 #include <algorithm>
@@ -678,72 +681,14 @@ __global__ void __launch_bounds__(256) k_mf_transpose(int tb, const int* __restr
 }
 
 // ---------------------------------------------------------------- solve
-__device__ __forceinline__ int64_t mf_sep_dof(int t, int i, int bs, const int* soff,
-                                              const int* sperm) {
-  return int64_t(sperm[soff[t] + i / bs]) * bs + i % bs;
-}
-__device__ __forceinline__ int64_t mf_bnd_dof(int t, int m, int bs, const int* bnd_off,
-                                              const int* bnd) {
-  return int64_t(bnd[bnd_off[t] + m / bs]) * bs + m % bs;
-}
-
-// front right-hand side f of front t: r on the separator, the children's update vectors
-// added in the order child 0, child 1 (one workgroup; f in global memory or in LDS)
-__device__ void mf_front_rhs(int t, int bs, const double* __restrict__ r,
-                             const int* __restrict__ soff, const int* __restrict__ sperm,
-                             const int* __restrict__ child0, const int* __restrict__ child1,
-                             const int* __restrict__ bnd_off, const int* __restrict__ bnd_pos,
-                             const int* __restrict__ fs, const int* __restrict__ fS,
-                             const int* __restrict__ fb, const int* __restrict__ fT,
-                             const int64_t* __restrict__ vo, const double* __restrict__ fv,
-                             double* f) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int s = fs[t];
-  const int Fp = fT[t] * 64;
-  for (int i = tid; i < Fp; i += nt) f[i] = i < s ? r[mf_sep_dof(t, i, bs, soff, sperm)] : 0.0;
-  for (int ci = 0; ci < 2; ++ci) {
-    const int c = ci ? child1[t] : child0[t];
-    if (c < 0) continue;
-    __syncthreads();
-    const int bc = fb[c];
-    const double* uc = fv + vo[c] + fS[c];
-    const int* pos = bnd_pos + bnd_off[c];
-    for (int i = tid; i < bc; i += nt) f[pos[i / bs] + i % bs] += uc[i];
-  }
-}
-
-// front right-hand sides fa of the fronts of one depth (fronts too large for the LDS copy
-// of the forward kernel)
-__global__ void __launch_bounds__(256) k_mf_rhs(int tb, int bs, const double* __restrict__ r,
-                                                const int* __restrict__ soff,
-                                                const int* __restrict__ sperm,
-                                                const int* __restrict__ child0,
-                                                const int* __restrict__ child1,
-                                                const int* __restrict__ bnd_off,
-                                                const int* __restrict__ bnd_pos,
-                                                const int* __restrict__ fs,
-                                                const int* __restrict__ fS,
-                                                const int* __restrict__ fb,
-                                                const int* __restrict__ fT,
-                                                const int64_t* __restrict__ vo,
-                                                double* __restrict__ fa,
-                                                const double* __restrict__ fv) {
-  const int t = tb + blockIdx.x;
-  mf_front_rhs(t, bs, r, soff, sperm, child0, child1, bnd_off, bnd_pos, fs, fS, fb, fT, vo, fv,
-               fa + vo[t]);
-}
-
 // Rows per wavefront in the solve kernels: each wave issues the loads of MF_R rows of the
 // factor back to back (row indices clamped, products masked) and shares the vector entries
 // among them; one row per wave left the mid depths of the tree waiting on memory latency.
 // MF_R divides 64.
 constexpr int MF_R = 4;
-constexpr int MF_XB = 2048;   // boundary values a backward workgroup stages in LDS
-constexpr int MF_FL = 8192;   // front right-hand side a forward workgroup assembles in LDS
-// The solve kernels run over per-depth work lists of (supernode, block of 4 MF_R rows)
-// pairs built at setup, so the grid holds exactly the workgroups the fronts of a depth
-// need (a grid sized by the depth's widest front was mostly idle workgroups).
-
+// The solve kernels run over per-depth work lists (one MFWork per workgroup) built at
+// setup, so the grid holds exactly the workgroups the fronts of a depth need.
+//
 // Column split of the solve kernels: KS = 1, each wavefront of a workgroup takes MF_R rows
 // of its own (4 * MF_R rows per workgroup); KS = 4, the four wavefronts share MF_R rows and
 // take every fourth 64-column stretch of them, the partial sums meeting in LDS (fixed
@@ -771,23 +716,35 @@ __device__ __forceinline__ double mf_split_sum(double mine) {
   }
 }
 
-// [y; u] = [X; -G] f_s + [0; f_b]: rows i0 .. i0+MF_R-1 of M, f the front's right-hand side
-// (KS = 1: one wavefront per row group; KS = 4: the workgroup's four wavefronts split the
-// columns).  With KS = 4 every wavefront of the workgroup reaches the LDS sum: i0, S and
-// rows are the same for all of them.
+// Forward rows i0 .. i0+MF_R-1 of M: [y; u] = [X; -G] f_s + [0; f_b].  The front's
+// right-hand side f is read where it is used: f = r (separator positions, tree order) +
+// slot 0 + slot 1 (the children's update vectors, already at the front's positions), the
+// same sum in the same order as assembling the front first.  y goes to fv; the update
+// vector u goes straight to its place in the parent's slot array.  With KS = 4 every
+// wavefront of the workgroup reaches the LDS sum: i0, S and rows are the same for all.
 template <int KS>
-__device__ void mf_fwd_rows(int t, int blk, const int* __restrict__ fS,
-                            const int* __restrict__ fb, const int64_t* __restrict__ mo,
-                            const int64_t* __restrict__ vo, const double* __restrict__ M,
-                            const double* f, double* __restrict__ fv) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int S = fS[t], rows = S + fb[t];
-  const int i0 = (KS == 1 ? blk * 4 + wv : blk) * MF_R;
+__global__ void __launch_bounds__(256) k_mf_fwd(const MFWork* __restrict__ wl, int bs, int tv,
+                                                const double* __restrict__ r,
+                                                const int* __restrict__ bnd_pos,
+                                                const double* __restrict__ M, double* us,
+                                                double* __restrict__ y) {
+  const MFWork w = wl[blockIdx.x];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int S = w.S, rows = w.S + w.b;
+  const int i0 = (KS == 1 ? w.blk * 4 + wv : w.blk) * MF_R;
   if (i0 >= rows) return;
-  double* out = fv + vo[t];
-  if (S == 0) {
-    if ((KS == 1 || wv == 0) && lane < MF_R && i0 + lane < rows) out[i0 + lane] = f[i0 + lane];
-    return;
+  const double* fr = r + w.roff;
+  const double* s0 = us + w.vo;
+  const double* s1 = us + int64_t(tv) + w.vo;
+  // the lane's own boundary row: its f_b entry and where its u entry goes
+  const int io = i0 + lane;
+  double fo = 0.0;
+  int64_t dst = 0;
+  if (lane < MF_R && io < rows && io >= S) {
+    if (w.nch) fo = s0[io] + s1[io];
+    const int m = io - S;
+    dst = int64_t(w.uoff) + bnd_pos[w.boff + m / bs] + m % bs;
   }
   const double* rowp[MF_R];
   int jend[MF_R];
@@ -797,14 +754,15 @@ __device__ void mf_fwd_rows(int t, int blk, const int* __restrict__ fS,
     const int i = i0 + q;
     jend[q] = i >= rows ? 0 : (i < S ? (i / 64 + 1) * 64 : S);
     jmax = max(jmax, jend[q]);
-    rowp[q] = M + mo[t] + int64_t(min(i, rows - 1)) * S;
+    rowp[q] = M + int64_t(w.mo) * 4096 + int64_t(min(i, rows - 1)) * S;
   }
   double acc[MF_R];
 #pragma unroll
   for (int q = 0; q < MF_R; ++q) acc[q] = 0.0;
 #pragma unroll 4
   for (int j = (KS == 1 ? 0 : wv * 64) + lane; j < jmax; j += 64 * KS) {
-    const double fj = f[j];
+    double fj = j < w.s ? fr[j] : 0.0;
+    if (w.nch) fj = fj + s0[j] + s1[j];
     double v[MF_R];
 #pragma unroll
     for (int q = 0; q < MF_R; ++q) v[q] = ld_stream(&rowp[q][j]);   // j < jmax <= S: inside the row
@@ -815,90 +773,39 @@ __device__ void mf_fwd_rows(int t, int blk, const int* __restrict__ fS,
   double mine = 0.0;
 #pragma unroll
   for (int q = 0; q < MF_R; ++q) {
-    const double r = wave_sum(acc[q]);
-    if (lane == q) mine = r;
+    const double t = wave_sum(acc[q]);
+    if (lane == q) mine = t;
   }
   mine = mf_split_sum<KS>(mine);
-  const int i = i0 + lane;
-  if ((KS == 1 || wv == 0) && lane < MF_R && i < rows) out[i] = i < S ? mine : f[i] - mine;
-}
-
-// forward rows with the right-hand side from fa (assembled by k_mf_rhs)
-template <int KS>
-__global__ void __launch_bounds__(256) k_mf_fwd(const int* __restrict__ wl,
-                                                const int* __restrict__ fS,
-                                                const int* __restrict__ fb,
-                                                const int64_t* __restrict__ mo,
-                                                const int64_t* __restrict__ vo,
-                                                const double* __restrict__ M,
-                                                const double* __restrict__ fa,
-                                                double* __restrict__ fv) {
-  const int t = wl[2 * blockIdx.x], blk = wl[2 * blockIdx.x + 1];
-  mf_fwd_rows<KS>(t, blk, fS, fb, mo, vo, M, fa + vo[t], fv);
-}
-
-// forward rows with the right-hand side assembled by the workgroup itself in LDS: every
-// workgroup of a front repeats the assembly (a few loads per row of the front against the
-// MF_R rows of the factor each wave reads), which saves the separate assembly launch of
-// every depth
-template <int KS>
-__global__ void __launch_bounds__(256) k_mf_fwd_lds(const int* __restrict__ wl, int bs,
-                                                    const double* __restrict__ r,
-                                                    const int* __restrict__ soff,
-                                                    const int* __restrict__ sperm,
-                                                    const int* __restrict__ child0,
-                                                    const int* __restrict__ child1,
-                                                    const int* __restrict__ bnd_off,
-                                                    const int* __restrict__ bnd_pos,
-                                                    const int* __restrict__ fs,
-                                                    const int* __restrict__ fS,
-                                                    const int* __restrict__ fb,
-                                                    const int* __restrict__ fT,
-                                                    const int64_t* __restrict__ mo,
-                                                    const int64_t* __restrict__ vo,
-                                                    const double* __restrict__ M,
-                                                    double* __restrict__ fv) {
-  extern __shared__ double fl[];
-  const int t = wl[2 * blockIdx.x], blk = wl[2 * blockIdx.x + 1];
-  mf_front_rhs(t, bs, r, soff, sperm, child0, child1, bnd_off, bnd_pos, fs, fS, fb, fT, vo, fv,
-               fl);
-  __syncthreads();
-  mf_fwd_rows<KS>(t, blk, fS, fb, mo, vo, M, fl, fv);
+  if ((KS == 1 || wv == 0) && lane < MF_R && io < rows) {
+    if (io < S) y[w.vo + io] = mine;
+    else us[dst] = fo - mine;
+  }
 }
 
 // x_s = X^T y - G^T x_b: separator rows j0 .. j0+MF_R-1 of MT (column split as in the
-// forward rows)
+// forward rows), x in tree order.  Each lane gathers the boundary values x_b of its own
+// columns: their index loads go out with the factor loads, so no workgroup barrier waits
+// for a staged copy.
 template <int KS>
-__global__ void __launch_bounds__(256) k_mf_bwd(const int* __restrict__ wl, int bs,
+__global__ void __launch_bounds__(256) k_mf_bwd(const MFWork* __restrict__ wl, int bs,
                                                 double* __restrict__ x,
-                                                const int* __restrict__ soff,
-                                                const int* __restrict__ sperm,
-                                                const int* __restrict__ bnd_off,
-                                                const int* __restrict__ bnd,
-                                                const int* __restrict__ fs,
-                                                const int* __restrict__ fS,
-                                                const int* __restrict__ fb,
-                                                const int* __restrict__ fT,
-                                                const int64_t* __restrict__ mo,
-                                                const int64_t* __restrict__ vo,
+                                                const int* __restrict__ bnd_tp,
                                                 const double* __restrict__ MT,
-                                                const double* __restrict__ fv) {
-  __shared__ double xbs[MF_XB];
-  const int t = wl[2 * blockIdx.x], blk = wl[2 * blockIdx.x + 1], lane = threadIdx.x & 63;
-  const int s = fs[t], S = fS[t], b = fb[t];
-  // the front's boundary values x_b, gathered once per workgroup (all its waves share them)
-  const bool staged = b <= MF_XB;
-  if (staged)
-    for (int m = threadIdx.x; m < b; m += 256) xbs[m] = x[mf_bnd_dof(t, m, bs, bnd_off, bnd)];
-  __syncthreads();
-  const int wv = threadIdx.x >> 6;
-  const int j0 = (KS == 1 ? blk * 4 + wv : blk) * MF_R;
+                                                const double* __restrict__ yv) {
+  const MFWork w = wl[blockIdx.x];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int s = w.s, S = w.S, b = w.b;
+  const int j0 = (KS == 1 ? w.blk * 4 + wv : w.blk) * MF_R;
   if (j0 >= s) return;
-  const int64_t Fp = int64_t(fT[t]) * 64;
-  const double* y = fv + vo[t];
+  const int64_t Fp = S + ((b + 63) & ~63);
+  const double* y = yv + w.vo;
+  const int* bt = bnd_tp + w.boff;
   const double* rowp[MF_R];
 #pragma unroll
-  for (int q = 0; q < MF_R; ++q) rowp[q] = MT + mo[t] + int64_t(min(j0 + q, s - 1)) * Fp;
+  for (int q = 0; q < MF_R; ++q)
+    rowp[q] = MT + int64_t(w.mo) * 4096 + int64_t(min(j0 + q, s - 1)) * Fp;
   double acc[MF_R];
 #pragma unroll
   for (int q = 0; q < MF_R; ++q) acc[q] = 0.0;
@@ -915,7 +822,7 @@ __global__ void __launch_bounds__(256) k_mf_bwd(const int* __restrict__ wl, int 
   }
 #pragma unroll 4
   for (int m = (KS == 1 ? 0 : wv * 64) + lane; m < b; m += 64 * KS) {
-    const double xb = staged ? xbs[m] : x[mf_bnd_dof(t, m, bs, bnd_off, bnd)];
+    const double xb = x[int64_t(bt[m / bs]) * bs + m % bs];
     double v[MF_R];
 #pragma unroll
     for (int q = 0; q < MF_R; ++q) v[q] = ld_stream(&rowp[q][S + m]);
@@ -926,12 +833,42 @@ __global__ void __launch_bounds__(256) k_mf_bwd(const int* __restrict__ wl, int 
   double mine = 0.0;
 #pragma unroll
   for (int q = 0; q < MF_R; ++q) {
-    const double r = wave_sum(acc[q]);
-    if (lane == q) mine = r;
+    const double t = wave_sum(acc[q]);
+    if (lane == q) mine = t;
   }
   mine = mf_split_sum<KS>(mine);
-  if ((KS == 1 || wv == 0) && lane < MF_R && j0 + lane < s)
-    x[mf_sep_dof(t, j0 + lane, bs, soff, sperm)] = mine;
+  if ((KS == 1 || wv == 0) && lane < MF_R && j0 + lane < s) x[w.roff + j0 + lane] = mine;
+}
+
+// tree order <-> the caller's order
+__global__ void k_mf_to_tree(int n, const int* __restrict__ tdof, const double* __restrict__ r,
+                             double* __restrict__ rt) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) rt[q] = r[tdof[q]];
+}
+__global__ void k_mf_index_to_tree(int n, const int* __restrict__ tdof,
+                                   const int* __restrict__ idx, int* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) out[q] = idx[tdof[q]];
+}
+__global__ void k_mf_from_tree(int n, const int* __restrict__ tdof,
+                               const double* __restrict__ xt, double* __restrict__ x) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) x[tdof[q]] = xt[q];
+}
+
+// tree-order node position of every boundary node, and the DOF of every tree position
+__global__ void k_mf_tree_pos(int used, int nn, int bs, const int* __restrict__ bnd,
+                              const int* __restrict__ snode, const int* __restrict__ soff,
+                              const int* __restrict__ sep_rank, const int* __restrict__ sperm,
+                              int* __restrict__ bnd_tp, int* __restrict__ tdof) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < used) {
+    const int u = bnd[i];
+    bnd_tp[i] = soff[snode[u]] + sep_rank[u];
+  }
+  if (i < nn)
+    for (int k = 0; k < bs; ++k) tdof[i * bs + k] = sperm[i] * bs + k;
 }
 
 // ---------------------------------------------------------------- host side
@@ -1033,7 +970,7 @@ void MFSolver::setup(Ctx& c, int n_, int bs_, const int* rp, const int* col,
   h_b.resize(ntree);
   h_T.resize(ntree);
   std::vector<int64_t> hfo(ntree), hmo(ntree), hvo(ntree);
-  int64_t tf = 0, tm = 0, tv = 0;
+  int64_t tf = 0, tm = 0, tvs = 0;
   for (int t = 0; t < ntree; ++t) {
     h_s[t] = bs * (hsoff[t + 1] - hsoff[t]);
     h_S[t] = (h_s[t] + 63) / 64 * 64;
@@ -1043,11 +980,14 @@ void MFSolver::setup(Ctx& c, int n_, int bs_, const int* rp, const int* col,
     h_T[t] = Fp / 64;
     hfo[t] = tf;
     hmo[t] = tm;
-    hvo[t] = tv;
+    hvo[t] = tvs;
     tf += int64_t(Fp) * Fp;
     tm += int64_t(Fp) * h_S[t];
-    tv += Fp;
+    tvs += Fp;
   }
+  AMGF_REQUIRE(tvs < (int64_t(1) << 30) && tm / 4096 < INT_MAX, AMGF_ENOMEM,
+               "multifrontal: fronts too large");
+  tv = int(tvs);
   for (int dd = 0; dd < ndepth; ++dd)
     AMGF_REQUIRE(tree_off[dd + 1] - tree_off[dd] <= 65535, AMGF_ENOMEM,
                  "multifrontal: too many fronts in one level");
@@ -1072,12 +1012,20 @@ void MFSolver::setup(Ctx& c, int n_, int bs_, const int* rp, const int* col,
   DBuf<double> F(size_t(std::max<int64_t>(tf, 1)));
   M.alloc(size_t(std::max<int64_t>(tm, 1)));
   MT.alloc(size_t(std::max<int64_t>(tm, 1)));
-  fa.alloc(size_t(std::max<int64_t>(tv, 1)));
-  fv.alloc(size_t(std::max<int64_t>(tv, 1)));
+  fv.alloc(size_t(std::max(tv, 1)));
+  us.alloc(2 * size_t(std::max(tv, 1)));
+  rt.alloc(size_t(n));
+  xt.alloc(size_t(n));
+  AMGF_HIP(hipMemsetAsync(us.p, 0, us.bytes(), c.s));
   bnd_pos.alloc(std::max<size_t>(used, 1));
+  bnd_tp.alloc(std::max<size_t>(used, 1));
+  tdof.alloc(size_t(n));
   AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
   hipLaunchKernelGGL(k_mf_bnd_pos, dim3(ntree), dim3(256), 0, c.s, bs, parent.p, snode.p,
                      sep_rank.p, bcnt.p, bnd_off.p, bnd.p, fS.p, bnd_pos.p, c.flag.p);
+  hipLaunchKernelGGL(k_mf_tree_pos, dim3(grid_for(std::max<int64_t>(int64_t(used), nn), 256)),
+                     dim3(256), 0, c.s, int(used), nn, bs, bnd.p, snode.p, soff.p, sep_rank.p,
+                     sperm.p, bnd_tp.p, tdof.p);
   // ---- numeric: original entries, then depth by depth from the leaves
   AMGF_HIP(hipMemsetAsync(F.p, 0, F.bytes(), c.s));
   AMGF_HIP(hipMemsetAsync(M.p, 0, M.bytes(), c.s));
@@ -1132,7 +1080,26 @@ void MFSolver::setup(Ctx& c, int n_, int bs_, const int* rp, const int* col,
   // with the columns split over the four wavefronts (ks = MF_KS) where a depth would give
   // fewer than MF_SPLIT_WG workgroups
   {
-    std::vector<int> wf, wb;
+    const std::vector<int> hbo = d2h(bnd_off.p, size_t(ntree), c.s);
+    const std::vector<int> hpar = d2h(parent.p, size_t(ntree), c.s);
+    const std::vector<int> hc0 = d2h(child0.p, size_t(ntree), c.s);
+    const std::vector<int> hc1 = d2h(child1.p, size_t(ntree), c.s);
+    auto work = [&](int t, int blk) {
+      MFWork w;
+      w.blk = blk;
+      w.S = h_S[t];
+      w.b = h_b[t];
+      w.s = h_s[t];
+      w.nch = (hc0[t] >= 0) + (hc1[t] >= 0);
+      w.roff = bs * hsoff[t];
+      w.vo = int(hvo[t]);
+      const int pa = hpar[t];
+      w.uoff = pa < 0 ? 0 : (hc0[pa] == t ? 0 : tv) + int(hvo[pa]);
+      w.boff = hbo[t];
+      w.mo = int(hmo[t] / 4096);
+      return w;
+    };
+    std::vector<MFWork> wf, wb;
     wl_fwd_off.assign(ndepth + 1, 0);
     wl_bwd_off.assign(ndepth + 1, 0);
     ks_fwd.assign(ndepth, 1);
@@ -1149,27 +1116,21 @@ void MFSolver::setup(Ctx& c, int n_, int bs_, const int* rp, const int* col,
       const int rbf = ks_fwd[dd] == 1 ? 4 * MF_R : MF_R;
       const int rbb = ks_bwd[dd] == 1 ? 4 * MF_R : MF_R;
       for (int t = tree_off[dd]; t < tree_off[dd + 1]; ++t) {
-        for (int k = 0; k < blocks(h_S[t] + h_b[t], rbf); ++k) {
-          wf.push_back(t);
-          wf.push_back(k);
-        }
-        for (int k = 0; k < blocks(h_s[t], rbb); ++k) {
-          wb.push_back(t);
-          wb.push_back(k);
-        }
+        for (int k = 0; k < blocks(h_S[t] + h_b[t], rbf); ++k) wf.push_back(work(t, k));
+        for (int k = 0; k < blocks(h_s[t], rbb); ++k) wb.push_back(work(t, k));
       }
-      wl_fwd_off[dd + 1] = int(wf.size() / 2);
-      wl_bwd_off[dd + 1] = int(wb.size() / 2);
+      wl_fwd_off[dd + 1] = int(wf.size());
+      wl_bwd_off[dd + 1] = int(wb.size());
     }
-    if (wf.empty()) wf.assign(2, 0);
-    if (wb.empty()) wb.assign(2, 0);
-    up(wl_fwd, wf);
-    up(wl_bwd, wb);
-    // largest front of each depth: the LDS the forward kernel assembles it in
-    fp_max.assign(ndepth, 0);
-    for (int dd = 0; dd < ndepth; ++dd)
-      for (int t = tree_off[dd]; t < tree_off[dd + 1]; ++t)
-        fp_max[dd] = std::max(fp_max[dd], h_T[t] * 64);
+    if (wf.empty()) wf.push_back(MFWork{});
+    if (wb.empty()) wb.push_back(MFWork{});
+    wl_fwd.alloc(wf.size());
+    wl_bwd.alloc(wb.size());
+    AMGF_HIP(hipMemcpyAsync(wl_fwd.p, wf.data(), wf.size() * sizeof(MFWork),
+                            hipMemcpyHostToDevice, c.s));
+    AMGF_HIP(hipMemcpyAsync(wl_bwd.p, wb.data(), wb.size() * sizeof(MFWork),
+                            hipMemcpyHostToDevice, c.s));
+    AMGF_HIP(hipStreamSynchronize(c.s));   // the host lists go out of scope
   }
   const int fl = d2h_scalar(c.flag.p, c.s);
   AMGF_REQUIRE(!(fl & 4), AMGF_EDEVICE, "multifrontal: inconsistent symbolic structure");
@@ -1178,36 +1139,38 @@ void MFSolver::setup(Ctx& c, int n_, int bs_, const int* rp, const int* col,
 
 void MFSolver::solve(Ctx& c, const double* r, double* x) const {
   if (n == 0) return;
-  // forward by depth, deepest first: the right-hand sides assembled inside the forward
-  // kernel (LDS) where the depth's fronts fit, by a separate launch otherwise
+  hipLaunchKernelGGL(k_mf_to_tree, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, tdof.p, r,
+                     rt.p);
+  solve_tree(c, rt.p, xt.p);
+  hipLaunchKernelGGL(k_mf_from_tree, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, tdof.p,
+                     xt.p, x);
+  AMGF_LAUNCH_CHECK();
+}
+
+void MFSolver::solve_tree(Ctx& c, const double* r, double* x) const {
+  if (n == 0) return;
+  // forward by depth, deepest first; each front's update vector lands in its parent's slot
   for (int dd = ndepth - 1; dd >= 0; --dd) {
-    const int b0 = tree_off[dd], nt = tree_off[dd + 1] - b0;
     const int nf = wl_fwd_off[dd + 1] - wl_fwd_off[dd];
-    const int* wl = wl_fwd.p + 2 * int64_t(wl_fwd_off[dd]);
-    const bool split = ks_fwd[dd] != 1;
-    if (fp_max[dd] <= MF_FL) {
-      if (nf > 0)
-        hipLaunchKernelGGL(split ? k_mf_fwd_lds<MF_KS> : k_mf_fwd_lds<1>, dim3(nf), dim3(256),
-                           size_t(fp_max[dd]) * 8, c.s, wl, bs, r, soff.p, sperm.p, child0.p,
-                           child1.p, bnd_off.p, bnd_pos.p, fs.p, fS.p, fb.p, fT.p, mo.p, vo.p,
-                           M.p, fv.p);
-      continue;
-    }
-    hipLaunchKernelGGL(k_mf_rhs, dim3(nt), dim3(256), 0, c.s, b0, bs, r, soff.p, sperm.p,
-                       child0.p, child1.p, bnd_off.p, bnd_pos.p, fs.p, fS.p, fb.p, fT.p, vo.p,
-                       fa.p, fv.p);
     if (nf > 0)
-      hipLaunchKernelGGL(split ? k_mf_fwd<MF_KS> : k_mf_fwd<1>, dim3(nf), dim3(256), 0, c.s,
-                         wl, fS.p, fb.p, mo.p, vo.p, M.p, fa.p, fv.p);
+      hipLaunchKernelGGL(ks_fwd[dd] != 1 ? k_mf_fwd<MF_KS> : k_mf_fwd<1>, dim3(nf), dim3(256),
+                         0, c.s, wl_fwd.p + wl_fwd_off[dd], bs, tv, r, bnd_pos.p, M.p, us.p,
+                         fv.p);
   }
+  // backward by depth, root first
   for (int dd = 0; dd < ndepth; ++dd) {
     const int nb = wl_bwd_off[dd + 1] - wl_bwd_off[dd];
     if (nb > 0)
       hipLaunchKernelGGL(ks_bwd[dd] != 1 ? k_mf_bwd<MF_KS> : k_mf_bwd<1>, dim3(nb), dim3(256),
-                         0, c.s, wl_bwd.p + 2 * int64_t(wl_bwd_off[dd]), bs, x,
-                         soff.p, sperm.p, bnd_off.p, bnd.p, fs.p, fS.p, fb.p, fT.p, mo.p, vo.p,
-                         MT.p, fv.p);
+                         0, c.s, wl_bwd.p + wl_bwd_off[dd], bs, x, bnd_tp.p, MT.p, fv.p);
   }
+  AMGF_LAUNCH_CHECK();
+}
+
+void MFSolver::tree_index(Ctx& c, const int* idx, int* out) const {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_mf_index_to_tree, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, tdof.p,
+                     idx, out);
   AMGF_LAUNCH_CHECK();
 }
 

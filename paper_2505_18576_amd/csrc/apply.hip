@@ -380,6 +380,15 @@ __global__ void k_pack_count(int nrows, const int* __restrict__ rp, int* __restr
   cnt[i] = (rp[i + 1] - rp[i] + PACK_PAD - 1) / PACK_PAD * PACK_PAD;
 }
 
+// Entries of one block that a lane loads together in the packed copy (16 bytes when the
+// block's entry count allows it): entry e of block k of a row with nbp padded blocks sits at
+// ((e / G) * nbp + k) * G + e % G, so each load instruction of a wavefront reads a
+// contiguous stretch of 16-byte groups.
+template <int B, class TV>
+constexpr int pack_group() {
+  return (B * B) % int(16 / sizeof(TV)) == 0 ? int(16 / sizeof(TV)) : 1;
+}
+
 // one wavefront per row, a lane per (padded) block
 template <int B, class TV>
 __global__ void __launch_bounds__(256) k_pack_fill(int nrows, const int* __restrict__ rp,
@@ -393,17 +402,18 @@ __global__ void __launch_bounds__(256) k_pack_fill(int nrows, const int* __restr
   if (i >= nrows) return;
   const int r0 = rp[i], nb = rp[i + 1] - r0;
   const int o0 = off[i], nbp = off[i + 1] - o0;
+  constexpr int G = pack_group<B, TV>();
   TV* pv = pval + int64_t(o0) * B * B;
   for (int k = lane; k < nbp; k += 64) {
     if (k < nb) {
       pcol[o0 + k] = col[r0 + k];
       const double* v = val + int64_t(r0 + k) * B * B;
 #pragma unroll
-      for (int e = 0; e < B * B; ++e) pv[int64_t(e) * nbp + k] = TV(v[e]);
+      for (int e = 0; e < B * B; ++e) pv[(int64_t(e / G) * nbp + k) * G + e % G] = TV(v[e]);
     } else {
       pcol[o0 + k] = i;
 #pragma unroll
-      for (int e = 0; e < B * B; ++e) pv[int64_t(e) * nbp + k] = TV(0);
+      for (int e = 0; e < B * B; ++e) pv[(int64_t(e / G) * nbp + k) * G + e % G] = TV(0);
     }
   }
 }
@@ -455,11 +465,13 @@ __global__ void __launch_bounds__(256) k_packed_spmv(int nrows, const int* __res
                                                      const T* __restrict__ w,
                                                      T* __restrict__ xo) {
   using Acc = std::conditional_t<sizeof(TV) == 8, double, T>;
+  constexpr int G = pack_group<B, TV>();
+  typedef TV TVG __attribute__((ext_vector_type(G)));
   const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (r >= nrows) return;
   const int o0 = off[r], nbp = off[r + 1] - o0;
-  const TV* pv = pval + int64_t(o0) * B * B;
+  const TVG* pv = reinterpret_cast<const TVG*>(pval + int64_t(o0) * B * B);
   Acc acc[B];
 #pragma unroll
   for (int p = 0; p < B; ++p) acc[p] = Acc(0);
@@ -470,10 +482,17 @@ __global__ void __launch_bounds__(256) k_packed_spmv(int nrows, const int* __res
 #pragma unroll
     for (int q = 0; q < B; ++q)
       xq[q] = Acc((MODE == SPMV_PRE) ? w[base + q] * b[base + q] : x[base + q]);
+    TV a[B * B];
+#pragma unroll
+    for (int g = 0; g < B * B / G; ++g) {
+      const TVG v = pv[int64_t(g) * nbp + k];
+#pragma unroll
+      for (int u = 0; u < G; ++u) a[g * G + u] = v[u];
+    }
 #pragma unroll
     for (int p = 0; p < B; ++p)
 #pragma unroll
-      for (int q = 0; q < B; ++q) acc[p] += Acc(pv[int64_t(B * p + q) * nbp + k]) * xq[q];
+      for (int q = 0; q < B; ++q) acc[p] += Acc(a[B * p + q]) * xq[q];
   }
 #pragma unroll
   for (int p = 0; p < B; ++p) acc[p] = wave_sum(acc[p]);

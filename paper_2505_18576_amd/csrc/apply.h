@@ -25,8 +25,10 @@ void bsr_spmv(Ctx& c, int mode, const BSR& A, const T* val, const T* x, T* y, co
 // and prolongation of the mixed V-cycle)
 void transfer_spmv(Ctx& c, int mode, const BSR& A, const float* x, float* y,
                    const float* w = nullptr, float* xo = nullptr);
-// b = FP16(a), one rounding to nearest even; *flag |= 1 when a value overflows FP16
-void cast_d2h(Ctx& c, const double* a, _Float16* b, int64_t n, int* flag);
+// b = FP16(a) in the chunked layout of BSR::valh (a: nb blocks of N entries; b holds nb
+// rounded up to a multiple of 64 blocks), one rounding to nearest even; *flag |= 1 when a
+// value overflows FP16
+void cast_d2h_chunked(Ctx& c, const double* a, _Float16* b, int64_t nb, int N, int* flag);
 
 // Build the sliced-ELL copy (FP64 values when fp64, FP32 values when fp32) of a 3x3
 // BSR matrix; bsr_spmv then reads it in place of the BSR arrays.

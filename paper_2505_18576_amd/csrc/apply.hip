@@ -10,22 +10,27 @@ namespace amgf {
 // ======================================================================================
 // BSR SpMV with fused smoother modes
 // ======================================================================================
-// one block's N values widened to T: FP16 blocks of even size as 2-value loads (the block
-// starts on a 4-byte boundary), everything else value by value
-typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+// one block's N values widened to T, value by value (FP32 and FP64 copies: block j at
+// N j)
 template <int N, class T, class TV>
 __device__ __forceinline__ void load_block(const TV* __restrict__ v, T* out) {
-  if constexpr (sizeof(TV) == 2 && N % 2 == 0) {
-    const half2v* v2 = reinterpret_cast<const half2v*>(v);
 #pragma unroll
-    for (int k = 0; k < N / 2; ++k) {
-      const half2v h = v2[k];
-      out[2 * k] = T(h.x);
-      out[2 * k + 1] = T(h.y);
-    }
-  } else {
+  for (int k = 0; k < N; ++k) out[k] = T(v[k]);
+}
+
+// block j of a chunked FP16 copy (BSR::valh) widened to T: N / G loads of G values, each
+// reading the same G entries of the chunk's 64 blocks side by side
+template <int N, class T>
+__device__ __forceinline__ void load_block_chunked(const _Float16* __restrict__ val, int64_t j,
+                                                   T* out) {
+  constexpr int G = fp16_group(N);
+  typedef _Float16 hG __attribute__((ext_vector_type(G)));
+  const hG* base = reinterpret_cast<const hG*>(val + (j >> 6) * (64 * N)) + (j & 63);
 #pragma unroll
-    for (int k = 0; k < N; ++k) out[k] = T(v[k]);
+  for (int g = 0; g < N / G; ++g) {
+    const hG h = base[64 * g];
+#pragma unroll
+    for (int u = 0; u < G; ++u) out[g * G + u] = T(h[u]);
   }
 }
 
@@ -54,7 +59,10 @@ __global__ void __launch_bounds__(256) k_bsr(int nrows, const int* __restrict__ 
       xv[q] = (MODE == SPMV_PRE) ? w[ix] * b[ix] : x[ix];
     }
     T v[BR * BC];
-    load_block<BR * BC>(val + int64_t(j) * (BR * BC), v);
+    if constexpr (std::is_same_v<TV, _Float16>)
+      load_block_chunked<BR * BC>(val, j, v);
+    else
+      load_block<BR * BC>(val + int64_t(j) * (BR * BC), v);
 #pragma unroll
     for (int p = 0; p < BR; ++p)
 #pragma unroll
@@ -190,21 +198,26 @@ void transfer_spmv(Ctx& c, int mode, const BSR& A, const float* x, float* y, con
 }
 
 // FP64 -> FP16 with one rounding to nearest even (truncate to FP32, mark inexactness in the
-// last bit, then the hardware's nearest-even FP32 -> FP16); flag bit 1 on a non-finite
-// result (a value beyond the FP16 range)
-__global__ void k_d2h(const double* __restrict__ a, _Float16* __restrict__ b, int64_t n,
-                      int* __restrict__ flag) {
+// last bit, then the hardware's nearest-even FP32 -> FP16) into the chunked layout of
+// BSR::valh (nb blocks of N entries); flag bit 1 on a non-finite result (a value beyond the
+// FP16 range)
+__global__ void k_d2h_chunked(const double* __restrict__ a, _Float16* __restrict__ b,
+                              int64_t nb, int N, int G, int* __restrict__ flag) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= nb * N) return;
+  const int64_t j = i / N;
+  const int e = int(i % N);
   const double v = a[i];
   float f = __double2float_rz(v);
   if (double(f) != v) f = __uint_as_float(__float_as_uint(f) | 1u);
   const _Float16 h = _Float16(f);
-  b[i] = h;
+  b[(j >> 6) * (64 * N) + (e / G) * (64 * G) + (j & 63) * G + e % G] = h;
   if (!__builtin_isfinite(float(h))) atomicOr(flag, 1);
 }
-void cast_d2h(Ctx& c, const double* a, _Float16* b, int64_t n, int* flag) {
-  if (n) hipLaunchKernelGGL(k_d2h, dim3(grid_for(n, 256)), dim3(256), 0, c.s, a, b, n, flag);
+void cast_d2h_chunked(Ctx& c, const double* a, _Float16* b, int64_t nb, int N, int* flag) {
+  if (nb)
+    hipLaunchKernelGGL(k_d2h_chunked, dim3(grid_for(nb * N, 256)), dim3(256), 0, c.s, a, b, nb,
+                       N, fp16_group(N), flag);
   AMGF_LAUNCH_CHECK();
 }
 

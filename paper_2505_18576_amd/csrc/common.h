@@ -133,13 +133,20 @@ struct DBuf {
 };
 
 // Block-row sparse matrix with br x bc row-major blocks and ascending columns.
+// FP16 entries of a transfer block that one lane loads together (chunked FP16 copy)
+constexpr int fp16_group(int n) { return n % 4 == 0 ? 4 : (n % 2 == 0 ? 2 : 1); }
+
 struct BSR {
   int nrows = 0, ncols = 0, br = 0, bc = 0;
   int64_t nnzb = 0;
   DBuf<int> rowptr, col;
   DBuf<double> val;
   DBuf<float> val32;       // FP32 copy used by the mixed-precision V-cycle
-  DBuf<_Float16> valh;     // FP16 copy (transfer operators of the mixed V-cycle)
+  // FP16 copy (transfer operators of the mixed V-cycle) in chunks of 64 blocks: entry e of
+  // block j at valh[64 N (j / 64) + 64 G (e / G) + G (j % 64) + e % G], N = br * bc entries
+  // per block, G = fp16_group(N), so lanes that read consecutive blocks read one contiguous
+  // stretch per load (nnzb rounded up to whole chunks)
+  DBuf<_Float16> valh;
   // Sliced-ELL copy of a 3x3 matrix for the apply phase (built by bsr_build_sell):
   // slices of 64 block rows, each padded to its longest row.  Slot j of slice s holds
   // the column ids at sell_col[sell_off[s] + 64 j + i] and entry (p,q) of row i's block
@@ -153,7 +160,9 @@ struct BSR {
   DBuf<uint16_t> sell_val16;
   // Packed copy of a square matrix (bsr_build_packed): row i's blocks padded with zero
   // blocks to a multiple of 16 from block offset pk_off[i], column ids pk_col[pk_off[i] + k]
-  // (padding: i), entry (p,q) of block k at pk_val[b*b*pk_off[i] + (b*p+q)*nbp_i + k]
+  // (padding: i), entry e = b*p+q of block k at
+  // pk_val[b*b*pk_off[i] + ((e / G) * nbp_i + k) * G + e % G], G the entries in 16 bytes
+  // when b*b is a multiple of it, else 1
   DBuf<int> pk_off, pk_col;
   DBuf<double> pk_val;
   DBuf<float> pk_val32;

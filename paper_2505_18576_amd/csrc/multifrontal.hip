@@ -68,8 +68,15 @@ __global__ void k_mf_node_graph(int nn, int bs, const int* __restrict__ rp,
 }
 
 // ---------------------------------------------------------------- ordering
+// Threads of a splitting workgroup, and lanes that share one frontier node's neighbour list
+// in its breadth-first search (the search steps level by level; a lane per frontier node
+// walked ~20 neighbours one dependent load after another at every level).
+constexpr int MF_SPLIT_THREADS = 1024;
+constexpr int MF_BFS_LANES = 8;
+
 // Breadth-first search restricted to part p from `start`.  Frontier queues qa/qb hold at
-// most np nodes each.  On return sh[0] = last level, sh[2] = nodes reached.
+// most np nodes each.  On return sh[0] = last level, sh[2] = nodes reached.  The levels
+// do not depend on the order in which the frontier is filled.
 __device__ void mf_bfs(int p, int start, const int* nodes, int np, const int* grp,
                        const int* gcol, const int* part, int* lvl, int* qa, int* qb,
                        int* sh) {
@@ -87,11 +94,13 @@ __device__ void mf_bfs(int p, int start, const int* nodes, int np, const int* gr
   int cur = 0;
   int* q = qa;
   int* qn = qb;
+  const int sub = tid % MF_BFS_LANES, gi = tid / MF_BFS_LANES, ng = nt / MF_BFS_LANES;
   while (true) {
     const int fsz = sh[0];
-    for (int i = tid; i < fsz; i += nt) {
+    for (int i = gi; i < fsz; i += ng) {
       const int v = q[i];
-      for (int e = grp[v]; e < grp[v + 1]; ++e) {
+      const int e1 = grp[v + 1];
+      for (int e = grp[v] + sub; e < e1; e += MF_BFS_LANES) {
         const int u = gcol[e];
         if (part[u] != p) continue;
         if (atomicCAS(&lvl[u], -1, cur + 1) == -1) qn[atomicAdd(&sh[1], 1)] = u;
@@ -119,7 +128,7 @@ __device__ void mf_bfs(int p, int start, const int* nodes, int np, const int* gr
 // One workgroup per part of depth d: leaf, or split into children 2p (lower levels) and
 // 2p+1 (higher levels and unreached nodes) with the middle level as separator.
 // npart[v] = child slot, or -1 when v joins supernode tb + p (snode[v]).
-__global__ void __launch_bounds__(256) k_mf_split(int tb, int force_leaf,
+__global__ void __launch_bounds__(MF_SPLIT_THREADS) k_mf_split(int tb, int force_leaf,
                                                   const int* __restrict__ poff,
                                                   const int* __restrict__ pperm,
                                                   const int* __restrict__ grp,
@@ -914,7 +923,8 @@ void MFSolver::setup(Ctx& c, int n_, int bs_, const int* rp, const int* col,
     DBuf<int> poff, pperm;
     group_by_key(c, part.p, nn, np, poff, pperm, false);   // order within a part unused
     DBuf<int> pinfo(size_t(np) + 1), rank(size_t(np) + 1);
-    hipLaunchKernelGGL(k_mf_split, dim3(np), dim3(256), 0, c.s, tb, int(d == MF_MAXD - 1),
+    hipLaunchKernelGGL(k_mf_split, dim3(np), dim3(MF_SPLIT_THREADS), 0, c.s, tb,
+                       int(d == MF_MAXD - 1),
                        poff.p, pperm.p, grp.p, gcol.p, part.p, npart.p, lvl.p, qa.p, qb.p,
                        snode.p, pinfo.p);
     AMGF_LAUNCH_CHECK();

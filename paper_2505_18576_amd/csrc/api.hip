@@ -74,6 +74,7 @@ struct Handle {
   DBuf<int> Ic;
   MFSolver aw;
   DBuf<int> Ic_t;               // I_c in the factor's tree order: Ic_t[q] = Ic[aw.tdof[q]]
+  DBuf<uint32_t> ic_mask;       // one bit per DOF, set on I_c
   DBuf<double> f_r, f_w;
   DBuf<int> aw_rp, aw_col;      // A_w = S[I_c, I_c] as scalar CSR (input of its factor)
   DBuf<double> aw_val;
@@ -442,6 +443,7 @@ static void setup(Handle& h, const int32_t* K_rowptr, const int32_t* K_col, cons
     h.ic_nodes.alloc(h.n_icn);
     AMGF_HIP(hipMemcpyAsync(h.ic_nodes.p, nodes.data(), sizeof(int) * h.n_icn,
                             hipMemcpyHostToDevice, c.s));
+    bit_mask(c, h.Ic.p, h.n_c, 3 * int64_t(nn), h.ic_mask);
     AMGF_HIP(hipStreamSynchronize(c.s));
   }
   if (o.filter && h.n_c > 0) {
@@ -898,18 +900,28 @@ static void filter_solve(Handle& h, const double* r, double* w) {
   h.aw.solve_tree(h.ctx, r, w);
 }
 
+// CG dot products that an AMGF step can form in its last kernel: out[0] = r.z and
+// out[1] = r.zo (device memory), part the dot-product partials (nullptr: the context's)
+struct StepDots {
+  const double* zo;
+  double* out;
+  double* part;
+};
+
 // z = M r, Definition 5.3:  z1 = B r;  z2 = z1 + P A_w^{-1} P^T (r - A z1);
 // z = z2 + B (r - A z2).  The filter residual is formed on the filter rows only.  In
 // mixed precision the second residual keeps the stiffness product in FP32 (it only
-// feeds the FP32 V-cycle) and the contact term in FP64.
-static void amgf_apply_impl(Handle& h, const double* r, double* z) {
+// feeds the FP32 V-cycle) and the contact term in FP64.  Returns true when it also formed
+// the dot products sd asks for (the mixed step does, in its final sum).
+static bool amgf_apply_impl(Handle& h, const double* r, double* z,
+                            const StepDots* sd = nullptr) {
   Ctx& c = h.ctx;
   const int64_t n = h.n();
   phase(h, PH_AMG);
   if (!h.opt.filter || h.filter_suspended) {
     vcycle(h, r, z);
     phase(h, PH_OTHER);
-    return;
+    return false;
   }
   Level& L0 = *h.lev[0];
   if (h.mixed() && h.plain_cycle() && h.ic_from_J) {
@@ -939,9 +951,14 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
     vcycle32(h, 0);                                   // B r2  (L0.fx)
     phase(h, PH_OTHER);
     std::swap(L0.fb, h.r2f);
+    if (sd && h.ic_mask.p) {                          // the same sums, with r.z and r.zo
+      add_ff_dots(c, n, h.zf.p, L0.fx.p, h.z1.p, h.ic_mask.p, r, sd->zo, z, sd->out,
+                  sd->part);
+      return true;
+    }
     add_ff(c, n, h.zf.p, L0.fx.p, z);                 // z = z2 + B r2 ...
     add_at(c, h.z1.p, L0.fx.p, h.Ic.p, h.n_c, z);     // ... with the FP64 z2 on I_c
-    return;
+    return false;
   }
   vcycle(h, r, h.z1.p);                               // z1 = B r
   if (h.n_c > 0) {
@@ -973,6 +990,7 @@ static void amgf_apply_impl(Handle& h, const double* r, double* z) {
     vcopy(c, h.z1.p, z, n);
     axpby(c, n, 1.0, h.z3.p, 1.0, z);                 // z = z2 + B r2
   }
+  return false;
 }
 
 static void set_damping(Handle& h, const float* W);
@@ -1348,13 +1366,13 @@ static amgf_status pcg_run(Handle& h, const double* b, double* x, amgf_solve_inf
       pcg_update_xr_dev(c, n, rz, dsc, h.pp.p, h.pq.p, x, h.pr.p);
     }
     std::swap(h.pz, h.pzo);
-    amgf_apply_impl(h, h.pr.p, h.pz.p);
-    h.r_cast_ready = false;
-    {
+    const StepDots sd{h.pzo.p, dsc + 1, dpart};
+    if (!amgf_apply_impl(h, h.pr.p, h.pz.p, &sd)) {   // r.z and r.z_old
       const double* xs[2] = {h.pr.p, h.pr.p};
       const double* ys[2] = {h.pz.p, h.pzo.p};
       dots_device(c, n, 2, xs, ys, dsc + 1, dpart);
     }
+    h.r_cast_ready = false;
     AMGF_HIP(hipMemcpyAsync(s3, dsc, 3 * sizeof(double), hipMemcpyDeviceToHost, c.s));
     if (!na) AMGF_HIP(hipEventRecord(ev, c.s));
     have_q = it + 1 < h.opt.max_iters && rel * (rel / rel_old) > h.opt.rtol;

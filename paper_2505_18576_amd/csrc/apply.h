@@ -106,6 +106,16 @@ void dots(Ctx& c, int64_t n, int nd, const double* const* xs, const double* cons
 void dots_device(Ctx& c, int64_t n, int nd, const double* const* xs, const double* const* ys,
                  double* out_dev, double* part = nullptr);
 
+// The end of the mixed AMGF step fused with the CG dot products: z = a + b (FP32 halves
+// widened), z = u + b on the DOFs set in mask; out_dev[0] = r.z, out_dev[1] = r.zo, bitwise
+// what dots_device gives over the finished z (same partition and order)
+void add_ff_dots(Ctx& c, int64_t n, const float* a, const float* b, const double* u,
+                 const uint32_t* mask, const double* r, const double* zo, double* z,
+                 double* out_dev, double* part = nullptr);
+// mask = one bit per index below nbits, set for idx[0 .. n-1] (allocated here when its size
+// differs)
+void bit_mask(Ctx& c, const int* idx, int n, int64_t nbits, DBuf<uint32_t>& mask);
+
 // x = y / sqrt(s[0]) with s in device memory
 void normalize_dev(Ctx& c, int64_t n, const double* s, const double* y, double* x);
 

@@ -882,6 +882,42 @@ __global__ void __launch_bounds__(256) k_dot_final(int nd, const double* __restr
   }
 }
 
+// z = a + b (FP32 values widened) except on the DOFs set in mask (one bit each), where
+// z = u + b; with the CG products r.z and r.zo as partial sums in the layout, element order
+// and per-thread order of k_dot_partial (same grid), so k_dot_final gives bitwise the sums
+// dots_device would give over the finished z
+__global__ void __launch_bounds__(256) k_add_ff_dots(int64_t n, const float* __restrict__ a,
+                                                     const float* __restrict__ b,
+                                                     const double* __restrict__ u,
+                                                     const uint32_t* __restrict__ mask,
+                                                     const double* __restrict__ r,
+                                                     const double* __restrict__ zo,
+                                                     double* __restrict__ z,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[4];
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const bool on = (mask[i >> 5] >> (i & 31)) & 1u;
+    const double zi = on ? u[i] + double(b[i]) : double(a[i]) + double(b[i]);
+    z[i] = zi;
+    const double ri = r[i];
+    acc0 += ri * zi;
+    acc1 += ri * zo[i];
+  }
+  const double s0 = block_sum(acc0, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s0;
+  const double s1 = block_sum(acc1, sh);
+  if (threadIdx.x == 0) part[DOT_BLOCKS + blockIdx.x] = s1;
+}
+
+__global__ void k_set_bits(const int* __restrict__ idx, int n, uint32_t* __restrict__ mask) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int i = idx[k];
+  atomicOr(&mask[i >> 5], 1u << (i & 31));
+}
+
 // the partial sums (DOT_SCRATCH doubles): the caller's buffer, else the context's own
 static double* dot_partials(Ctx& c, double* part) {
   if (part) return part;
@@ -900,6 +936,24 @@ void dots_device(Ctx& c, int64_t n, int nd, const double* const* xs, const doubl
   }
   hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, nd, a, pp);
   hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, c.s, nd, pp, out_dev);
+  AMGF_LAUNCH_CHECK();
+}
+
+void add_ff_dots(Ctx& c, int64_t n, const float* a, const float* b, const double* u,
+                 const uint32_t* mask, const double* r, const double* zo, double* z,
+                 double* out_dev, double* part) {
+  double* pp = dot_partials(c, part);
+  hipLaunchKernelGGL(k_add_ff_dots, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, a, b, u, mask, r,
+                     zo, z, pp);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, c.s, 2, pp, out_dev);
+  AMGF_LAUNCH_CHECK();
+}
+
+void bit_mask(Ctx& c, const int* idx, int n, int64_t nbits, DBuf<uint32_t>& mask) {
+  const size_t words = size_t((nbits + 31) / 32);
+  if (mask.n != std::max<size_t>(words, 1)) mask.alloc(std::max<size_t>(words, 1));
+  AMGF_HIP(hipMemsetAsync(mask.p, 0, mask.bytes(), c.s));
+  if (n) hipLaunchKernelGGL(k_set_bits, dim3(grid_for(n, 256)), dim3(256), 0, c.s, idx, n, mask.p);
   AMGF_LAUNCH_CHECK();
 }
 

@@ -29,6 +29,7 @@ __global__ void k_bsr_to_dense(int nrows, int b, const int* __restrict__ rp,
 }
 
 constexpr int SWEEP_B = 32;
+static_assert(SWEEP_B % 4 == 0, "four wavefronts share a sweep block's rows");
 
 // entry (i, j) of the symmetric matrix held in the upper triangle
 __device__ __forceinline__ double sym_at(const double* X, int n, int i, int j) {
@@ -65,38 +66,50 @@ __global__ void __launch_bounds__(256) k_sweep_pivot(int n, const double* __rest
   for (int e = tid; e < kb * kb; e += 256) Pi[e] = -P[e / kb][e % kb];
 }
 
-// V = A_K. (rows of the block, from the upper triangle) and W = Pi V, one thread per column
+// V = A_K. (rows of the block, from the upper triangle) and W = Pi V for 64 columns per
+// workgroup: the four wavefronts read 8 rows of V each into LDS, then each forms 8 rows of W
 __global__ void __launch_bounds__(256) k_sweep_rows(int n, const double* __restrict__ X,
                                                     int k0, int kb,
                                                     const double* __restrict__ Pi,
                                                     double* __restrict__ V,
                                                     double* __restrict__ W) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  double v[SWEEP_B];
+  __shared__ double vs[SWEEP_B][64];
+  const int jj = threadIdx.x & 63, q0 = (threadIdx.x >> 6) * (SWEEP_B / 4);
+  const int j = blockIdx.x * 64 + jj;
 #pragma unroll
-  for (int q = 0; q < SWEEP_B; ++q) {
-    v[q] = q < kb ? sym_at(X, n, k0 + q, j) : 0.0;
-    if (q < kb) V[int64_t(q) * n + j] = v[q];
+  for (int q = q0; q < q0 + SWEEP_B / 4; ++q) {
+    const double v = (q < kb && j < n) ? sym_at(X, n, k0 + q, j) : 0.0;
+    vs[q][jj] = v;
+    if (q < kb && j < n) V[int64_t(q) * n + j] = v;
   }
-  for (int p = 0; p < kb; ++p) {
+  __syncthreads();
+  if (j >= n) return;
+  for (int p = q0; p < q0 + SWEEP_B / 4 && p < kb; ++p) {
     double w = 0.0;
 #pragma unroll
     for (int q = 0; q < SWEEP_B; ++q)
-      if (q < kb) w += Pi[p * kb + q] * v[q];
+      if (q < kb) w += Pi[p * kb + q] * vs[q][jj];
     W[int64_t(p) * n + j] = w;
   }
 }
 
-// one block step on the upper triangle (j >= i) in 16 x 16 tiles; tiles below the
-// diagonal exit
+// one block step on the upper triangle (j >= i) in 16 x 16 tiles, the tile's rows of V and
+// columns of W staged in LDS; tiles below the diagonal exit
 __global__ void __launch_bounds__(256) k_sweep_update(int n, double* __restrict__ X, int k0,
                                                       int kb, const double* __restrict__ Pi,
                                                       const double* __restrict__ V,
                                                       const double* __restrict__ W) {
   if (blockIdx.y > blockIdx.x) return;
-  const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
-  const int j = blockIdx.x * 16 + (threadIdx.x & 15);
+  __shared__ double vt[SWEEP_B][16], wt[SWEEP_B][16];
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  for (int e = threadIdx.x; e < SWEEP_B * 16; e += 256) {
+    const int p = e >> 4, c = e & 15;
+    vt[p][c] = (p < kb && i0 + c < n) ? V[int64_t(p) * n + i0 + c] : 0.0;
+    wt[p][c] = (p < kb && j0 + c < n) ? W[int64_t(p) * n + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int i = i0 + ti, j = j0 + tj;
   if (i >= n || j >= n || j < i) return;
   const bool iK = i >= k0 && i < k0 + kb, jK = j >= k0 && j < k0 + kb;
   const int64_t t = int64_t(i) * n + j;
@@ -104,12 +117,12 @@ __global__ void __launch_bounds__(256) k_sweep_update(int n, double* __restrict_
   if (iK && jK) {
     x = -Pi[(i - k0) * kb + (j - k0)];
   } else if (iK) {
-    x = W[int64_t(i - k0) * n + j];
+    x = wt[i - k0][tj];
   } else if (jK) {
     x = W[int64_t(j - k0) * n + i];
   } else {
     double acc = 0.0;
-    for (int p = 0; p < kb; ++p) acc += V[int64_t(p) * n + i] * W[int64_t(p) * n + j];
+    for (int p = 0; p < kb; ++p) acc += vt[p][ti] * wt[p][tj];
     x = X[t] - acc;
   }
   X[t] = x;
@@ -155,7 +168,7 @@ bool DenseInverse::setup(Ctx& c, const BSR& A) {
     const int kb = std::min(SWEEP_B, n - k0);
     hipLaunchKernelGGL(k_sweep_pivot, dim3(1), dim3(256), 0, c.s, n, X.p, k0, kb, Pi.p,
                        c.flag.p);
-    hipLaunchKernelGGL(k_sweep_rows, dim3(grid_for(n, 256)), dim3(256), 0, c.s, n, X.p, k0, kb,
+    hipLaunchKernelGGL(k_sweep_rows, dim3(grid_for(n, 64)), dim3(256), 0, c.s, n, X.p, k0, kb,
                        Pi.p, V.p, W.p);
     hipLaunchKernelGGL(k_sweep_update, dim3(nt, nt), dim3(256), 0, c.s, n, X.p, k0, kb, Pi.p,
                        V.p, W.p);

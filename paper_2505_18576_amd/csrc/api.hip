@@ -613,14 +613,15 @@ static void smoothing_copies(Handle& h, Level& L) {
 
 // Contact term of a level inside the V-cycle: through J and D on level 0 (the fine
 // interface, where the assembled block would be larger than J) and on the coarse levels
-// where that still reads fewer bytes (factored_contact_pays), through the assembled
-// Galerkin block C = J^T D J on the others (one kernel instead of two).
+// where that still reads fewer bytes (factored_contact_pays); on the other coarse levels
+// the assembled Galerkin block C_l is part of the smoothing matrix A_l = K_l + C_l, or
+// empty (no contact rows: nothing to add).
 template <class T>
 static void level_contact(Handle& h, Level& L, int mode, const T* x, T* y, const T* w) {
   if (L.contact_in_A) return;                         // inside the level's smoothing matrix
   if (&L == h.lev[0].get() || L.contact_factored)
     contact_apply<T, T>(h.ctx, mode, L.J, L.JT, L.crows.p, L.ncrows, h.D.p, x, h.t.p, y, w);
-  else
+  else if (L.nccrows > 0)
     throw Error(AMGF_EDEVICE, "coarse contact term without a form");
 }
 

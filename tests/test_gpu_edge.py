@@ -1,5 +1,5 @@
 """Degenerate cases on the GPU against the oracle: no contact (m = 0, an empty filtering
-space, so M = 2B - BAB), a hierarchy of one dense level (B = A^{-1}, so CG stops after one
+space, so M = 2B - BAB; also with a coarse level that has no contact term), a hierarchy of one dense level (B = A^{-1}, so CG stops after one
 step), and the filter switched off (M = B)."""
 import numpy as np
 import pytest
@@ -51,6 +51,27 @@ def test_no_contact_mixed_precision():
     print(f"no contact, FP32 V-cycle: apply {e_m:.2e}, its {info.iterations}, solution {e_x:.2e}")
     assert e_m <= MIXED_TOL
     assert info.converged and e_x <= 1e-8
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_no_contact_three_levels(precision):
+    """No contact with a smoothed coarse level between level 0 and the coarsest one (N = 12,
+    three levels): the coarse V-cycle levels have no contact term at all."""
+    p = make_two_block(12, contact=False, top_bc="clamped", rhs_seed=37)
+    h, o = _pair(p, coarse_max_nodes=32, precision=precision)
+    assert o.n_c == 0 and o.nlev == 3 and h.n_levels == 3
+    r = np.random.default_rng(38).standard_normal(o.n)
+    e_b = rel(h.vcycle(r).cpu().numpy(), o.vcycle(r))
+    x, info = h.pcg(p.b)
+    ref = o.pcg(p.b)
+    e_x = rel(x.cpu().numpy(), ref.x)
+    print(f"no contact, three levels, precision {precision}: vcycle {e_b:.2e}, its "
+          f"{info.iterations} / {ref.iterations}, solution {e_x:.2e}")
+    assert e_b <= (1e-10 if precision == 0 else MIXED_TOL)
+    assert info.converged and e_x <= 1e-8
+    if precision == 0:
+        assert abs(info.iterations - ref.iterations) <= 1
     h.close()
 
 

@@ -859,16 +859,46 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
-__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, int nd, DotArgs a,
+template <int ND>
+__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, DotArgs a,
                                                      double* __restrict__ part) {
+  constexpr int U = 4;   // elements per thread whose loads go out together (order kept)
   __shared__ double sh[4];
-  double acc[DOT_MAX] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x)
-    for (int d = 0; d < nd; ++d) acc[d] += a.x[d][i] * a.y[d][i];
-  for (int d = 0; d < nd; ++d) {
+  double acc[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) acc[d] = 0.0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += U * stride) {
+    double xv[U][ND], yv[U][ND];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int64_t i = i0 + k * stride;
+      const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        xv[k][d] = a.x[d][ic];
+        yv[k][d] = a.y[d][ic];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      if (i0 + k * stride >= n) break;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) acc[d] += xv[k][d] * yv[k][d];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
     const double s = block_sum(acc[d], sh);
     if (threadIdx.x == 0) part[d * DOT_BLOCKS + blockIdx.x] = s;
+  }
+}
+static void launch_dot_partial(Ctx& c, int64_t n, int nd, const DotArgs& a, double* part) {
+  switch (nd) {
+    case 1: hipLaunchKernelGGL(k_dot_partial<1>, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, a, part); break;
+    case 2: hipLaunchKernelGGL(k_dot_partial<2>, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, a, part); break;
+    case 3: hipLaunchKernelGGL(k_dot_partial<3>, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, a, part); break;
+    default: hipLaunchKernelGGL(k_dot_partial<4>, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, a, part);
   }
 }
 __global__ void __launch_bounds__(256) k_dot_final(int nd, const double* __restrict__ part,
@@ -894,16 +924,34 @@ __global__ void __launch_bounds__(256) k_add_ff_dots(int64_t n, const float* __r
                                                      const double* __restrict__ zo,
                                                      double* __restrict__ z,
                                                      double* __restrict__ part) {
+  constexpr int U = 4;   // elements per thread whose loads go out together
   __shared__ double sh[4];
   double acc0 = 0.0, acc1 = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const bool on = (mask[i >> 5] >> (i & 31)) & 1u;
-    const double zi = on ? u[i] + double(b[i]) : double(a[i]) + double(b[i]);
-    z[i] = zi;
-    const double ri = r[i];
-    acc0 += ri * zi;
-    acc1 += ri * zo[i];
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += U * stride) {
+    float av[U], bv[U];
+    double rv[U], ov[U];
+    uint32_t mv[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int64_t i = i0 + k * stride;
+      const int64_t ic = i < n ? i : n - 1;
+      av[k] = a[ic];
+      bv[k] = b[ic];
+      rv[k] = r[ic];
+      ov[k] = zo[ic];
+      mv[k] = mask[ic >> 5];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int64_t i = i0 + k * stride;
+      if (i >= n) break;
+      const bool on = (mv[k] >> (i & 31)) & 1u;
+      const double zi = (on ? u[i] : double(av[k])) + double(bv[k]);
+      z[i] = zi;
+      acc0 += rv[k] * zi;
+      acc1 += rv[k] * ov[k];
+    }
   }
   const double s0 = block_sum(acc0, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s0;
@@ -934,7 +982,7 @@ void dots_device(Ctx& c, int64_t n, int nd, const double* const* xs, const doubl
     a.x[d] = xs[d];
     a.y[d] = ys[d];
   }
-  hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, nd, a, pp);
+  launch_dot_partial(c, n, nd, a, pp);
   hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, c.s, nd, pp, out_dev);
   AMGF_LAUNCH_CHECK();
 }
@@ -966,7 +1014,7 @@ void dots(Ctx& c, int64_t n, int nd, const double* const* xs, const double* cons
     a.x[d] = xs[d];
     a.y[d] = ys[d];
   }
-  hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(256), 0, c.s, n, nd, a, pp);
+  launch_dot_partial(c, n, nd, a, pp);
   hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, c.s, nd, pp, pp + DOT_MAX * DOT_BLOCKS);
   AMGF_LAUNCH_CHECK();
   AMGF_HIP(hipMemcpyAsync(out_host, pp + DOT_MAX * DOT_BLOCKS, nd * sizeof(double),

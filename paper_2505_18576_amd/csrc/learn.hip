@@ -85,6 +85,31 @@ __device__ __forceinline__ void mlp_forward(const float* __restrict__ W, const d
   s.y = y;
 }
 
+// The network's output for one row without keeping the second hidden layer (theta only):
+// the operations and their order are those of mlp_forward, so y is bitwise the same; the
+// first hidden layer stays in registers (loops unrolled) instead of per-lane memory.
+__device__ __forceinline__ double mlp_output(const float* __restrict__ W, const double* f) {
+  double fh[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) fh[j] = (f[j] - double(W[OFF_MU + j])) / double(W[OFF_SD + j]);
+  double h1[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    double a = double(W[OFF_B1 + j]);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) a += double(W[OFF_W1 + j * 6 + q]) * fh[q];
+    h1[j] = tanh(a);
+  }
+  double y = double(W[OFF_B3]);
+  for (int j = 0; j < 32; ++j) {                    // h2_j, then its term of y
+    double a = double(W[OFF_B2 + j]);
+#pragma unroll
+    for (int q = 0; q < 32; ++q) a += double(W[OFF_W2 + j * 32 + q]) * h1[q];
+    y += double(W[OFF_W3 + j]) * tanh(a);
+  }
+  return y;
+}
+
 // theta_i = 1 + 0.98 tanh(y_i), w_i = theta_i / d_i
 __global__ void k_mlp_theta(int64_t n, const float* __restrict__ W, const double* __restrict__ F,
                             int64_t ld, const double* __restrict__ d, double* __restrict__ theta,
@@ -92,10 +117,9 @@ __global__ void k_mlp_theta(int64_t n, const float* __restrict__ W, const double
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double f[6];
+#pragma unroll
   for (int q = 0; q < 6; ++q) f[q] = F[q * ld + i];
-  MLPState s;
-  mlp_forward(W, f, s);
-  const double th = 1.0 + 0.98 * tanh(s.y);
+  const double th = 1.0 + 0.98 * tanh(mlp_output(W, f));
   theta[i] = th;
   w[i] = th / d[i];
 }

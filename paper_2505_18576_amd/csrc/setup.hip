@@ -850,6 +850,105 @@ __global__ void __launch_bounds__(256) k_sa_numeric(int n, const int* __restrict
   }
 }
 
+// The same for short rows (level 0: about 27 blocks of A and 5 of P per row): two rows per
+// wavefront, a half-wavefront (32 lanes) each, so each staged chunk serves two rows.  A
+// half's blocks of A go through in chunks of 32 in ascending order, as the full-wavefront
+// form takes them in chunks of 64, so each block of P gets the same sums in the same order.
+// Both halves run the loops to the larger trip count (the other half idles) so that every
+// lane reaches the shuffles and ballots.
+template <int B, int NC>
+__global__ void __launch_bounds__(256) k_sa_numeric_half(int n, const int* __restrict__ arp,
+                                                         const int* __restrict__ acol,
+                                                         const double* __restrict__ aval,
+                                                         const int* __restrict__ agg,
+                                                         const double* __restrict__ Pt,
+                                                         const double* __restrict__ d,
+                                                         double omega,
+                                                         const int* __restrict__ prp,
+                                                         const int* __restrict__ pcol,
+                                                         double* __restrict__ pval) {
+  constexpr int E = B * NC;
+  __shared__ double prod[4][64][E + 1];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int half = lane >> 5, hl = lane & 31;
+  const int i = (blockIdx.x * 4 + wv) * 2 + half;
+  const bool row_on = i < n && agg[i] >= 0;
+  const int ai = row_on ? agg[i] : -1;
+  const int t0 = row_on ? arp[i] : 0, t1 = row_on ? arp[i + 1] : 0;
+  const int p0 = row_on ? prp[i] : 0, p1 = row_on ? prp[i + 1] : 0;
+  // trip counts of the slot and block chunks, the larger of the two halves
+  const int ns_mine = (p1 - p0 + 31) / 32, nc_mine = (t1 - t0 + 31) / 32;
+  const int ns_it = max(__shfl(ns_mine, 0, 64), __shfl(ns_mine, 32, 64));
+  const int nc_it = max(__shfl(nc_mine, 0, 64), __shfl(nc_mine, 32, 64));
+  const unsigned long long half_mask = half ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull;
+  for (int si = 0; si < ns_it; ++si) {
+    const int sb = p0 + si * 32;
+    const int nslot = max(0, min(32, p1 - sb));
+    const bool act = hl < nslot;
+    const int J = act ? pcol[sb + hl] : INT_MAX;
+    double acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = 0.0;
+    for (int ci = 0; ci < nc_it; ++ci) {
+      const int t = t0 + ci * 32 + hl;
+      int kj = -1;
+      if (t < t1) {
+        const int v = acol[t];
+        kj = agg[v];
+        if (kj >= 0) {
+          const double* A = aval + int64_t(t) * B * B;
+          const double* Q = Pt + int64_t(v) * E;
+#pragma unroll
+          for (int p = 0; p < B; ++p)
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+              double a = 0.0;
+#pragma unroll
+              for (int r = 0; r < B; ++r) a += A[p * B + r] * Q[r * NC + q];
+              prod[wv][lane][p * NC + q] = a;
+            }
+        }
+      }
+      // the lane of this half owning column kj (binary search over the half's columns)
+      int pos = 0;
+#pragma unroll
+      for (int st = 16; st > 0; st >>= 1) {
+        const int v = __shfl(J, min(pos + st - 1, 31), 32);
+        if (pos + st <= nslot && v < kj) pos += st;
+      }
+      const int hit = __shfl(J, min(pos, 31), 32);
+      const int slot = (kj >= 0 && pos < nslot && hit == kj) ? pos : -1;
+      wave_lds_sync();
+      // one ballot per slot, to the larger slot count of the two halves (uniform)
+      const int nslot_max = max(__shfl(nslot, 0, 64), __shfl(nslot, 32, 64));
+      unsigned long long mine = 0;
+      for (int s2 = 0; s2 < nslot_max; ++s2) {
+        const unsigned long long m = __ballot(slot == s2);
+        if (hl == s2) mine = m & half_mask;
+      }
+      while (mine) {
+        const int u = __ffsll(mine) - 1;
+        mine &= mine - 1;
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] += prod[wv][u][e];
+      }
+      wave_lds_sync();
+    }
+    if (act) {
+      double* out = pval + int64_t(sb + hl) * E;
+#pragma unroll
+      for (int p = 0; p < B; ++p) {
+        const double sc = omega / d[int64_t(i) * B + p];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          const double v = -(acc[p * NC + q] * sc);
+          out[p * NC + q] = J == ai ? Pt[int64_t(i) * E + p * NC + q] + v : v;
+        }
+      }
+    }
+  }
+}
+
 void smooth_prolongator(Ctx& c, const BSR& A, const int* agg, int n_agg, int nc,
                         const double* Pt, const double* d, double omega, BSR& P) {
   const int n = A.nrows;
@@ -863,8 +962,9 @@ void smooth_prolongator(Ctx& c, const BSR& A, const int* agg, int n_agg, int nc,
   AMGF_REQUIRE((A.br == 3 && (nc == 3 || nc == 6)) || (A.br == 6 && nc == 6), AMGF_EINVAL,
                "prolongator block size");
   if (A.br == 3 && nc == 6)
-    hipLaunchKernelGGL((k_sa_numeric<3, 6>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
-                       A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p, P.val.p);
+    hipLaunchKernelGGL((k_sa_numeric_half<3, 6>), dim3(grid_for(n, 8)), dim3(256), 0, c.s, n,
+                       A.rowptr.p, A.col.p, A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p,
+                       P.val.p);
   else if (A.br == 3)
     hipLaunchKernelGGL((k_sa_numeric<3, 3>), g, dim3(256), 0, c.s, n, A.rowptr.p, A.col.p,
                        A.val.p, agg, Pt, d, omega, P.rowptr.p, P.col.p, P.val.p);

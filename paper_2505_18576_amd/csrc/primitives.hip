@@ -536,8 +536,12 @@ __global__ void k_merge_count(int nrows, const int* __restrict__ ra, const int* 
   counts[r] = n;
 }
 
+constexpr int MERGE_LDS = 256;   // column ids of A's and of B's row a wavefront stages
+
 // one wavefront per row: rows without entries of B are copied block-parallel (the
-// common case), rows with both are merged by lane 0
+// common case); for rows with both, the column lists go to LDS, lane 0 merges them there
+// into (entry of A, entry of B) pairs and the wavefront then writes the blocks; rows longer
+// than the staging are merged by lane 0 from memory
 __global__ void __launch_bounds__(256) k_merge_fill(int nrows, int bsz, const int* __restrict__ ra,
                                                     const int* __restrict__ ca,
                                                     const double* __restrict__ va,
@@ -555,6 +559,43 @@ __global__ void __launch_bounds__(256) k_merge_fill(int nrows, int bsz, const in
     for (int k = lane; k < ie - i0; k += 64) cc[o0 + k] = ca[i0 + k];
     const int64_t nv = int64_t(ie - i0) * bsz;
     for (int64_t e = lane; e < nv; e += 64) vc[int64_t(o0) * bsz + e] = va[int64_t(i0) * bsz + e];
+    return;
+  }
+  const int na = ie - i0, nb = je - j0;
+  if (na <= MERGE_LDS && nb <= MERGE_LDS) {
+    __shared__ int sa[4][MERGE_LDS], sb[4][MERGE_LDS];
+    __shared__ int2 pair[4][2 * MERGE_LDS];
+    const int wv = threadIdx.x >> 6;
+    for (int k = lane; k < na; k += 64) sa[wv][k] = ca[i0 + k];
+    for (int k = lane; k < nb; k += 64) sb[wv][k] = cb[j0 + k];
+    wave_lds_sync();
+    if (lane == 0) {
+      int i = 0, j = 0, o = 0;
+      while (i < na || j < nb) {
+        if (j >= nb || (i < na && sa[wv][i] < sb[wv][j])) pair[wv][o] = make_int2(i++, -1);
+        else if (i >= na || sb[wv][j] < sa[wv][i]) pair[wv][o] = make_int2(-1, j++);
+        else pair[wv][o] = make_int2(i++, j++);
+        ++o;
+      }
+    }
+    wave_lds_sync();
+    const int no = rc[r + 1] - o0;
+    for (int k = lane; k < no; k += 64) {
+      const int2 pr = pair[wv][k];
+      cc[o0 + k] = pr.x >= 0 ? sa[wv][pr.x] : sb[wv][pr.y];
+    }
+    for (int64_t e = lane; e < int64_t(no) * bsz; e += 64) {
+      const int k = int(e / bsz), q = int(e % bsz);
+      const int2 pr = pair[wv][k];
+      double v;
+      if (pr.x >= 0 && pr.y >= 0)
+        v = add_rn(va[int64_t(i0 + pr.x) * bsz + q], vb[int64_t(j0 + pr.y) * bsz + q]);
+      else if (pr.x >= 0)
+        v = va[int64_t(i0 + pr.x) * bsz + q];
+      else
+        v = vb[int64_t(j0 + pr.y) * bsz + q];
+      vc[int64_t(o0) * bsz + e] = v;
+    }
     return;
   }
   if (lane != 0) return;

@@ -775,12 +775,6 @@ __device__ __forceinline__ void add_staged(int slot, int nslot, const double (*p
   }
 }
 
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 // P = P_t - omega D_l1^{-1} A P_t, one wavefront per aggregated row i: the row's blocks of
 // A go through in chunks of 64, a lane per block (i, v) forming A_iv P_t,v (key agg(v)),
 // summed per block (i, J) of P in ascending block order; then the lane of (i, J) scales by

@@ -210,9 +210,8 @@ static double power_estimate(Handle& h, Level& L, const unsigned char* dec) {
 // FP16 values of a transfer operator (FP32 when a value would overflow FP16)
 static void to_fp16_or_fp32(Ctx& c, BSR& A) {
   const int64_t nv = std::max<int64_t>(A.nnzb, 1) * A.bsz();
-  A.valh.alloc(size_t((std::max<int64_t>(A.nnzb, 1) + 63) / 64 * 64) * A.bsz());
   AMGF_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int), c.s));
-  cast_d2h_chunked(c, A.val.p, A.valh.p, A.nnzb, int(A.bsz()), c.flag.p);
+  cast_d2h_transfer(c, A, c.flag.p);
   if (d2h_scalar(c.flag.p, c.s) == 0) return;
   A.valh = DBuf<_Float16>();
   A.val32.alloc(nv);

@@ -29,6 +29,11 @@ void transfer_spmv(Ctx& c, int mode, const BSR& A, const float* x, float* y,
 // rounded up to a multiple of 64 blocks), one rounding to nearest even; *flag |= 1 when a
 // value overflows FP16
 void cast_d2h_chunked(Ctx& c, const double* a, _Float16* b, int64_t nb, int N, int* flag);
+// A.valh = FP16(A.val) in the layout the FP16 transfer kernel for A reads (chunked when it
+// gives a block row a whole wavefront, row-major blocks otherwise; allocated here)
+void cast_d2h_transfer(Ctx& c, BSR& A, int* flag);
+// lanes per block row of the FP16 transfer kernel for A's shape and density
+int transfer_lanes(const BSR& A);
 
 // Build the sliced-ELL copy (FP64 values when fp64, FP32 values when fp32) of a 3x3
 // BSR matrix; bsr_spmv then reads it in place of the BSR arrays.

@@ -18,6 +18,25 @@ __device__ __forceinline__ void load_block(const TV* __restrict__ v, T* out) {
   for (int k = 0; k < N; ++k) out[k] = T(v[k]);
 }
 
+// block j of a row-major FP16 copy widened to T, two values per load (N even: the block
+// starts on a 4-byte boundary)
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+template <int N, class T>
+__device__ __forceinline__ void load_block_h(const _Float16* __restrict__ v, T* out) {
+  if constexpr (N % 2 == 0) {
+    const half2v* v2 = reinterpret_cast<const half2v*>(v);
+#pragma unroll
+    for (int k = 0; k < N / 2; ++k) {
+      const half2v h = v2[k];
+      out[2 * k] = T(h.x);
+      out[2 * k + 1] = T(h.y);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[k] = T(v[k]);
+  }
+}
+
 // block j of a chunked FP16 copy (BSR::valh) widened to T: N / G loads of G values, each
 // reading the same G entries of the chunk's 64 blocks side by side
 template <int N, class T>
@@ -59,8 +78,10 @@ __global__ void __launch_bounds__(256) k_bsr(int nrows, const int* __restrict__ 
       xv[q] = (MODE == SPMV_PRE) ? w[ix] * b[ix] : x[ix];
     }
     T v[BR * BC];
-    if constexpr (std::is_same_v<TV, _Float16>)
+    if constexpr (std::is_same_v<TV, _Float16> && G == 64)
       load_block_chunked<BR * BC>(val, j, v);
+    else if constexpr (std::is_same_v<TV, _Float16>)
+      load_block_h<BR * BC>(val + int64_t(j) * (BR * BC), v);
     else
       load_block<BR * BC>(val + int64_t(j) * (BR * BC), v);
 #pragma unroll
@@ -182,11 +203,20 @@ static void launch_bsr_h(Ctx& c, int mode, const BSR& A, const float* x, float* 
   AMGF_LAUNCH_CHECK();
 }
 
+// lanes per block row of the FP16 transfer kernel for this operator's shape and density
+int transfer_lanes(const BSR& A) {
+  if (A.br == 6 && A.bc == 3) return 64;
+  if (A.br == 6 && A.bc == 6) return A.nrows > 0 && double(A.nnzb) / A.nrows > 24 ? 64 : 16;
+  return 8;
+}
+
 void transfer_spmv(Ctx& c, int mode, const BSR& A, const float* x, float* y, const float* w,
                    float* xo) {
   if (A.nrows == 0) return;
   if (!A.valh.p) return bsr_spmv<float>(c, mode, A, A.val32.p, x, y, nullptr, w, xo);
   const double avg = double(A.nnzb) / A.nrows;
+  AMGF_REQUIRE(A.valh_chunked == (transfer_lanes(A) == 64), AMGF_EDEVICE,
+               "FP16 copy laid out for another launch");
   if (A.br == 3 && A.bc == 3) return launch_bsr_h<3, 3, 8>(c, mode, A, x, y, w, xo);
   if (A.br == 3 && A.bc == 6) return launch_bsr_h<3, 6, 8>(c, mode, A, x, y, w, xo);
   if (A.br == 6 && A.bc == 3) return launch_bsr_h<6, 3, 64>(c, mode, A, x, y, w, xo);
@@ -213,6 +243,31 @@ __global__ void k_d2h_chunked(const double* __restrict__ a, _Float16* __restrict
   const _Float16 h = _Float16(f);
   b[(j >> 6) * (64 * N) + (e / G) * (64 * G) + (j & 63) * G + e % G] = h;
   if (!__builtin_isfinite(float(h))) atomicOr(flag, 1);
+}
+__global__ void k_d2h(const double* __restrict__ a, _Float16* __restrict__ b, int64_t n,
+                      int* __restrict__ flag) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = a[i];
+  float f = __double2float_rz(v);
+  if (double(f) != v) f = __uint_as_float(__float_as_uint(f) | 1u);
+  const _Float16 h = _Float16(f);
+  b[i] = h;
+  if (!__builtin_isfinite(float(h))) atomicOr(flag, 1);
+}
+void cast_d2h_transfer(Ctx& c, BSR& A, int* flag) {
+  const int N = int(A.bsz());
+  A.valh_chunked = transfer_lanes(A) == 64;
+  if (A.valh_chunked) {
+    A.valh.alloc(size_t((std::max<int64_t>(A.nnzb, 1) + 63) / 64 * 64) * N);
+    cast_d2h_chunked(c, A.val.p, A.valh.p, A.nnzb, N, flag);
+    return;
+  }
+  A.valh.alloc(size_t(std::max<int64_t>(A.nnzb, 1)) * N);
+  if (A.nnzb)
+    hipLaunchKernelGGL(k_d2h, dim3(grid_for(A.nnzb * N, 256)), dim3(256), 0, c.s, A.val.p,
+                       A.valh.p, A.nnzb * N, flag);
+  AMGF_LAUNCH_CHECK();
 }
 void cast_d2h_chunked(Ctx& c, const double* a, _Float16* b, int64_t nb, int N, int* flag) {
   if (nb)

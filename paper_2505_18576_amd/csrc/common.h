@@ -142,11 +142,14 @@ struct BSR {
   DBuf<int> rowptr, col;
   DBuf<double> val;
   DBuf<float> val32;       // FP32 copy used by the mixed-precision V-cycle
-  // FP16 copy (transfer operators of the mixed V-cycle) in chunks of 64 blocks: entry e of
-  // block j at valh[64 N (j / 64) + 64 G (e / G) + G (j % 64) + e % G], N = br * bc entries
-  // per block, G = fp16_group(N), so lanes that read consecutive blocks read one contiguous
-  // stretch per load (nnzb rounded up to whole chunks)
+  // FP16 copy (transfer operators of the mixed V-cycle).  Chunked (valh_chunked) where
+  // the transfer kernel gives a block row a whole wavefront: chunks of 64 blocks, entry e
+  // of block j at valh[64 N (j / 64) + 64 G (e / G) + G (j % 64) + e % G], N = br * bc
+  // entries per block, G = fp16_group(N), so the lanes, which read consecutive blocks, read
+  // one contiguous stretch per load (nnzb rounded up to whole chunks); otherwise row-major
+  // blocks like val (lanes of short rows read a few blocks each)
   DBuf<_Float16> valh;
+  bool valh_chunked = false;
   // Sliced-ELL copy of a 3x3 matrix for the apply phase (built by bsr_build_sell):
   // slices of 64 block rows, each padded to its longest row.  Slot j of slice s holds
   // the column ids at sell_col[sell_off[s] + 64 j + i] and entry (p,q) of row i's block

@@ -145,6 +145,8 @@ __global__ void __launch_bounds__(256) k_neg_gemv(int n, const double* __restric
   if (i >= n) return;
   const double* row = X + int64_t(i) * n;
   double s = 0.0;
+  // unrolled so that several loads of the row are in flight (the sum keeps its order)
+#pragma unroll 8
   for (int j = lane; j < n; j += 64) s += row[j] * b[j];
   s = wave_sum(s);
   if (lane == 0) y[i] = -s;

@@ -817,6 +817,10 @@ static void vcycle32_from(Handle& h, size_t l, bool x0_ready) {
   Ctx& c = h.ctx;
   Level& L = *h.lev[l];
   if (l + 1 == h.lev.size()) {
+    if (h.coarse_inverse) {                           // FP32 in and out, FP64 product
+      h.coarse_inv.solve_f32(c, L.fb.p, L.fx.p);
+      return;
+    }
     cast_f2d(c, L.fb.p, h.coarse_b.p, L.n());
     coarse_solve(h, h.coarse_b.p, h.coarse_x.p);
     cast_d2f(c, h.coarse_x.p, L.fx.p, L.n());

@@ -16,6 +16,9 @@ struct DenseInverse {
   bool setup(Ctx& c, const BSR& A);
   // x = A^{-1} b (b, x: n FP64, may not alias)
   void solve(Ctx& c, const double* b, double* x) const;
+  // the same for FP32 vectors: b widened exactly, the product in FP64, x rounded once
+  // (bitwise the FP64 solve between the two casts)
+  void solve_f32(Ctx& c, const float* b, float* x) const;
 };
 
 }  // namespace amgf

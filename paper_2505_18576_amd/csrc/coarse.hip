@@ -136,10 +136,12 @@ __global__ void k_mirror(int n, double* __restrict__ X) {
   if (j < i) X[t] = X[int64_t(j) * n + i];
 }
 
-// y_i = -sum_j X_ij b_j, one wavefront per row
+// y_i = -sum_j X_ij b_j, one wavefront per row (FP64 sums; b and y FP64, or FP32 widened
+// exactly and rounded once)
+template <class TB>
 __global__ void __launch_bounds__(256) k_neg_gemv(int n, const double* __restrict__ X,
-                                                  const double* __restrict__ b,
-                                                  double* __restrict__ y) {
+                                                  const TB* __restrict__ b,
+                                                  TB* __restrict__ y) {
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= n) return;
@@ -147,9 +149,9 @@ __global__ void __launch_bounds__(256) k_neg_gemv(int n, const double* __restric
   double s = 0.0;
   // unrolled so that several loads of the row are in flight (the sum keeps its order)
 #pragma unroll 8
-  for (int j = lane; j < n; j += 64) s += row[j] * b[j];
+  for (int j = lane; j < n; j += 64) s += row[j] * double(b[j]);
   s = wave_sum(s);
-  if (lane == 0) y[i] = -s;
+  if (lane == 0) y[i] = TB(-s);
 }
 
 }  // namespace
@@ -183,7 +185,15 @@ bool DenseInverse::setup(Ctx& c, const BSR& A) {
 
 void DenseInverse::solve(Ctx& c, const double* b, double* x) const {
   if (!n) return;
-  hipLaunchKernelGGL(k_neg_gemv, dim3(grid_for(n, 4)), dim3(256), 0, c.s, n, X.p, b, x);
+  hipLaunchKernelGGL(k_neg_gemv<double>, dim3(grid_for(n, 4)), dim3(256), 0, c.s, n, X.p, b,
+                     x);
+  AMGF_LAUNCH_CHECK();
+}
+
+void DenseInverse::solve_f32(Ctx& c, const float* b, float* x) const {
+  if (!n) return;
+  hipLaunchKernelGGL(k_neg_gemv<float>, dim3(grid_for(n, 4)), dim3(256), 0, c.s, n, X.p, b,
+                     x);
   AMGF_LAUNCH_CHECK();
 }
 
